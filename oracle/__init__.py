@@ -1,0 +1,27 @@
+"""CPU oracle for the messenger-field Wiener filter and Wiener-posterior sampler.
+
+TEST INFRASTRUCTURE ONLY.  This package is a plain, slow, FP64 numpy
+implementation of what the GPU library computes, written from the paper
+(Jeffrey, Heavens & Fortio, "Fast Sampling from Wiener Posteriors for Image
+Data with Dataflow Engines"):
+
+* ``philox``    - the counter-based normal stream both sides draw from
+                  (Philox4x32-10 + Box-Muller; the paper's CPU code uses
+                  Box-Muller, Sec. 3.2);
+* ``messenger`` - Algorithm 1 (messenger-field sampler) step by step, its
+                  G(0,1) -> 0 variant that converges to the Wiener filter
+                  (Sec. 2.2), cooling and the convergence residual;
+* ``dense``     - the plain definitions the method converges to: the Wiener
+                  filter of Eq. 2-3 and the posterior covariance of Eq. 7,
+                  by dense linear algebra on small images, plus the exact
+                  stationary law of the Gibbs chain;
+* ``adjoint``   - gradients of the Wiener-filter map with respect to the data
+                  and to band amplitudes of the power spectrum (implicit
+                  differentiation of the normal equations of Eq. 7).
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import it.  It shares no code with the GPU path and never
+imports it; the two meet only through the seeded inputs of
+``paper_1810_02821_amd.synth``.
+"""
+from . import philox, messenger, dense, adjoint  # noqa: F401

@@ -1,0 +1,203 @@
+"""Pins of the messenger oracle (Algorithm 1 and its Wiener-filter variant)
+against the dense definitions, closed forms and invariants."""
+import numpy as np
+import pytest
+
+from oracle import dense, messenger as M
+from paper_1810_02821_amd import synth
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(np.ravel(a - b)) / np.linalg.norm(np.ravel(b)))
+
+
+@pytest.fixture(scope="module")
+def small16():
+    p = synth.config_small(0, 16)
+    S = dense.signal_covariance(p.spectrum, 16, 16)
+    return p, S
+
+
+def test_wiener_converges_to_dense_eq2(small16):
+    p, S = small16
+    s, info = M.wiener(p, M.Schedule((1.0,), (0,), 1e-12, 100000, 10))
+    assert info.converged
+    assert _rel(s, dense.wiener_dense(S, p.noise_var, p.d)) < 1e-9
+
+
+def test_wiener_32_with_cooling_matches_dense_1024_solve():
+    # the small workload: 32x32, 100 geometric levels from 1e4 to 1
+    p = synth.config_small(0, 32)
+    S = dense.signal_covariance(p.spectrum, 32, 32)
+    sched = M.Schedule.geometric(1e4, 1.0, 100, 10, tol=1e-11, max_sweeps=100000)
+    s, info = M.wiener(p, sched)
+    assert info.converged
+    assert _rel(s, dense.wiener_dense(S, p.noise_var, p.d)) < 1e-8
+
+
+@pytest.mark.parametrize("lam", [3.0, 30.0])
+def test_cooling_level_fixed_point_is_wiener_with_inflated_noise(small16, lam):
+    p, S = small16
+    s, info = M.wiener(p, M.Schedule((lam,), (0,), 1e-12, 100000, 10))
+    ref = dense.wiener_dense(S, dense.effective_noise(p.noise_var, lam), p.d)
+    assert info.converged and _rel(s, ref) < 1e-9
+
+
+def test_gibbs_chain_stationary_law_is_the_wiener_posterior(small16):
+    """The sweep is affine in (s, xi, eta); its exact stationary mean and
+    covariance (discrete Lyapunov) must be s_W and (S^-1 + N^-1)^-1 (Eq. 7)."""
+    p, S = small16
+    c = M.coefficients(p.noise_var, p.spectrum)
+    b = c.ninv * p.d
+    fn = lambda s, xi, eta: M.sweep(s, b, c, xi, eta)[0]
+    Mm, cc, B = dense.chain_transition(fn, 16, 16)
+    mean, Sigma = dense.stationary_law(Mm, cc, B)
+    assert _rel(mean, dense.wiener_dense(S, p.noise_var, p.d).ravel()) < 1e-11
+    assert _rel(Sigma, dense.posterior_covariance(S, p.noise_var)) < 1e-11
+
+
+def test_pair_chains_are_independent_real_samples():
+    # the imaginary chain of a pair sees the same conditional law as the real
+    # one and no cross-covariance: probe the response of Im to every input
+    p = synth.config_small(1, 8)
+    c = M.coefficients(p.noise_var, p.spectrum)
+    b = c.ninv * p.d
+    zero = np.zeros((8, 8), dtype=complex)
+    base = M.sweep(zero, b, c, zero, zero)[0]
+    Br, Bi = [], []
+    for i in range(64):
+        e = np.zeros(64, dtype=complex)
+        e[i] = 1.0
+        e = e.reshape(8, 8)
+        for z in (e, 1j * e):
+            Br.append((M.sweep(zero, b, c, z, zero)[0] - base).real.ravel())
+            Bi.append((M.sweep(zero, b, c, z, zero)[0] - base).imag.ravel())
+            Br.append((M.sweep(zero, b, c, zero, z)[0] - base).real.ravel())
+            Bi.append((M.sweep(zero, b, c, zero, z)[0] - base).imag.ravel())
+    Br, Bi = np.array(Br).T, np.array(Bi).T
+    assert np.allclose(Br @ Br.T, Bi @ Bi.T, atol=1e-12)
+    assert np.allclose(Br @ Bi.T, 0.0, atol=1e-12)
+    assert np.allclose(base.real, base.imag, atol=1e-12)
+
+
+def test_homoscedastic_unmasked_one_sweep_is_fourier_wiener_filter():
+    H = W = 16
+    spec = synth.spectrum_powerlaw(1.0, 1.0, 2.0)
+    rng = np.random.default_rng(2)
+    d = rng.standard_normal((H, W))
+    nv = np.full((H, W), 0.8)
+    p = synth.Problem(H, W, d, nv, np.zeros((H, W), bool), spec, d)
+    s, _ = M.wiener(p, M.Schedule.fixed(1))
+    S = dense.signal_covariance(spec, H, W)
+    assert _rel(s, dense.wiener_dense(S, nv, d)) < 1e-12
+    # and a single sampler sweep is already an exact posterior draw: its
+    # transition ignores the old state and injects exactly the posterior covariance
+    c = M.coefficients(nv, spec)
+    fn = lambda s_, xi, eta: M.sweep(s_, c.ninv * d, c, xi, eta)[0]
+    Mm, cc, B = dense.chain_transition(fn, H, W)
+    assert np.max(np.abs(Mm)) < 1e-12
+    assert _rel(B @ B.T, dense.posterior_covariance(S, nv)) < 1e-11
+
+
+def test_all_masked_filter_is_zero_and_chain_samples_the_prior():
+    H = W = 8
+    spec = synth.spectrum_powerlaw(1.0, 1.0, 2.0)
+    nv = np.full((H, W), np.inf)
+    p = synth.Problem(H, W, np.zeros((H, W)), nv, np.ones((H, W), bool), spec, np.zeros((H, W)))
+    s, _ = M.wiener(p, M.Schedule.fixed(50))
+    assert np.all(s == 0)
+    c = M.coefficients(nv, spec)
+    fn = lambda s_, xi, eta: M.sweep(s_, np.zeros((H, W)), c, xi, eta)[0]
+    Mm, cc, B = dense.chain_transition(fn, H, W)
+    mean, Sigma = dense.stationary_law(Mm, cc, B)
+    assert np.allclose(mean, 0)
+    assert _rel(Sigma, dense.signal_covariance(spec, H, W)) < 1e-11
+
+
+def test_residual_identity(small16):
+    """||t_k - t_{k+1}|| / (T ||N^-1 d||) equals the normal-equation residual."""
+    p, _ = small16
+    c = M.coefficients(p.noise_var, p.spectrum)
+    b = c.ninv * p.d
+    s = np.zeros((16, 16))
+    for _ in range(37):
+        s, t_k = M.sweep(s, b, c)
+    s_next, t_k1 = M.sweep(s, b, c)
+    lhs = np.linalg.norm(t_k - t_k1) / (c.T * np.linalg.norm(b))
+    assert abs(lhs - M.residual(p, s)) < 1e-12 * max(1.0, lhs)
+
+
+def test_wiener_is_linear_and_shift_equivariant(small16):
+    p, _ = small16
+    sched = M.Schedule.fixed(200)
+    s1, _ = M.wiener(p, sched)
+    q = synth.Problem(p.H, p.W, 2.5 * p.d, p.noise_var, p.mask, p.spectrum, p.s_true)
+    s2, _ = M.wiener(q, sched)
+    assert _rel(s2, 2.5 * s1) < 1e-12
+    sh = (3, -5)
+    r = synth.Problem(p.H, p.W, np.roll(p.d, sh, (0, 1)), np.roll(p.noise_var, sh, (0, 1)),
+                      np.roll(p.mask, sh, (0, 1)), p.spectrum, p.s_true)
+    s3, _ = M.wiener(r, sched)
+    assert _rel(s3, np.roll(s1, sh, (0, 1))) < 1e-12
+
+
+def test_masked_pixels_ignore_data(small16):
+    p, _ = small16
+    d2 = p.d.copy()
+    d2[p.mask] = 123.0
+    q = synth.Problem(p.H, p.W, d2, p.noise_var, p.mask, p.spectrum, p.s_true)
+    a, _ = M.wiener(p, M.Schedule.fixed(100))
+    b, _ = M.wiener(q, M.Schedule.fixed(100))
+    assert np.array_equal(a, b)
+
+
+def test_sampler_mean_and_variance_match_posterior():
+    """Monte Carlo over independent chains (the paper's Fig. 3 checks): mean of
+    samples ~ Wiener filter, variance ~ diag of the posterior covariance."""
+    p = synth.config_small(2, 8)
+    S = dense.signal_covariance(p.spectrum, 8, 8)
+    sw = dense.wiener_dense(S, p.noise_var, p.d)
+    C = dense.posterior_covariance(S, p.noise_var)
+    smp = M.sample(p, seed=1000, problem_index=0, n_chains=48, burn_in=30, n_samples=400)
+    chain_means = smp.mean(axis=1)                 # (48, 8, 8), nearly independent
+    se = chain_means.std(axis=0, ddof=1) / np.sqrt(chain_means.shape[0])
+    z = np.abs(chain_means.mean(axis=0) - sw) / se
+    assert z.max() < 5.0
+    var = smp.reshape(-1, 64).var(axis=0)
+    chain_vars = smp.var(axis=1).reshape(48, 64)
+    se_v = chain_vars.std(axis=0, ddof=1) / np.sqrt(48)
+    zv = np.abs(var - np.diag(C)) / se_v
+    assert zv.max() < 5.0
+    # variance is larger on masked pixels than on observed ones (Sec. 4.1)
+    assert var.reshape(8, 8)[p.mask].mean() > var.reshape(8, 8)[~p.mask].mean()
+
+
+def _rhat(x):
+    m = x.shape[1]
+    W = x.var(axis=1, ddof=1).mean(axis=0)
+    B = m * x.mean(axis=1).var(axis=0, ddof=1)
+    return np.sqrt(((m - 1) / m * W + B / m) / W)
+
+
+def test_dispersed_chains_converge_rhat():
+    """Chains from dispersed starts converge (Fig. 1): Gelman-Rubin R-hat of
+    the post-burn-in samples is below the usual 1.1, while the first sweeps
+    of the same chains are far from converged."""
+    p = synth.config_small(3, 8)
+    smp = M.sample(p, seed=1000, problem_index=0, n_chains=8, burn_in=0,
+                   n_samples=1400, init_scale=30.0)
+    assert _rhat(smp[:, :60]).max() > 1.5
+    assert _rhat(smp[:, 400:]).max() < 1.1
+    s0 = M.initial_state(1000, 0, 0, 8, 8, 30.0)
+    assert np.abs(s0).std() > 10
+
+
+def test_sample_pair_resume_is_exact():
+    """Counter-based draws make 30 sweeps == 12 sweeps + resume for 18."""
+    p = synth.config_small(0, 8)
+    full, s_full = M.sample_pair(p, 1000, 0, 0, burn_in=0, n_samples=30)
+    _, s_mid = M.sample_pair(p, 1000, 0, 0, burn_in=12, n_samples=0)
+    rest, s_end = M.sample_pair(p, 1000, 0, 0, burn_in=0, n_samples=18, s0=s_mid,
+                                sweep_offset=12)
+    assert np.array_equal(full[:, 12:], rest)
+    assert np.array_equal(s_full, s_end)
