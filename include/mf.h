@@ -1,0 +1,206 @@
+/*
+ * mf.h - messenger-field Wiener filter and Wiener-posterior sampler for
+ *        AMD Instinct MI355X (gfx950).
+ *
+ * The method (Jeffrey, Heavens & Fortio, "Fast Sampling from Wiener Posteriors
+ * for Image Data with Dataflow Engines"):
+ *   data model d = A s + n with A = I (Sec. 1.1, Eq. 1); diagonal pixel noise
+ *   covariance N, missing pixels having infinite variance (Sec. 1.1); a
+ *   statistically homogeneous signal whose covariance S is diagonal in Fourier
+ *   space with an isotropic power spectrum P(|k|) (Eq. 8-9).  The Wiener filter
+ *   s_W = S (S + N)^-1 d (Eq. 2-3) is the mean of the Wiener posterior (Eq. 7);
+ *   Algorithm 1 (Sec. 2.2) draws posterior samples with a messenger field t of
+ *   covariance T = tau I, tau = min N, alternating a pixel-space draw of t and a
+ *   Fourier-space draw of s; with its Gaussian variates set to zero the same
+ *   iteration converges to s_W (Sec. 2.2).
+ *
+ * Conventions used throughout:
+ *   - images are H x W, row-major, float32; several problems are concatenated
+ *     in one array in problem order (mf_plan_pixel_offset gives the offsets);
+ *   - wavenumbers are integer grid indices, |k| = sqrt(kx^2 + ky^2); P is in the
+ *     synthesis convention s_x = sum_k s_k exp(+2 pi i k.x/N), <|s_k|^2> = P;
+ *   - tau = min N_i over observed pixels (1 if none is observed); a cooling
+ *     level lambda >= 1 uses T = lambda tau with Nbar = N - tau fixed, whose fixed
+ *     point is the Wiener filter for noise N + (lambda - 1) tau;
+ *   - two chains travel as the real and imaginary parts of one complex field
+ *     (a "pair"); chain 2p is Re and chain 2p+1 is Im of pair p;
+ *   - Gaussian variates come from Philox4x32-10 with Box-Muller (Sec. 3.2 uses
+ *     Box-Muller on the CPU): key = (seed lo, seed hi), counter =
+ *     (elem >> 1, global sweep, (problem << 8) | stage, pair); words (x0,x1)
+ *     feed element 2j and (x2,x3) element 2j+1; u1 = ((x>>8)+1) 2^-24,
+ *     u2 = (x>>8) 2^-24, z0 = sqrt(-2 ln u1) cos(2 pi u2), z1 = ... sin(...).
+ *     stage 0 = pixel draw of t (elem = row-major pixel), stage 1 = Fourier
+ *     draw of s (elem = row-major mode index in unshifted FFT order), stage 2 =
+ *     dispersed initial state.  The stream does not depend on how the work is
+ *     tiled or batched, so every execution form yields the same samples.
+ *
+ * Memory: every pointer argument documented "device" is memory on the current
+ * HIP device owned by the caller; the plan owns its own tables and workspaces
+ * and frees them in mf_plan_destroy.  "host" pointers are read during the
+ * call only.  All entry points enqueue work on `stream` (a hipStream_t; NULL
+ * is the null stream) and return once it is enqueued, except where a result is
+ * returned to the host (mf_info, convergence tests), which synchronises the
+ * stream.  A plan must not be used from two streams at once.
+ *
+ * Errors: every entry point returns an mf_status; no C++ exception crosses the
+ * boundary.  mf_last_error() returns a thread-local message for the last
+ * failure on the calling thread.
+ */
+#ifndef MF_H
+#define MF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct mf_plan_s* mf_plan;
+typedef void* mf_stream; /* hipStream_t */
+
+typedef enum {
+    MF_OK = 0,
+    MF_ERR_INVALID_ARG = 1,      /* a pointer, size, variance or count is invalid */
+    MF_ERR_UNSUPPORTED_SIZE = 2, /* H or W is not 2^a with 16 <= N <= 4096 (W even) */
+    MF_ERR_OUT_OF_MEMORY = 3,    /* a plan table or workspace could not be allocated */
+    MF_ERR_DEVICE = 4,           /* a HIP runtime call failed */
+    MF_ERR_NOT_CONVERGED = 5,    /* tol > 0 not reached within max_sweeps (result still written) */
+    MF_ERR_NONFINITE = 6         /* a NaN/Inf appeared in an output */
+} mf_status;
+
+/* Power spectrum P(|k|) of the signal (Eq. 9). */
+enum { MF_PK_POWERLAW = 0, MF_PK_BANDS = 1 };
+typedef struct {
+    int32_t kind;              /* MF_PK_POWERLAW or MF_PK_BANDS */
+    double amp, k0, n;         /* powerlaw: P(k) = amp * (k + k0)^(-n), P > 0 everywhere */
+    int32_t n_bands;           /* bands: P(k) = band_amps[b] for band_edges[b] <= k < band_edges[b+1] */
+    const double* band_edges;  /* host, n_bands + 1 increasing values; the last band is closed */
+    const double* band_amps;   /* host, n_bands values > 0 */
+} mf_spectrum;
+
+/* One image problem. */
+typedef struct {
+    int32_t H, W;              /* image size; each a power of two in [16, 4096] */
+    const float* noise_var;    /* host, H*W: N_i > 0, +INFINITY marks a missing pixel */
+    mf_spectrum spectrum;
+} mf_problem;
+
+/* Cooling schedule of the Wiener filter (zero-variate Algorithm 1).
+ * Level j runs sweeps[j] sweeps at T = lambda[j] tau.  Then, if tol > 0, the
+ * last level continues until the residual r = ||t_k - t_{k-1}|| / (T ||b||)
+ * (b = N_eff^-1 d, so r = ||(S^-1 + N_eff^-1) s - b|| / ||b||) is <= tol,
+ * tested on sweeps whose global count is a multiple of check_every, or until
+ * max_sweeps sweeps have run in total. */
+typedef struct {
+    int32_t n_levels;          /* >= 1 */
+    const double* lambda;      /* host, n_levels values >= 1 (the last is normally 1) */
+    const int32_t* sweeps;     /* host, n_levels values >= 0 */
+    double tol;                /* <= 0: no convergence phase */
+    int32_t max_sweeps;        /* total cap when tol > 0 */
+    int32_t check_every;       /* >= 2 when tol > 0 */
+} mf_schedule;
+
+/* Per-problem outcome of an iterative solve (host). */
+typedef struct {
+    int32_t sweeps;            /* sweeps run */
+    int32_t converged;         /* 1 if tol was reached (or tol <= 0) */
+    double residual;           /* last tested residual, NaN if none was tested */
+} mf_info;
+
+/* Execution forms of the sampler. */
+enum {
+    MF_FORM_AUTO = 0,          /* persistent LDS-resident kernel where the image fits, else streamed */
+    MF_FORM_PERSISTENT = 1,    /* one launch runs every sweep of every chain pair (H = W <= 128) */
+    MF_FORM_STREAMED = 2,      /* two kernels per sweep over all pairs, field in HBM between them */
+    MF_FORM_PLAIN = 3          /* one chain pair at a time, per-sweep kernels, no batching */
+};
+
+/* Plan flags. */
+enum {
+    MF_FLAG_NONE = 0,
+    MF_FLAG_AUTOTUNE = 1       /* time candidate tilings of the streamed kernels at plan creation */
+};
+
+/* Arguments of mf_sample. */
+typedef struct {
+    uint64_t seed;             /* Philox key */
+    int32_t chains_per_problem;/* >= 1; pairs = ceil(chains / 2), an odd count drops the last Im chain */
+    int32_t burn_in;           /* sweeps before the first sample (>= 0) */
+    int32_t n_samples;         /* samples per chain (>= 0) */
+    int32_t thin;              /* sweeps per sample after burn-in (>= 1) */
+    int64_t sweep_offset;      /* global sweep index of the first sweep (for resuming a chain) */
+    float init_scale;          /* > 0: start from init_scale * stage-2 normals (ignored if state_in) */
+    int32_t form;              /* MF_FORM_* */
+} mf_sample_args;
+
+/* Create a plan for n_problems problems (Algorithm 1's definitions: tau, Nbar,
+ * n P(|k|) evaluated in FP64 and stored in FP32, FFT twiddles evaluated in FP64).
+ * Copies all tables to the current device.  *out receives the plan. */
+mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* problems,
+                         uint32_t flags, mf_stream stream);
+
+/* Release the plan and every device buffer it owns. NULL is accepted. */
+mf_status mf_plan_destroy(mf_plan plan);
+
+/* Replace the spectrum of one problem (same kind and band count for bands).
+ * Used by gradient-based training loops over band amplitudes. */
+mf_status mf_plan_set_spectrum(mf_plan plan, int32_t problem, const mf_spectrum* spectrum);
+
+/* Element offset of problem p in concatenated image arrays (p == n_problems
+ * gives the total pixel count); -1 on a bad argument. */
+int64_t mf_plan_pixel_offset(mf_plan plan, int32_t problem);
+
+/* tau of problem p (host copy), or -1 on a bad argument. */
+double mf_plan_tau(mf_plan plan, int32_t problem);
+
+/* Wiener filter of every problem (Algorithm 1 with G(0,1) -> 0, Sec. 2.2).
+ *   d       device, concatenated float32 data (values on missing pixels are ignored)
+ *   s_init  device, concatenated start (NULL: zero)
+ *   s_out   device, concatenated result
+ *   info    host array of n_problems entries, or NULL (then no host sync unless tol > 0)
+ * Returns MF_ERR_NOT_CONVERGED if any problem missed tol (s_out still holds the
+ * last iterate). */
+mf_status mf_wiener(mf_plan plan, const float* d, const mf_schedule* schedule,
+                    const float* s_init, float* s_out, mf_info* info, mf_stream stream);
+
+/* Draw posterior samples (Algorithm 1).
+ *   d            device, concatenated float32 data
+ *   state_in     device, complex pair states [problem][pair][H][W] (float2), or NULL
+ *   state_out    device, same layout, final states, or NULL
+ *   samples_out  device, float32 [problem][chain][sample][H][W] concatenated over
+ *                problems (problem p starts at chains * n_samples * pixel_offset(p)), or NULL
+ */
+mf_status mf_sample(mf_plan plan, const float* d, const mf_sample_args* args,
+                    const float* state_in, float* state_out, float* samples_out,
+                    mf_stream stream);
+
+/* Vector-Jacobian product of the Wiener-filter map (d, P) -> s_W by implicit
+ * differentiation of the normal equations (S^-1 + N^-1) s_W = N^-1 d read off
+ * Eq. 7: v solves (S^-1 + N^-1) v = grad_s by the messenger iteration (pixel
+ * step t = (1 - a) v + T grad_s), then
+ *   grad_d     = N^-1 v (0 on missing pixels)                     device, concatenated
+ *   grad_bands = sum_{k in b} Re(conj(v_k) s_k) / (n^2 theta_b^2)  device float64,
+ *                bands of every band-spectrum problem concatenated (NULL allowed)
+ * with v_k, s_k the unnormalised DFTs of v and s_wf.  grad_bands needs s_wf.
+ *   s_wf, grad_s device, concatenated;  v_out device or NULL (the adjoint field).
+ */
+mf_status mf_wiener_backward(mf_plan plan, const float* s_wf, const float* grad_s,
+                             const mf_schedule* schedule, float* grad_d, double* grad_bands,
+                             float* v_out, mf_info* info, mf_stream stream);
+
+/* Band cross-power sum_{k in b} Re(conj(x_k) y_k) of two concatenated real
+ * fields (unnormalised DFTs) for every band-spectrum problem; device float64 out. */
+mf_status mf_band_power(mf_plan plan, const float* x, const float* y, double* out,
+                        mf_stream stream);
+
+/* Number of bands over all band-spectrum problems (length of grad_bands). */
+int32_t mf_plan_total_bands(mf_plan plan);
+
+const char* mf_status_string(mf_status status);
+const char* mf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MF_H */

@@ -1,0 +1,272 @@
+"""ctypes binding of libmf (include/mf.h).  Argument marshalling only: every
+step of the messenger sweep runs in the library's HIP kernels.  Torch supplies
+device memory (tensors on the GPU) and the stream (the current torch stream).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmf.so")
+
+MF_OK = 0
+MF_ERR_NOT_CONVERGED = 5
+STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported size", 3: "out of memory",
+          4: "device error", 5: "not converged", 6: "non-finite value"}
+MF_PK_POWERLAW, MF_PK_BANDS = 0, 1
+FORMS = {"auto": 0, "persistent": 1, "streamed": 2, "plain": 3}
+MF_FLAG_AUTOTUNE = 1
+
+
+class MFError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class NotConverged(MFError):
+    pass
+
+
+class _Spectrum(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("amp", C.c_double), ("k0", C.c_double), ("n", C.c_double),
+                ("n_bands", C.c_int32), ("band_edges", C.POINTER(C.c_double)),
+                ("band_amps", C.POINTER(C.c_double))]
+
+
+class _Problem(C.Structure):
+    _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("noise_var", C.POINTER(C.c_float)),
+                ("spectrum", _Spectrum)]
+
+
+class _Schedule(C.Structure):
+    _fields_ = [("n_levels", C.c_int32), ("lam", C.POINTER(C.c_double)),
+                ("sweeps", C.POINTER(C.c_int32)), ("tol", C.c_double),
+                ("max_sweeps", C.c_int32), ("check_every", C.c_int32)]
+
+
+class Info(C.Structure):
+    _fields_ = [("sweeps", C.c_int32), ("converged", C.c_int32), ("residual", C.c_double)]
+
+    def __repr__(self):
+        return f"Info(sweeps={self.sweeps}, converged={bool(self.converged)}, residual={self.residual:.3e})"
+
+
+class _SampleArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("chains_per_problem", C.c_int32), ("burn_in", C.c_int32),
+                ("n_samples", C.c_int32), ("thin", C.c_int32), ("sweep_offset", C.c_int64),
+                ("init_scale", C.c_float), ("form", C.c_int32)]
+
+
+EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_plan_pixel_offset",
+           "mf_plan_tau", "mf_plan_total_bands", "mf_wiener", "mf_sample", "mf_wiener_backward",
+           "mf_band_power", "mf_status_string", "mf_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libmf.so (built by __graft_entry__.build()); fails loudly if absent."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libmf.so not found at {LIB_PATH}: build it first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    L = C.CDLL(LIB_PATH)
+    vp = C.c_void_p
+    L.mf_plan_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(_Problem), C.c_uint32, vp]
+    L.mf_plan_destroy.argtypes = [vp]
+    L.mf_plan_set_spectrum.argtypes = [vp, C.c_int32, C.POINTER(_Spectrum)]
+    L.mf_plan_pixel_offset.argtypes = [vp, C.c_int32]
+    L.mf_plan_pixel_offset.restype = C.c_int64
+    L.mf_plan_tau.argtypes = [vp, C.c_int32]
+    L.mf_plan_tau.restype = C.c_double
+    L.mf_plan_total_bands.argtypes = [vp]
+    L.mf_plan_total_bands.restype = C.c_int32
+    L.mf_wiener.argtypes = [vp, vp, C.POINTER(_Schedule), vp, vp, C.POINTER(Info), vp]
+    L.mf_sample.argtypes = [vp, vp, C.POINTER(_SampleArgs), vp, vp, vp, vp]
+    L.mf_wiener_backward.argtypes = [vp, vp, vp, C.POINTER(_Schedule), vp, vp, vp, C.POINTER(Info), vp]
+    L.mf_band_power.argtypes = [vp, vp, vp, vp, vp]
+    L.mf_status_string.argtypes = [C.c_int]
+    L.mf_status_string.restype = C.c_char_p
+    L.mf_last_error.restype = C.c_char_p
+    for name in ("mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_wiener",
+                 "mf_sample", "mf_wiener_backward", "mf_band_power"):
+        getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _check(status: int, allow_not_converged: bool = False):
+    if status == MF_OK:
+        return
+    msg = lib().mf_last_error().decode()
+    if status == MF_ERR_NOT_CONVERGED:
+        if allow_not_converged:
+            return
+        raise NotConverged(status, msg)
+    raise MFError(status, msg)
+
+
+def _ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream():
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Schedule:
+    """Cooling schedule: sweeps[j] sweeps at lambda[j], then (tol > 0) run the
+    last level until the residual is <= tol, testing every check_every sweeps."""
+
+    def __init__(self, lambdas: Sequence[float] = (1.0,), sweeps: Sequence[int] = (0,),
+                 tol: float = 0.0, max_sweeps: int = 0, check_every: int = 10):
+        self.lambdas = [float(x) for x in lambdas]
+        self.sweeps = [int(x) for x in sweeps]
+        self.tol, self.max_sweeps, self.check_every = float(tol), int(max_sweeps), int(check_every)
+
+    @staticmethod
+    def geometric(lam_start, lam_end, levels, sweeps_per_level, tol=0.0, max_sweeps=0, check_every=10):
+        lams = list(np.geomspace(lam_start, lam_end, levels)) if levels > 1 else [lam_end]
+        return Schedule(lams, [sweeps_per_level] * levels, tol, max_sweeps, check_every)
+
+    @staticmethod
+    def fixed(n_sweeps: int, lam: float = 1.0):
+        return Schedule([lam], [n_sweeps])
+
+    def _c(self):
+        lam = (C.c_double * len(self.lambdas))(*self.lambdas)
+        sw = (C.c_int32 * len(self.sweeps))(*self.sweeps)
+        s = _Schedule(len(self.lambdas), lam, sw, self.tol, self.max_sweeps, self.check_every)
+        s._keep = (lam, sw)
+        return s
+
+
+def _spectrum_c(spec):
+    kind = getattr(spec, "kind")
+    if kind == "powerlaw":
+        return _Spectrum(MF_PK_POWERLAW, float(spec.amp), float(spec.k0), float(spec.n), 0, None, None), ()
+    edges = np.ascontiguousarray(spec.edges, dtype=np.float64)
+    amps = np.ascontiguousarray(spec.amps, dtype=np.float64)
+    s = _Spectrum(MF_PK_BANDS, 0.0, 0.0, 0.0, len(amps),
+                  edges.ctypes.data_as(C.POINTER(C.c_double)), amps.ctypes.data_as(C.POINTER(C.c_double)))
+    return s, (edges, amps)
+
+
+class Plan:
+    """A set of image problems (size, noise variance map with +inf on missing
+    pixels, isotropic power spectrum) with their device tables."""
+
+    def __init__(self, problems, autotune: bool = False):
+        L = lib()
+        self.problems = list(problems)
+        keep = []
+        arr = (_Problem * len(self.problems))()
+        for i, p in enumerate(self.problems):
+            nv = np.ascontiguousarray(p.noise_var, dtype=np.float32)
+            spec, k = _spectrum_c(p.spectrum)
+            keep += [nv, k]
+            arr[i] = _Problem(int(p.H), int(p.W), nv.ctypes.data_as(C.POINTER(C.c_float)), spec)
+        h = C.c_void_p()
+        _check(L.mf_plan_create(C.byref(h), len(self.problems), arr,
+                                MF_FLAG_AUTOTUNE if autotune else 0, None))
+        self._h = h
+        self.offsets = [L.mf_plan_pixel_offset(h, i) for i in range(len(self.problems) + 1)]
+        self.total_pixels = self.offsets[-1]
+        self.total_bands = L.mf_plan_total_bands(h)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().mf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def tau(self, i: int) -> float:
+        return lib().mf_plan_tau(self._h, i)
+
+    def set_spectrum(self, i: int, spectrum):
+        s, keep = _spectrum_c(spectrum)
+        _check(lib().mf_plan_set_spectrum(self._h, i, C.byref(s)))
+
+    # ---- data marshalling helpers (host numpy <-> concatenated device arrays)
+    def concat(self, arrays, device="cuda"):
+        import torch
+        flat = np.concatenate([np.asarray(a, dtype=np.float32).ravel() for a in arrays])
+        return torch.from_numpy(flat).to(device)
+
+    def split(self, flat):
+        x = flat.detach().cpu().numpy()
+        return [x[self.offsets[i]:self.offsets[i + 1]].reshape(p.H, p.W)
+                for i, p in enumerate(self.problems)]
+
+    # ---- entry points
+    def wiener(self, d, schedule: Schedule, s_init=None, out=None, allow_not_converged=False):
+        import torch
+        out = torch.empty_like(d) if out is None else out
+        info = (Info * len(self.problems))()
+        sch = schedule._c()
+        st = lib().mf_wiener(self._h, _ptr(d), C.byref(sch), _ptr(s_init), _ptr(out), info, _stream())
+        _check(st, allow_not_converged)
+        return out, list(info)
+
+    def sample(self, d, seed: int, chains: int, burn_in: int, n_samples: int, thin: int = 1,
+               sweep_offset: int = 0, init_scale: float = 0.0, form: str = "auto",
+               state_in=None, state_out=None, samples=True):
+        """Returns (samples [concat over problems of chains*n_samples*H*W] or None,
+        state_out or None)."""
+        import torch
+        out = None
+        if samples and n_samples > 0:
+            out = torch.empty(chains * n_samples * self.total_pixels, dtype=torch.float32, device=d.device)
+        args = _SampleArgs(int(seed), int(chains), int(burn_in), int(n_samples), int(thin),
+                           int(sweep_offset), float(init_scale), FORMS[form])
+        st = lib().mf_sample(self._h, _ptr(d), C.byref(args), _ptr(state_in), _ptr(state_out),
+                             _ptr(out), _stream())
+        _check(st)
+        return out, state_out
+
+    def sample_view(self, flat, problem: int, chains: int, n_samples: int):
+        p = self.problems[problem]
+        off = chains * n_samples * self.offsets[problem]
+        return flat[off:off + chains * n_samples * p.H * p.W].view(chains, n_samples, p.H, p.W)
+
+    def state_buffer(self, chains: int, device="cuda"):
+        import torch
+        pairs = (chains + 1) // 2
+        return torch.zeros(2 * pairs * self.total_pixels, dtype=torch.float32, device=device)
+
+    def wiener_backward(self, s_wf, grad_s, schedule: Schedule, want_bands=True, want_v=False,
+                        allow_not_converged=False):
+        import torch
+        grad_d = torch.empty_like(grad_s)
+        gb = None
+        if want_bands and self.total_bands > 0:
+            gb = torch.zeros(self.total_bands, dtype=torch.float64, device=grad_s.device)
+        v = torch.empty_like(grad_s) if want_v else None
+        info = (Info * len(self.problems))()
+        sch = schedule._c()
+        st = lib().mf_wiener_backward(self._h, _ptr(s_wf), _ptr(grad_s), C.byref(sch), _ptr(grad_d),
+                                      _ptr(gb), _ptr(v), info, _stream())
+        _check(st, allow_not_converged)
+        return grad_d, gb, v, list(info)
+
+    def band_power(self, x, y):
+        import torch
+        out = torch.zeros(max(self.total_bands, 1), dtype=torch.float64, device=x.device)
+        _check(lib().mf_band_power(self._h, _ptr(x), _ptr(y), _ptr(out), _stream()))
+        return out[:self.total_bands]

@@ -1,0 +1,768 @@
+// Host side of the messenger-field library: plan creation (Algorithm 1's
+// definitions evaluated in FP64), the sweep-loop drivers of every execution
+// form, and the C entry points declared in mf.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/mf.h"
+#include "mf_kernels.hpp"
+#include "mf_resident.hpp"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mf_status fail(mf_status st, const std::string& msg) {
+    g_last_error = msg;
+    return st;
+}
+
+#define MF_HIP(call)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (call);                                                                   \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(MF_ERR_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));        \
+    } while (0)
+
+bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+bool size_ok(int v) { return is_pow2(v) && v >= 16 && v <= 2048; }
+
+struct HostProblem {
+    int H = 0, W = 0;
+    int64_t pix_off = 0;
+    double tau = 1.0;
+    int kind = MF_PK_POWERLAW;
+    int n_bands = 0;
+    int band_base = 0;
+    std::vector<double> edges, amps;
+    double amp = 1, k0 = 1, n = 2;
+};
+
+// A device buffer that grows on demand and is freed with the plan.
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipError_t ensure(size_t want) {
+        if (want <= bytes) return hipSuccess;
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+        hipError_t e = hipMalloc(&p, want);
+        if (e == hipSuccess) bytes = want;
+        return e;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <typename T> T* as() const { return static_cast<T*>(p); }
+};
+
+}  // namespace
+
+struct mf_plan_s {
+    int device = 0;
+    uint32_t flags = 0;
+    std::vector<HostProblem> probs;
+    int64_t total_px = 0;
+    int total_bands = 0;
+    // (H, W) -> problems of that size, in problem order
+    std::map<std::pair<int, int>, std::vector<int>> classes;
+    // device tables
+    mf::ProbDev* d_probs = nullptr;
+    float* d_nbar = nullptr;
+    float* d_nP = nullptr;
+    int16_t* d_band = nullptr;
+    int32_t* d_band_base = nullptr;
+    int32_t* d_band_count = nullptr;
+    double* d_band_scale = nullptr;  // 1 / (n^2 theta_b^2)
+    std::map<int, float2*> d_tw;     // W_L^r for every transform length L
+    // workspaces
+    DevBuf items, field, t_save, partials, aux;
+    std::vector<float> host_nbar;    // for residual norms
+    ~mf_plan_s() {
+        (void)hipFree(d_probs);
+        (void)hipFree(d_nbar);
+        (void)hipFree(d_nP);
+        (void)hipFree(d_band);
+        (void)hipFree(d_band_base);
+        (void)hipFree(d_band_count);
+        (void)hipFree(d_band_scale);
+        for (auto& kv : d_tw) (void)hipFree(kv.second);
+        items.release();
+        field.release();
+        t_save.release();
+        partials.release();
+        aux.release();
+    }
+};
+
+namespace {
+
+// P(|k|) of one problem, evaluated in FP64 (Eq. 9).
+double spectrum_at(const HostProblem& p, double k) {
+    if (p.kind == MF_PK_POWERLAW) return p.amp * std::pow(k + p.k0, -p.n);
+    const int nb = p.n_bands;
+    for (int b = 0; b < nb; ++b) {
+        const bool in = k >= p.edges[b] && (k < p.edges[b + 1] || (b == nb - 1 && k <= p.edges[b + 1]));
+        if (in) return p.amps[b];
+    }
+    return 0.0;
+}
+
+int band_of(const HostProblem& p, double k) {
+    const int nb = p.n_bands;
+    for (int b = 0; b < nb; ++b)
+        if (k >= p.edges[b] && (k < p.edges[b + 1] || (b == nb - 1 && k <= p.edges[b + 1]))) return b;
+    return -1;
+}
+
+double kmag(int ky_idx, int kx_idx, int H, int W) {
+    const double ky = ky_idx < H - H / 2 ? ky_idx : ky_idx - H;  // numpy fftfreq * N order
+    const double kx = kx_idx < W - W / 2 ? kx_idx : kx_idx - W;
+    return std::sqrt(ky * ky + kx * kx);
+}
+
+mf_status copy_spectrum(HostProblem& hp, const mf_spectrum& s, int pidx) {
+    hp.kind = s.kind;
+    if (s.kind == MF_PK_POWERLAW) {
+        if (!(s.amp > 0) || !std::isfinite(s.amp) || !std::isfinite(s.k0) || !std::isfinite(s.n) || s.k0 <= 0)
+            return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(pidx) + ": power law needs amp > 0, k0 > 0");
+        hp.amp = s.amp;
+        hp.k0 = s.k0;
+        hp.n = s.n;
+        hp.n_bands = 0;
+        return MF_OK;
+    }
+    if (s.kind != MF_PK_BANDS) return fail(MF_ERR_INVALID_ARG, "unknown spectrum kind");
+    if (s.n_bands < 1 || s.n_bands > mf::kMaxBandsPerProblem || !s.band_edges || !s.band_amps)
+        return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(pidx) + ": bands need 1..64 bands and arrays");
+    hp.n_bands = s.n_bands;
+    hp.edges.assign(s.band_edges, s.band_edges + s.n_bands + 1);
+    hp.amps.assign(s.band_amps, s.band_amps + s.n_bands);
+    for (int b = 0; b < s.n_bands; ++b) {
+        if (!(hp.edges[b + 1] > hp.edges[b])) return fail(MF_ERR_INVALID_ARG, "band edges must increase");
+        if (!(hp.amps[b] > 0) || !std::isfinite(hp.amps[b])) return fail(MF_ERR_INVALID_ARG, "band amplitudes must be > 0");
+    }
+    return MF_OK;
+}
+
+// Upload n P(|k|) (FP64 -> FP32) for one problem; also its band map and scales.
+mf_status upload_spectrum(mf_plan p, int i) {
+    const HostProblem& hp = p->probs[i];
+    const int H = hp.H, W = hp.W;
+    const double n = (double)H * W;
+    std::vector<float> nP((size_t)H * W);
+    std::vector<int16_t> band((size_t)H * W, -1);
+    for (int ky = 0; ky < H; ++ky)
+        for (int kx = 0; kx < W; ++kx) {
+            const double k = kmag(ky, kx, H, W);
+            const double P = spectrum_at(hp, k);
+            if (!(P > 0) || !std::isfinite(n * P))
+                return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": P(k) must be finite and > 0 on every mode");
+            nP[(size_t)ky * W + kx] = (float)(n * P);
+            if (hp.kind == MF_PK_BANDS) band[(size_t)ky * W + kx] = (int16_t)band_of(hp, k);
+        }
+    MF_HIP(hipMemcpy(p->d_nP + hp.pix_off, nP.data(), nP.size() * sizeof(float), hipMemcpyHostToDevice));
+    MF_HIP(hipMemcpy(p->d_band + hp.pix_off, band.data(), band.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+    if (hp.kind == MF_PK_BANDS) {
+        std::vector<double> sc(hp.n_bands);
+        for (int b = 0; b < hp.n_bands; ++b) sc[b] = 1.0 / (n * n * hp.amps[b] * hp.amps[b]);
+        MF_HIP(hipMemcpy(p->d_band_scale + hp.band_base, sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice));
+    }
+    return MF_OK;
+}
+
+mf_status upload_twiddles(mf_plan p, int L) {
+    if (p->d_tw.count(L)) return MF_OK;
+    std::vector<float2> tw(L);
+    for (int r = 0; r < L; ++r) {
+        const double ang = -2.0 * M_PI * (double)r / (double)L;
+        tw[r] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+    }
+    float2* d = nullptr;
+    MF_HIP(hipMalloc(&d, L * sizeof(float2)));
+    p->d_tw[L] = d;
+    MF_HIP(hipMemcpy(d, tw.data(), L * sizeof(float2), hipMemcpyHostToDevice));
+    return MF_OK;
+}
+
+mf_status validate_schedule(const mf_schedule* s) {
+    if (!s) return fail(MF_ERR_INVALID_ARG, "schedule is NULL");
+    if (s->n_levels < 1 || !s->lambda || !s->sweeps) return fail(MF_ERR_INVALID_ARG, "schedule needs >= 1 level");
+    for (int j = 0; j < s->n_levels; ++j) {
+        if (!(s->lambda[j] >= 1.0) || !std::isfinite(s->lambda[j]))
+            return fail(MF_ERR_INVALID_ARG, "cooling levels need 1 <= lambda < inf");
+        if (s->sweeps[j] < 0) return fail(MF_ERR_INVALID_ARG, "negative sweep count");
+    }
+    if (s->tol > 0 && (s->check_every < 2 || s->max_sweeps < 1))
+        return fail(MF_ERR_INVALID_ARG, "tol > 0 needs check_every >= 2 and max_sweeps >= 1");
+    return MF_OK;
+}
+
+mf::SweepArgs base_args(mf_plan p, int H, int W) {
+    mf::SweepArgs a{};
+    a.probs = p->d_probs;
+    a.nbar = p->d_nbar;
+    a.nP = p->d_nP;
+    a.tw_row = p->d_tw.at(W);
+    a.tw_col = p->d_tw.at(H);
+    a.lambda = 1.0f;
+    a.emit_index = -1;
+    return a;
+}
+
+// Upload a work list at element offset `slot` of the items workspace.
+mf_status put_items(mf_plan p, const std::vector<mf::ItemDev>& it, size_t slot, hipStream_t s,
+                    mf::ItemDev** out) {
+    const size_t need = (slot + it.size()) * sizeof(mf::ItemDev);
+    if (need > p->items.bytes) return fail(MF_ERR_INVALID_ARG, "internal: items workspace too small");
+    mf::ItemDev* d = p->items.as<mf::ItemDev>() + slot;
+    MF_HIP(hipMemcpyAsync(d, it.data(), it.size() * sizeof(mf::ItemDev), hipMemcpyHostToDevice, s));
+    MF_HIP(hipStreamSynchronize(s));  // the host vector may die right after
+    *out = d;
+    return MF_OK;
+}
+
+// -------------------------------------------------------------------------
+// Deterministic solve (Wiener filter or adjoint) on the streamed kernels for
+// the problems of one size class.  Field layout: one complex field per problem
+// at field_off = pix_off (float2 units).
+// -------------------------------------------------------------------------
+mf_status solve_class(mf_plan p, const std::vector<int>& pids, int H, int W, const float* src, int src_kind,
+                      const mf_schedule* sch, const float* s_init, std::vector<double>& bnorm2,
+                      std::vector<mf_info>& info, hipStream_t s) {
+    const int n_items = (int)pids.size();
+    std::vector<mf::ItemDev> items(n_items);
+    for (int i = 0; i < n_items; ++i) items[i] = {pids[i], 0, p->probs[pids[i]].pix_off};
+    mf::ItemDev* d_items = nullptr;
+    mf_status st = put_items(p, items, 0, s, &d_items);
+    if (st != MF_OK) return st;
+    mf::SweepArgs a = base_args(p, H, W);
+    a.items = d_items;
+    a.n_items = n_items;
+    a.field = p->field.as<float2>();
+    a.src = src;
+    a.src_kind = src_kind;
+    a.stochastic = 0;
+    a.real_only = 1;
+    a.t_save = p->t_save.as<float2>();
+    a.partials = p->partials.as<double>();
+    MF_HIP(mf::launch_load_real(W, H, a, s_init, s));
+
+    bool first = true;
+    int total = 0;
+    auto sweep = [&](double lam, bool save_t, bool check_t) -> mf_status {
+        a.lambda = (float)lam;
+        a.save_t = save_t;
+        a.check_t = check_t;
+        MF_HIP(mf::launch_row(W, H, first ? mf::kRowFwd : mf::kRowInvFwd, a, s));
+        a.save_t = a.check_t = 0;
+        MF_HIP(mf::launch_col(W, H, a, s));
+        first = false;
+        ++total;
+        return MF_OK;
+    };
+    for (int j = 0; j < sch->n_levels; ++j)
+        for (int k = 0; k < sch->sweeps[j]; ++k)
+            if ((st = sweep(sch->lambda[j], false, false)) != MF_OK) return st;
+    const int levels_total = total;
+    std::vector<int> done(n_items, 0);
+    for (int i = 0; i < n_items; ++i) info[pids[i]] = {total, sch->tol > 0 ? 0 : 1, std::nan("")};
+    if (sch->tol > 0) {
+        const double lam = sch->lambda[sch->n_levels - 1];
+        std::vector<double> part((size_t)n_items * H);
+        int remaining = n_items;
+        std::vector<mf::ItemDev> live = items;
+        while (total < sch->max_sweeps && remaining > 0) {
+            const int c = total + 1;  // count after this sweep
+            const bool check = (c % sch->check_every == 0) && (c - 1 >= levels_total + 1);
+            const bool save = ((c + 1) % sch->check_every == 0);
+            if ((st = sweep(lam, save, check)) != MF_OK) return st;
+            if (!check) continue;
+            MF_HIP(hipMemcpyAsync(part.data(), a.partials, (size_t)a.n_items * H * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+            MF_HIP(hipStreamSynchronize(s));
+            std::vector<mf::ItemDev> conv, keep;
+            for (int i = 0; i < a.n_items; ++i) {
+                double acc = 0;
+                for (int y = 0; y < H; ++y) acc += part[(size_t)i * H + y];
+                const int pid = live[i].prob;
+                const double T = lam * p->probs[pid].tau;
+                const double r = bnorm2[pid] > 0 ? std::sqrt(acc) / (T * std::sqrt(bnorm2[pid])) : 0.0;
+                info[pid].residual = r;
+                info[pid].sweeps = total;
+                if (r <= sch->tol) {
+                    info[pid].converged = 1;
+                    conv.push_back(live[i]);
+                } else {
+                    keep.push_back(live[i]);
+                }
+            }
+            if (!conv.empty()) {
+                // finish converged items with the inverse row pass and drop them
+                mf::ItemDev* d_conv = nullptr;
+                if ((st = put_items(p, conv, (size_t)n_items, s, &d_conv)) != MF_OK) return st;
+                mf::SweepArgs b = a;
+                b.items = d_conv;
+                b.n_items = (int)conv.size();
+                MF_HIP(mf::launch_row(W, H, mf::kRowInv, b, s));
+                remaining -= (int)conv.size();
+                live = keep;
+                if (!live.empty()) {
+                    if ((st = put_items(p, live, 0, s, &d_items)) != MF_OK) return st;
+                }
+                a.items = d_items;
+                a.n_items = (int)live.size();
+                MF_HIP(hipStreamSynchronize(s));
+            }
+        }
+        for (auto& it : live) info[it.prob].sweeps = total;
+        if (!live.empty() && !first) {
+            MF_HIP(mf::launch_row(W, H, mf::kRowInv, a, s));
+        }
+        return MF_OK;
+    }
+    if (!first) MF_HIP(mf::launch_row(W, H, mf::kRowInv, a, s));
+    return MF_OK;
+}
+
+mf_status ensure_solve_workspace(mf_plan p, hipStream_t s) {
+    (void)s;
+    size_t max_items = 0, max_rows = 0;
+    for (auto& kv : p->classes) {
+        max_items = std::max(max_items, kv.second.size());
+        max_rows = std::max(max_rows, kv.second.size() * (size_t)kv.first.first);
+    }
+    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
+    MF_HIP(p->field.ensure((size_t)p->total_px * sizeof(float2)));
+    MF_HIP(p->t_save.ensure((size_t)p->total_px * sizeof(float2)));
+    size_t part = std::max(max_rows, max_items * mf::kBandBlocks * 64);
+    MF_HIP(p->partials.ensure(part * sizeof(double)));
+    return MF_OK;
+}
+
+// ||b||^2 per problem with b = N_eff^-1 d at cooling level lam (data) or b = g.
+mf_status rhs_norms(mf_plan p, const float* src, int src_kind, double lam, std::vector<double>& out,
+                    hipStream_t s) {
+    std::vector<float> h((size_t)p->total_px);
+    MF_HIP(hipMemcpyAsync(h.data(), src, h.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+    MF_HIP(hipStreamSynchronize(s));
+    out.assign(p->probs.size(), 0.0);
+    for (size_t i = 0; i < p->probs.size(); ++i) {
+        const HostProblem& hp = p->probs[i];
+        const double T = lam * hp.tau;
+        double acc = 0;
+        for (int64_t e = 0; e < (int64_t)hp.H * hp.W; ++e) {
+            const double nb = p->host_nbar[hp.pix_off + e];
+            double b;
+            if (src_kind == mf::kSrcData) b = std::isfinite(nb) ? (double)h[hp.pix_off + e] / (nb + T) : 0.0;
+            else b = h[hp.pix_off + e];
+            acc += b * b;
+        }
+        out[i] = acc;
+    }
+    return MF_OK;
+}
+
+mf_status run_solve(mf_plan p, const float* src, int src_kind, const mf_schedule* sch, const float* s_init,
+                    mf_info* info_out, hipStream_t s) {
+    mf_status st = validate_schedule(sch);
+    if (st != MF_OK) return st;
+    if ((st = ensure_solve_workspace(p, s)) != MF_OK) return st;
+    std::vector<double> bn;
+    if (sch->tol > 0) {
+        if ((st = rhs_norms(p, src, src_kind, sch->lambda[sch->n_levels - 1], bn, s)) != MF_OK) return st;
+    }
+    std::vector<mf_info> info(p->probs.size());
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        if ((st = solve_class(p, kv.second, H, W, src, src_kind, sch, s_init, bn, info, s)) != MF_OK) return st;
+        // leave the class's result in the field buffer (pixel space, real part)
+    }
+    bool all = true;
+    for (auto& i : info) all = all && i.converged;
+    if (info_out) {
+        MF_HIP(hipStreamSynchronize(s));
+        std::copy(info.begin(), info.end(), info_out);
+    }
+    if (!all) return fail(MF_ERR_NOT_CONVERGED, "tolerance not reached within max_sweeps");
+    return MF_OK;
+}
+
+mf_status copy_field_real(mf_plan p, float* out, hipStream_t s) {
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        std::vector<mf::ItemDev> items;
+        for (int pid : kv.second) items.push_back({pid, 0, p->probs[pid].pix_off});
+        mf::ItemDev* d = nullptr;
+        mf_status st = put_items(p, items, 0, s, &d);
+        if (st != MF_OK) return st;
+        mf::SweepArgs a = base_args(p, H, W);
+        a.items = d;
+        a.n_items = (int)items.size();
+        a.field = p->field.as<float2>();
+        MF_HIP(mf::launch_copy_out_real(W, H, a, out, s));
+    }
+    return MF_OK;
+}
+
+// -------------------------------------------------------------------------
+// Sampler
+// -------------------------------------------------------------------------
+mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int H, int W, const float* d,
+                          const mf_sample_args* g, float2* work, const float2* state_in, float* samples,
+                          hipStream_t s) {
+    mf::SweepArgs a = base_args(p, H, W);
+    a.items = d_items;
+    a.n_items = n_items;
+    a.field = work;
+    a.src = d;
+    a.src_kind = mf::kSrcData;
+    a.stochastic = 1;
+    a.key0 = (uint32_t)(g->seed & 0xffffffffu);
+    a.key1 = (uint32_t)(g->seed >> 32);
+    a.samples = samples;
+    a.chains = g->chains_per_problem;
+    a.n_samples = g->n_samples;
+    if (state_in != work)  // copy the given states, or make zero / dispersed starts
+        MF_HIP(mf::launch_init_items(W, H, a, state_in, state_in ? 0.f : g->init_scale, s));
+    const int64_t K = (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin;
+    auto emit_of = [&](int64_t k) -> int {
+        if (!samples || k < g->burn_in) return -1;
+        const int64_t q = k - g->burn_in + 1;
+        return (q % g->thin == 0) ? (int)(q / g->thin - 1) : -1;
+    };
+    for (int64_t k = 0; k < K; ++k) {
+        a.sweep = (uint32_t)(g->sweep_offset + k);
+        a.emit_index = k > 0 ? emit_of(k - 1) : -1;
+        MF_HIP(mf::launch_row(W, H, k == 0 ? mf::kRowFwd : mf::kRowInvFwd, a, s));
+        a.emit_index = -1;
+        MF_HIP(mf::launch_col(W, H, a, s));
+    }
+    if (K > 0) {
+        a.emit_index = emit_of(K - 1);
+        MF_HIP(mf::launch_row(W, H, mf::kRowInv, a, s));
+    }
+    return MF_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+// C entry points
+// =========================================================================
+extern "C" {
+
+const char* mf_status_string(mf_status st) {
+    switch (st) {
+        case MF_OK: return "ok";
+        case MF_ERR_INVALID_ARG: return "invalid argument";
+        case MF_ERR_UNSUPPORTED_SIZE: return "unsupported size";
+        case MF_ERR_OUT_OF_MEMORY: return "out of memory";
+        case MF_ERR_DEVICE: return "device error";
+        case MF_ERR_NOT_CONVERGED: return "not converged";
+        case MF_ERR_NONFINITE: return "non-finite value";
+    }
+    return "unknown status";
+}
+
+const char* mf_last_error(void) { return g_last_error.c_str(); }
+
+mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* problems, uint32_t flags,
+                         mf_stream stream) {
+    (void)stream;
+    if (!out) return fail(MF_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_problems < 1 || n_problems >= (1 << 24) || !problems)
+        return fail(MF_ERR_INVALID_ARG, "need 1 <= n_problems < 2^24 and a problem array");
+    mf_plan p = new (std::nothrow) mf_plan_s();
+    if (!p) return fail(MF_ERR_OUT_OF_MEMORY, "host allocation failed");
+    p->flags = flags;
+    (void)hipGetDevice(&p->device);
+    int64_t off = 0;
+    int bands = 0;
+    p->probs.resize(n_problems);
+    for (int i = 0; i < n_problems; ++i) {
+        const mf_problem& q = problems[i];
+        HostProblem& hp = p->probs[i];
+        if (!size_ok(q.H) || !size_ok(q.W)) {
+            delete p;
+            return fail(MF_ERR_UNSUPPORTED_SIZE, "problem " + std::to_string(i) + ": H and W must be powers of two in [16, 2048]");
+        }
+        if (!q.noise_var) {
+            delete p;
+            return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": noise_var is NULL");
+        }
+        hp.H = q.H;
+        hp.W = q.W;
+        hp.pix_off = off;
+        off += (int64_t)q.H * q.W;
+        mf_status st = copy_spectrum(hp, q.spectrum, i);
+        if (st != MF_OK) {
+            delete p;
+            return st;
+        }
+        hp.band_base = bands;
+        bands += hp.n_bands;
+        p->classes[{q.H, q.W}].push_back(i);
+    }
+    p->total_px = off;
+    p->total_bands = bands;
+    p->host_nbar.resize(off);
+    std::vector<mf::ProbDev> pd(n_problems);
+    for (int i = 0; i < n_problems; ++i) {
+        HostProblem& hp = p->probs[i];
+        const float* nv = problems[i].noise_var;
+        double tau = INFINITY;
+        const int64_t n = (int64_t)hp.H * hp.W;
+        for (int64_t e = 0; e < n; ++e) {
+            const float v = nv[e];
+            if (std::isnan(v) || v <= 0.f) {
+                delete p;
+                return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": noise variances must be > 0 (+inf = missing)");
+            }
+            if (std::isfinite(v)) tau = std::min(tau, (double)v);
+        }
+        if (!std::isfinite(tau)) tau = 1.0;  // every pixel missing: any T samples the prior
+        hp.tau = tau;
+        for (int64_t e = 0; e < n; ++e) {
+            const float v = nv[e];
+            p->host_nbar[hp.pix_off + e] = std::isfinite(v) ? (float)((double)v - tau) : INFINITY;
+        }
+        pd[i] = {hp.H, hp.W, hp.pix_off, (float)tau, i};
+    }
+    std::vector<int32_t> bb(n_problems), bc(n_problems);
+    for (int i = 0; i < n_problems; ++i) {
+        bb[i] = p->probs[i].band_base;
+        bc[i] = p->probs[i].n_bands;
+    }
+#define MF_TRY(call)                                                              \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            delete p;                                                             \
+            return fail(e_ == hipErrorOutOfMemory ? MF_ERR_OUT_OF_MEMORY : MF_ERR_DEVICE, \
+                        std::string(#call) + ": " + hipGetErrorString(e_));       \
+        }                                                                         \
+    } while (0)
+    MF_TRY(hipMalloc(&p->d_probs, n_problems * sizeof(mf::ProbDev)));
+    MF_TRY(hipMalloc(&p->d_nbar, off * sizeof(float)));
+    MF_TRY(hipMalloc(&p->d_nP, off * sizeof(float)));
+    MF_TRY(hipMalloc(&p->d_band, off * sizeof(int16_t)));
+    MF_TRY(hipMalloc(&p->d_band_base, n_problems * sizeof(int32_t)));
+    MF_TRY(hipMalloc(&p->d_band_count, n_problems * sizeof(int32_t)));
+    MF_TRY(hipMalloc(&p->d_band_scale, std::max(bands, 1) * sizeof(double)));
+    MF_TRY(hipMemcpy(p->d_probs, pd.data(), n_problems * sizeof(mf::ProbDev), hipMemcpyHostToDevice));
+    MF_TRY(hipMemcpy(p->d_nbar, p->host_nbar.data(), off * sizeof(float), hipMemcpyHostToDevice));
+    MF_TRY(hipMemcpy(p->d_band_base, bb.data(), n_problems * sizeof(int32_t), hipMemcpyHostToDevice));
+    MF_TRY(hipMemcpy(p->d_band_count, bc.data(), n_problems * sizeof(int32_t), hipMemcpyHostToDevice));
+#undef MF_TRY
+    for (int i = 0; i < n_problems; ++i) {
+        mf_status st = upload_spectrum(p, i);
+        if (st != MF_OK) {
+            delete p;
+            return st;
+        }
+    }
+    for (auto& kv : p->classes) {
+        mf_status st = upload_twiddles(p, kv.first.first);
+        if (st == MF_OK) st = upload_twiddles(p, kv.first.second);
+        if (st != MF_OK) {
+            delete p;
+            return st;
+        }
+    }
+    *out = p;
+    return MF_OK;
+}
+
+mf_status mf_plan_destroy(mf_plan plan) {
+    delete plan;
+    return MF_OK;
+}
+
+mf_status mf_plan_set_spectrum(mf_plan p, int32_t problem, const mf_spectrum* spectrum) {
+    if (!p || !spectrum || problem < 0 || problem >= (int)p->probs.size())
+        return fail(MF_ERR_INVALID_ARG, "bad plan, problem index or spectrum");
+    HostProblem& hp = p->probs[problem];
+    const int old_kind = hp.kind, old_nb = hp.n_bands;
+    HostProblem tmp = hp;
+    mf_status st = copy_spectrum(tmp, *spectrum, problem);
+    if (st != MF_OK) return st;
+    if (tmp.kind != old_kind || tmp.n_bands != old_nb)
+        return fail(MF_ERR_INVALID_ARG, "set_spectrum must keep the spectrum kind and band count");
+    hp = tmp;
+    return upload_spectrum(p, problem);
+}
+
+int64_t mf_plan_pixel_offset(mf_plan p, int32_t problem) {
+    if (!p || problem < 0 || problem > (int)p->probs.size()) return -1;
+    if (problem == (int)p->probs.size()) return p->total_px;
+    return p->probs[problem].pix_off;
+}
+
+double mf_plan_tau(mf_plan p, int32_t problem) {
+    if (!p || problem < 0 || problem >= (int)p->probs.size()) return -1;
+    return p->probs[problem].tau;
+}
+
+int32_t mf_plan_total_bands(mf_plan p) { return p ? p->total_bands : -1; }
+
+mf_status mf_wiener(mf_plan p, const float* d, const mf_schedule* schedule, const float* s_init, float* s_out,
+                    mf_info* info, mf_stream stream) {
+    if (!p || !d || !s_out) return fail(MF_ERR_INVALID_ARG, "plan, d and s_out are required");
+    hipStream_t s = (hipStream_t)stream;
+    mf_status st = run_solve(p, d, mf::kSrcData, schedule, s_init, info, s);
+    if (st != MF_OK && st != MF_ERR_NOT_CONVERGED) return st;
+    mf_status st2 = copy_field_real(p, s_out, s);
+    return st2 != MF_OK ? st2 : st;
+}
+
+mf_status mf_wiener_backward(mf_plan p, const float* s_wf, const float* grad_s, const mf_schedule* schedule,
+                             float* grad_d, double* grad_bands, float* v_out, mf_info* info, mf_stream stream) {
+    if (!p || !grad_s) return fail(MF_ERR_INVALID_ARG, "plan and grad_s are required");
+    if (grad_bands && !s_wf) return fail(MF_ERR_INVALID_ARG, "grad_bands needs s_wf");
+    hipStream_t s = (hipStream_t)stream;
+    mf_status st = run_solve(p, grad_s, mf::kSrcGrad, schedule, nullptr, info, s);
+    if (st != MF_OK && st != MF_ERR_NOT_CONVERGED) return st;
+    mf_status conv = st;
+    if (v_out && (st = copy_field_real(p, v_out, s)) != MF_OK) return st;
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        std::vector<mf::ItemDev> items;
+        for (int pid : kv.second) items.push_back({pid, 0, p->probs[pid].pix_off});
+        mf::ItemDev* di = nullptr;
+        if ((st = put_items(p, items, 0, s, &di)) != MF_OK) return st;
+        mf::SweepArgs a = base_args(p, H, W);
+        a.items = di;
+        a.n_items = (int)items.size();
+        a.field = p->field.as<float2>();
+        if (grad_d) MF_HIP(mf::launch_grad_d(W, H, a, grad_d, s));
+    }
+    if (grad_bands && p->total_bands > 0) {
+        // v is needed as a real array: reuse the aux workspace
+        MF_HIP(p->aux.ensure((size_t)p->total_px * sizeof(float)));
+        float* v = p->aux.as<float>();
+        if ((st = copy_field_real(p, v, s)) != MF_OK) return st;
+        for (auto& kv : p->classes) {
+            const int H = kv.first.first, W = kv.first.second;
+            std::vector<mf::ItemDev> items;
+            for (int pid : kv.second)
+                if (p->probs[pid].kind == MF_PK_BANDS) items.push_back({pid, 0, p->probs[pid].pix_off});
+            if (items.empty()) continue;
+            mf::ItemDev* di = nullptr;
+            if ((st = put_items(p, items, 0, s, &di)) != MF_OK) return st;
+            mf::SweepArgs a = base_args(p, H, W);
+            a.items = di;
+            a.n_items = (int)items.size();
+            a.field = p->field.as<float2>();
+            a.partials = p->partials.as<double>();
+            MF_HIP(mf::launch_band_power(W, H, a, v, s_wf, p->d_band, p->d_band_base, p->d_band_count,
+                                         p->d_band_scale, grad_bands, s));
+        }
+    }
+    return conv;
+}
+
+mf_status mf_band_power(mf_plan p, const float* x, const float* y, double* out, mf_stream stream) {
+    if (!p || !x || !y || !out) return fail(MF_ERR_INVALID_ARG, "plan, x, y and out are required");
+    hipStream_t s = (hipStream_t)stream;
+    mf_status st = ensure_solve_workspace(p, s);
+    if (st != MF_OK) return st;
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        std::vector<mf::ItemDev> items;
+        for (int pid : kv.second)
+            if (p->probs[pid].kind == MF_PK_BANDS) items.push_back({pid, 0, p->probs[pid].pix_off});
+        if (items.empty()) continue;
+        mf::ItemDev* di = nullptr;
+        if ((st = put_items(p, items, 0, s, &di)) != MF_OK) return st;
+        mf::SweepArgs a = base_args(p, H, W);
+        a.items = di;
+        a.n_items = (int)items.size();
+        a.field = p->field.as<float2>();
+        a.partials = p->partials.as<double>();
+        MF_HIP(mf::launch_band_power(W, H, a, x, y, p->d_band, p->d_band_base, p->d_band_count, nullptr, out, s));
+    }
+    return MF_OK;
+}
+
+mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const float* state_in, float* state_out,
+                    float* samples_out, mf_stream stream) {
+    if (!p || !d || !g) return fail(MF_ERR_INVALID_ARG, "plan, d and args are required");
+    if (g->chains_per_problem < 1 || g->burn_in < 0 || g->n_samples < 0 || g->thin < 1 || g->sweep_offset < 0)
+        return fail(MF_ERR_INVALID_ARG, "need chains >= 1, burn_in >= 0, n_samples >= 0, thin >= 1, sweep_offset >= 0");
+    if (g->sweep_offset + (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin > 0xffffffffLL)
+        return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
+    if (g->form < MF_FORM_AUTO || g->form > MF_FORM_PLAIN) return fail(MF_ERR_INVALID_ARG, "unknown form");
+    if (g->n_samples > 0 && !samples_out && !state_out)
+        return fail(MF_ERR_INVALID_ARG, "nothing to write: samples_out and state_out are NULL");
+    hipStream_t s = (hipStream_t)stream;
+    const int pairs = (g->chains_per_problem + 1) / 2;
+    const size_t field_elems = (size_t)p->total_px * pairs;
+    float2* work;
+    if (state_out) {
+        work = reinterpret_cast<float2*>(state_out);
+    } else {
+        MF_HIP(p->field.ensure(field_elems * sizeof(float2)));
+        work = p->field.as<float2>();
+    }
+    const float2* sin = reinterpret_cast<const float2*>(state_in);
+    size_t max_items = 0;
+    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size() * (size_t)pairs);
+    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        std::vector<mf::ItemDev> items;
+        for (int pid : kv.second)
+            for (int q = 0; q < pairs; ++q)
+                items.push_back({pid, q, (int64_t)pairs * p->probs[pid].pix_off + (int64_t)q * H * W});
+        int form = g->form;
+        if (form == MF_FORM_AUTO) form = mf::resident_supported(H, W) ? MF_FORM_PERSISTENT : MF_FORM_STREAMED;
+        mf::ItemDev* di = nullptr;
+        mf_status st = put_items(p, items, 0, s, &di);
+        if (st != MF_OK) return st;
+        if (form == MF_FORM_PERSISTENT) {
+            if (!mf::resident_supported(H, W))
+                return fail(MF_ERR_UNSUPPORTED_SIZE, "the persistent form needs H = W <= 128");
+            mf::ResidentArgs r{};
+            r.probs = p->d_probs;
+            r.items = di;
+            r.n_items = (int)items.size();
+            r.field = work;
+            r.state_in = sin;
+            r.init_scale = g->init_scale;
+            r.d = d;
+            r.nbar = p->d_nbar;
+            r.nP = p->d_nP;
+            r.tw = p->d_tw.at(W);
+            r.key0 = (uint32_t)(g->seed & 0xffffffffu);
+            r.key1 = (uint32_t)(g->seed >> 32);
+            r.sweep0 = (uint32_t)g->sweep_offset;
+            r.burn_in = g->burn_in;
+            r.n_samples = g->n_samples;
+            r.thin = g->thin;
+            r.samples = samples_out;
+            r.chains = g->chains_per_problem;
+            MF_HIP(mf::launch_resident_sample(H, r, s));
+        } else if (form == MF_FORM_STREAMED) {
+            st = sample_streamed(p, di, (int)items.size(), H, W, d, g, work, sin, samples_out, s);
+        } else {  // plain: one chain pair per launch sequence
+            for (size_t i = 0; i < items.size() && st == MF_OK; ++i)
+                st = sample_streamed(p, di + i, 1, H, W, d, g, work, sin, samples_out, s);
+        }
+        if (st != MF_OK) return st;
+    }
+    return MF_OK;
+}
+
+}  // extern "C"

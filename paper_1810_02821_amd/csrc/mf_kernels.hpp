@@ -1,0 +1,80 @@
+// Kernel-side descriptors and host launchers shared by the HIP sources and
+// the host plan code.  No torch types; plain pointers only.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mf {
+
+// One problem as the kernels see it.
+struct ProbDev {
+    int32_t H, W;
+    int64_t pix_off;    // offset in concatenated pixel / mode arrays
+    float tau;          // min observed noise variance
+    int32_t pid;        // problem index (random-stream counter word)
+};
+
+// One unit of work: a chain pair of a problem (or a single real solve).
+struct ItemDev {
+    int32_t prob;
+    int32_t pair;
+    int64_t field_off;  // float2 offset of this item's field in the work buffer
+};
+
+// What the right-hand side pointer holds.
+enum SrcKind : int32_t {
+    kSrcData = 0,   // b = N_eff^-1 d, pixel source a * d
+    kSrcGrad = 1,   // b = g (adjoint solve), pixel source T * g
+};
+
+struct SweepArgs {
+    const ProbDev* probs;
+    const ItemDev* items;
+    int32_t n_items;
+    float2* field;            // work buffer: items' complex fields
+    const float* src;         // concatenated data d or adjoint rhs g
+    int32_t src_kind;
+    const float* nbar;        // concatenated Nbar (+inf missing)
+    const float* nP;          // concatenated n P(|k|) per mode (unshifted order)
+    const float2* tw_row;     // twiddles W_W^r
+    const float2* tw_col;     // twiddles W_H^r
+    float lambda;             // cooling level: T = lambda * tau
+    int32_t stochastic;       // 1: draw variates (sampler), 0: Wiener iteration
+    uint32_t key0, key1;      // Philox key
+    uint32_t sweep;           // global sweep index of the pixel / harmonic draws
+    // sample emission (row kernel, inverse pass)
+    float* samples;           // [problem][chain][sample][H][W] or null
+    int32_t emit_index;       // sample slot to write, < 0: none
+    int32_t chains;           // chains per problem
+    int32_t n_samples;        // samples per chain
+    // residual support (row kernel, forward pass)
+    float2* t_save;           // messenger snapshot buffer (same layout as field), or null
+    int32_t save_t;           // 1: write t to t_save
+    int32_t check_t;          // 1: accumulate |t - t_save|^2 into partials
+    double* partials;         // [item][row block] partial sums
+    int32_t real_only;        // 1: the imaginary channel is unused (Wiener / adjoint)
+};
+
+// Host launchers (defined in mf_streamed.hip).  mode bit 1: inverse row FFT +
+// emission first; bit 2: pixel update + forward row FFT.
+enum RowMode : int32_t { kRowInv = 1, kRowFwd = 2, kRowInvFwd = 3 };
+hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_t s);
+hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s);
+int row_blocks_per_item(int W, int H);
+
+// Elementwise helpers (mf_streamed.hip).
+hipError_t launch_init_items(int W, int H, const SweepArgs& a, const float2* state_in, float init_scale,
+                             hipStream_t s);
+hipError_t launch_copy_out_real(int W, int H, const SweepArgs& a, float* out, hipStream_t s);
+hipError_t launch_copy_out_pairs(int W, int H, const SweepArgs& a, float2* out, hipStream_t s);
+hipError_t launch_grad_d(int W, int H, const SweepArgs& a, float* grad_d, hipStream_t s);
+hipError_t launch_load_real(int W, int H, const SweepArgs& a, const float* s_init, hipStream_t s);
+// Band cross-power of two real fields per item (a.partials must hold
+// n_items * kBandBlocks * kMaxBands doubles); out[band_base[p] + b] = scale * sum.
+constexpr int kBandBlocks = 64;
+constexpr int kMaxBandsPerProblem = 64;
+hipError_t launch_band_power(int W, int H, const SweepArgs& a, const float* x, const float* y,
+                             const int16_t* band, const int32_t* band_base, const int32_t* band_count,
+                             const double* scale, double* out, hipStream_t s);
+
+}  // namespace mf

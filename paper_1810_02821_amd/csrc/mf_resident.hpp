@@ -1,0 +1,32 @@
+// Persistent LDS-resident form of the sampler: one workgroup keeps one chain
+// pair's whole image on chip for every sweep.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mf_kernels.hpp"
+
+namespace mf {
+
+struct ResidentArgs {
+    const ProbDev* probs;
+    const ItemDev* items;
+    int32_t n_items;
+    float2* field;            // final pair states [item] (pixel space)
+    const float2* state_in;   // start states or null
+    float init_scale;         // dispersed starts when state_in is null and > 0
+    const float* d;           // concatenated data
+    const float* nbar;        // concatenated Nbar
+    const float* nP;          // concatenated n P(|k|)
+    const float2* tw;         // W_N^r, r < N
+    uint32_t key0, key1;
+    uint32_t sweep0;          // global index of the first sweep
+    int32_t burn_in, n_samples, thin;
+    float* samples;           // [problem][chain][sample][H][W] or null
+    int32_t chains;
+};
+
+bool resident_supported(int H, int W);
+hipError_t launch_resident_sample(int N, const ResidentArgs& a, hipStream_t s);
+
+}  // namespace mf

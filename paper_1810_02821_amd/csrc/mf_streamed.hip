@@ -1,0 +1,516 @@
+// Streamed form of the messenger sweep: the complex field of every work item
+// stays in HBM between two kernels per sweep.
+//
+//   row kernel:    [inverse row FFT -> emit sample] -> pixel-space draw of t
+//                  (Algorithm 1, first two lines) -> forward row FFT
+//   column kernel: forward column FFT -> Fourier-space draw of s (lines 4-5)
+//                  -> inverse column FFT
+//
+// Each 1D transform is a Stockham FFT staged in LDS.  Rows (columns) of all
+// work items of one launch are flattened, so small images still fill a block.
+#include "mf_device.hpp"
+#include "mf_kernels.hpp"
+
+namespace mf {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ __forceinline__ float pix_a(float T, float nb) {
+    // a = T / (T + Nbar); Nbar = +inf on missing pixels gives a = 0
+    return T * __builtin_amdgcn_rcpf(T + nb);
+}
+
+template <int L>
+struct RowShape {
+    static constexpr int ROWS = (2048 / L) < 1 ? 1 : (2048 / L);  // rows per block
+    static constexpr int TPR = kThreads / ROWS;                   // threads per row
+};
+
+template <int L, int MODE>
+__global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
+    constexpr int ROWS = RowShape<L>::ROWS;
+    constexpr int TPR = RowShape<L>::TPR;
+    constexpr int W = L;
+    __shared__ float2 lds[ROWS * L];
+    __shared__ double red[kThreads];
+
+    const int tid = threadIdx.x;
+    const int rid = tid / TPR;
+    const int lane = tid % TPR;
+    const int64_t total_rows = (int64_t)a.n_items * H;
+    const int64_t grow0 = (int64_t)blockIdx.x * ROWS;
+
+    // ---- load ROWS rows (coalesced along x)
+#pragma unroll
+    for (int i = 0; i < ROWS * L / kThreads; ++i) {
+        const int e = tid + i * kThreads;
+        const int r = e / L, x = e % L;
+        const int64_t gr = grow0 + r;
+        float2 v = make_float2(0.f, 0.f);
+        if (gr < total_rows) {
+            const ItemDev it = a.items[gr / H];
+            v = a.field[it.field_off + (gr % H) * W + x];
+        }
+        lds[e] = v;
+    }
+    __syncthreads();
+
+    const int64_t gr = grow0 + rid;
+    const bool valid = gr < total_rows;
+    const int item = valid ? (int)(gr / H) : 0;
+    const int y = valid ? (int)(gr % H) : 0;
+    const ItemDev it = a.items[item];
+    const ProbDev pr = a.probs[it.prob];
+    float2* row = lds + rid * L;
+
+    if constexpr (MODE & kRowInv) {
+        stockham_fft<L, 1, TPR, 1, true>(row, lane, a.tw_row);
+        if (a.emit_index >= 0 && valid) {
+            const int64_t base = (int64_t)a.chains * a.n_samples * pr.pix_off;
+            const int64_t n = (int64_t)pr.H * pr.W;
+            const int c0 = 2 * it.pair, c1 = 2 * it.pair + 1;
+            float* o0 = a.samples + base + ((int64_t)c0 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
+            float* o1 = a.samples + base + ((int64_t)c1 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
+            for (int x = lane; x < L; x += TPR) {
+                const float2 s = row[x];
+                o0[x] = s.x;
+                if (c1 < a.chains) o1[x] = s.y;
+            }
+        }
+        if constexpr (!(MODE & kRowFwd)) {
+            if (valid)
+                for (int x = lane; x < L; x += TPR) a.field[it.field_off + (int64_t)y * W + x] = row[x];
+            return;
+        }
+    }
+
+    if constexpr (MODE & kRowFwd) {
+        // ---- pixel-space messenger update t = (1 - a) s + src + sigma_t xi
+        const float T = a.lambda * pr.tau;
+        double acc = 0.0;
+        for (int pp = lane; pp < L / 2; pp += TPR) {
+            const int x = 2 * pp;
+            const int64_t pix = pr.pix_off + (int64_t)y * W + x;
+            const float2 nb = *reinterpret_cast<const float2*>(a.nbar + pix);
+            const float2 sv = *reinterpret_cast<const float2*>(a.src + pix);
+            float aa[2] = {pix_a(T, nb.x), pix_a(T, nb.y)};
+            float sr[2] = {sv.x, sv.y};
+            float2 s[2] = {row[x], row[x + 1]};
+            float2 z[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+            if (a.stochastic && valid) {
+                const uint32_t j = (uint32_t)(((int64_t)y * W + x) >> 1);
+                const Normals2 nz = pair_normals(j, a.sweep, (uint32_t)pr.pid, kStagePixel, (uint32_t)it.pair,
+                                                 a.key0, a.key1);
+                z[0] = nz.a;
+                z[1] = nz.b;
+            }
+            float2 t[2];
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                const float oma = 1.0f - aa[q];
+                float src;
+                if (a.src_kind == kSrcData) src = aa[q] > 0.f ? aa[q] * sr[q] : 0.f;
+                else src = T * sr[q];
+                const float sig = a.stochastic ? __builtin_amdgcn_sqrtf(T * oma) : 0.f;
+                t[q].x = fmaf(oma, s[q].x, fmaf(sig, z[q].x, src));
+                t[q].y = a.real_only ? 0.f : fmaf(oma, s[q].y, fmaf(sig, z[q].y, src));
+            }
+            if (valid) {
+                const int64_t f = it.field_off + (int64_t)y * W + x;
+                if (a.check_t) {
+                    const float2 p0 = a.t_save[f], p1 = a.t_save[f + 1];
+                    const double d0 = (double)t[0].x - p0.x, d1 = (double)t[1].x - p1.x;
+                    const double e0 = (double)t[0].y - p0.y, e1 = (double)t[1].y - p1.y;
+                    acc += d0 * d0 + d1 * d1 + e0 * e0 + e1 * e1;
+                }
+                if (a.save_t) {
+                    a.t_save[f] = t[0];
+                    a.t_save[f + 1] = t[1];
+                }
+            }
+            row[x] = t[0];
+            row[x + 1] = t[1];
+        }
+        if (a.check_t) {
+            red[tid] = acc;
+            __syncthreads();
+            if (lane == 0 && valid) {
+                double s = 0.0;
+                for (int i = 0; i < TPR; ++i) s += red[rid * TPR + i];
+                a.partials[gr] = s;
+            }
+        }
+        __syncthreads();
+        stockham_fft<L, 1, TPR, 1, false>(row, lane, a.tw_row);
+        if (valid)
+            for (int x = lane; x < L; x += TPR) a.field[it.field_off + (int64_t)y * W + x] = row[x];
+    }
+}
+
+template <int L>
+struct ColShape {
+    static constexpr int TC = (8192 / L) > 16 ? 16 : (8192 / L);  // columns per block
+    static constexpr int TPC = kThreads / TC;
+    static constexpr int PITCH = L + 1;
+};
+
+template <int L>
+__global__ __launch_bounds__(kThreads) void col_kernel(SweepArgs a, int W) {
+    constexpr int TC = ColShape<L>::TC;
+    constexpr int TPC = ColShape<L>::TPC;
+    constexpr int PITCH = ColShape<L>::PITCH;
+    constexpr int H = L;
+    __shared__ float2 lds[TC * PITCH];
+    const int tid = threadIdx.x;
+    const int64_t gc0 = (int64_t)blockIdx.x * TC;
+    const int item = (int)(gc0 / W);
+    const int x0 = (int)(gc0 % W);
+    const ItemDev it = a.items[item];
+    const ProbDev pr = a.probs[it.prob];
+    float2* fld = a.field + it.field_off + x0;
+
+#pragma unroll 4
+    for (int e = tid; e < TC * L; e += kThreads) {
+        const int c = e % TC, y = e / TC;
+        lds[c * PITCH + y] = fld[(int64_t)y * W + c];
+    }
+    __syncthreads();
+    const int cid = tid / TPC, lane = tid % TPC;
+    stockham_fft<L, 1, TPC, 1, false>(lds + cid * PITCH, lane, a.tw_col);
+
+    // ---- Fourier-space update S = f T / n + w eta / n on column pairs
+    const float T = a.lambda * pr.tau;
+    const float inv_n = 1.0f / ((float)H * (float)W);
+    for (int e = tid; e < (TC / 2) * L; e += kThreads) {
+        const int j = e % (TC / 2), ky = e / (TC / 2);
+        const int kx = x0 + 2 * j;
+        const int64_t mode = (int64_t)ky * W + kx;
+        const float2 np = *reinterpret_cast<const float2*>(a.nP + pr.pix_off + mode);
+        float2 z[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+        if (a.stochastic) {
+            const Normals2 nz = pair_normals((uint32_t)(mode >> 1), a.sweep, (uint32_t)pr.pid, kStageHarmonic,
+                                             (uint32_t)it.pair, a.key0, a.key1);
+            z[0] = nz.a;
+            z[1] = nz.b;
+        }
+        const float npv[2] = {np.x, np.y};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const float P = npv[q];
+            const float rden = __builtin_amdgcn_rcpf(P + T);
+            const float f = P * rden * inv_n;
+            float2& v = lds[(2 * j + q) * PITCH + ky];
+            float2 o = cscale(v, f);
+            if (a.stochastic) {
+                const float w = __builtin_amdgcn_sqrtf(P * T * rden * inv_n);
+                o.x = fmaf(w, z[q].x, o.x);
+                o.y = fmaf(w, z[q].y, o.y);
+            }
+            v = o;
+        }
+    }
+    __syncthreads();
+    stockham_fft<L, 1, TPC, 1, true>(lds + cid * PITCH, lane, a.tw_col);
+
+#pragma unroll 4
+    for (int e = tid; e < TC * L; e += kThreads) {
+        const int c = e % TC, y = e / TC;
+        fld[(int64_t)y * W + c] = lds[c * PITCH + y];
+    }
+}
+
+// ------------------------------------------------------------ elementwise --
+__global__ void init_kernel(SweepArgs a, int H, int W, const float2* state_in, float init_scale) {
+    const int64_t n = (int64_t)H * W;
+    const int64_t total = (int64_t)a.n_items * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total / 2;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = 2 * e;
+        const int item = (int)(g / n);
+        const int64_t i = g % n;
+        const ItemDev it = a.items[item];
+        float2 v0 = make_float2(0.f, 0.f), v1 = v0;
+        if (state_in) {
+            v0 = state_in[it.field_off + i];
+            v1 = state_in[it.field_off + i + 1];
+        } else if (init_scale > 0.f) {
+            const ProbDev pr = a.probs[it.prob];
+            const Normals2 nz = pair_normals((uint32_t)(i >> 1), 0u, (uint32_t)pr.pid, kStageInit,
+                                             (uint32_t)it.pair, a.key0, a.key1);
+            v0 = cscale(nz.a, init_scale);
+            v1 = cscale(nz.b, init_scale);
+        }
+        a.field[it.field_off + i] = v0;
+        a.field[it.field_off + i + 1] = v1;
+    }
+}
+
+__global__ void copy_out_real_kernel(SweepArgs a, int H, int W, float* out) {
+    const int64_t n = (int64_t)H * W;
+    const int64_t total = (int64_t)a.n_items * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int item = (int)(e / n);
+        const int64_t i = e % n;
+        const ItemDev it = a.items[item];
+        out[a.probs[it.prob].pix_off + i] = a.field[it.field_off + i].x;
+    }
+}
+
+__global__ void copy_out_pairs_kernel(SweepArgs a, int H, int W, float2* out) {
+    const int64_t n = (int64_t)H * W;
+    const int64_t total = (int64_t)a.n_items * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int item = (int)(e / n);
+        const int64_t i = e % n;
+        const ItemDev it = a.items[item];
+        out[it.field_off + i] = a.field[it.field_off + i];
+    }
+}
+
+__global__ void grad_d_kernel(SweepArgs a, int H, int W, float* grad_d) {
+    const int64_t n = (int64_t)H * W;
+    const int64_t total = (int64_t)a.n_items * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int item = (int)(e / n);
+        const int64_t i = e % n;
+        const ItemDev it = a.items[item];
+        const ProbDev pr = a.probs[it.prob];
+        const float nb = a.nbar[pr.pix_off + i];
+        // N^-1 v with N = Nbar + tau; 0 on missing pixels (Nbar = +inf)
+        grad_d[pr.pix_off + i] = a.field[it.field_off + i].x * __builtin_amdgcn_rcpf(nb + pr.tau);
+    }
+}
+
+// Pack z = x + i y into the field so one complex FFT gives both spectra.
+__global__ void pack_pair_kernel(SweepArgs a, int H, int W, const float* x, const float* y) {
+    const int64_t n = (int64_t)H * W;
+    const int64_t total = (int64_t)a.n_items * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int item = (int)(e / n);
+        const int64_t i = e % n;
+        const ItemDev it = a.items[item];
+        const int64_t p = a.probs[it.prob].pix_off + i;
+        a.field[it.field_off + i] = make_float2(x[p], y[p]);
+    }
+}
+
+// Forward row FFTs only (for the band reduction).
+template <int L>
+__global__ __launch_bounds__(kThreads) void row_fft_kernel(SweepArgs a, int H) {
+    constexpr int ROWS = RowShape<L>::ROWS;
+    constexpr int TPR = RowShape<L>::TPR;
+    __shared__ float2 lds[ROWS * L];
+    const int tid = threadIdx.x;
+    const int64_t total_rows = (int64_t)a.n_items * H;
+    const int64_t grow0 = (int64_t)blockIdx.x * ROWS;
+    for (int i = 0; i < ROWS * L / kThreads; ++i) {
+        const int e = tid + i * kThreads;
+        const int64_t gr = grow0 + e / L;
+        lds[e] = gr < total_rows ? a.field[a.items[gr / H].field_off + (gr % H) * L + e % L] : make_float2(0.f, 0.f);
+    }
+    __syncthreads();
+    stockham_fft<L, 1, TPR, 1, false>(lds + (tid / TPR) * L, tid % TPR, a.tw_row);
+    for (int i = 0; i < ROWS * L / kThreads; ++i) {
+        const int e = tid + i * kThreads;
+        const int64_t gr = grow0 + e / L;
+        if (gr < total_rows) a.field[a.items[gr / H].field_off + (gr % H) * L + e % L] = lds[e];
+    }
+}
+
+template <int L>
+__global__ __launch_bounds__(kThreads) void col_fft_kernel(SweepArgs a, int W) {
+    constexpr int TC = ColShape<L>::TC;
+    constexpr int TPC = ColShape<L>::TPC;
+    constexpr int PITCH = ColShape<L>::PITCH;
+    __shared__ float2 lds[TC * PITCH];
+    const int tid = threadIdx.x;
+    const int64_t gc0 = (int64_t)blockIdx.x * TC;
+    const ItemDev it = a.items[gc0 / W];
+    float2* fld = a.field + it.field_off + gc0 % W;
+    for (int e = tid; e < TC * L; e += kThreads) lds[(e % TC) * PITCH + e / TC] = fld[(int64_t)(e / TC) * W + e % TC];
+    __syncthreads();
+    stockham_fft<L, 1, TPC, 1, false>(lds + (tid / TPC) * PITCH, tid % TPC, a.tw_col);
+    for (int e = tid; e < TC * L; e += kThreads) fld[(int64_t)(e / TC) * W + e % TC] = lds[(e % TC) * PITCH + e / TC];
+}
+
+// Per-block, per-band partial sums of Re(conj(X_k) Y_k) with X = (Z_k + conj Z_-k)/2,
+// Y = (Z_k - conj Z_-k)/(2i) from the packed spectrum Z; FP64 accumulation.
+constexpr int kMaxBands = 64;
+__global__ __launch_bounds__(kThreads) void band_partial_kernel(SweepArgs a, int H, int W, const int16_t* band,
+                                                                 int32_t nb_max, double* partial) {
+    __shared__ double acc[kMaxBands];
+    const int tid = threadIdx.x;
+    for (int b = tid; b < kMaxBands; b += kThreads) acc[b] = 0.0;
+    __syncthreads();
+    const int64_t n = (int64_t)H * W;
+    const int item = blockIdx.y;
+    const ItemDev it = a.items[item];
+    const ProbDev pr = a.probs[it.prob];
+    const float2* Z = a.field + it.field_off;
+    for (int64_t m = (int64_t)blockIdx.x * kThreads + tid; m < n; m += (int64_t)gridDim.x * kThreads) {
+        const int b = band[pr.pix_off + m];
+        if (b < 0) continue;
+        const int ky = (int)(m / W), kx = (int)(m % W);
+        const int64_t mm = (int64_t)((H - ky) % H) * W + (W - kx) % W;
+        const float2 zk = Z[m], zm = Z[mm];
+        // X = (zk + conj zm)/2, Y = (zk - conj zm)/(2i)
+        const double xr = 0.5 * ((double)zk.x + zm.x), xi = 0.5 * ((double)zk.y - zm.y);
+        const double yr = 0.5 * ((double)zk.y + zm.y), yi = -0.5 * ((double)zk.x - zm.x);
+        atomicAdd(&acc[b], xr * yr + xi * yi);  // LDS atomic
+    }
+    __syncthreads();
+    for (int b = tid; b < nb_max; b += kThreads)
+        partial[((int64_t)item * gridDim.x + blockIdx.x) * nb_max + b] = acc[b];
+}
+
+__global__ void band_sum_kernel(SweepArgs a, const double* partial, int nblocks, int32_t nb_max,
+                                const int32_t* band_base, const int32_t* band_count, const double* scale,
+                                double* out) {
+    const int item = blockIdx.x;
+    const ItemDev it = a.items[item];
+    const int base = band_base[it.prob];
+    const int cnt = band_count[it.prob];
+    for (int b = threadIdx.x; b < cnt; b += blockDim.x) {
+        double s = 0.0;
+        for (int k = 0; k < nblocks; ++k) s += partial[((int64_t)item * nblocks + k) * nb_max + b];
+        out[base + b] = scale ? s * scale[base + b] : s;
+    }
+}
+
+__global__ void load_real_kernel(SweepArgs a, int H, int W, const float* s_init) {
+    const int64_t n = (int64_t)H * W;
+    const int64_t total = (int64_t)a.n_items * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int item = (int)(e / n);
+        const int64_t i = e % n;
+        const ItemDev it = a.items[item];
+        a.field[it.field_off + i] = make_float2(s_init ? s_init[a.probs[it.prob].pix_off + i] : 0.f, 0.f);
+    }
+}
+
+// Launch KERNEL<L>(args...) for the supported transform lengths.
+#define MF_DISPATCH(L, KERNEL, GRID, BLOCK, STREAM, ...)                                     \
+    switch (L) {                                                                             \
+        case 16: hipLaunchKernelGGL(KERNEL<16>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;     \
+        case 32: hipLaunchKernelGGL(KERNEL<32>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;     \
+        case 64: hipLaunchKernelGGL(KERNEL<64>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;     \
+        case 128: hipLaunchKernelGGL(KERNEL<128>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;   \
+        case 256: hipLaunchKernelGGL(KERNEL<256>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;   \
+        case 512: hipLaunchKernelGGL(KERNEL<512>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;   \
+        case 1024: hipLaunchKernelGGL(KERNEL<1024>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+        case 2048: hipLaunchKernelGGL(KERNEL<2048>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
+        default: return hipErrorInvalidValue;                                                \
+    }
+
+template <int MODE>
+hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
+    int rows = 2048 / W;
+    if (rows < 1) rows = 1;
+    const int64_t total = (int64_t)a.n_items * H;
+    dim3 grid((unsigned)((total + rows - 1) / rows));
+    switch (W) {
+#define MF_CASE(N) \
+    case N: hipLaunchKernelGGL((row_kernel<N, MODE>), grid, dim3(kThreads), 0, s, a, H); break;
+        MF_CASE(16) MF_CASE(32) MF_CASE(64) MF_CASE(128) MF_CASE(256) MF_CASE(512) MF_CASE(1024) MF_CASE(2048)
+#undef MF_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int col_tc(int H) {
+    int tc = 8192 / H;
+    return tc > 16 ? 16 : tc;
+}
+
+dim3 elementwise_grid(int64_t total) {
+    int64_t b = (total + 255) / 256;
+    if (b > 65536) b = 65536;
+    if (b < 1) b = 1;
+    return dim3((unsigned)b);
+}
+
+}  // namespace
+
+int row_blocks_per_item(int W, int H) {
+    int rows = 2048 / W;
+    if (rows < 1) rows = 1;
+    return (H + rows - 1) / rows;
+}
+
+hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_t s) {
+    switch (row_mode) {
+        case kRowInv: return launch_row_mode<kRowInv>(W, H, a, s);
+        case kRowFwd: return launch_row_mode<kRowFwd>(W, H, a, s);
+        case kRowInvFwd: return launch_row_mode<kRowInvFwd>(W, H, a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s) {
+    const int tc = col_tc(H);
+    if (tc > W || tc < 2) return hipErrorInvalidValue;
+    const int64_t cols = (int64_t)a.n_items * W;
+    MF_DISPATCH(H, col_kernel, dim3((unsigned)(cols / tc)), dim3(kThreads), s, a, W);
+    return hipGetLastError();
+}
+
+hipError_t launch_init_items(int W, int H, const SweepArgs& a, const float2* state_in, float init_scale,
+                             hipStream_t s) {
+    const int64_t total = (int64_t)a.n_items * H * W / 2;
+    hipLaunchKernelGGL(init_kernel, elementwise_grid(total), dim3(256), 0, s, a, H, W, state_in, init_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_out_real(int W, int H, const SweepArgs& a, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(copy_out_real_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a, H,
+                       W, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_copy_out_pairs(int W, int H, const SweepArgs& a, float2* out, hipStream_t s) {
+    hipLaunchKernelGGL(copy_out_pairs_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a,
+                       H, W, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_d(int W, int H, const SweepArgs& a, float* grad_d, hipStream_t s) {
+    hipLaunchKernelGGL(grad_d_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a, H, W,
+                       grad_d);
+    return hipGetLastError();
+}
+
+hipError_t launch_load_real(int W, int H, const SweepArgs& a, const float* s_init, hipStream_t s) {
+    hipLaunchKernelGGL(load_real_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a, H, W,
+                       s_init);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_power(int W, int H, const SweepArgs& a, const float* x, const float* y,
+                             const int16_t* band, const int32_t* band_base, const int32_t* band_count,
+                             const double* scale, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(pack_pair_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a, H, W,
+                       x, y);
+    int rows = 2048 / W;
+    if (rows < 1) rows = 1;
+    const int64_t total_rows = (int64_t)a.n_items * H;
+    MF_DISPATCH(W, row_fft_kernel, dim3((unsigned)((total_rows + rows - 1) / rows)), dim3(kThreads), s, a, H);
+    const int tc = col_tc(H);
+    MF_DISPATCH(H, col_fft_kernel, dim3((unsigned)((int64_t)a.n_items * W / tc)), dim3(kThreads), s, a, W);
+    // partial buffer: the caller provides a.partials sized n_items * nblocks * kMaxBands
+    const int nblocks = 64;
+    hipLaunchKernelGGL(band_partial_kernel, dim3(nblocks, a.n_items), dim3(kThreads), 0, s, a, H, W, band,
+                       (int32_t)kMaxBands, a.partials);
+    hipLaunchKernelGGL(band_sum_kernel, dim3(a.n_items), dim3(64), 0, s, a, a.partials, nblocks,
+                       (int32_t)kMaxBands, band_base, band_count, scale, out);
+    return hipGetLastError();
+}
+
+}  // namespace mf
