@@ -1,0 +1,207 @@
+"""Throughput of the messenger-field Wiener-posterior sampler on one MI355X.
+
+Workload (the paper's benchmark image size): a 128x128 image, power spectrum
+P(k) = (k+2)^-2.5, noise sigma ~ U[0.3, 3], 25% of pixels missing in 4x4
+tiles; 1024 chains (512 complex pairs), 200 burn-in sweeps then 98 samples per
+chain = 100,352 posterior samples per step.  Synthetic data (seed 0).
+
+One step = one mf_sample call over every chain, inputs already in HBM, output
+samples written to HBM.  Prints ONE JSON line.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-plain]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+N = 128
+CHAINS = 1024
+BURN_IN = 200
+N_SAMPLES = 98
+DATA_SEED = 0
+
+# MI355X published peaks
+PEAK_HBM_GBPS = 8000.0
+# Non-packed 32-bit VALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def algorithmic_ops_per_pixel_pair_sweep(n_pixels: int) -> float:
+    """32-bit operations one chain pair needs per pixel per sweep (FMA = 1):
+    two complex 2D FFTs at the conventional 5 log2(n) per point each;
+    per pixel and per mode one Philox4x32-10 call per two elements
+    (10 rounds x [two 32x32->64 products + two 3-input XORs] = 40 ops) and one
+    Box-Muller pair (14 ops: two uniforms, log, sqrt, sin, cos, scalings);
+    the pixel update t = (1-a)s + a d + sigma xi (2 FMA per chain) and the
+    Fourier update S = f T + w eta (2 ops per real component)."""
+    fft = 2 * 5 * math.log2(n_pixels)
+    rng = 2 * (40 / 2 + 14)
+    updates = 4 + 4
+    return fft + rng + updates
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+# ----------------------------------------------------------------- oracle leg
+def _oracle_worker(args):
+    os.environ["OMP_NUM_THREADS"] = "1"
+    pair, n_sweeps = args
+    from oracle import messenger as om
+    from paper_1810_02821_amd import synth
+    prob = synth.config_128(DATA_SEED, N)
+    t0 = time.perf_counter()
+    om.sample_pair(prob, synth.philox_seed(DATA_SEED), 0, pair, burn_in=0, n_samples=n_sweeps)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(budget_s: float):
+    """The FP64 oracle sampler on the host cores, one chain pair per process."""
+    import multiprocessing as mp
+    cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
+    cores = max(cores, 1)
+    # calibrate one sweep on one core, then spread ~budget_s CPU-seconds over the cores
+    t_one = _oracle_worker((0, 3)) / 3.0
+    sweeps = max(2, min(2000, int(budget_s / cores / max(t_one, 1e-4))))
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with ctx.Pool(cores) as pool:
+        pool.map(_oracle_worker, [(p, sweeps) for p in range(cores)])
+    wall = time.perf_counter() - t0
+    samples = cores * 2 * sweeps  # two chains per pair, one sample per sweep
+    return {"value": samples / wall, "unit": "posterior samples/s", "cores": cores, "kind": "oracle",
+            "sample": f"{cores} chain pairs x {sweeps} sweeps of the 128x128 workload "
+                      f"(FP64 numpy, one process per pair, samples counted without burn-in; "
+                      f"{wall:.1f} s wall)"}
+
+
+# ----------------------------------------------------------------- GPU leg
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU: the sampler's chains are independent and this build "
+              f"runs on a single MI355X (asked for --gpus {args.gpus}).", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_1810_02821_amd as mf
+    from paper_1810_02821_amd import synth
+
+    torch.cuda.set_device(0)
+    prob = synth.config_128(DATA_SEED, N)
+    seed = synth.philox_seed(DATA_SEED)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    out = plan.samples_buffer(CHAINS, N_SAMPLES)
+    state = plan.state_buffer(CHAINS)
+    n_pix = N * N
+    pairs = CHAINS // 2
+    sweeps = BURN_IN + N_SAMPLES
+    samples_per_step = CHAINS * N_SAMPLES
+
+    def step(form="persistent", chains=CHAINS, o=out, s=state):
+        plan.sample(d, seed, chains=chains, burn_in=BURN_IN, n_samples=N_SAMPLES, form=form,
+                    state_out=s, out=o)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        ev[i][0].record(stream)
+        step()
+        ev[i][1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per_call_ms = [a.elapsed_time(b) for a, b in ev]
+    ms_per_step = wall * 1000.0 / args.steps
+    value = samples_per_step / (ms_per_step / 1000.0)
+    kern_ms = float(np.mean(per_call_ms))
+
+    ops = algorithmic_ops_per_pixel_pair_sweep(n_pix) * n_pix * pairs * sweeps
+    achieved_tops = ops / (kern_ms / 1000.0) / 1e12
+    hbm_bytes = samples_per_step * n_pix * 4 + pairs * n_pix * 8 + 3 * n_pix * 4
+    hbm_gbps = hbm_bytes / (kern_ms / 1000.0) / 1e9
+
+    extra = {}
+    if not args.no_plain:
+        # plain form: one chain pair per launch sequence, field in HBM between kernels
+        sub_chains = 8
+        o2 = plan.samples_buffer(sub_chains, N_SAMPLES)
+        s2 = plan.state_buffer(sub_chains)
+        print("[bench] plain form (8 chains)", file=sys.stderr, flush=True)
+        step("plain", sub_chains, o2, s2)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        step("plain", sub_chains, o2, s2)
+        torch.cuda.synchronize()
+        tp = time.perf_counter() - t1
+        plain = sub_chains * N_SAMPLES / tp
+        print("[bench] streamed form (all chains)", file=sys.stderr, flush=True)
+        step("streamed")
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        step("streamed")
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t2
+        extra["plain_form"] = {"value": plain, "unit": "posterior samples/s",
+                               "sample": f"{sub_chains} chains x ({BURN_IN}+{N_SAMPLES}) sweeps, one pair per launch sequence"}
+        extra["streamed_form"] = {"value": samples_per_step / ts, "unit": "posterior samples/s"}
+        extra["speedup_vs_plain"] = value / plain
+
+    result = {
+        "metric": "posterior samples/sec at 128^2 (batched chains) vs plain form; % HBM roofline",
+        "value": value,
+        "unit": "posterior samples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "128x128 Gaussian-random-field image, P=(k+2)^-2.5, sigma~U[0.3,3], "
+                               "25% masked 4x4 tiles; 1024 chains, 200 burn-in + 98 samples each",
+                   "chains": CHAINS, "burn_in": BURN_IN, "samples_per_chain": N_SAMPLES,
+                   "samples_per_step": samples_per_step, "form": "persistent"},
+        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
+                     "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": None,
+                     "kernel": "resident_sample_kernel<128>", "kernel_ms": kern_ms,
+                     "ops_per_pixel_pair_sweep": algorithmic_ops_per_pixel_pair_sweep(n_pix),
+                     "hbm_achieved_GBps": hbm_gbps, "hbm_frac": hbm_gbps / PEAK_HBM_GBPS},
+    }
+    result.update(extra)
+    if not args.no_cpu:
+        print("[bench] cpu baseline (oracle)", file=sys.stderr, flush=True)
+        result["cpu_baseline"] = cpu_baseline(args.cpu_seconds)
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

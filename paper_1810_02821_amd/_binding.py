@@ -224,15 +224,19 @@ class Plan:
         _check(st, allow_not_converged)
         return out, list(info)
 
+    def samples_buffer(self, chains: int, n_samples: int, device="cuda"):
+        import torch
+        return torch.empty(chains * n_samples * self.total_pixels, dtype=torch.float32, device=device)
+
     def sample(self, d, seed: int, chains: int, burn_in: int, n_samples: int, thin: int = 1,
                sweep_offset: int = 0, init_scale: float = 0.0, form: str = "auto",
-               state_in=None, state_out=None, samples=True):
+               state_in=None, state_out=None, samples=True, out=None):
         """Returns (samples [concat over problems of chains*n_samples*H*W] or None,
-        state_out or None)."""
-        import torch
-        out = None
-        if samples and n_samples > 0:
-            out = torch.empty(chains * n_samples * self.total_pixels, dtype=torch.float32, device=d.device)
+        state_out or None).  `out` may hold a preallocated samples buffer."""
+        if out is None and samples and n_samples > 0:
+            out = self.samples_buffer(chains, n_samples, d.device)
+        if out is not None and out.numel() < chains * n_samples * self.total_pixels:
+            raise ValueError("samples buffer too small")
         args = _SampleArgs(int(seed), int(chains), int(burn_in), int(n_samples), int(thin),
                            int(sweep_offset), float(init_scale), FORMS[form])
         st = lib().mf_sample(self._h, _ptr(d), C.byref(args), _ptr(state_in), _ptr(state_out),

@@ -87,6 +87,7 @@ struct mf_plan_s {
     std::map<int, float2*> d_tw;     // W_L^r for every transform length L
     // workspaces
     DevBuf items, field, t_save, partials, aux;
+    std::vector<mf::ItemDev> items_cached;  // what items[0..] holds (skip re-uploads)
     std::vector<float> host_nbar;    // for residual norms
     ~mf_plan_s() {
         (void)hipFree(d_probs);
@@ -226,8 +227,18 @@ mf_status put_items(mf_plan p, const std::vector<mf::ItemDev>& it, size_t slot, 
     const size_t need = (slot + it.size()) * sizeof(mf::ItemDev);
     if (need > p->items.bytes) return fail(MF_ERR_INVALID_ARG, "internal: items workspace too small");
     mf::ItemDev* d = p->items.as<mf::ItemDev>() + slot;
+    auto same = [](const mf::ItemDev& x, const mf::ItemDev& y) {
+        return x.prob == y.prob && x.pair == y.pair && x.field_off == y.field_off;
+    };
+    if (slot == 0 && p->items_cached.size() == it.size() &&
+        std::equal(it.begin(), it.end(), p->items_cached.begin(), same)) {
+        *out = d;  // already on the device
+        return MF_OK;
+    }
     MF_HIP(hipMemcpyAsync(d, it.data(), it.size() * sizeof(mf::ItemDev), hipMemcpyHostToDevice, s));
     MF_HIP(hipStreamSynchronize(s));  // the host vector may die right after
+    if (slot == 0) p->items_cached = it;
+    else p->items_cached.clear();     // slot 0 is intact, but keep the rule simple
     *out = d;
     return MF_OK;
 }
@@ -342,6 +353,7 @@ mf_status ensure_solve_workspace(mf_plan p, hipStream_t s) {
         max_items = std::max(max_items, kv.second.size());
         max_rows = std::max(max_rows, kv.second.size() * (size_t)kv.first.first);
     }
+    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
     MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
     MF_HIP(p->field.ensure((size_t)p->total_px * sizeof(float2)));
     MF_HIP(p->t_save.ensure((size_t)p->total_px * sizeof(float2)));
@@ -719,6 +731,7 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
     const float2* sin = reinterpret_cast<const float2*>(state_in);
     size_t max_items = 0;
     for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size() * (size_t)pairs);
+    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
     MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;

@@ -113,7 +113,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
                 float src;
                 if (a.src_kind == kSrcData) src = aa[q] > 0.f ? aa[q] * sr[q] : 0.f;
                 else src = T * sr[q];
-                const float sig = a.stochastic ? __builtin_amdgcn_sqrtf(T * oma) : 0.f;
+                const float sig = a.stochastic ? __builtin_amdgcn_sqrtf(fmaxf(T * oma, 0.f)) : 0.f;
                 t[q].x = fmaf(oma, s[q].x, fmaf(sig, z[q].x, src));
                 t[q].y = a.real_only ? 0.f : fmaf(oma, s[q].y, fmaf(sig, z[q].y, src));
             }

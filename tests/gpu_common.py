@@ -9,8 +9,12 @@ REL_TOL = 1e-4
 
 
 def rel(a, b):
+    """Relative L2 distance; +inf if either side holds a NaN or Inf (so a
+    max() over cases or a < comparison can never hide one)."""
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
+    if not (np.all(np.isfinite(a)) and np.all(np.isfinite(b))):
+        return float("inf")
     return float(np.linalg.norm((a - b).ravel()) / np.linalg.norm(b.ravel()))
 
 

@@ -35,8 +35,9 @@ def _check_samples(plan, flat, prob, pid, chains, n_samples, seed, burn_in, thin
                 assert r < REL_TOL, f"problem {pid} chain {c} sample {k}: rel {r:.2e}"
 
 
-@pytest.mark.parametrize("size", [16, 32, 64, 128, 256])
-@pytest.mark.parametrize("form", ["streamed"])
+@pytest.mark.parametrize("size,form", [(16, "streamed"), (32, "streamed"), (64, "streamed"),
+                                       (128, "streamed"), (256, "streamed"), (32, "persistent"),
+                                       (64, "persistent"), (128, "persistent")])
 def test_samples_match_oracle(torch_cuda, size, form):
     mf = _mf()
     banner(f"samples {form} {size}x{size}")
@@ -50,15 +51,16 @@ def test_samples_match_oracle(torch_cuda, size, form):
     _check_samples(plan, flat, prob, 0, 4, n, seed, 2)
 
 
-def test_thousand_sweeps_per_sample_parity(torch_cuda):
+@pytest.mark.parametrize("form", ["streamed", "persistent"])
+def test_thousand_sweeps_per_sample_parity(torch_cuda, form):
     """Samples after 1, 10, 100 and 1000 sweeps on the same Philox stream."""
     mf = _mf()
-    banner("1000 sweeps 32x32")
+    banner(f"1000 sweeps 32x32 {form}")
     prob = synth.config_small(0, 32)
     plan = mf.Plan([prob])
     d = plan.concat([prob.d])
     seed = synth.philox_seed(0)
-    flat, _ = plan.sample(d, seed, chains=2, burn_in=0, n_samples=1000, form="streamed")
+    flat, _ = plan.sample(d, seed, chains=2, burn_in=0, n_samples=1000, form=form)
     got = plan.sample_view(flat, 0, 2, 1000).cpu().numpy()
     ref, _ = om.sample_pair(prob, seed, 0, 0, 0, 1000)
     worst = 0.0
@@ -210,3 +212,42 @@ def test_band_power_matches_numpy(torch_cuda):
     out = plan.band_power(plan.concat([x]), plan.concat([y])).cpu().numpy()
     ref = oa.band_cross_power(x, y, prob.spectrum.edges, 64, 64)
     assert np.max(np.abs(out - ref)) < 1e-4 * np.max(np.abs(ref))
+
+
+def test_persistent_agrees_with_streamed_128_batch(torch_cuda):
+    """The paper-size image with many chains: both forms draw the same samples
+    (different FFT factorisations, so agreement is to FP32 rounding)."""
+    mf = _mf()
+    banner("persistent vs streamed 128, 64 chains")
+    prob = synth.config_128(0)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    seed = synth.philox_seed(0)
+    a, _ = plan.sample(d, seed, chains=64, burn_in=20, n_samples=5, form="persistent")
+    b, _ = plan.sample(d, seed, chains=64, burn_in=20, n_samples=5, form="streamed")
+    va = plan.sample_view(a, 0, 64, 5).cpu().numpy()
+    vb = plan.sample_view(b, 0, 64, 5).cpu().numpy()
+    worst = max(rel(va[c, k], vb[c, k]) for c in range(64) for k in range(5))
+    print(f"worst persistent/streamed rel {worst:.2e}")
+    assert worst < 1e-5
+    _check_samples(plan, a, prob, 0, 64, 5, seed, 20, pairs=[0, 31])
+
+
+def test_persistent_multi_problem_and_state(torch_cuda):
+    mf = _mf()
+    banner("persistent multi-problem")
+    probs = [synth.config_small(i, 32) for i in range(3)] + [synth.config_128(3, 64)]
+    plan = mf.Plan(probs)
+    d = plan.concat([p.d for p in probs])
+    st = plan.state_buffer(4)
+    flat, _ = plan.sample(d, 11, chains=4, burn_in=3, n_samples=4, thin=2, form="persistent", state_out=st)
+    for i, p in enumerate(probs):
+        _check_samples(plan, flat, p, i, 4, 4, 11, 3, thin=2)
+    # resume from the persistent state with the streamed form
+    more, _ = plan.sample(d, 11, chains=4, burn_in=0, n_samples=2, sweep_offset=11, form="streamed",
+                          state_in=st)
+    full, _ = plan.sample(d, 11, chains=4, burn_in=11, n_samples=2, form="persistent")
+    worst = max(rel(plan.sample_view(more, i, 4, 2).cpu().numpy()[c, k],
+                    plan.sample_view(full, i, 4, 2).cpu().numpy()[c, k])
+                for i in range(4) for c in range(4) for k in range(2))
+    assert worst < 1e-5
