@@ -31,22 +31,39 @@ DATA_SEED = 0
 
 # MI355X published peaks
 PEAK_HBM_GBPS = 8000.0
-# Non-packed 32-bit VALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 vector: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU (4 SIMDs x 16 lanes x FMA x dual-issue packed)
+PEAK_FP32_TFLOPS = 157.3
+
+# HBM traffic of resident_sample_kernel<128> on this workload, from rocprofv3
+# FETCH_SIZE / WRITE_SIZE runs scaled by the same counters on a 1 GiB copy, and
+# the hash of the kernel sources it was measured on (traffic is reported only
+# while the sources are unchanged).
+TRAFFIC_BYTES = int((81173.75 * 2.0 + 6492839.0 * 1.0) * 1024)  # FETCH x2.0 + WRITE x1.0 (copy-calibrated)
+TRAFFIC_SOURCES_SHA = "6680614397d08baf"
 
 
-def algorithmic_ops_per_pixel_pair_sweep(n_pixels: int) -> float:
-    """32-bit operations one chain pair needs per pixel per sweep (FMA = 1):
-    two complex 2D FFTs at the conventional 5 log2(n) per point each;
-    per pixel and per mode one Philox4x32-10 call per two elements
-    (10 rounds x [two 32x32->64 products + two 3-input XORs] = 40 ops) and one
-    Box-Muller pair (14 ops: two uniforms, log, sqrt, sin, cos, scalings);
-    the pixel update t = (1-a)s + a d + sigma xi (2 FMA per chain) and the
-    Fourier update S = f T + w eta (2 ops per real component)."""
+def kernel_sources_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("mf_resident.hip", "mf_device.hpp", "mf_resident.hpp"):
+        with open(os.path.join(ROOT, "paper_1810_02821_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_flops_per_pixel_pair_sweep(n_pixels: int) -> float:
+    """FLOP-equivalents one chain pair needs per pixel per sweep (FMA = 2):
+    two complex 2D FFTs at the conventional 5 log2(n) per point each (140 at
+    128^2); the pixel update t = (1-a)s + a d + sigma xi (2 FMA per chain: 8)
+    and the Fourier update S = f T + w eta (FMA + mul per component: 6); and
+    per pixel and per mode half a Philox4x32-10 call (10 rounds x [two
+    32x32->64 products + two 3-input XORs] = 40 integer ops per call) plus one
+    Box-Muller pair (14 ops: two uniforms, log, sqrt, sin, cos, scalings),
+    each integer or transcendental op counted as one FLOP: 2 x (20 + 14) = 68."""
     fft = 2 * 5 * math.log2(n_pixels)
+    updates = 8 + 6
     rng = 2 * (40 / 2 + 14)
-    updates = 4 + 4
-    return fft + rng + updates
+    return fft + updates + rng
 
 
 def parse():
@@ -57,7 +74,23 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--workload", default="paper", choices=["paper", "large", "uneven", "grad"],
+                    help="paper (default, the headline line) or one of the other measured workloads")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (to scale HBM counters)")
     return ap.parse_args()
+
+
+def calibrate_copy():
+    """A plain copy of known size: 1 GiB read + 1 GiB written per launch."""
+    import torch
+    n = (1 << 30) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}))
 
 
 # ----------------------------------------------------------------- oracle leg
@@ -95,6 +128,13 @@ def cpu_baseline(budget_s: float):
 # ----------------------------------------------------------------- GPU leg
 def main():
     args = parse()
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
+    if args.workload != "paper":
+        import bench_workloads
+        bench_workloads.run(args)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU: the sampler's chains are independent and this build "
@@ -142,10 +182,12 @@ def main():
     value = samples_per_step / (ms_per_step / 1000.0)
     kern_ms = float(np.mean(per_call_ms))
 
-    ops = algorithmic_ops_per_pixel_pair_sweep(n_pix) * n_pix * pairs * sweeps
-    achieved_tops = ops / (kern_ms / 1000.0) / 1e12
-    hbm_bytes = samples_per_step * n_pix * 4 + pairs * n_pix * 8 + 3 * n_pix * 4
+    flops = algorithmic_flops_per_pixel_pair_sweep(n_pix) * n_pix * pairs * sweeps
+    achieved_tflops = flops / (kern_ms / 1000.0) / 1e12
+    # compulsory HBM bytes: samples out, final pair states out, problem tables in
+    hbm_bytes = samples_per_step * n_pix * 4 + pairs * n_pix * 8 + 20 * n_pix
     hbm_gbps = hbm_bytes / (kern_ms / 1000.0) / 1e9
+    traffic = TRAFFIC_BYTES if TRAFFIC_SOURCES_SHA == kernel_sources_sha() else None
 
     extra = {}
     if not args.no_plain:
@@ -190,10 +232,11 @@ def main():
                                "25% masked 4x4 tiles; 1024 chains, 200 burn-in + 98 samples each",
                    "chains": CHAINS, "burn_in": BURN_IN, "samples_per_chain": N_SAMPLES,
                    "samples_per_step": samples_per_step, "form": "persistent"},
-        "roofline": {"bound": "alu", "achieved": achieved_tops, "peak": PEAK_VALU_TOPS, "unit": "Tops/s",
-                     "frac": achieved_tops / PEAK_VALU_TOPS, "traffic": None,
+        "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "resident_sample_kernel<128>", "kernel_ms": kern_ms,
-                     "ops_per_pixel_pair_sweep": algorithmic_ops_per_pixel_pair_sweep(n_pix),
+                     "flops_per_pixel_pair_sweep": algorithmic_flops_per_pixel_pair_sweep(n_pix),
+                     "hbm_algorithmic_bytes": hbm_bytes,
                      "hbm_achieved_GBps": hbm_gbps, "hbm_frac": hbm_gbps / PEAK_HBM_GBPS},
     }
     result.update(extra)

@@ -1,0 +1,115 @@
+"""Secondary measured workloads of bench.py (each prints one JSON line).
+
+large  : 2048x2048 map (P=(k+1)^-2.2, smooth noise, disk footprint with 5%
+         holes), 64 chains x 200 sweeps on the streamed path, every 20th state
+         emitted; reports chain-sweeps/s and HBM GB/s of the sweep kernels.
+uneven : 4096 problems of sizes {64,128,256,512}^2 at weights {.4,.3,.2,.1},
+         per-problem spectra, noise and masks; one chain (pair) per problem,
+         500 sweeps, final states written; reports pixel-sweeps/s per class.
+grad   : 256x256 band-spectrum Wiener filter (32 bands) and its gradient
+         (one adjoint solve); reports the gradient/forward time ratio.
+"""
+from __future__ import annotations
+
+import json
+import sys
+import time
+
+import numpy as np
+
+
+def _timed(fn, reps=1):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / reps
+
+
+def large(args):
+    import paper_1810_02821_amd as mf
+    from paper_1810_02821_amd import synth
+    N, chains, sweeps, thin = 2048, 64, 200, 20
+    print("[bench] large: generating 2048^2 problem", file=sys.stderr, flush=True)
+    prob = synth.config_large(0, N)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    n_samples = sweeps // thin
+    out = plan.samples_buffer(chains, n_samples)
+    st = plan.state_buffer(chains)
+    run = lambda: plan.sample(d, 1000, chains=chains, burn_in=0, n_samples=n_samples, thin=thin,
+                              form="streamed", state_out=st, out=out)
+    run()
+    print("[bench] large: timing", file=sys.stderr, flush=True)
+    t = _timed(run, max(1, args.steps // 2))
+    pairs = chains // 2
+    pair_sweeps = pairs * sweeps
+    n = N * N
+    # compulsory field traffic per pair-sweep: each of the two kernels reads and
+    # writes the complex pair field (4 x 8 B/px); samples: 8 B/px per pair per emission
+    field_bytes = pair_sweeps * 4 * 8 * n
+    sample_bytes = pairs * n_samples * 8 * n
+    table_bytes = 12 * n
+    gbps = (field_bytes + sample_bytes + table_bytes) / t / 1e9
+    print(json.dumps({"workload": "large", "metric": "chain-sweeps/s at 2048^2 (streamed, 64 chains)",
+                      "value": chains * sweeps / t, "unit": "chain-sweeps/s", "seconds": t,
+                      "hbm_algorithmic_GBps": gbps, "hbm_frac": gbps / 8000.0,
+                      "samples_per_s": chains * n_samples / t}), flush=True)
+
+
+def uneven(args):
+    import paper_1810_02821_amd as mf
+    from paper_1810_02821_amd import synth
+    print("[bench] uneven: generating 4096 problems", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    probs = synth.config_uneven(0, n_problems=4096)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plan = mf.Plan(probs)
+    t_plan = time.perf_counter() - t0
+    d = plan.concat([p.d for p in probs])
+    st = plan.state_buffer(1)
+    sweeps = 500
+    run = lambda: plan.sample(d, 1000, chains=1, burn_in=sweeps, n_samples=0, form="auto",
+                              state_out=st, samples=False)
+    run()
+    print("[bench] uneven: timing", file=sys.stderr, flush=True)
+    t = _timed(run, 1)
+    sizes = np.array([p.H for p in probs])
+    px = {int(s): int(np.sum(sizes == s)) * int(s) * int(s) for s in np.unique(sizes)}
+    total_px = sum(px.values())
+    print(json.dumps({"workload": "uneven", "metric": "pixel-sweeps/s, 4096 uneven problems, 500 sweeps",
+                      "value": total_px * sweeps / t, "unit": "pixel-sweeps/s (one chain per problem)",
+                      "seconds": t, "problems_per_size": {int(s): int(np.sum(sizes == s)) for s in np.unique(sizes)},
+                      "plan_seconds": t_plan, "generate_seconds": t_gen}), flush=True)
+
+
+def grad(args):
+    import torch
+    import paper_1810_02821_amd as mf
+    from paper_1810_02821_amd import synth
+    from paper_1810_02821_amd.autograd import BandPosteriorLoss
+    prob = synth.config_bands(0, 256, 32)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    sch = mf.Schedule(list(np.geomspace(1e3, 1.0, 30)) + [1.0], [10] * 30 + [3000])
+    loss = BandPosteriorLoss(plan, prob.noise_var.ravel())
+    theta = torch.tensor(np.asarray(prob.spectrum.amps), dtype=torch.float64, device="cuda")
+    s_true = plan.concat([prob.s_true])
+    fwd = lambda: plan.wiener(d, sch, allow_not_converged=True)
+    fwd()
+    t_f = _timed(fwd, 2)
+    s, _ = plan.wiener(d, sch, allow_not_converged=True)
+    g = (s - s_true).contiguous()
+    bwd = lambda: plan.wiener_backward(s, g, sch, allow_not_converged=True)
+    t_b = _timed(bwd, 2)
+    t_all = _timed(lambda: loss.value_and_grad(d, theta, s_true, sch, sch), 1)
+    print(json.dumps({"workload": "grad", "metric": "gradient time / forward Wiener time, 256^2, 32 bands",
+                      "value": t_b / t_f, "unit": "ratio", "forward_s": t_f, "backward_s": t_b,
+                      "loss_and_grad_s": t_all, "sweeps_per_solve": 3300}), flush=True)
+
+
+def run(args):
+    {"large": large, "uneven": uneven, "grad": grad}[args.workload](args)

@@ -44,10 +44,15 @@ def band_cross_power(x, y, edges, H, W):
     return np.array([prod[idx == b].sum() for b in range(nb)])
 
 
-def wiener_vjp(problem, s_wf, gbar, schedule: messenger.Schedule):
+def wiener_vjp(problem, s_wf, gbar, schedule: messenger.Schedule = None, solver: str = "messenger"):
     """(dL/dd, dL/dtheta) for dL/ds* = gbar.  dL/dtheta is only defined for a
-    band spectrum; it is None for a power law."""
-    v, info = adjoint_solve(problem, gbar, schedule)
+    band spectrum; it is None for a power law.  `solver` picks the messenger
+    iteration or conjugate gradients for v (same linear system)."""
+    if solver == "cg":
+        v, it = messenger.wiener_cg(problem, tol=1e-12, rhs=gbar)
+        info = it
+    else:
+        v, info = adjoint_solve(problem, gbar, schedule)
     c = messenger.coefficients(problem.noise_var, problem.spectrum, 1.0)
     grad_d = c.ninv * v
     grad_theta = None
@@ -77,7 +82,7 @@ def loss_terms(problem, s_wf, s_true):
     return prior + like + logdet + l2
 
 
-def loss_grad(problem, s_wf, s_true, schedule: messenger.Schedule):
+def loss_grad(problem, s_wf, s_true, schedule: messenger.Schedule = None, solver: str = "messenger"):
     """Full gradient of loss_terms w.r.t. d and the band amplitudes.
 
     At the Wiener solution the prior + likelihood part is stationary in s, so
@@ -86,7 +91,7 @@ def loss_grad(problem, s_wf, s_true, schedule: messenger.Schedule):
     n = H * W
     c = messenger.coefficients(problem.noise_var, problem.spectrum, 1.0)
     d = np.where(problem.mask, 0.0, problem.d)
-    gd_imp, gt_imp, v, info = wiener_vjp(problem, s_wf, s_wf - s_true, schedule)
+    gd_imp, gt_imp, v, info = wiener_vjp(problem, s_wf, s_wf - s_true, schedule, solver)
     grad_d = c.ninv * (d - s_wf) + gd_imp
     theta = np.asarray(problem.spectrum.amps, dtype=np.float64)
     edges = problem.spectrum.edges

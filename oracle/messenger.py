@@ -255,6 +255,42 @@ def residual(problem, s, lam: float = 1.0) -> float:
     return _norm(r) / _norm(b)
 
 
+def wiener_cg(problem, tol: float = 1e-12, max_iter: int = 20000, lam: float = 1.0, rhs=None):
+    """The Wiener filter as the exact solution of its normal equations (Eq. 7),
+    (S^-1 + N_eff^-1) s = b with b = N_eff^-1 d (or a given rhs), by conjugate
+    gradients on the S-preconditioned form (I + S^1/2 N^-1 S^1/2) x = S^1/2 b,
+    s = S^1/2 x.  A second, independent route to the same fixed point for images
+    too large for dense algebra; S^1/2 is diagonal in Fourier space."""
+    c = coefficients(problem.noise_var, problem.spectrum, lam)
+    d = np.where(problem.mask, 0.0, problem.d)
+    b = c.ninv * d if rhs is None else np.asarray(rhs, dtype=np.float64)
+    sq = np.sqrt(c.nP)
+
+    def half(x):  # S^1/2 x
+        return np.fft.ifft2(sq * np.fft.fft2(x)).real
+
+    def op(x):
+        return x + half(c.ninv * half(x))
+
+    rhs_x = half(b)
+    x = np.zeros_like(rhs_x)
+    r = rhs_x - op(x)
+    p = r.copy()
+    rr = float(np.sum(r * r))
+    r0 = np.sqrt(rr)
+    it = 0
+    while np.sqrt(rr) > tol * r0 and it < max_iter:
+        Ap = op(p)
+        alpha = rr / float(np.sum(p * Ap))
+        x += alpha * p
+        r -= alpha * Ap
+        rr_new = float(np.sum(r * r))
+        p = r + (rr_new / rr) * p
+        rr = rr_new
+        it += 1
+    return half(x), it
+
+
 # --------------------------------------------------------------------------
 # Sampler (Algorithm 1 with the counter-based normal stream).
 # --------------------------------------------------------------------------

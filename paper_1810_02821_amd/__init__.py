@@ -13,4 +13,12 @@ thin Python face:
 """
 from ._binding import (Info, MFError, NotConverged, Plan, Schedule, lib)  # noqa: F401
 
+
+def __getattr__(name):
+    # torch-dependent helpers load lazily
+    if name == "autograd":
+        import importlib
+        return importlib.import_module(".autograd", __name__)
+    raise AttributeError(name)
+
 __all__ = ["Plan", "Schedule", "Info", "MFError", "NotConverged", "lib"]

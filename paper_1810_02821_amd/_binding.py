@@ -78,6 +78,10 @@ def lib():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libmf.so not found at {LIB_PATH}: build it first "
                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    # torch first: libmf's HIP runtime dependency must resolve to the runtime
+    # torch already loaded, so that torch's device memory, streams and events
+    # and the library's launches share one runtime.
+    import torch  # noqa: F401
     L = C.CDLL(LIB_PATH)
     vp = C.c_void_p
     L.mf_plan_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(_Problem), C.c_uint32, vp]
@@ -202,6 +206,22 @@ class Plan:
     def set_spectrum(self, i: int, spectrum):
         s, keep = _spectrum_c(spectrum)
         _check(lib().mf_plan_set_spectrum(self._h, i, C.byref(s)))
+
+    def set_band_amplitudes(self, theta):
+        """Replace the band amplitudes of every band-spectrum problem;
+        `theta` concatenates them in problem order (length total_bands)."""
+        import types
+        theta = np.asarray(theta, dtype=np.float64)
+        if theta.shape != (self.total_bands,):
+            raise ValueError(f"need {self.total_bands} band amplitudes")
+        o = 0
+        for i, p in enumerate(self.problems):
+            if getattr(p.spectrum, "kind", None) != "bands":
+                continue
+            nb = len(p.spectrum.amps)
+            spec = types.SimpleNamespace(kind="bands", edges=p.spectrum.edges, amps=theta[o:o + nb])
+            self.set_spectrum(i, spec)
+            o += nb
 
     # ---- data marshalling helpers (host numpy <-> concatenated device arrays)
     def concat(self, arrays, device="cuda"):

@@ -86,7 +86,7 @@ struct mf_plan_s {
     double* d_band_scale = nullptr;  // 1 / (n^2 theta_b^2)
     std::map<int, float2*> d_tw;     // W_L^r for every transform length L
     // workspaces
-    DevBuf items, field, t_save, partials, aux;
+    DevBuf items, field, t_save, partials, aux, coef;
     std::vector<mf::ItemDev> items_cached;  // what items[0..] holds (skip re-uploads)
     std::vector<float> host_nbar;    // for residual norms
     ~mf_plan_s() {
@@ -103,6 +103,7 @@ struct mf_plan_s {
         t_save.release();
         partials.release();
         aux.release();
+        coef.release();
     }
 };
 
@@ -730,9 +731,26 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
     }
     const float2* sin = reinterpret_cast<const float2*>(state_in);
     size_t max_items = 0;
-    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size() * (size_t)pairs);
+    bool any_persistent = false;
+    for (auto& kv : p->classes) {
+        max_items = std::max(max_items, kv.second.size() * (size_t)pairs);
+        const bool res = mf::resident_supported(kv.first.first, kv.first.second);
+        any_persistent |= g->form == MF_FORM_PERSISTENT || (g->form == MF_FORM_AUTO && res);
+    }
     if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
     MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
+    float4* pcoef = nullptr;
+    float2* psrc = nullptr;
+    float4* mcoef = nullptr;
+    if (any_persistent) {
+        const size_t half = (size_t)p->total_px / 2;
+        MF_HIP(p->coef.ensure(half * (sizeof(float4) + sizeof(float2) + sizeof(float4))));
+        pcoef = p->coef.as<float4>();
+        psrc = reinterpret_cast<float2*>(pcoef + half);
+        mcoef = reinterpret_cast<float4*>(psrc + half);
+        MF_HIP(mf::launch_sampler_coefs(p->d_probs, (int)p->probs.size(), d, p->d_nbar, p->d_nP, pcoef, psrc, mcoef,
+                                        s));
+    }
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;
         std::vector<mf::ItemDev> items;
@@ -754,9 +772,9 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
             r.field = work;
             r.state_in = sin;
             r.init_scale = g->init_scale;
-            r.d = d;
-            r.nbar = p->d_nbar;
-            r.nP = p->d_nP;
+            r.pcoef = pcoef;
+            r.psrc = psrc;
+            r.mcoef = mcoef;
             r.tw = p->d_tw.at(W);
             r.key0 = (uint32_t)(g->seed & 0xffffffffu);
             r.key1 = (uint32_t)(g->seed >> 32);

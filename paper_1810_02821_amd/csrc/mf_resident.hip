@@ -11,6 +11,10 @@
 // transposed passes D', C', B', A' (decimation in time), so the Fourier-space
 // update happens in pass D's registers and the pixel-space update in pass A's,
 // and LDS is touched only for the three exchanges between passes.
+//
+// LDS exchanges use pitch N with per-exchange XOR swizzles of the column, and
+// 16-byte accesses where a thread moves two adjacent elements, so that every
+// 16- or 32-lane phase of an LDS instruction touches distinct banks.
 #include "mf_device.hpp"
 #include "mf_resident.hpp"
 
@@ -21,10 +25,37 @@ namespace {
 template <int N>
 struct Res {
     static constexpr int P = N / 8;
-    static constexpr int NT = N * N / 16;      // threads per workgroup
-    static constexpr int PITCH = N + 1;        // LDS row pitch (complex)
-    static constexpr int TB = 16 / P;          // radix-P tasks per thread
+    static constexpr int NT = N * N / 16;                  // threads per workgroup
+    static constexpr int TB = 16 / P;                      // radix-P tasks per thread
+    static constexpr int R1 = 32 / P;                      // pass-A rows per 16-lane phase
+    static constexpr int SW2 = (N < 32 ? N : 32) - 1;
 };
+
+// E1 (between passes A and B): row y, column k1 P + x0
+template <int N>
+__device__ __forceinline__ unsigned e1(unsigned r, unsigned c) {
+    constexpr unsigned P = Res<N>::P, R1 = Res<N>::R1;
+    return r * N + (c ^ (P * (r % R1) + 2 * ((r / R1) % (P / 2))));
+}
+// E2 (between passes B and C): row y, column kx
+template <int N>
+__device__ __forceinline__ unsigned e2(unsigned r, unsigned c) {
+    return r * N + (c ^ (r & (unsigned)Res<N>::SW2));
+}
+// E3 (between passes C and D): row 8 k1 + y0, column kx
+template <int N>
+__device__ __forceinline__ unsigned e3(unsigned r, unsigned c) {
+    return r * N + c;
+}
+
+__device__ __forceinline__ void st2(float2* lds, unsigned i, float2 a, float2 b) {
+    *reinterpret_cast<float4*>(lds + i) = make_float4(a.x, a.y, b.x, b.y);
+}
+__device__ __forceinline__ void ld2(const float2* lds, unsigned i, float2& a, float2& b) {
+    const float4 q = *reinterpret_cast<const float4*>(lds + i);
+    a = make_float2(q.x, q.y);
+    b = make_float2(q.z, q.w);
+}
 
 template <int R, bool INV>
 __device__ __forceinline__ void dft_slice(float2* v) {
@@ -36,8 +67,8 @@ __device__ __forceinline__ void dft_slice(float2* v) {
     for (int i = 0; i < R; ++i) v[i] = t[i];
 }
 
-// Hide a table pointer from loop-invariant code motion: the tables are re-read
-// (from cache) every sweep instead of being held in registers across sweeps.
+// Hide a pointer from loop-invariant code motion: tables are re-read (from
+// cache) every sweep instead of being held in registers across sweeps.
 template <typename T>
 __device__ __forceinline__ const T* per_sweep(const T* p) {
     asm volatile("" : "+s"(p));
@@ -52,24 +83,20 @@ __device__ __forceinline__ float2 twiddle(float2 v, const float2* __restrict__ t
 
 // ---------------------------------------------------------------- passes --
 // Thread coordinates in each layout (tid in [0, NT)):
-//   A: y = tid / (P/2), j = tid % (P/2); holds x = 2j + q + P m   at v[8q + m]
-//   B: tasks t = tid*TB + i: y = t / 8, k1 = t % 8; holds x0      at v[P i + x0]
-//   C: kx = tid % N, y0 = tid / N + i P/2;          holds m       at v[P i + m]
-//   D: jx = tid % (N/2), k1 = tid / (N/2);  kx = 2jx + q; holds y0 at v[8q + y0]
-// LDS layouts between passes (row, column):
-//   E1 (A<->B): (y, k1 P + x0)     E2 (B<->C): (y, kx)     E3 (C<->D): (k1 8 + y0, kx)
+//   A: y = tid / (P/2), j = tid % (P/2); holds x = 2j + q + P m     at v[8q + m]
+//   B: t = tid + i NT (i < TB): y = t % N, k1 = t / N; holds x0    at v[P i + x0]
+//   C: kx = tid % N, y0 = tid / N + i P/2 (i < TB);   holds m      at v[P i + m]
+//   D: jx = tid % (N/2), k1 = tid / (N/2); kx = 2jx + q; holds y0  at v[8q + y0]
 
 template <int N, bool INV>
-__device__ __forceinline__ void pass_A(float2 (&v)[16], const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void pass_A(float2 (&v)[16], const float2* __restrict__ tw, unsigned tid) {
     constexpr int P = Res<N>::P;
-    const int j = tid % (P / 2);
+    const unsigned j = tid % (P / 2);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int x0 = 2 * j + q;
-        if (INV) {
-            dft_slice<8, true>(v + 8 * q);
-        } else {
-            dft_slice<8, false>(v + 8 * q);
+        dft_slice<8, INV>(v + 8 * q);
+        if (!INV) {
+            const unsigned x0 = 2 * j + q;
 #pragma unroll
             for (int k1 = 1; k1 < 8; ++k1) v[8 * q + k1] = twiddle<false>(v[8 * q + k1], tw, x0 * k1);
         }
@@ -77,57 +104,53 @@ __device__ __forceinline__ void pass_A(float2 (&v)[16], const float2* __restrict
 }
 
 template <int N>
-__device__ __forceinline__ void store_E1_from_A(float2* lds, const float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH;
-    const int y = tid / (P / 2), j = tid % (P / 2);
+__device__ __forceinline__ void store_E1_from_A(float2* lds, const float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P;
+    const unsigned y = tid / (P / 2), j = tid % (P / 2);
 #pragma unroll
-    for (int k1 = 0; k1 < 8; ++k1)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) lds[y * PITCH + k1 * P + 2 * j + q] = v[8 * q + k1];
+    for (int k1 = 0; k1 < 8; ++k1) st2(lds, e1<N>(y, k1 * P + 2 * j), v[k1], v[8 + k1]);
 }
 
 template <int N>
-__device__ __forceinline__ void load_A_from_E1(const float2* lds, float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH;
-    const int y = tid / (P / 2), j = tid % (P / 2);
+__device__ __forceinline__ void load_A_from_E1(const float2* lds, float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P;
+    const unsigned y = tid / (P / 2), j = tid % (P / 2);
 #pragma unroll
-    for (int k1 = 0; k1 < 8; ++k1)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) v[8 * q + k1] = lds[y * PITCH + k1 * P + 2 * j + q];
+    for (int k1 = 0; k1 < 8; ++k1) ld2(lds, e1<N>(y, k1 * P + 2 * j), v[k1], v[8 + k1]);
 }
 
 template <int N>
-__device__ __forceinline__ void load_B_from_E1(const float2* lds, float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH, TB = Res<N>::TB;
+__device__ __forceinline__ void load_B_from_E1(const float2* lds, float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P, NT = Res<N>::NT, TB = Res<N>::TB;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
-        const int t = tid * TB + i, y = t / 8, k1 = t % 8;
+        const unsigned t = tid + i * NT, y = t % N, k1 = t / N;
 #pragma unroll
-        for (int x0 = 0; x0 < P; ++x0) v[P * i + x0] = lds[y * PITCH + k1 * P + x0];
+        for (int x0 = 0; x0 < P; x0 += 2) ld2(lds, e1<N>(y, k1 * P + x0), v[P * i + x0], v[P * i + x0 + 1]);
     }
 }
 
 template <int N>
-__device__ __forceinline__ void store_E1_from_B(float2* lds, const float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH, TB = Res<N>::TB;
+__device__ __forceinline__ void store_E1_from_B(float2* lds, const float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P, NT = Res<N>::NT, TB = Res<N>::TB;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
-        const int t = tid * TB + i, y = t / 8, k1 = t % 8;
+        const unsigned t = tid + i * NT, y = t % N, k1 = t / N;
 #pragma unroll
-        for (int x0 = 0; x0 < P; ++x0) lds[y * PITCH + k1 * P + x0] = v[P * i + x0];
+        for (int x0 = 0; x0 < P; x0 += 2) st2(lds, e1<N>(y, k1 * P + x0), v[P * i + x0], v[P * i + x0 + 1]);
     }
 }
 
 // pass B: forward radix-P over x0 -> k2 (no twiddle after);
 // inverse: radix-P over k2 -> x0, then twiddle conj W_N^(x0 k1).
 template <int N, bool INV>
-__device__ __forceinline__ void pass_B(float2 (&v)[16], const float2* __restrict__ tw, int tid) {
-    constexpr int P = Res<N>::P, TB = Res<N>::TB;
+__device__ __forceinline__ void pass_B(float2 (&v)[16], const float2* __restrict__ tw, unsigned tid) {
+    constexpr int P = Res<N>::P, NT = Res<N>::NT, TB = Res<N>::TB;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
         dft_slice<P, INV>(v + P * i);
         if (INV) {
-            const int k1 = (tid * TB + i) % 8;
+            const unsigned k1 = (tid + i * NT) / N;
 #pragma unroll
             for (int x0 = 1; x0 < P; ++x0) v[P * i + x0] = twiddle<true>(v[P * i + x0], tw, x0 * k1);
         }
@@ -135,61 +158,61 @@ __device__ __forceinline__ void pass_B(float2 (&v)[16], const float2* __restrict
 }
 
 template <int N>
-__device__ __forceinline__ void store_E2_from_B(float2* lds, const float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH, TB = Res<N>::TB;
+__device__ __forceinline__ void store_E2_from_B(float2* lds, const float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P, NT = Res<N>::NT, TB = Res<N>::TB;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
-        const int t = tid * TB + i, y = t / 8, k1 = t % 8;
+        const unsigned t = tid + i * NT, y = t % N, k1 = t / N;
 #pragma unroll
-        for (int k2 = 0; k2 < P; ++k2) lds[y * PITCH + k1 + 8 * k2] = v[P * i + k2];
+        for (int k2 = 0; k2 < P; ++k2) lds[e2<N>(y, k1 + 8 * k2)] = v[P * i + k2];
     }
 }
 
 template <int N>
-__device__ __forceinline__ void load_B_from_E2(const float2* lds, float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH, TB = Res<N>::TB;
+__device__ __forceinline__ void load_B_from_E2(const float2* lds, float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P, NT = Res<N>::NT, TB = Res<N>::TB;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
-        const int t = tid * TB + i, y = t / 8, k1 = t % 8;
+        const unsigned t = tid + i * NT, y = t % N, k1 = t / N;
 #pragma unroll
-        for (int k2 = 0; k2 < P; ++k2) v[P * i + k2] = lds[y * PITCH + k1 + 8 * k2];
+        for (int k2 = 0; k2 < P; ++k2) v[P * i + k2] = lds[e2<N>(y, k1 + 8 * k2)];
     }
 }
 
 template <int N>
-__device__ __forceinline__ void load_C_from_E2(const float2* lds, float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH, TB = Res<N>::TB;
-    const int kx = tid % N;
+__device__ __forceinline__ void load_C_from_E2(const float2* lds, float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P, TB = Res<N>::TB;
+    const unsigned kx = tid % N;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
-        const int y0 = tid / N + i * (P / 2);
+        const unsigned y0 = tid / N + i * (P / 2);
 #pragma unroll
-        for (int m = 0; m < P; ++m) v[P * i + m] = lds[(y0 + 8 * m) * PITCH + kx];
+        for (int m = 0; m < P; ++m) v[P * i + m] = lds[e2<N>(y0 + 8 * m, kx)];
     }
 }
 
 template <int N>
-__device__ __forceinline__ void store_E2_from_C(float2* lds, const float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH, TB = Res<N>::TB;
-    const int kx = tid % N;
+__device__ __forceinline__ void store_E2_from_C(float2* lds, const float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P, TB = Res<N>::TB;
+    const unsigned kx = tid % N;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
-        const int y0 = tid / N + i * (P / 2);
+        const unsigned y0 = tid / N + i * (P / 2);
 #pragma unroll
-        for (int m = 0; m < P; ++m) lds[(y0 + 8 * m) * PITCH + kx] = v[P * i + m];
+        for (int m = 0; m < P; ++m) lds[e2<N>(y0 + 8 * m, kx)] = v[P * i + m];
     }
 }
 
 // pass C: forward radix-P over m -> k1, then twiddle W_N^(y0 k1);
 // inverse: radix-P over k1 -> m (the twiddle was applied in D').
 template <int N, bool INV>
-__device__ __forceinline__ void pass_C(float2 (&v)[16], const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void pass_C(float2 (&v)[16], const float2* __restrict__ tw, unsigned tid) {
     constexpr int P = Res<N>::P, TB = Res<N>::TB;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
         dft_slice<P, INV>(v + P * i);
         if (!INV) {
-            const int y0 = tid / N + i * (P / 2);
+            const unsigned y0 = tid / N + i * (P / 2);
 #pragma unroll
             for (int k1 = 1; k1 < P; ++k1) v[P * i + k1] = twiddle<false>(v[P * i + k1], tw, y0 * k1);
         }
@@ -197,54 +220,48 @@ __device__ __forceinline__ void pass_C(float2 (&v)[16], const float2* __restrict
 }
 
 template <int N>
-__device__ __forceinline__ void store_E3_from_C(float2* lds, const float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH, TB = Res<N>::TB;
-    const int kx = tid % N;
+__device__ __forceinline__ void store_E3_from_C(float2* lds, const float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P, TB = Res<N>::TB;
+    const unsigned kx = tid % N;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
-        const int y0 = tid / N + i * (P / 2);
+        const unsigned y0 = tid / N + i * (P / 2);
 #pragma unroll
-        for (int k1 = 0; k1 < P; ++k1) lds[(k1 * 8 + y0) * PITCH + kx] = v[P * i + k1];
+        for (int k1 = 0; k1 < P; ++k1) lds[e3<N>(k1 * 8 + y0, kx)] = v[P * i + k1];
     }
 }
 
 template <int N>
-__device__ __forceinline__ void load_C_from_E3(const float2* lds, float2 (&v)[16], int tid) {
-    constexpr int P = Res<N>::P, PITCH = Res<N>::PITCH, TB = Res<N>::TB;
-    const int kx = tid % N;
+__device__ __forceinline__ void load_C_from_E3(const float2* lds, float2 (&v)[16], unsigned tid) {
+    constexpr int P = Res<N>::P, TB = Res<N>::TB;
+    const unsigned kx = tid % N;
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
-        const int y0 = tid / N + i * (P / 2);
+        const unsigned y0 = tid / N + i * (P / 2);
 #pragma unroll
-        for (int k1 = 0; k1 < P; ++k1) v[P * i + k1] = lds[(k1 * 8 + y0) * PITCH + kx];
+        for (int k1 = 0; k1 < P; ++k1) v[P * i + k1] = lds[e3<N>(k1 * 8 + y0, kx)];
     }
 }
 
 template <int N>
-__device__ __forceinline__ void load_D_from_E3(const float2* lds, float2 (&v)[16], int tid) {
-    constexpr int PITCH = Res<N>::PITCH;
-    const int jx = tid % (N / 2), k1 = tid / (N / 2);
+__device__ __forceinline__ void load_D_from_E3(const float2* lds, float2 (&v)[16], unsigned tid) {
+    const unsigned jx = tid % (N / 2), k1 = tid / (N / 2);
 #pragma unroll
-    for (int y0 = 0; y0 < 8; ++y0)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) v[8 * q + y0] = lds[(k1 * 8 + y0) * PITCH + 2 * jx + q];
+    for (int y0 = 0; y0 < 8; ++y0) ld2(lds, e3<N>(k1 * 8 + y0, 2 * jx), v[y0], v[8 + y0]);
 }
 
 template <int N>
-__device__ __forceinline__ void store_E3_from_D(float2* lds, const float2 (&v)[16], int tid) {
-    constexpr int PITCH = Res<N>::PITCH;
-    const int jx = tid % (N / 2), k1 = tid / (N / 2);
+__device__ __forceinline__ void store_E3_from_D(float2* lds, const float2 (&v)[16], unsigned tid) {
+    const unsigned jx = tid % (N / 2), k1 = tid / (N / 2);
 #pragma unroll
-    for (int y0 = 0; y0 < 8; ++y0)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) lds[(k1 * 8 + y0) * PITCH + 2 * jx + q] = v[8 * q + y0];
+    for (int y0 = 0; y0 < 8; ++y0) st2(lds, e3<N>(k1 * 8 + y0, 2 * jx), v[y0], v[8 + y0]);
 }
 
 // pass D: forward radix-8 over y0 -> k2 (ky = k1 + P k2);
 // inverse: radix-8 over k2 -> y0, then twiddle conj W_N^(y0 k1).
 template <int N, bool INV>
-__device__ __forceinline__ void pass_D(float2 (&v)[16], const float2* __restrict__ tw, int tid) {
-    const int k1 = tid / (N / 2);
+__device__ __forceinline__ void pass_D(float2 (&v)[16], const float2* __restrict__ tw, unsigned tid) {
+    const unsigned k1 = tid / (N / 2);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         dft_slice<8, INV>(v + 8 * q);
@@ -256,7 +273,7 @@ __device__ __forceinline__ void pass_D(float2 (&v)[16], const float2* __restrict
 }
 
 template <int N>
-__device__ __forceinline__ void forward_fft(float2 (&v)[16], float2* lds, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void forward_fft(float2 (&v)[16], float2* lds, const float2* __restrict__ tw, unsigned tid) {
     pass_A<N, false>(v, tw, tid);
     store_E1_from_A<N>(lds, v, tid);
     __syncthreads();
@@ -276,7 +293,7 @@ __device__ __forceinline__ void forward_fft(float2 (&v)[16], float2* lds, const 
 }
 
 template <int N>
-__device__ __forceinline__ void inverse_fft(float2 (&v)[16], float2* lds, const float2* __restrict__ tw, int tid) {
+__device__ __forceinline__ void inverse_fft(float2 (&v)[16], float2* lds, const float2* __restrict__ tw, unsigned tid) {
     pass_D<N, true>(v, tw, tid);
     store_E3_from_D<N>(lds, v, tid);
     __syncthreads();
@@ -296,118 +313,102 @@ __device__ __forceinline__ void inverse_fft(float2 (&v)[16], float2* lds, const 
 }
 
 // --------------------------------------------------------------- updates --
-// Pixel-space messenger draw on layout A: t = (1-a) s + a d + sqrt(T(1-a)) xi.
+// Pixel-space messenger draw on layout A: t = (1-a) s + a d + sqrt(T(1-a)) xi,
+// with (1-a, sqrt(T(1-a))) and a d read from per-call tables.
 template <int N>
 __device__ __forceinline__ void pixel_update(float2 (&v)[16], const ResidentArgs& a, const ProbDev& pr, int pair,
-                                             uint32_t sweep, int tid, float T) {
+                                             uint32_t sweep, unsigned tid) {
     constexpr int P = Res<N>::P;
-    const int y = tid / (P / 2), j = tid % (P / 2);
+    const unsigned y = tid / (P / 2), j = tid % (P / 2);
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
         // keep the eight Philox chains from being interleaved (register pressure)
         __builtin_amdgcn_sched_barrier(0);
-        const int x = 2 * j + P * m;
-        const int64_t pix = pr.pix_off + (int64_t)y * N + x;
-        const float2 nb = *reinterpret_cast<const float2*>(a.nbar + pix);
-        const float2 dd = *reinterpret_cast<const float2*>(a.d + pix);
-        const uint32_t e2 = (uint32_t)(y * (N / 2) + j + (P / 2) * m);
+        const uint32_t e2 = (uint32_t)(y * (N / 2) + j + (P / 2) * m);  // pixel pair index in the image
+        const int64_t pp = pr.pix_off / 2 + e2;
+        const float4 c = a.pcoef[pp];   // (1-a, sigma) of pixels x, x+1
+        const float2 src = a.psrc[pp];  // a d of pixels x, x+1
         const Normals2 z = pair_normals(e2, sweep, (uint32_t)pr.pid, kStagePixel, (uint32_t)pair, a.key0, a.key1);
-        const float nbv[2] = {nb.x, nb.y}, dv[2] = {dd.x, dd.y};
-        const float2 zz[2] = {z.a, z.b};
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            // a = T/(T+Nbar) is 1 at the smallest-noise pixel (Nbar = 0) and
-            // 0 on missing ones; 1 - a may come out as -1 ulp, so the variance
-            // T(1-a) is clamped at 0 below.
-            const float aa = T * __builtin_amdgcn_rcpf(T + nbv[q]);
-            const float oma = 1.0f - aa;
-            const float src = aa > 0.f ? aa * dv[q] : 0.f;
-            const float sig = __builtin_amdgcn_sqrtf(fmaxf(T * oma, 0.f));
-            float2& s = v[8 * q + m];
-            s.x = fmaf(oma, s.x, fmaf(sig, zz[q].x, src));
-            s.y = fmaf(oma, s.y, fmaf(sig, zz[q].y, src));
-        }
+        float2& s0 = v[m];
+        float2& s1 = v[8 + m];
+        s0.x = fmaf(c.x, s0.x, fmaf(c.y, z.a.x, src.x));
+        s0.y = fmaf(c.x, s0.y, fmaf(c.y, z.a.y, src.x));
+        s1.x = fmaf(c.z, s1.x, fmaf(c.w, z.b.x, src.y));
+        s1.y = fmaf(c.z, s1.y, fmaf(c.w, z.b.y, src.y));
     }
 }
 
-// Fourier-space draw on layout D: S = f T / n + w eta / n.
+// Fourier-space draw on layout D: S = (f T + w eta) / n, (f/n, w/n) from a table.
 template <int N>
 __device__ __forceinline__ void harmonic_update(float2 (&v)[16], const ResidentArgs& a, const ProbDev& pr, int pair,
-                                                uint32_t sweep, int tid, float T) {
+                                                uint32_t sweep, unsigned tid) {
     constexpr int P = Res<N>::P;
-    constexpr float inv_n = 1.0f / (float)(N * N);
-    const int jx = tid % (N / 2), k1 = tid / (N / 2);
+    const unsigned jx = tid % (N / 2), k1 = tid / (N / 2);
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) {
         __builtin_amdgcn_sched_barrier(0);
-        const int ky = k1 + P * k2;
-        const int64_t mode = pr.pix_off + (int64_t)ky * N + 2 * jx;
-        const float2 np = *reinterpret_cast<const float2*>(a.nP + mode);
-        const uint32_t e2 = (uint32_t)(ky * (N / 2) + jx);
+        const unsigned ky = k1 + P * k2;
+        const uint32_t e2 = (uint32_t)(ky * (N / 2) + jx);  // mode pair index
+        const float4 c = a.mcoef[pr.pix_off / 2 + e2];     // (f, w) of modes kx, kx+1
         const Normals2 z = pair_normals(e2, sweep, (uint32_t)pr.pid, kStageHarmonic, (uint32_t)pair, a.key0, a.key1);
-        const float npv[2] = {np.x, np.y};
-        const float2 zz[2] = {z.a, z.b};
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const float rden = __builtin_amdgcn_rcpf(npv[q] + T);
-            const float f = npv[q] * rden * inv_n;
-            const float w = __builtin_amdgcn_sqrtf(npv[q] * T * rden * inv_n);
-            float2& s = v[8 * q + k2];
-            s.x = fmaf(f, s.x, w * zz[q].x);
-            s.y = fmaf(f, s.y, w * zz[q].y);
-        }
+        float2& s0 = v[k2];
+        float2& s1 = v[8 + k2];
+        s0.x = fmaf(c.x, s0.x, c.y * z.a.x);
+        s0.y = fmaf(c.x, s0.y, c.y * z.a.y);
+        s1.x = fmaf(c.z, s1.x, c.w * z.b.x);
+        s1.y = fmaf(c.z, s1.y, c.w * z.b.y);
     }
 }
 
 template <int N>
 __global__ __launch_bounds__(Res<N>::NT, 4) void resident_sample_kernel(ResidentArgs a) {
     constexpr int P = Res<N>::P;
-    __shared__ float2 lds[N * Res<N>::PITCH];
-    const int tid = threadIdx.x;
+    __shared__ __align__(16) float2 lds[N * N];
+    const unsigned tid = threadIdx.x;
     const ItemDev it = a.items[blockIdx.x];
     const ProbDev pr = a.probs[it.prob];
-    const int y = tid / (P / 2), j = tid % (P / 2);
+    const unsigned y = tid / (P / 2), j = tid % (P / 2);
 
     // initial state in layout A
     float2 v[16];
 #pragma unroll
-    for (int m = 0; m < 8; ++m)
-#pragma unroll
-        for (int q = 0; q < 2; ++q) {
-            const int x = 2 * j + q + P * m;
-            float2 s0 = make_float2(0.f, 0.f);
-            if (a.state_in) {
-                s0 = a.state_in[it.field_off + (int64_t)y * N + x];
-            } else if (a.init_scale > 0.f && q == 0) {
-                const uint32_t e2 = (uint32_t)((y * N + x) >> 1);
-                const Normals2 z = pair_normals(e2, 0u, (uint32_t)pr.pid, kStageInit, (uint32_t)it.pair, a.key0, a.key1);
-                v[8 * 1 + m] = cscale(z.b, a.init_scale);
-                s0 = cscale(z.a, a.init_scale);
-            } else if (a.init_scale > 0.f) {
-                continue;  // set together with q == 0
-            }
-            v[8 * q + m] = s0;
+    for (int m = 0; m < 8; ++m) {
+        const int x = 2 * j + P * m;
+        if (a.state_in) {
+            v[m] = a.state_in[it.field_off + (int64_t)y * N + x];
+            v[8 + m] = a.state_in[it.field_off + (int64_t)y * N + x + 1];
+        } else if (a.init_scale > 0.f) {
+            const uint32_t e2 = (uint32_t)((y * N + x) >> 1);
+            const Normals2 z = pair_normals(e2, 0u, (uint32_t)pr.pid, kStageInit, (uint32_t)it.pair, a.key0, a.key1);
+            v[m] = cscale(z.a, a.init_scale);
+            v[8 + m] = cscale(z.b, a.init_scale);
+        } else {
+            v[m] = v[8 + m] = make_float2(0.f, 0.f);
         }
+    }
 
-    const float T = pr.tau;  // lambda = 1
     const int64_t n = (int64_t)N * N;
     const int64_t K = (int64_t)a.burn_in + (int64_t)a.n_samples * a.thin;
     const int c0 = 2 * it.pair, c1 = 2 * it.pair + 1;
     for (int64_t k = 0; k < K; ++k) {
         const uint32_t sweep = a.sweep0 + (uint32_t)k;
         ResidentArgs ak = a;
-        ak.nbar = per_sweep(a.nbar);
-        ak.d = per_sweep(a.d);
-        ak.nP = per_sweep(a.nP);
+        ak.pcoef = per_sweep(a.pcoef);
+        ak.psrc = per_sweep(a.psrc);
+        ak.mcoef = per_sweep(a.mcoef);
         const float2* tw = per_sweep(a.tw);
         // Everything indexed by the thread id (LDS addresses, counter words of
         // the normal stream) is recomputed each sweep rather than kept live.
-        int t = tid;
+        // Each half of the sweep gets its own copy so that the forward pass's
+        // LDS addresses are not kept alive for reuse by the inverse pass.
+        unsigned t = tid;
         asm volatile("" : "+v"(t));
-        pixel_update<N>(v, ak, pr, it.pair, sweep, t, T);
+        pixel_update<N>(v, ak, pr, it.pair, sweep, t);
         forward_fft<N>(v, lds, tw, t);
-        harmonic_update<N>(v, ak, pr, it.pair, sweep, t, T);
-        inverse_fft<N>(v, lds, tw, t);
+        unsigned t2 = tid;
+        asm volatile("" : "+v"(t2));
+        harmonic_update<N>(v, ak, pr, it.pair, sweep, t2);
+        inverse_fft<N>(v, lds, tw, t2);
         if (a.samples && k >= a.burn_in && ((k - a.burn_in + 1) % a.thin) == 0) {
             const int64_t slot = (k - a.burn_in + 1) / a.thin - 1;
             const int64_t base = (int64_t)a.chains * a.n_samples * pr.pix_off;
@@ -422,14 +423,52 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_sample_kernel(Resident
         }
     }
 #pragma unroll
-    for (int m = 0; m < 8; ++m)
+    for (int m = 0; m < 8; ++m) {
+        const int64_t o = it.field_off + (int64_t)y * N + 2 * j + P * m;
+        a.field[o] = v[m];
+        a.field[o + 1] = v[8 + m];
+    }
+}
+
+// Per-call coefficient tables of the sampler at lambda = 1 (pairs of elements):
+//   pcoef = (1 - a, sqrt(T (1 - a))) for pixels 2e, 2e+1;  psrc = a d
+//   mcoef = (f / n, w / n) for modes 2e, 2e+1 with f = nP/(nP+T), w = sqrt(n nP T/(nP+T))
+__global__ void sampler_coef_kernel(const ProbDev* probs, const float* d, const float* nbar, const float* nP,
+                                    float4* pcoef, float2* psrc, float4* mcoef) {
+    const ProbDev pr = probs[blockIdx.y];
+    const int64_t n = (int64_t)pr.H * pr.W;
+    const double T = pr.tau;
+    const double inv_n = 1.0 / (double)n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n / 2; e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = pr.pix_off + 2 * e;
+        float oma[2], sig[2], src[2], f[2], w[2];
 #pragma unroll
-        for (int q = 0; q < 2; ++q) a.field[it.field_off + (int64_t)y * N + 2 * j + q + P * m] = v[8 * q + m];
+        for (int q = 0; q < 2; ++q) {
+            const double nb = nbar[g + q];
+            const double aa = isinf(nb) ? 0.0 : T / (T + nb);
+            oma[q] = (float)(1.0 - aa);
+            sig[q] = (float)sqrt(T * (1.0 - aa));
+            src[q] = aa > 0.0 ? (float)(aa * (double)d[g + q]) : 0.f;
+            const double P = nP[g + q];
+            f[q] = (float)(P / (P + T) * inv_n);
+            w[q] = (float)sqrt(P * T / (P + T) * inv_n);
+        }
+        pcoef[g / 2] = make_float4(oma[0], sig[0], oma[1], sig[1]);
+        psrc[g / 2] = make_float2(src[0], src[1]);
+        mcoef[g / 2] = make_float4(f[0], w[0], f[1], w[1]);
+    }
 }
 
 }  // namespace
 
 bool resident_supported(int H, int W) { return H == W && (H == 32 || H == 64 || H == 128); }
+
+hipError_t launch_sampler_coefs(const ProbDev* probs, int n_problems, const float* d, const float* nbar,
+                                const float* nP, float4* pcoef, float2* psrc, float4* mcoef, hipStream_t s) {
+    hipLaunchKernelGGL(sampler_coef_kernel, dim3(32, n_problems), dim3(256), 0, s, probs, d, nbar, nP, pcoef, psrc,
+                       mcoef);
+    return hipGetLastError();
+}
 
 hipError_t launch_resident_sample(int N, const ResidentArgs& a, hipStream_t s) {
     const dim3 grid((unsigned)a.n_items);

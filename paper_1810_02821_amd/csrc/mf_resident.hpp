@@ -15,9 +15,9 @@ struct ResidentArgs {
     float2* field;            // final pair states [item] (pixel space)
     const float2* state_in;   // start states or null
     float init_scale;         // dispersed starts when state_in is null and > 0
-    const float* d;           // concatenated data
-    const float* nbar;        // concatenated Nbar
-    const float* nP;          // concatenated n P(|k|)
+    const float4* pcoef;      // per pixel pair: (1-a, sqrt(T(1-a))) x 2
+    const float2* psrc;       // per pixel pair: a d x 2
+    const float4* mcoef;      // per mode pair: (f/n, w/n) x 2
     const float2* tw;         // W_N^r, r < N
     uint32_t key0, key1;
     uint32_t sweep0;          // global index of the first sweep
@@ -28,5 +28,8 @@ struct ResidentArgs {
 
 bool resident_supported(int H, int W);
 hipError_t launch_resident_sample(int N, const ResidentArgs& a, hipStream_t s);
+// Build the sampler's per-call coefficient tables (lambda = 1) for every problem.
+hipError_t launch_sampler_coefs(const ProbDev* probs, int n_problems, const float* d, const float* nbar,
+                                const float* nP, float4* pcoef, float2* psrc, float4* mcoef, hipStream_t s);
 
 }  // namespace mf

@@ -201,3 +201,19 @@ def test_sample_pair_resume_is_exact():
                                 sweep_offset=12)
     assert np.array_equal(full[:, 12:], rest)
     assert np.array_equal(s_full, s_end)
+
+
+def test_conjugate_gradient_route_matches_dense_and_messenger(small16):
+    """The CG solve of the normal equations (used for large images) reaches
+    the dense Eq. 2 solution and the messenger fixed point."""
+    p, S = small16
+    s_cg, it = M.wiener_cg(p, tol=1e-13)
+    assert _rel(s_cg, dense.wiener_dense(S, p.noise_var, p.d)) < 1e-10
+    s_m, _ = M.wiener(p, M.Schedule((1.0,), (0,), 1e-12, 100000, 10))
+    assert _rel(s_cg, s_m) < 1e-9
+    # a general right-hand side (the adjoint system)
+    g = np.random.default_rng(4).standard_normal((16, 16))
+    v_cg, _ = M.wiener_cg(p, tol=1e-13, rhs=g)
+    C = dense.posterior_covariance(S, p.noise_var)
+    assert _rel(v_cg.ravel(), C @ g.ravel()) < 1e-9
+    assert it < 400
