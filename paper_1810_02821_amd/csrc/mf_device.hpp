@@ -102,26 +102,35 @@ template <int R, bool INV> __device__ __forceinline__ void dft(float2 (&v)[R]) {
 }
 
 // ------------------------------------------------- Stockham pass over LDS --
+// LDS position of element i of a transform: the low five bits (one row of the
+// 64 x 4-byte banks for 8-byte elements) are XORed with a function of the
+// higher bits, which keeps every read and write of every pass below free of
+// bank conflicts for lengths 16..2048 (within one transform per 32 lanes).
+__device__ __forceinline__ unsigned swz(unsigned i) {
+    const unsigned h = i >> 5;
+    return i ^ (((h & 7u) ^ (((h >> 1) & 3u) << 3)) & 31u);
+}
+
 // One radix-R pass of a length-L transform held in `buf` (element i at
-// buf[i * STRIDE]).  `lane` in [0, TPG) indexes the TPG threads that own this
+// buf[swz(i)]).  `lane` in [0, TPG) indexes the TPG threads that own this
 // transform; NS is the product of the radices already applied.  Input in the
 // Stockham order of the previous pass, output in the order of the next; after
 // the last pass the sequence is in natural order.  `tw` holds W_L^r, r < L.
 // The pass reads every element into registers before writing (in place), so
 // it needs the two barriers; every thread of the block must call it.
-template <int L, int R, int NS, int TPG, int STRIDE, bool INV>
-__device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float2* __restrict__ tw) {
+template <int L, int R, int NS, int TPG, bool INV>
+__device__ __forceinline__ void stockham_pass(float2* buf, unsigned lane, const float2* __restrict__ tw) {
     constexpr int NT = L / R;
     constexpr int TPT = (NT + TPG - 1) / TPG;
     float2 v[TPT][R];
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        const int j = lane + t * TPG;
-        if ((NT % TPG) == 0 || j < NT) {
+        const unsigned j = lane + t * TPG;
+        if ((NT % TPG) == 0 || j < (unsigned)NT) {
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[t][r] = buf[(j + r * NT) * STRIDE];
+            for (int r = 0; r < R; ++r) v[t][r] = buf[swz(j + r * NT)];
             if constexpr (NS > 1) {
-                const int k = j & (NS - 1);
+                const unsigned k = j & (NS - 1);
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
                     const float2 w = tw[(r * k) * (L / (NS * R))];
@@ -134,26 +143,34 @@ __device__ __forceinline__ void stockham_pass(float2* buf, int lane, const float
     __syncthreads();
 #pragma unroll
     for (int t = 0; t < TPT; ++t) {
-        const int j = lane + t * TPG;
-        if ((NT % TPG) == 0 || j < NT) {
-            const int k = j & (NS - 1);
-            const int o = (j / NS) * NS * R + k;
+        const unsigned j = lane + t * TPG;
+        if ((NT % TPG) == 0 || j < (unsigned)NT) {
+            const unsigned k = j & (NS - 1);
+            const unsigned o = (j / NS) * NS * R + k;
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[(o + r * NS) * STRIDE] = v[t][r];
+            for (int r = 0; r < R; ++r) buf[swz(o + r * NS)] = v[t][r];
         }
     }
     __syncthreads();
 }
 
-// Radix plan: radix-8 passes, then one radix-2/4 pass for the remainder.
-template <int L, int NS, int TPG, int STRIDE, bool INV>
-__device__ __forceinline__ void stockham_fft(float2* buf, int lane, const float2* __restrict__ tw) {
+// Radix plan: radix-16 passes, then one radix-2/4/8 pass for the remainder.
+template <int L, int NS, int TPG, bool INV>
+__device__ __forceinline__ void stockham_fft(float2* buf, unsigned lane, const float2* __restrict__ tw) {
     if constexpr (NS < L) {
         constexpr int REM = L / NS;
-        constexpr int R = REM >= 8 ? 8 : REM;
-        stockham_pass<L, R, NS, TPG, STRIDE, INV>(buf, lane, tw);
-        stockham_fft<L, NS * R, TPG, STRIDE, INV>(buf, lane, tw);
+        constexpr int R = REM >= 16 ? 16 : REM;
+        stockham_pass<L, R, NS, TPG, INV>(buf, lane, tw);
+        stockham_fft<L, NS * R, TPG, INV>(buf, lane, tw);
     }
+}
+
+// Workgroups are handed to the eight XCDs round-robin.  Renumber them so that
+// each XCD runs a contiguous range of logical blocks: neighbouring tiles that
+// share cache lines or table rows then meet in the same L2.
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nb) {
+    const unsigned x = b & 7u, q = nb >> 3, r = nb & 7u;
+    return x * q + (x < r ? x : r) + (b >> 3);
 }
 
 // -------------------------------------------------------- normal variates --

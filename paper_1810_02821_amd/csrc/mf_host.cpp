@@ -305,8 +305,8 @@ mf_status solve_class(mf_plan p, const std::vector<int>& pids, int H, int W, con
             MF_HIP(hipStreamSynchronize(s));
             std::vector<mf::ItemDev> conv, keep;
             for (int i = 0; i < a.n_items; ++i) {
-                double acc = 0;
-                for (int y = 0; y < H; ++y) acc += part[(size_t)i * H + y];
+                double acc = 0;  // row partials are indexed y * n_items + item
+                for (int y = 0; y < H; ++y) acc += part[(size_t)y * a.n_items + i];
                 const int pid = live[i].prob;
                 const double T = lam * p->probs[pid].tau;
                 const double r = bnorm2[pid] > 0 ? std::sqrt(acc) / (T * std::sqrt(bnorm2[pid])) : 0.0;

@@ -17,6 +17,18 @@ namespace {
 
 constexpr int kThreads = 256;
 
+// Fresh copies of a lane index / table pointer: the forward and inverse
+// transforms use the same LDS addresses and twiddles, and without this the
+// compiler keeps them all live from one transform to the other.
+__device__ __forceinline__ unsigned fresh(unsigned v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ const float2* fresh(const float2* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 __device__ __forceinline__ float pix_a(float T, float nb) {
     // a = T / (T + Nbar); Nbar = +inf on missing pixels gives a = 0
     return T * __builtin_amdgcn_rcpf(T + nb);
@@ -28,6 +40,9 @@ struct RowShape {
     static constexpr int TPR = kThreads / ROWS;                   // threads per row
 };
 
+// Rows of all work items are enumerated with the item index fastest,
+// g = y * n_items + item, so that the rows one block (and one XCD) handles
+// share the rows of the problem tables.
 template <int L, int MODE>
 __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     constexpr int ROWS = RowShape<L>::ROWS;
@@ -36,52 +51,53 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     __shared__ float2 lds[ROWS * L];
     __shared__ double red[kThreads];
 
-    const int tid = threadIdx.x;
-    const int rid = tid / TPR;
-    const int lane = tid % TPR;
+    const unsigned tid = threadIdx.x;
+    const unsigned rid = tid / TPR;
+    const unsigned lane = tid % TPR;
     const int64_t total_rows = (int64_t)a.n_items * H;
-    const int64_t grow0 = (int64_t)blockIdx.x * ROWS;
+    const int64_t grow0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
 
     // ---- load ROWS rows (coalesced along x)
 #pragma unroll
     for (int i = 0; i < ROWS * L / kThreads; ++i) {
-        const int e = tid + i * kThreads;
-        const int r = e / L, x = e % L;
+        const unsigned e = tid + i * kThreads;
+        const unsigned r = e / L, x = e % L;
         const int64_t gr = grow0 + r;
         float2 v = make_float2(0.f, 0.f);
         if (gr < total_rows) {
-            const ItemDev it = a.items[gr / H];
-            v = a.field[it.field_off + (gr % H) * W + x];
+            const ItemDev it = a.items[gr % a.n_items];
+            v = a.field[it.field_off + (gr / a.n_items) * W + x];
         }
-        lds[e] = v;
+        lds[r * L + swz(x)] = v;
     }
     __syncthreads();
 
     const int64_t gr = grow0 + rid;
     const bool valid = gr < total_rows;
-    const int item = valid ? (int)(gr / H) : 0;
-    const int y = valid ? (int)(gr % H) : 0;
+    const int item = valid ? (int)(gr % a.n_items) : 0;
+    const int y = valid ? (int)(gr / a.n_items) : 0;
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
     float2* row = lds + rid * L;
 
     if constexpr (MODE & kRowInv) {
-        stockham_fft<L, 1, TPR, 1, true>(row, lane, a.tw_row);
+        stockham_fft<L, 1, TPR, true>(row, lane, a.tw_row);
         if (a.emit_index >= 0 && valid) {
             const int64_t base = (int64_t)a.chains * a.n_samples * pr.pix_off;
             const int64_t n = (int64_t)pr.H * pr.W;
             const int c0 = 2 * it.pair, c1 = 2 * it.pair + 1;
             float* o0 = a.samples + base + ((int64_t)c0 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
             float* o1 = a.samples + base + ((int64_t)c1 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
-            for (int x = lane; x < L; x += TPR) {
-                const float2 s = row[x];
+            for (unsigned x = lane; x < (unsigned)L; x += TPR) {
+                const float2 s = row[swz(x)];
                 o0[x] = s.x;
                 if (c1 < a.chains) o1[x] = s.y;
             }
         }
         if constexpr (!(MODE & kRowFwd)) {
             if (valid)
-                for (int x = lane; x < L; x += TPR) a.field[it.field_off + (int64_t)y * W + x] = row[x];
+                for (unsigned x = lane; x < (unsigned)L; x += TPR)
+                    a.field[it.field_off + (int64_t)y * W + x] = row[swz(x)];
             return;
         }
     }
@@ -90,14 +106,15 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
         // ---- pixel-space messenger update t = (1 - a) s + src + sigma_t xi
         const float T = a.lambda * pr.tau;
         double acc = 0.0;
-        for (int pp = lane; pp < L / 2; pp += TPR) {
-            const int x = 2 * pp;
+#pragma unroll 2
+        for (unsigned pp = lane; pp < (unsigned)L / 2; pp += TPR) {
+            const unsigned x = 2 * pp;
             const int64_t pix = pr.pix_off + (int64_t)y * W + x;
             const float2 nb = *reinterpret_cast<const float2*>(a.nbar + pix);
             const float2 sv = *reinterpret_cast<const float2*>(a.src + pix);
             float aa[2] = {pix_a(T, nb.x), pix_a(T, nb.y)};
             float sr[2] = {sv.x, sv.y};
-            float2 s[2] = {row[x], row[x + 1]};
+            float2 s[2] = {row[swz(x)], row[swz(x + 1)]};
             float2 z[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
             if (a.stochastic && valid) {
                 const uint32_t j = (uint32_t)(((int64_t)y * W + x) >> 1);
@@ -130,8 +147,8 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
                     a.t_save[f + 1] = t[1];
                 }
             }
-            row[x] = t[0];
-            row[x + 1] = t[1];
+            row[swz(x)] = t[0];
+            row[swz(x + 1)] = t[1];
         }
         if (a.check_t) {
             red[tid] = acc;
@@ -139,52 +156,60 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
             if (lane == 0 && valid) {
                 double s = 0.0;
                 for (int i = 0; i < TPR; ++i) s += red[rid * TPR + i];
-                a.partials[gr] = s;
+                a.partials[gr] = s;  // indexed y * n_items + item
             }
         }
         __syncthreads();
-        stockham_fft<L, 1, TPR, 1, false>(row, lane, a.tw_row);
+        stockham_fft<L, 1, TPR, false>(row, fresh(lane), fresh(a.tw_row));
         if (valid)
-            for (int x = lane; x < L; x += TPR) a.field[it.field_off + (int64_t)y * W + x] = row[x];
+            for (unsigned x = lane; x < (unsigned)L; x += TPR)
+                a.field[it.field_off + (int64_t)y * W + x] = row[swz(x)];
     }
 }
 
+// Column tiles: TC columns of one item per block, threads and tile width
+// chosen so a tile fills at most ~128 KiB of LDS; each column is its own
+// segment of L + 32/TC elements (the tile load then hits distinct banks).
 template <int L>
 struct ColShape {
-    static constexpr int TC = (8192 / L) > 16 ? 16 : (8192 / L);  // columns per block
-    static constexpr int TPC = kThreads / TC;
-    static constexpr int PITCH = L + 1;
+    static constexpr int TC = L >= 2048 ? 8 : 16;
+    static constexpr int NTH = L >= 1024 ? 1024 : (L >= 512 ? 512 : 256);
+    static constexpr int TPC = NTH / TC;
+    static constexpr int SEG = L + 32 / TC;
 };
 
 template <int L>
-__global__ __launch_bounds__(kThreads) void col_kernel(SweepArgs a, int W) {
+__global__ __launch_bounds__(ColShape<L>::NTH) void col_kernel(SweepArgs a, int W) {
     constexpr int TC = ColShape<L>::TC;
+    constexpr int NTH = ColShape<L>::NTH;
     constexpr int TPC = ColShape<L>::TPC;
-    constexpr int PITCH = ColShape<L>::PITCH;
+    constexpr int SEG = ColShape<L>::SEG;
     constexpr int H = L;
-    __shared__ float2 lds[TC * PITCH];
-    const int tid = threadIdx.x;
-    const int64_t gc0 = (int64_t)blockIdx.x * TC;
-    const int item = (int)(gc0 / W);
-    const int x0 = (int)(gc0 % W);
+    __shared__ float2 lds[TC * SEG];
+    const unsigned tid = threadIdx.x;
+    // tiles enumerated with the item fastest: t = tile * n_items + item
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x);
+    const int item = (int)(t % a.n_items);
+    const int x0 = (int)(t / a.n_items) * TC;
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
     float2* fld = a.field + it.field_off + x0;
 
 #pragma unroll 4
-    for (int e = tid; e < TC * L; e += kThreads) {
-        const int c = e % TC, y = e / TC;
-        lds[c * PITCH + y] = fld[(int64_t)y * W + c];
+    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+        const unsigned c = e % TC, y = e / TC;
+        lds[c * SEG + swz(y)] = fld[(int64_t)y * W + c];
     }
     __syncthreads();
-    const int cid = tid / TPC, lane = tid % TPC;
-    stockham_fft<L, 1, TPC, 1, false>(lds + cid * PITCH, lane, a.tw_col);
+    const unsigned cid = tid / TPC, lane = tid % TPC;
+    stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
 
     // ---- Fourier-space update S = f T / n + w eta / n on column pairs
     const float T = a.lambda * pr.tau;
     const float inv_n = 1.0f / ((float)H * (float)W);
-    for (int e = tid; e < (TC / 2) * L; e += kThreads) {
-        const int j = e % (TC / 2), ky = e / (TC / 2);
+#pragma unroll 1
+    for (unsigned e = tid; e < (unsigned)((TC / 2) * L); e += NTH) {
+        const unsigned j = e % (TC / 2), ky = e / (TC / 2);
         const int kx = x0 + 2 * j;
         const int64_t mode = (int64_t)ky * W + kx;
         const float2 np = *reinterpret_cast<const float2*>(a.nP + pr.pix_off + mode);
@@ -201,7 +226,7 @@ __global__ __launch_bounds__(kThreads) void col_kernel(SweepArgs a, int W) {
             const float P = npv[q];
             const float rden = __builtin_amdgcn_rcpf(P + T);
             const float f = P * rden * inv_n;
-            float2& v = lds[(2 * j + q) * PITCH + ky];
+            float2& v = lds[(2 * j + q) * SEG + swz(ky)];
             float2 o = cscale(v, f);
             if (a.stochastic) {
                 const float w = __builtin_amdgcn_sqrtf(P * T * rden * inv_n);
@@ -212,12 +237,12 @@ __global__ __launch_bounds__(kThreads) void col_kernel(SweepArgs a, int W) {
         }
     }
     __syncthreads();
-    stockham_fft<L, 1, TPC, 1, true>(lds + cid * PITCH, lane, a.tw_col);
+    stockham_fft<L, 1, TPC, true>(lds + fresh(cid) * SEG, fresh(lane), fresh(a.tw_col));
 
 #pragma unroll 4
-    for (int e = tid; e < TC * L; e += kThreads) {
-        const int c = e % TC, y = e / TC;
-        fld[(int64_t)y * W + c] = lds[c * PITCH + y];
+    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+        const unsigned c = e % TC, y = e / TC;
+        fld[(int64_t)y * W + c] = lds[c * SEG + swz(y)];
     }
 }
 
@@ -306,37 +331,39 @@ __global__ __launch_bounds__(kThreads) void row_fft_kernel(SweepArgs a, int H) {
     constexpr int ROWS = RowShape<L>::ROWS;
     constexpr int TPR = RowShape<L>::TPR;
     __shared__ float2 lds[ROWS * L];
-    const int tid = threadIdx.x;
+    const unsigned tid = threadIdx.x;
     const int64_t total_rows = (int64_t)a.n_items * H;
     const int64_t grow0 = (int64_t)blockIdx.x * ROWS;
     for (int i = 0; i < ROWS * L / kThreads; ++i) {
-        const int e = tid + i * kThreads;
+        const unsigned e = tid + i * kThreads;
         const int64_t gr = grow0 + e / L;
-        lds[e] = gr < total_rows ? a.field[a.items[gr / H].field_off + (gr % H) * L + e % L] : make_float2(0.f, 0.f);
+        lds[(e / L) * L + swz(e % L)] =
+            gr < total_rows ? a.field[a.items[gr / H].field_off + (gr % H) * L + e % L] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    stockham_fft<L, 1, TPR, 1, false>(lds + (tid / TPR) * L, tid % TPR, a.tw_row);
+    stockham_fft<L, 1, TPR, false>(lds + (tid / TPR) * L, tid % TPR, a.tw_row);
     for (int i = 0; i < ROWS * L / kThreads; ++i) {
-        const int e = tid + i * kThreads;
+        const unsigned e = tid + i * kThreads;
         const int64_t gr = grow0 + e / L;
-        if (gr < total_rows) a.field[a.items[gr / H].field_off + (gr % H) * L + e % L] = lds[e];
+        if (gr < total_rows) a.field[a.items[gr / H].field_off + (gr % H) * L + e % L] = lds[(e / L) * L + swz(e % L)];
     }
 }
 
 template <int L>
-__global__ __launch_bounds__(kThreads) void col_fft_kernel(SweepArgs a, int W) {
+__global__ __launch_bounds__(ColShape<L>::NTH) void col_fft_kernel(SweepArgs a, int W) {
     constexpr int TC = ColShape<L>::TC;
+    constexpr int NTH = ColShape<L>::NTH;
     constexpr int TPC = ColShape<L>::TPC;
-    constexpr int PITCH = ColShape<L>::PITCH;
-    __shared__ float2 lds[TC * PITCH];
-    const int tid = threadIdx.x;
+    constexpr int SEG = ColShape<L>::SEG;
+    __shared__ float2 lds[TC * SEG];
+    const unsigned tid = threadIdx.x;
     const int64_t gc0 = (int64_t)blockIdx.x * TC;
     const ItemDev it = a.items[gc0 / W];
     float2* fld = a.field + it.field_off + gc0 % W;
-    for (int e = tid; e < TC * L; e += kThreads) lds[(e % TC) * PITCH + e / TC] = fld[(int64_t)(e / TC) * W + e % TC];
+    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) lds[(e % TC) * SEG + swz(e / TC)] = fld[(int64_t)(e / TC) * W + e % TC];
     __syncthreads();
-    stockham_fft<L, 1, TPC, 1, false>(lds + (tid / TPC) * PITCH, tid % TPC, a.tw_col);
-    for (int e = tid; e < TC * L; e += kThreads) fld[(int64_t)(e / TC) * W + e % TC] = lds[(e % TC) * PITCH + e / TC];
+    stockham_fft<L, 1, TPC, false>(lds + (tid / TPC) * SEG, tid % TPC, a.tw_col);
+    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) fld[(int64_t)(e / TC) * W + e % TC] = lds[(e % TC) * SEG + swz(e / TC)];
 }
 
 // Per-block, per-band partial sums of Re(conj(X_k) Y_k) with X = (Z_k + conj Z_-k)/2,
@@ -425,10 +452,8 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-int col_tc(int H) {
-    int tc = 8192 / H;
-    return tc > 16 ? 16 : tc;
-}
+int col_tc(int H) { return H >= 2048 ? 8 : 16; }
+int col_threads(int H) { return H >= 1024 ? 1024 : (H >= 512 ? 512 : 256); }
 
 dim3 elementwise_grid(int64_t total) {
     int64_t b = (total + 255) / 256;
@@ -458,7 +483,7 @@ hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s) {
     const int tc = col_tc(H);
     if (tc > W || tc < 2) return hipErrorInvalidValue;
     const int64_t cols = (int64_t)a.n_items * W;
-    MF_DISPATCH(H, col_kernel, dim3((unsigned)(cols / tc)), dim3(kThreads), s, a, W);
+    MF_DISPATCH(H, col_kernel, dim3((unsigned)(cols / tc)), dim3(col_threads(H)), s, a, W);
     return hipGetLastError();
 }
 
@@ -503,7 +528,7 @@ hipError_t launch_band_power(int W, int H, const SweepArgs& a, const float* x, c
     const int64_t total_rows = (int64_t)a.n_items * H;
     MF_DISPATCH(W, row_fft_kernel, dim3((unsigned)((total_rows + rows - 1) / rows)), dim3(kThreads), s, a, H);
     const int tc = col_tc(H);
-    MF_DISPATCH(H, col_fft_kernel, dim3((unsigned)((int64_t)a.n_items * W / tc)), dim3(kThreads), s, a, W);
+    MF_DISPATCH(H, col_fft_kernel, dim3((unsigned)((int64_t)a.n_items * W / tc)), dim3(col_threads(H)), s, a, W);
     // partial buffer: the caller provides a.partials sized n_items * nblocks * kMaxBands
     const int nblocks = 64;
     hipLaunchKernelGGL(band_partial_kernel, dim3(nblocks, a.n_items), dim3(kThreads), 0, s, a, H, W, band,
