@@ -62,7 +62,7 @@ typedef void* mf_stream; /* hipStream_t */
 typedef enum {
     MF_OK = 0,
     MF_ERR_INVALID_ARG = 1,      /* a pointer, size, variance or count is invalid */
-    MF_ERR_UNSUPPORTED_SIZE = 2, /* H or W is not 2^a with 16 <= N <= 4096 (W even) */
+    MF_ERR_UNSUPPORTED_SIZE = 2, /* H or W is not a power of two in [16, 2048] */
     MF_ERR_OUT_OF_MEMORY = 3,    /* a plan table or workspace could not be allocated */
     MF_ERR_DEVICE = 4,           /* a HIP runtime call failed */
     MF_ERR_NOT_CONVERGED = 5,    /* tol > 0 not reached within max_sweeps (result still written) */
@@ -81,7 +81,7 @@ typedef struct {
 
 /* One image problem. */
 typedef struct {
-    int32_t H, W;              /* image size; each a power of two in [16, 4096] */
+    int32_t H, W;              /* image size; each a power of two in [16, 2048] */
     const float* noise_var;    /* host, H*W: N_i > 0, +INFINITY marks a missing pixel */
     mf_spectrum spectrum;
 } mf_problem;
@@ -119,7 +119,12 @@ enum {
 /* Plan flags. */
 enum {
     MF_FLAG_NONE = 0,
-    MF_FLAG_AUTOTUNE = 1       /* time candidate tilings of the streamed kernels at plan creation */
+    MF_FLAG_AUTOTUNE = 1,      /* time the column-tile shapes of each streamed size class (>= 256) at plan
+                                  creation and keep the fastest; with MF_TUNE_CACHE=<file> in the
+                                  environment the choices are read from / appended to that file */
+    MF_FLAG_GRAPH = 2          /* capture the streamed sampler's sweep loop of each size class as a HIP
+                                  graph, once per launch configuration (pointers, counts, seed, sweep
+                                  range), and replay it; the plan keeps up to 8 graphs */
 };
 
 /* Arguments of mf_sample. */
@@ -188,6 +193,24 @@ mf_status mf_sample(mf_plan plan, const float* d, const mf_sample_args* args,
 mf_status mf_wiener_backward(mf_plan plan, const float* s_wf, const float* grad_s,
                              const mf_schedule* schedule, float* grad_d, double* grad_bands,
                              float* v_out, mf_info* info, mf_stream stream);
+
+/* Gradient of a truncated Wiener iteration ("unrolled" mode).  s_K is the
+ * result of the schedule's sweeps (tol must be <= 0: a fixed sweep count,
+ * cooling levels included) from s_0 = 0.  The call re-runs those sweeps, keeping
+ * the state every checkpoint_every sweeps, then runs the transposed sweeps in
+ * reverse (sweep k maps t_k = (1 - a_k) s_{k-1} + a_k d, s_k = F^-1 f_k F t_k;
+ * its transpose filters by f_k, then scales by 1 - a_k), recomputing each
+ * segment from its checkpoint and storing that segment's transforms F t_k:
+ *   grad_d     = dL/dd                                   device, concatenated
+ *   grad_bands = dL/dtheta for band-spectrum problems    device float64, or NULL
+ *                (sum over sweeps and over modes of the band of
+ *                 Re(conj(F sbar_k) F t_k) T_k / (n P_k + T_k)^2)
+ *   s_out      = s_K                                     device, or NULL
+ * for dL/ds_K = grad_s (device, concatenated).  Workspace: (ceil(K/C) + C + 2)
+ * complex fields per size class, allocated by the plan on first use. */
+mf_status mf_wiener_backward_unrolled(mf_plan plan, const float* d, const mf_schedule* schedule,
+                                      int32_t checkpoint_every, const float* grad_s, float* s_out,
+                                      float* grad_d, double* grad_bands, mf_stream stream);
 
 /* Band cross-power sum_{k in b} Re(conj(x_k) y_k) of two concatenated real
  * fields (unnormalised DFTs) for every band-spectrum problem; device float64 out. */

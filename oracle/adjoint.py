@@ -66,6 +66,78 @@ def wiener_vjp(problem, s_wf, gbar, schedule: messenger.Schedule = None, solver:
 
 
 # --------------------------------------------------------------------------
+# Unrolled mode: the gradient of a *truncated* Wiener iteration (a fixed number
+# of deterministic sweeps through cooling levels), by reverse-mode through the
+# sweeps.  Sweep k maps s_{k-1} -> t_k = (1 - a_k) s_{k-1} + a_k d,
+# s_k = ifft2(f_k fft2(t_k)); its transpose filters by f_k in Fourier space and
+# then scales by (1 - a_k) in pixel space.
+# --------------------------------------------------------------------------
+
+def level_sequence(schedule: messenger.Schedule):
+    seq = []
+    for lam, k in zip(schedule.lambdas, schedule.sweeps):
+        seq += [float(lam)] * int(k)
+    return seq
+
+
+def unrolled_vjp(problem, schedule: messenger.Schedule, gbar):
+    """(s_K, dL/dd, dL/dtheta) for L with dL/ds_K = gbar, where s_K is the
+    result of the schedule's sweeps from s_0 = 0 (no convergence phase)."""
+    H, W = problem.H, problem.W
+    n = H * W
+    d = np.where(problem.mask, 0.0, problem.d)
+    s = np.zeros((H, W))
+    tape = []
+    for lam in level_sequence(schedule):
+        c = messenger.coefficients(problem.noise_var, problem.spectrum, lam)
+        s_new, t = messenger.sweep(s, c.ninv * d, c)
+        tape.append((t, c))
+        s = s_new
+    bands = problem.spectrum.kind == "bands"
+    if bands:
+        idx = band_of_modes(problem.spectrum.edges, H, W)
+        nb = len(problem.spectrum.amps)
+        gtheta = np.zeros(nb)
+    sbar = np.asarray(gbar, dtype=np.float64)
+    dbar = np.zeros((H, W))
+    for t, c in reversed(tape):
+        F_sbar = np.fft.fft2(sbar)
+        if bands:
+            # dL/df = Re(conj(F sbar) F t)/n and df/dtheta_b = n T/(nP + T)^2 on band b
+            contrib = np.real(np.conj(F_sbar) * np.fft.fft2(t)) * c.T / (c.nP + c.T) ** 2
+            gtheta += np.array([contrib[idx == b].sum() for b in range(nb)])
+        tbar = np.fft.ifft2(c.f * F_sbar).real
+        dbar += c.a * tbar
+        sbar = (1.0 - c.a) * tbar
+    return s, dbar, (gtheta if bands else None)
+
+
+def unrolled_vjp_torch(problem, schedule: messenger.Schedule, gbar):
+    """The same gradient by torch autograd through the truncated iteration
+    written directly from the sweep's definition (float64, CPU)."""
+    import torch
+    H, W = problem.H, problem.W
+    n = H * W
+    nv = problem.noise_var
+    obs = np.isfinite(nv)
+    tau = float(np.min(nv[obs])) if obs.any() else 1.0
+    nbar = torch.from_numpy(np.where(obs, nv - tau, np.inf))
+    idx = torch.from_numpy(band_of_modes(problem.spectrum.edges, H, W))
+    theta = torch.tensor(np.asarray(problem.spectrum.amps, dtype=np.float64), requires_grad=True)
+    d = torch.tensor(np.where(problem.mask, 0.0, problem.d), requires_grad=True)
+    nP = n * theta[idx]
+    s = torch.zeros((H, W), dtype=torch.float64)
+    for lam in level_sequence(schedule):
+        T = lam * tau
+        a = torch.where(torch.isfinite(nbar), T / (T + nbar), torch.zeros_like(nbar))
+        t = (1 - a) * s + a * d
+        s = torch.fft.ifft2(nP / (nP + T) * torch.fft.fft2(t)).real
+    L = torch.sum(s * torch.from_numpy(np.asarray(gbar, dtype=np.float64)))
+    gd, gt = torch.autograd.grad(L, (d, theta))
+    return s.detach().numpy(), gd.numpy(), gt.numpy()
+
+
+# --------------------------------------------------------------------------
 # Loss of the differentiation workload: negative log-posterior of the
 # Wiener image (Eq. 5-7, up to constants) plus an L2 distance to the true field.
 # --------------------------------------------------------------------------

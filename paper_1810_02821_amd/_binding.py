@@ -21,6 +21,7 @@ STATUS = {0: "ok", 1: "invalid argument", 2: "unsupported size", 3: "out of memo
 MF_PK_POWERLAW, MF_PK_BANDS = 0, 1
 FORMS = {"auto": 0, "persistent": 1, "streamed": 2, "plain": 3}
 MF_FLAG_AUTOTUNE = 1
+MF_FLAG_GRAPH = 2
 
 
 class MFError(RuntimeError):
@@ -65,7 +66,7 @@ class _SampleArgs(C.Structure):
 
 EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_plan_pixel_offset",
            "mf_plan_tau", "mf_plan_total_bands", "mf_wiener", "mf_sample", "mf_wiener_backward",
-           "mf_band_power", "mf_status_string", "mf_last_error"]
+           "mf_wiener_backward_unrolled", "mf_band_power", "mf_status_string", "mf_last_error"]
 
 _lib = None
 
@@ -97,11 +98,12 @@ def lib():
     L.mf_sample.argtypes = [vp, vp, C.POINTER(_SampleArgs), vp, vp, vp, vp]
     L.mf_wiener_backward.argtypes = [vp, vp, vp, C.POINTER(_Schedule), vp, vp, vp, C.POINTER(Info), vp]
     L.mf_band_power.argtypes = [vp, vp, vp, vp, vp]
+    L.mf_wiener_backward_unrolled.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_int32, vp, vp, vp, vp, vp]
     L.mf_status_string.argtypes = [C.c_int]
     L.mf_status_string.restype = C.c_char_p
     L.mf_last_error.restype = C.c_char_p
     for name in ("mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_wiener",
-                 "mf_sample", "mf_wiener_backward", "mf_band_power"):
+                 "mf_sample", "mf_wiener_backward", "mf_wiener_backward_unrolled", "mf_band_power"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -171,7 +173,7 @@ class Plan:
     """A set of image problems (size, noise variance map with +inf on missing
     pixels, isotropic power spectrum) with their device tables."""
 
-    def __init__(self, problems, autotune: bool = False):
+    def __init__(self, problems, autotune: bool = False, graph: bool = False):
         L = lib()
         self.problems = list(problems)
         keep = []
@@ -182,8 +184,8 @@ class Plan:
             keep += [nv, k]
             arr[i] = _Problem(int(p.H), int(p.W), nv.ctypes.data_as(C.POINTER(C.c_float)), spec)
         h = C.c_void_p()
-        _check(L.mf_plan_create(C.byref(h), len(self.problems), arr,
-                                MF_FLAG_AUTOTUNE if autotune else 0, None))
+        flags = (MF_FLAG_AUTOTUNE if autotune else 0) | (MF_FLAG_GRAPH if graph else 0)
+        _check(L.mf_plan_create(C.byref(h), len(self.problems), arr, flags, None))
         self._h = h
         self.offsets = [L.mf_plan_pixel_offset(h, i) for i in range(len(self.problems) + 1)]
         self.total_pixels = self.offsets[-1]
@@ -288,6 +290,20 @@ class Plan:
                                       _ptr(gb), _ptr(v), info, _stream())
         _check(st, allow_not_converged)
         return grad_d, gb, v, list(info)
+
+    def wiener_backward_unrolled(self, d, grad_s, schedule: Schedule, checkpoint_every: int = 20,
+                                 want_bands=True):
+        """Gradient of the truncated iteration: returns (s_K, grad_d, grad_bands)."""
+        import torch
+        s_out = torch.empty_like(grad_s)
+        grad_d = torch.empty_like(grad_s)
+        gb = None
+        if want_bands and self.total_bands > 0:
+            gb = torch.zeros(self.total_bands, dtype=torch.float64, device=grad_s.device)
+        sch = schedule._c()
+        _check(lib().mf_wiener_backward_unrolled(self._h, _ptr(d), C.byref(sch), int(checkpoint_every),
+                                                 _ptr(grad_s), _ptr(s_out), _ptr(grad_d), _ptr(gb), _stream()))
+        return s_out, grad_d, gb
 
     def band_power(self, x, y):
         import torch

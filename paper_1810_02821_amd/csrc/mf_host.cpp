@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <string>
@@ -87,7 +88,18 @@ struct mf_plan_s {
     std::map<int, float2*> d_tw;     // W_L^r for every transform length L
     // workspaces
     DevBuf items, field, t_save, partials, aux, coef;
+    DevBuf field_adj, ckpt, tstore, slots;  // unrolled-gradient workspaces
     std::vector<mf::ItemDev> items_cached;  // what items[0..] holds (skip re-uploads)
+    // column-kernel tile shape per size class: (H, W) -> (tc, nth)
+    std::map<std::pair<int, int>, std::pair<int, int>> col_shape;
+    // captured sweep loops of the streamed sampler, keyed by launch configuration
+    struct GraphEntry {
+        std::vector<uint64_t> key;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+    };
+    std::vector<GraphEntry> graphs;
+    hipStream_t cap_stream = nullptr;
     std::vector<float> host_nbar;    // for residual norms
     ~mf_plan_s() {
         (void)hipFree(d_probs);
@@ -104,6 +116,15 @@ struct mf_plan_s {
         partials.release();
         aux.release();
         coef.release();
+        field_adj.release();
+        ckpt.release();
+        tstore.release();
+        slots.release();
+        for (auto& g : graphs) {
+            if (g.exec) (void)hipGraphExecDestroy(g.exec);
+            if (g.graph) (void)hipGraphDestroy(g.graph);
+        }
+        if (cap_stream) (void)hipStreamDestroy(cap_stream);
     }
 };
 
@@ -210,6 +231,19 @@ mf_status validate_schedule(const mf_schedule* s) {
     return MF_OK;
 }
 
+std::pair<int, int> class_shape(mf_plan p, int H, int W) {
+    auto it = p->col_shape.find({H, W});
+    if (it != p->col_shape.end()) return it->second;
+    int tc[8], nth[8];
+    mf::col_shape_candidates(H, tc, nth, 8);  // the first candidate is the default shape
+    return {tc[0], nth[0]};
+}
+
+hipError_t launch_col_class(mf_plan p, int W, int H, const mf::SweepArgs& a, hipStream_t s) {
+    const auto sh = class_shape(p, H, W);
+    return mf::launch_col_shape(W, H, sh.first, sh.second, a, s);
+}
+
 mf::SweepArgs base_args(mf_plan p, int H, int W) {
     mf::SweepArgs a{};
     a.probs = p->d_probs;
@@ -278,7 +312,7 @@ mf_status solve_class(mf_plan p, const std::vector<int>& pids, int H, int W, con
         a.check_t = check_t;
         MF_HIP(mf::launch_row(W, H, first ? mf::kRowFwd : mf::kRowInvFwd, a, s));
         a.save_t = a.check_t = 0;
-        MF_HIP(mf::launch_col(W, H, a, s));
+        MF_HIP(launch_col_class(p, W, H, a, s));
         first = false;
         ++total;
         return MF_OK;
@@ -431,9 +465,10 @@ mf_status copy_field_real(mf_plan p, float* out, hipStream_t s) {
 // -------------------------------------------------------------------------
 // Sampler
 // -------------------------------------------------------------------------
-mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int H, int W, const float* d,
-                          const mf_sample_args* g, float2* work, const float2* state_in, float* samples,
-                          hipStream_t s) {
+// Enqueue the streamed sweep loop of one size class on stream s.
+mf_status enqueue_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int H, int W, const float* d,
+                           const mf_sample_args* g, float2* work, const float2* state_in, float* samples,
+                           hipStream_t s) {
     mf::SweepArgs a = base_args(p, H, W);
     a.items = d_items;
     a.n_items = n_items;
@@ -459,11 +494,130 @@ mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, in
         a.emit_index = k > 0 ? emit_of(k - 1) : -1;
         MF_HIP(mf::launch_row(W, H, k == 0 ? mf::kRowFwd : mf::kRowInvFwd, a, s));
         a.emit_index = -1;
-        MF_HIP(mf::launch_col(W, H, a, s));
+        MF_HIP(launch_col_class(p, W, H, a, s));
     }
     if (K > 0) {
         a.emit_index = emit_of(K - 1);
         MF_HIP(mf::launch_row(W, H, mf::kRowInv, a, s));
+    }
+    return MF_OK;
+}
+
+// The streamed sampler for one size class; with MF_FLAG_GRAPH the whole sweep
+// loop is captured once per launch configuration and replayed as one graph.
+mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int H, int W, const float* d,
+                          const mf_sample_args* g, float2* work, const float2* state_in, float* samples,
+                          hipStream_t s) {
+    if (!(p->flags & MF_FLAG_GRAPH)) return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, s);
+    uint32_t init_bits;
+    std::memcpy(&init_bits, &g->init_scale, sizeof(init_bits));
+    const auto sh = class_shape(p, H, W);
+    const std::vector<uint64_t> key = {(uint64_t)H, (uint64_t)W, (uint64_t)n_items, (uint64_t)(uintptr_t)d_items,
+                                       (uint64_t)(uintptr_t)d, (uint64_t)(uintptr_t)work,
+                                       (uint64_t)(uintptr_t)state_in, (uint64_t)(uintptr_t)samples, g->seed,
+                                       (uint64_t)g->sweep_offset, (uint64_t)g->burn_in, (uint64_t)g->n_samples,
+                                       (uint64_t)g->thin, (uint64_t)g->chains_per_problem, (uint64_t)init_bits,
+                                       (uint64_t)sh.first, (uint64_t)sh.second};
+    for (auto& e : p->graphs)
+        if (e.key == key) {
+            MF_HIP(hipGraphLaunch(e.exec, s));
+            return MF_OK;
+        }
+    if (!p->cap_stream) MF_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    MF_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    mf_status st = enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, p->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (st != MF_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(MF_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(MF_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    if (p->graphs.size() >= 8) {  // keep the cache small
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        (void)hipGraphDestroy(p->graphs.front().graph);
+        p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({key, graph, exec});
+    MF_HIP(hipGraphLaunch(exec, s));
+    return MF_OK;
+}
+
+// Time every column-tile shape of each streamed size class on a scratch field
+// and keep the fastest (all shapes do the same arithmetic, element for
+// element).  Choices can be persisted in the file named by MF_TUNE_CACHE.
+mf_status autotune(mf_plan p) {
+    const char* cache_path = std::getenv("MF_TUNE_CACHE");
+    std::map<std::pair<int, int>, std::pair<int, int>> cached;
+    if (cache_path) {
+        if (FILE* f = std::fopen(cache_path, "r")) {
+            char arch[64];
+            int H, W, tc, nth;
+            while (std::fscanf(f, "%63s %d %d %d %d", arch, &H, &W, &tc, &nth) == 5)
+                if (std::string(arch) == "gfx950") cached[{H, W}] = {tc, nth};
+            std::fclose(f);
+        }
+    }
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        if (H < 256) continue;  // small classes run on the persistent kernel or are launch-bound
+        auto c = cached.find({H, W});
+        if (c != cached.end()) {
+            p->col_shape[{H, W}] = c->second;
+            continue;
+        }
+        int tc[8], nth[8];
+        const int nc = mf::col_shape_candidates(H, tc, nth, 8);
+        if (nc <= 1) continue;
+        const int pid = kv.second[0];
+        const int n_items = std::max(1, std::min(16, (int)(2 * (4096 * 4096 / ((int64_t)H * W)))));
+        std::vector<mf::ItemDev> items(n_items);
+        for (int i = 0; i < n_items; ++i) items[i] = {pid, i, (int64_t)i * H * W};
+        DevBuf fld, it;
+        MF_HIP(fld.ensure((size_t)n_items * H * W * sizeof(float2)));
+        MF_HIP(it.ensure(items.size() * sizeof(mf::ItemDev)));
+        MF_HIP(hipMemcpy(it.p, items.data(), items.size() * sizeof(mf::ItemDev), hipMemcpyHostToDevice));
+        MF_HIP(hipMemset(fld.p, 0, (size_t)n_items * H * W * sizeof(float2)));
+        mf::SweepArgs a = base_args(p, H, W);
+        a.items = it.as<mf::ItemDev>();
+        a.n_items = n_items;
+        a.field = fld.as<float2>();
+        a.stochastic = 1;
+        hipEvent_t e0, e1;
+        MF_HIP(hipEventCreate(&e0));
+        MF_HIP(hipEventCreate(&e1));
+        float best = 1e30f;
+        int bi = 0;
+        for (int ci = 0; ci < nc; ++ci) {
+            MF_HIP(mf::launch_col_shape(W, H, tc[ci], nth[ci], a, nullptr));  // warm-up
+            MF_HIP(hipEventRecord(e0, nullptr));
+            for (int r = 0; r < 3; ++r) MF_HIP(mf::launch_col_shape(W, H, tc[ci], nth[ci], a, nullptr));
+            MF_HIP(hipEventRecord(e1, nullptr));
+            MF_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            MF_HIP(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best) {
+                best = ms;
+                bi = ci;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        fld.release();
+        it.release();
+        p->col_shape[{H, W}] = {tc[bi], nth[bi]};
+        if (cache_path) {
+            if (FILE* f = std::fopen(cache_path, "a")) {
+                std::fprintf(f, "gfx950 %d %d %d %d\n", H, W, tc[bi], nth[bi]);
+                std::fclose(f);
+            }
+        }
     }
     return MF_OK;
 }
@@ -594,6 +748,13 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
             return st;
         }
     }
+    if (flags & MF_FLAG_AUTOTUNE) {
+        mf_status st = autotune(p);
+        if (st != MF_OK) {
+            delete p;
+            return st;
+        }
+    }
     *out = p;
     return MF_OK;
 }
@@ -684,6 +845,117 @@ mf_status mf_wiener_backward(mf_plan p, const float* s_wf, const float* grad_s, 
         }
     }
     return conv;
+}
+
+mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedule* sch, int32_t C,
+                                      const float* grad_s, float* s_out, float* grad_d, double* grad_bands,
+                                      mf_stream stream) {
+    if (!p || !d || !grad_s || !grad_d) return fail(MF_ERR_INVALID_ARG, "plan, d, grad_s and grad_d are required");
+    mf_status st = validate_schedule(sch);
+    if (st != MF_OK) return st;
+    if (sch->tol > 0) return fail(MF_ERR_INVALID_ARG, "the unrolled gradient needs a fixed sweep count (tol <= 0)");
+    if (C < 1) return fail(MF_ERR_INVALID_ARG, "checkpoint_every must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<double> lam;
+    for (int j = 0; j < sch->n_levels; ++j)
+        for (int k = 0; k < sch->sweeps[j]; ++k) lam.push_back(sch->lambda[j]);
+    const int K = (int)lam.size();
+    const int ncp = (K + C - 1) / C;
+    MF_HIP(hipMemsetAsync(grad_d, 0, (size_t)p->total_px * sizeof(float), s));
+    if (grad_bands && p->total_bands > 0)
+        MF_HIP(hipMemsetAsync(grad_bands, 0, (size_t)p->total_bands * sizeof(double), s));
+    if (s_out) MF_HIP(hipMemsetAsync(s_out, 0, (size_t)p->total_px * sizeof(float), s));
+    if (K == 0) return MF_OK;  // s_K = s_0 = 0 does not depend on d or P
+    size_t max_items = 0;
+    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size());
+    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
+    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        const int n_items = (int)kv.second.size();
+        const size_t n_cls = (size_t)n_items * H * W;
+        std::vector<mf::ItemDev> items;
+        for (int i = 0; i < n_items; ++i) items.push_back({kv.second[i], 0, (int64_t)i * H * W});
+        mf::ItemDev* di = nullptr;
+        if ((st = put_items(p, items, 0, s, &di)) != MF_OK) return st;
+        const auto sh = class_shape(p, H, W);
+        const size_t n_tiles = (size_t)n_items * (W / sh.first);
+        MF_HIP(p->field.ensure(n_cls * sizeof(float2)));
+        MF_HIP(p->field_adj.ensure(n_cls * sizeof(float2)));
+        MF_HIP(p->ckpt.ensure((size_t)ncp * n_cls * sizeof(float2)));
+        MF_HIP(p->tstore.ensure((size_t)std::min(C, K) * n_cls * sizeof(float2)));
+        MF_HIP(p->slots.ensure(n_tiles * mf::kMaxBandsPerProblem * sizeof(double)));
+        float2* F = p->field.as<float2>();
+        float2* FA = p->field_adj.as<float2>();
+        float2* ck = p->ckpt.as<float2>();
+        float2* ts = p->tstore.as<float2>();
+        mf::SweepArgs a = base_args(p, H, W);
+        a.items = di;
+        a.n_items = n_items;
+        a.src = d;
+        a.src_kind = mf::kSrcData;
+        a.stochastic = 0;
+        a.real_only = 1;
+        a.band = p->d_band;
+        a.grad_d = grad_d;
+        // ---- forward sweeps, keeping s_{jC}
+        a.field = F;
+        MF_HIP(mf::launch_load_real(W, H, a, nullptr, s));
+        MF_HIP(hipMemsetAsync(ck, 0, n_cls * sizeof(float2), s));
+        for (int k = 1; k <= K; ++k) {
+            a.lambda = (float)lam[k - 1];
+            a.pix_mode = mf::kPixUpdate;
+            a.s_save = (k - 1 > 0 && (k - 1) % C == 0) ? ck + (size_t)((k - 1) / C) * n_cls : nullptr;
+            MF_HIP(mf::launch_row(W, H, k == 1 ? mf::kRowFwd : mf::kRowInvFwd, a, s));
+            a.s_save = nullptr;
+            MF_HIP(launch_col_class(p, W, H, a, s));
+        }
+        MF_HIP(mf::launch_row(W, H, mf::kRowInv, a, s));
+        if (s_out) MF_HIP(mf::launch_copy_out_real(W, H, a, s_out, s));
+        // ---- reverse sweeps, each segment recomputed from its checkpoint
+        MF_HIP(hipMemsetAsync(p->slots.p, 0, n_tiles * mf::kMaxBandsPerProblem * sizeof(double), s));
+        mf::SweepArgs b = a;
+        b.field = FA;
+        b.band_slots = p->slots.as<double>();
+        MF_HIP(mf::launch_load_real(W, H, b, grad_s, s));
+        bool first = true;
+        for (int j = ncp - 1; j >= 0; --j) {
+            const int k0 = j * C, k1 = std::min(K, k0 + C);
+            mf::SweepArgs f = a;
+            f.field = F;
+            MF_HIP(mf::launch_init_items(W, H, f, ck + (size_t)j * n_cls, 0.f, s));
+            for (int k = k0 + 1; k <= k1; ++k) {
+                f.lambda = (float)lam[k - 1];
+                f.pix_mode = mf::kPixUpdate;
+                MF_HIP(mf::launch_row(W, H, k == k0 + 1 ? mf::kRowFwd : mf::kRowInvFwd, f, s));
+                f.t_store = ts + (size_t)(k - k0 - 1) * n_cls;
+                MF_HIP(launch_col_class(p, W, H, f, s));
+                f.t_store = nullptr;
+            }
+            for (int k = k1; k >= k0 + 1; --k) {
+                mf::SweepArgs r = b;
+                if (first) {
+                    r.pix_mode = mf::kPixIdentity;
+                    MF_HIP(mf::launch_row(W, H, mf::kRowFwd, r, s));
+                } else {
+                    r.pix_mode = mf::kPixAdjoint;  // transpose of sweep k+1's pixel step
+                    r.lambda = (float)lam[k];
+                    MF_HIP(mf::launch_row(W, H, mf::kRowInvFwd, r, s));
+                }
+                first = false;
+                r.lambda = (float)lam[k - 1];
+                r.t_load = ts + (size_t)(k - k0 - 1) * n_cls;
+                MF_HIP(launch_col_class(p, W, H, r, s));
+            }
+        }
+        mf::SweepArgs r = b;
+        r.pix_mode = mf::kPixAdjoint;  // transpose of sweep 1's pixel step
+        r.lambda = (float)lam[0];
+        MF_HIP(mf::launch_row(W, H, mf::kRowInv, r, s));
+        if (grad_bands && p->total_bands > 0)
+            MF_HIP(mf::launch_band_slots_reduce(W, H, sh.first, r, p->d_band_base, p->d_band_count, grad_bands, s));
+    }
+    return MF_OK;
 }
 
 mf_status mf_band_power(mf_plan p, const float* x, const float* y, double* out, mf_stream stream) {

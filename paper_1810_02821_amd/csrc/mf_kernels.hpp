@@ -53,6 +53,20 @@ struct SweepArgs {
     int32_t check_t;          // 1: accumulate |t - t_save|^2 into partials
     double* partials;         // [item][row block] partial sums
     int32_t real_only;        // 1: the imaginary channel is unused (Wiener / adjoint)
+    // reverse-mode sweeps (unrolled gradient)
+    int32_t pix_mode;         // kPixUpdate, kPixAdjoint or kPixIdentity (row kernel)
+    float* grad_d;            // kPixAdjoint: grad_d += a t (concatenated pixels)
+    float2* s_save;           // row kernel: state after the inverse row FFT (field layout), or null
+    float2* t_store;          // col kernel: forward 2D transform of t (field layout), or null
+    const float2* t_load;     // col kernel: stored transform to pair with for band sums, or null
+    double* band_slots;       // col kernel: per-tile band sums [tile][kMaxBandsPerProblem], accumulated
+    const int16_t* band;      // per-mode band index (concatenated), -1 = none
+};
+
+enum PixMode : int32_t {
+    kPixUpdate = 0,    // messenger step t = (1 - a) s + src (+ sigma xi)
+    kPixAdjoint = 1,   // transpose of the pixel step: grad_d += a t, t <- (1 - a) t
+    kPixIdentity = 2,  // leave the row as it is
 };
 
 // Host launchers (defined in mf_streamed.hip).  mode bit 1: inverse row FFT +
@@ -60,6 +74,13 @@ struct SweepArgs {
 enum RowMode : int32_t { kRowInv = 1, kRowFwd = 2, kRowInvFwd = 3 };
 hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_t s);
 hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s);
+// Column kernel with an explicit tile shape (TC columns, nth threads), and the
+// shapes available for a column length (returns how many were written).
+hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, hipStream_t s);
+int col_shape_candidates(int H, int* tc, int* nth, int max_n);
+// Sum per-tile band slots into out[band_base[prob] + b] for every item.
+hipError_t launch_band_slots_reduce(int W, int H, int tc, const SweepArgs& a, const int32_t* band_base,
+                                    const int32_t* band_count, double* out, hipStream_t s);
 int row_blocks_per_item(int W, int H);
 
 // Elementwise helpers (mf_streamed.hip).

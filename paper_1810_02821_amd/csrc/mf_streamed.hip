@@ -82,6 +82,9 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
 
     if constexpr (MODE & kRowInv) {
         stockham_fft<L, 1, TPR, true>(row, lane, a.tw_row);
+        if (a.s_save && valid)
+            for (unsigned x = lane; x < (unsigned)L; x += TPR)
+                a.s_save[it.field_off + (int64_t)y * W + x] = row[swz(x)];
         if (a.emit_index >= 0 && valid) {
             const int64_t base = (int64_t)a.chains * a.n_samples * pr.pix_off;
             const int64_t n = (int64_t)pr.H * pr.W;
@@ -95,6 +98,17 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
             }
         }
         if constexpr (!(MODE & kRowFwd)) {
+            if (a.pix_mode == kPixAdjoint) {
+                // transpose of the pixel step on the last reverse sweep
+                const float T = a.lambda * pr.tau;
+                for (unsigned x = lane; x < (unsigned)L; x += TPR) {
+                    const int64_t pix = pr.pix_off + (int64_t)y * W + x;
+                    const float aa = pix_a(T, a.nbar[pix]);
+                    const float2 tb = row[swz(x)];
+                    if (valid) a.grad_d[pix] += aa * tb.x;
+                    row[swz(x)] = cscale(tb, 1.0f - aa);
+                }
+            }
             if (valid)
                 for (unsigned x = lane; x < (unsigned)L; x += TPR)
                     a.field[it.field_off + (int64_t)y * W + x] = row[swz(x)];
@@ -103,6 +117,20 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     }
 
     if constexpr (MODE & kRowFwd) {
+      if (a.pix_mode == kPixAdjoint) {
+        // transpose of the pixel step: grad_d += a t, t <- (1 - a) t
+        const float T = a.lambda * pr.tau;
+        for (unsigned x = lane; x < (unsigned)L; x += TPR) {
+            const int64_t pix = pr.pix_off + (int64_t)y * W + x;
+            const float aa = pix_a(T, a.nbar[pix]);
+            const float2 tb = row[swz(x)];
+            if (valid) a.grad_d[pix] += aa * tb.x;
+            row[swz(x)] = cscale(tb, 1.0f - aa);
+        }
+        __syncthreads();
+      } else if (a.pix_mode == kPixIdentity) {
+        __syncthreads();
+      } else {
         // ---- pixel-space messenger update t = (1 - a) s + src + sigma_t xi
         const float T = a.lambda * pr.tau;
         double acc = 0.0;
@@ -160,6 +188,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
             }
         }
         __syncthreads();
+      }
         stockham_fft<L, 1, TPR, false>(row, fresh(lane), fresh(a.tw_row));
         if (valid)
             for (unsigned x = lane; x < (unsigned)L; x += TPR)
@@ -167,9 +196,10 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     }
 }
 
-// Column tiles: TC columns of one item per block, threads and tile width
-// chosen so a tile fills at most ~128 KiB of LDS; each column is its own
-// segment of L + 32/TC elements (the tile load then hits distinct banks).
+// Column tiles: TC columns of one item per block of NTH threads; each column
+// is its own LDS segment of L + 32/TC elements (the tile load then hits
+// distinct banks).  The default shape fills at most ~128 KiB of LDS; the
+// autotuner may pick another feasible (TC, NTH).
 template <int L>
 struct ColShape {
     static constexpr int TC = L >= 2048 ? 8 : 16;
@@ -178,12 +208,12 @@ struct ColShape {
     static constexpr int SEG = L + 32 / TC;
 };
 
-template <int L>
-__global__ __launch_bounds__(ColShape<L>::NTH) void col_kernel(SweepArgs a, int W) {
-    constexpr int TC = ColShape<L>::TC;
-    constexpr int NTH = ColShape<L>::NTH;
-    constexpr int TPC = ColShape<L>::TPC;
-    constexpr int SEG = ColShape<L>::SEG;
+template <int L, int TC_, int NTH_>
+__global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
+    constexpr int TC = TC_;
+    constexpr int NTH = NTH_;
+    constexpr int TPC = NTH / TC;
+    constexpr int SEG = L + 32 / TC;
     constexpr int H = L;
     __shared__ float2 lds[TC * SEG];
     const unsigned tid = threadIdx.x;
@@ -204,8 +234,37 @@ __global__ __launch_bounds__(ColShape<L>::NTH) void col_kernel(SweepArgs a, int 
     const unsigned cid = tid / TPC, lane = tid % TPC;
     stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
 
-    // ---- Fourier-space update S = f T / n + w eta / n on column pairs
     const float T = a.lambda * pr.tau;
+    if (a.t_store) {
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const unsigned c = e % TC, y = e / TC;
+            a.t_store[it.field_off + (int64_t)y * W + x0 + c] = lds[c * SEG + swz(y)];
+        }
+    }
+    if (a.t_load) {
+        // band sums of Re(conj(F sbar) F t) T/(nP + T)^2: the derivative of a
+        // sweep's Fourier filter f = nP/(nP + T) with respect to a band amplitude
+        __shared__ double bacc[kMaxBandsPerProblem];
+        for (unsigned b = tid; b < (unsigned)kMaxBandsPerProblem; b += NTH) bacc[b] = 0.0;
+        __syncthreads();
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const unsigned c = e % TC, y = e / TC;
+            const int64_t mode = (int64_t)y * W + x0 + c;
+            const int b = a.band[pr.pix_off + mode];
+            if (b < 0) continue;
+            const float2 v = lds[c * SEG + swz(y)];
+            const float2 tt = a.t_load[it.field_off + mode];
+            const double P = a.nP[pr.pix_off + mode];
+            const double den = P + (double)T;
+            atomicAdd(&bacc[b], ((double)v.x * tt.x + (double)v.y * tt.y) * (double)T / (den * den));
+        }
+        __syncthreads();
+        for (unsigned b = tid; b < (unsigned)kMaxBandsPerProblem; b += NTH)
+            a.band_slots[t * kMaxBandsPerProblem + b] += bacc[b];
+        __syncthreads();
+    }
+
+    // ---- Fourier-space update S = f T / n + w eta / n on column pairs
     const float inv_n = 1.0f / ((float)H * (float)W);
 #pragma unroll 1
     for (unsigned e = tid; e < (unsigned)((TC / 2) * L); e += NTH) {
@@ -245,6 +304,23 @@ __global__ __launch_bounds__(ColShape<L>::NTH) void col_kernel(SweepArgs a, int 
         fld[(int64_t)y * W + c] = lds[c * SEG + swz(y)];
     }
 }
+
+__global__ void band_slots_reduce_kernel(SweepArgs a, int n_tiles, const int32_t* band_base,
+                                         const int32_t* band_count, double* out) {
+    const int item = blockIdx.x;
+    const ItemDev it = a.items[item];
+    const int cnt = band_count[it.prob];
+    for (int b = threadIdx.x; b < cnt; b += blockDim.x) {
+        double s = 0.0;
+        for (int t = item; t < n_tiles; t += a.n_items) s += a.band_slots[(int64_t)t * kMaxBandsPerProblem + b];
+        out[band_base[it.prob] + b] = s;
+    }
+}
+
+// Shapes the launcher can use (tile width, threads), per column length.
+struct ColCfg {
+    int tc, nth;
+};
 
 // ------------------------------------------------------------ elementwise --
 __global__ void init_kernel(SweepArgs a, int H, int W, const float2* state_in, float init_scale) {
@@ -479,11 +555,50 @@ hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_
     }
 }
 
-hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s) {
-    const int tc = col_tc(H);
+#define MF_COL_CASE(LL, TCC, NN)                                                              \
+    if (H == LL && tc == TCC && nth == NN) {                                                   \
+        hipLaunchKernelGGL((col_kernel_t<LL, TCC, NN>), dim3((unsigned)(cols / TCC)), dim3(NN), 0, s, a, W); \
+        return hipGetLastError();                                                              \
+    }
+
+hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, hipStream_t s) {
     if (tc > W || tc < 2) return hipErrorInvalidValue;
     const int64_t cols = (int64_t)a.n_items * W;
-    MF_DISPATCH(H, col_kernel, dim3((unsigned)(cols / tc)), dim3(col_threads(H)), s, a, W);
+    MF_COL_CASE(16, 16, 256) MF_COL_CASE(32, 16, 256) MF_COL_CASE(64, 16, 256) MF_COL_CASE(128, 16, 256)
+    MF_COL_CASE(256, 16, 256) MF_COL_CASE(256, 8, 256) MF_COL_CASE(256, 16, 512) MF_COL_CASE(256, 8, 512)
+    MF_COL_CASE(512, 16, 512) MF_COL_CASE(512, 8, 512) MF_COL_CASE(512, 16, 256) MF_COL_CASE(512, 16, 1024)
+    MF_COL_CASE(1024, 16, 1024) MF_COL_CASE(1024, 8, 1024) MF_COL_CASE(1024, 8, 512) MF_COL_CASE(1024, 16, 512)
+    MF_COL_CASE(2048, 8, 1024) MF_COL_CASE(2048, 8, 512) MF_COL_CASE(2048, 4, 512) MF_COL_CASE(2048, 4, 256)
+    return hipErrorInvalidValue;
+}
+#undef MF_COL_CASE
+
+int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
+    static const int table[][3] = {{16, 16, 256}, {32, 16, 256}, {64, 16, 256}, {128, 16, 256},
+                                   {256, 16, 256}, {256, 8, 256}, {256, 16, 512}, {256, 8, 512},
+                                   {512, 16, 512}, {512, 8, 512}, {512, 16, 256}, {512, 16, 1024},
+                                   {1024, 16, 1024}, {1024, 8, 1024}, {1024, 8, 512}, {1024, 16, 512},
+                                   {2048, 8, 1024}, {2048, 8, 512}, {2048, 4, 512}, {2048, 4, 256}};
+    int n = 0;
+    for (const auto& r : table)
+        if (r[0] == H && n < max_n) {
+            tc[n] = r[1];
+            nth[n] = r[2];
+            ++n;
+        }
+    return n;
+}
+
+hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s) {
+    return launch_col_shape(W, H, col_tc(H), col_threads(H), a, s);
+}
+
+hipError_t launch_band_slots_reduce(int W, int H, int tc, const SweepArgs& a, const int32_t* band_base,
+                                    const int32_t* band_count, double* out, hipStream_t s) {
+    (void)H;
+    const int n_tiles = a.n_items * (W / tc);
+    hipLaunchKernelGGL(band_slots_reduce_kernel, dim3(a.n_items), dim3(64), 0, s, a, n_tiles, band_base, band_count,
+                       out);
     return hipGetLastError();
 }
 

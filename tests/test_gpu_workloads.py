@@ -102,3 +102,63 @@ def test_large_map_wiener_1024(torch_cuda):
     r = rel(plan.split(s)[0], ref)
     print(f"rel {r:.2e}")
     assert r < REL_TOL
+
+
+def test_graph_replays_match_eager(torch_cuda):
+    """The streamed sweep loop captured as a HIP graph: several replays, with
+    eager work and synchronisation between them, each equal to the eager run."""
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("hipGraph replays 256")
+    prob = synth.config_128(2, 256)
+    eager = mf.Plan([prob])
+    graph = mf.Plan([prob], graph=True)
+    d = eager.concat([prob.d])
+    ref, _ = eager.sample(d, 21, chains=4, burn_in=5, n_samples=3, form="streamed")
+    out = graph.samples_buffer(4, 3)
+    for rep in range(3):
+        out.fill_(float("nan"))
+        graph.sample(d, 21, chains=4, burn_in=5, n_samples=3, form="streamed", out=out)
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), f"replay {rep}"
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        torch.cuda.synchronize()
+    ref2, _ = eager.sample(d, 22, chains=4, burn_in=5, n_samples=3, form="streamed")
+    got2, _ = graph.sample(d, 22, chains=4, burn_in=5, n_samples=3, form="streamed")
+    assert torch.equal(got2, ref2)
+    _check = om.sample_pair(prob, 22, 0, 1, 5, 3)[0]
+    assert rel(graph.sample_view(got2, 0, 4, 3).cpu().numpy()[2, 2], _check[0, 2]) < REL_TOL
+
+
+def test_autotuned_shapes_give_identical_samples(torch_cuda):
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("autotune 256/512/1024/2048")
+    probs = [synth.config_128(1, 256), synth.config_128(2, 512), synth.config_large(0, 1024),
+             synth.config_large(1, 2048)]
+    base = mf.Plan(probs)
+    tuned = mf.Plan(probs, autotune=True)
+    d = base.concat([p.d for p in probs])
+    a, _ = base.sample(d, 5, chains=2, burn_in=1, n_samples=2, form="streamed")
+    b, _ = tuned.sample(d, 5, chains=2, burn_in=1, n_samples=2, form="streamed")
+    assert torch.equal(a, b)
+
+
+@pytest.mark.parametrize("size,ckpt", [(64, 7), (64, 500), (256, 20)])
+def test_unrolled_gradient_matches_oracle(torch_cuda, size, ckpt):
+    """Reverse-mode through a truncated cooling schedule with checkpoints every
+    `ckpt` sweeps (7 does not divide the sweep count; 500 is one segment)."""
+    import paper_1810_02821_amd as mf
+    banner(f"unrolled gradient {size} ckpt {ckpt}")
+    prob = synth.config_bands(7, size, 32)
+    plan = mf.Plan([prob])
+    lams, sweeps = (50.0, 5.0, 1.0), (30, 30, 60) if size <= 64 else (20, 20, 60)
+    g = np.random.default_rng(8).standard_normal((size, size))
+    sK, gd, gb = plan.wiener_backward_unrolled(plan.concat([prob.d]), plan.concat([g]),
+                                               mf.Schedule(list(lams), list(sweeps)), checkpoint_every=ckpt)
+    s_ref, gd_ref, gt_ref = oa.unrolled_vjp(prob, om.Schedule(lams, sweeps), g)
+    rs = rel(plan.split(sK)[0], s_ref)
+    rd = rel(plan.split(gd)[0], gd_ref)
+    rt = float(np.max(np.abs(gb.cpu().numpy() - gt_ref)) / np.max(np.abs(gt_ref)))
+    print(f"s {rs:.2e} grad_d {rd:.2e} grad_theta {rt:.2e}")
+    assert rs < REL_TOL and rd < 1e-4 and rt < 1e-4

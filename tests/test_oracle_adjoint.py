@@ -75,3 +75,29 @@ def test_log_posterior_part_has_no_implicit_term():
     sw = dense.wiener_dense(S, p.noise_var, p.d)
     dJ = M.apply_S_inverse(sw, c) - c.ninv * (p.d - sw)
     assert np.linalg.norm(dJ) < 1e-8 * np.linalg.norm(c.ninv * p.d)
+
+
+def test_unrolled_vjp_matches_autograd_through_truncated_iteration():
+    """Reverse-mode through a cooling schedule of deterministic sweeps equals
+    torch autograd through the same truncated iteration."""
+    p = synth.config_bands(4, 16, 8)
+    sched = M.Schedule((40.0, 8.0, 1.0), (7, 6, 11))
+    g = np.random.default_rng(5).standard_normal((16, 16))
+    s, gd, gt = A.unrolled_vjp(p, sched, g)
+    s2, gd2, gt2 = A.unrolled_vjp_torch(p, sched, g)
+    assert np.allclose(s, s2, atol=1e-12)
+    assert np.linalg.norm(gd - gd2) < 1e-10 * np.linalg.norm(gd2)
+    assert np.max(np.abs(gt - gt2)) < 1e-10 * np.max(np.abs(gt2))
+    ref, _ = M.wiener(p, sched)
+    assert np.allclose(s, ref, atol=1e-12)
+
+
+def test_unrolled_gradient_tends_to_implicit_gradient():
+    """With enough sweeps the truncated iteration is at its fixed point and the
+    unrolled gradient equals the implicit one."""
+    p = synth.config_bands(6, 16, 8)
+    g = np.random.default_rng(6).standard_normal((16, 16))
+    s, gd, gt = A.unrolled_vjp(p, M.Schedule((1.0,), (6000,)), g)
+    gd_i, gt_i, _, _ = A.wiener_vjp(p, s, g, solver="cg")
+    assert np.linalg.norm(gd - gd_i) < 1e-8 * np.linalg.norm(gd_i)
+    assert np.max(np.abs(gt - gt_i)) < 1e-8 * np.max(np.abs(gt_i))
