@@ -122,9 +122,13 @@ enum {
     MF_FLAG_AUTOTUNE = 1,      /* time the column-tile shapes of each streamed size class (>= 256) at plan
                                   creation and keep the fastest; with MF_TUNE_CACHE=<file> in the
                                   environment the choices are read from / appended to that file */
-    MF_FLAG_GRAPH = 2          /* capture the streamed sampler's sweep loop of each size class as a HIP
+    MF_FLAG_GRAPH = 2,         /* capture the streamed sampler's sweep loop of each size class as a HIP
                                   graph, once per launch configuration (pointers, counts, seed, sweep
                                   range), and replay it; the plan keeps up to 8 graphs */
+    MF_FLAG_STREAMED_SOLVE = 4 /* run mf_wiener / mf_wiener_backward on the streamed kernels for every size
+                                  class; without it, classes with H = W in {32, 64, 128} use the persistent
+                                  solve kernel (one workgroup per problem, every level and the residual
+                                  test on the device, no host synchronisation per check) */
 };
 
 /* Arguments of mf_sample. */
@@ -161,9 +165,12 @@ double mf_plan_tau(mf_plan plan, int32_t problem);
 
 /* Wiener filter of every problem (Algorithm 1 with G(0,1) -> 0, Sec. 2.2).
  *   d       device, concatenated float32 data (values on missing pixels are ignored)
- *   s_init  device, concatenated start (NULL: zero)
+ *   s_init  device, concatenated start (NULL: zero); may be s_out
  *   s_out   device, concatenated result
  *   info    host array of n_problems entries, or NULL (then no host sync unless tol > 0)
+ * The convergence phase (tol > 0) runs at the last level and tests, every
+ * check_every sweeps (never on the first sweep of the phase), the residual
+ * ||t_k - t_{k-1}|| / (T ||b||) of Sec. 2.2 in FP64, b = N_eff^-1 d at that level.
  * Returns MF_ERR_NOT_CONVERGED if any problem missed tol (s_out still holds the
  * last iterate). */
 mf_status mf_wiener(mf_plan plan, const float* d, const mf_schedule* schedule,

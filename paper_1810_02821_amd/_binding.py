@@ -22,6 +22,7 @@ MF_PK_POWERLAW, MF_PK_BANDS = 0, 1
 FORMS = {"auto": 0, "persistent": 1, "streamed": 2, "plain": 3}
 MF_FLAG_AUTOTUNE = 1
 MF_FLAG_GRAPH = 2
+MF_FLAG_STREAMED_SOLVE = 4
 
 
 class MFError(RuntimeError):
@@ -173,7 +174,7 @@ class Plan:
     """A set of image problems (size, noise variance map with +inf on missing
     pixels, isotropic power spectrum) with their device tables."""
 
-    def __init__(self, problems, autotune: bool = False, graph: bool = False):
+    def __init__(self, problems, autotune: bool = False, graph: bool = False, streamed_solve: bool = False):
         L = lib()
         self.problems = list(problems)
         keep = []
@@ -184,7 +185,8 @@ class Plan:
             keep += [nv, k]
             arr[i] = _Problem(int(p.H), int(p.W), nv.ctypes.data_as(C.POINTER(C.c_float)), spec)
         h = C.c_void_p()
-        flags = (MF_FLAG_AUTOTUNE if autotune else 0) | (MF_FLAG_GRAPH if graph else 0)
+        flags = ((MF_FLAG_AUTOTUNE if autotune else 0) | (MF_FLAG_GRAPH if graph else 0)
+                 | (MF_FLAG_STREAMED_SOLVE if streamed_solve else 0))
         _check(L.mf_plan_create(C.byref(h), len(self.problems), arr, flags, None))
         self._h = h
         self.offsets = [L.mf_plan_pixel_offset(h, i) for i in range(len(self.problems) + 1)]

@@ -89,6 +89,7 @@ struct mf_plan_s {
     // workspaces
     DevBuf items, field, t_save, partials, aux, coef;
     DevBuf field_adj, ckpt, tstore, slots;  // unrolled-gradient workspaces
+    DevBuf sched;                           // persistent solve: levels, sweeps, per-item outcome
     std::vector<mf::ItemDev> items_cached;  // what items[0..] holds (skip re-uploads)
     // column-kernel tile shape per size class: (H, W) -> (tc, nth)
     std::map<std::pair<int, int>, std::pair<int, int>> col_shape;
@@ -120,6 +121,7 @@ struct mf_plan_s {
         ckpt.release();
         tstore.release();
         slots.release();
+        sched.release();
         for (auto& g : graphs) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
             if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -420,20 +422,103 @@ mf_status rhs_norms(mf_plan p, const float* src, int src_kind, double lam, std::
     return MF_OK;
 }
 
+// Real part of the field buffer of one streamed size class into `out`.
+mf_status copy_class_real(mf_plan p, const std::vector<int>& pids, int H, int W, float* out, hipStream_t s) {
+    std::vector<mf::ItemDev> items;
+    for (int pid : pids) items.push_back({pid, 0, p->probs[pid].pix_off});
+    mf::ItemDev* d = nullptr;
+    mf_status st = put_items(p, items, 0, s, &d);
+    if (st != MF_OK) return st;
+    mf::SweepArgs a = base_args(p, H, W);
+    a.items = d;
+    a.n_items = (int)items.size();
+    a.field = p->field.as<float2>();
+    MF_HIP(mf::launch_copy_out_real(W, H, a, out, s));
+    return MF_OK;
+}
+
+// Deterministic solve of one size class in the persistent kernel: one
+// workgroup per problem runs every level and the residual test on the device.
+mf_status solve_class_resident(mf_plan p, const std::vector<int>& pids, int N, const float* src, int src_kind,
+                               const mf_schedule* sch, const float* s_init, float* out, std::vector<mf_info>& info,
+                               bool want_info, hipStream_t s) {
+    const int n_items = (int)pids.size();
+    std::vector<mf::ItemDev> items(n_items);
+    for (int i = 0; i < n_items; ++i) items[i] = {pids[i], 0, p->probs[pids[i]].pix_off};
+    mf::ItemDev* d_items = nullptr;
+    mf_status st = put_items(p, items, 0, s, &d_items);
+    if (st != MF_OK) return st;
+    const int L = sch->n_levels;
+    const size_t info_off = (size_t)L * sizeof(double) + (size_t)L * sizeof(int32_t);
+    const size_t info_at = (info_off + 255) / 256 * 256;
+    MF_HIP(p->sched.ensure(info_at + (size_t)n_items * 3 * sizeof(double)));
+    std::vector<char> stage(info_off);
+    std::memcpy(stage.data(), sch->lambda, (size_t)L * sizeof(double));
+    std::memcpy(stage.data() + (size_t)L * sizeof(double), sch->sweeps, (size_t)L * sizeof(int32_t));
+    char* base = p->sched.as<char>();
+    MF_HIP(hipMemcpyAsync(base, stage.data(), info_off, hipMemcpyHostToDevice, s));
+    mf::SolveArgs a{};
+    a.probs = p->d_probs;
+    a.items = d_items;
+    a.n_items = n_items;
+    a.src = src;
+    a.src_kind = src_kind;
+    a.s_init = s_init;
+    a.s_out = out;
+    a.nbar = p->d_nbar;
+    a.nP = p->d_nP;
+    a.tw = p->d_tw.at(N);
+    a.lambda = reinterpret_cast<const double*>(base);
+    a.sweeps = reinterpret_cast<const int32_t*>(base + (size_t)L * sizeof(double));
+    a.n_levels = L;
+    a.tol = sch->tol;
+    a.max_sweeps = sch->max_sweeps;
+    a.check_every = sch->check_every > 0 ? sch->check_every : 1;
+    a.info = reinterpret_cast<double*>(base + info_at);
+    MF_HIP(mf::launch_resident_solve(N, a, s));
+    if (!want_info) {
+        int total = 0;
+        for (int j = 0; j < L; ++j) total += sch->sweeps[j];
+        for (int pid : pids) info[pid] = {total, 1, std::nan("")};
+        MF_HIP(hipStreamSynchronize(s));  // the staging vector dies on return
+        return MF_OK;
+    }
+    std::vector<double> h((size_t)n_items * 3);
+    MF_HIP(hipMemcpyAsync(h.data(), a.info, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < n_items; ++i)
+        info[pids[i]] = {(int32_t)h[3 * i], (int32_t)h[3 * i + 1], h[3 * i + 2]};
+    return MF_OK;
+}
+
+bool solve_resident(mf_plan p, int H, int W) {
+    return !(p->flags & MF_FLAG_STREAMED_SOLVE) && mf::resident_supported(H, W);
+}
+
+// Run the deterministic solve of every problem and write the real result to
+// `out` (concatenated).  The streamed classes also leave it in the field buffer.
 mf_status run_solve(mf_plan p, const float* src, int src_kind, const mf_schedule* sch, const float* s_init,
-                    mf_info* info_out, hipStream_t s) {
+                    float* out, mf_info* info_out, hipStream_t s) {
     mf_status st = validate_schedule(sch);
     if (st != MF_OK) return st;
     if ((st = ensure_solve_workspace(p, s)) != MF_OK) return st;
+    bool any_streamed = false;
+    for (auto& kv : p->classes) any_streamed = any_streamed || !solve_resident(p, kv.first.first, kv.first.second);
     std::vector<double> bn;
-    if (sch->tol > 0) {
+    if (sch->tol > 0 && any_streamed) {
         if ((st = rhs_norms(p, src, src_kind, sch->lambda[sch->n_levels - 1], bn, s)) != MF_OK) return st;
     }
     std::vector<mf_info> info(p->probs.size());
+    const bool want_info = info_out != nullptr || sch->tol > 0;
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;
+        if (solve_resident(p, H, W)) {
+            st = solve_class_resident(p, kv.second, H, src, src_kind, sch, s_init, out, info, want_info, s);
+            if (st != MF_OK) return st;
+            continue;
+        }
         if ((st = solve_class(p, kv.second, H, W, src, src_kind, sch, s_init, bn, info, s)) != MF_OK) return st;
-        // leave the class's result in the field buffer (pixel space, real part)
+        if ((st = copy_class_real(p, kv.second, H, W, out, s)) != MF_OK) return st;
     }
     bool all = true;
     for (auto& i : info) all = all && i.converged;
@@ -442,23 +527,6 @@ mf_status run_solve(mf_plan p, const float* src, int src_kind, const mf_schedule
         std::copy(info.begin(), info.end(), info_out);
     }
     if (!all) return fail(MF_ERR_NOT_CONVERGED, "tolerance not reached within max_sweeps");
-    return MF_OK;
-}
-
-mf_status copy_field_real(mf_plan p, float* out, hipStream_t s) {
-    for (auto& kv : p->classes) {
-        const int H = kv.first.first, W = kv.first.second;
-        std::vector<mf::ItemDev> items;
-        for (int pid : kv.second) items.push_back({pid, 0, p->probs[pid].pix_off});
-        mf::ItemDev* d = nullptr;
-        mf_status st = put_items(p, items, 0, s, &d);
-        if (st != MF_OK) return st;
-        mf::SweepArgs a = base_args(p, H, W);
-        a.items = d;
-        a.n_items = (int)items.size();
-        a.field = p->field.as<float2>();
-        MF_HIP(mf::launch_copy_out_real(W, H, a, out, s));
-    }
     return MF_OK;
 }
 
@@ -794,11 +862,7 @@ int32_t mf_plan_total_bands(mf_plan p) { return p ? p->total_bands : -1; }
 mf_status mf_wiener(mf_plan p, const float* d, const mf_schedule* schedule, const float* s_init, float* s_out,
                     mf_info* info, mf_stream stream) {
     if (!p || !d || !s_out) return fail(MF_ERR_INVALID_ARG, "plan, d and s_out are required");
-    hipStream_t s = (hipStream_t)stream;
-    mf_status st = run_solve(p, d, mf::kSrcData, schedule, s_init, info, s);
-    if (st != MF_OK && st != MF_ERR_NOT_CONVERGED) return st;
-    mf_status st2 = copy_field_real(p, s_out, s);
-    return st2 != MF_OK ? st2 : st;
+    return run_solve(p, d, mf::kSrcData, schedule, s_init, s_out, info, (hipStream_t)stream);
 }
 
 mf_status mf_wiener_backward(mf_plan p, const float* s_wf, const float* grad_s, const mf_schedule* schedule,
@@ -806,43 +870,40 @@ mf_status mf_wiener_backward(mf_plan p, const float* s_wf, const float* grad_s, 
     if (!p || !grad_s) return fail(MF_ERR_INVALID_ARG, "plan and grad_s are required");
     if (grad_bands && !s_wf) return fail(MF_ERR_INVALID_ARG, "grad_bands needs s_wf");
     hipStream_t s = (hipStream_t)stream;
-    mf_status st = run_solve(p, grad_s, mf::kSrcGrad, schedule, nullptr, info, s);
+    float* v = v_out;
+    if (!v) {
+        MF_HIP(p->aux.ensure((size_t)p->total_px * sizeof(float)));
+        v = p->aux.as<float>();
+    }
+    mf_status st = run_solve(p, grad_s, mf::kSrcGrad, schedule, nullptr, v, info, s);
     if (st != MF_OK && st != MF_ERR_NOT_CONVERGED) return st;
-    mf_status conv = st;
-    if (v_out && (st = copy_field_real(p, v_out, s)) != MF_OK) return st;
+    const mf_status conv = st;
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;
         std::vector<mf::ItemDev> items;
-        for (int pid : kv.second) items.push_back({pid, 0, p->probs[pid].pix_off});
+        for (int pid : kv.second)
+            if (grad_d || p->probs[pid].kind == MF_PK_BANDS) items.push_back({pid, 0, p->probs[pid].pix_off});
+        if (items.empty()) continue;
         mf::ItemDev* di = nullptr;
         if ((st = put_items(p, items, 0, s, &di)) != MF_OK) return st;
         mf::SweepArgs a = base_args(p, H, W);
         a.items = di;
         a.n_items = (int)items.size();
         a.field = p->field.as<float2>();
-        if (grad_d) MF_HIP(mf::launch_grad_d(W, H, a, grad_d, s));
-    }
-    if (grad_bands && p->total_bands > 0) {
-        // v is needed as a real array: reuse the aux workspace
-        MF_HIP(p->aux.ensure((size_t)p->total_px * sizeof(float)));
-        float* v = p->aux.as<float>();
-        if ((st = copy_field_real(p, v, s)) != MF_OK) return st;
-        for (auto& kv : p->classes) {
-            const int H = kv.first.first, W = kv.first.second;
-            std::vector<mf::ItemDev> items;
-            for (int pid : kv.second)
-                if (p->probs[pid].kind == MF_PK_BANDS) items.push_back({pid, 0, p->probs[pid].pix_off});
-            if (items.empty()) continue;
-            mf::ItemDev* di = nullptr;
-            if ((st = put_items(p, items, 0, s, &di)) != MF_OK) return st;
-            mf::SweepArgs a = base_args(p, H, W);
+        if (grad_d) MF_HIP(mf::launch_grad_d(W, H, a, v, grad_d, s));
+        if (!grad_bands || p->total_bands <= 0) continue;
+        std::vector<mf::ItemDev> band_items;
+        for (auto& it : items)
+            if (p->probs[it.prob].kind == MF_PK_BANDS) band_items.push_back(it);
+        if (band_items.empty()) continue;
+        if (band_items.size() != items.size()) {
+            if ((st = put_items(p, band_items, 0, s, &di)) != MF_OK) return st;
             a.items = di;
-            a.n_items = (int)items.size();
-            a.field = p->field.as<float2>();
-            a.partials = p->partials.as<double>();
-            MF_HIP(mf::launch_band_power(W, H, a, v, s_wf, p->d_band, p->d_band_base, p->d_band_count,
-                                         p->d_band_scale, grad_bands, s));
+            a.n_items = (int)band_items.size();
         }
+        a.partials = p->partials.as<double>();
+        MF_HIP(mf::launch_band_power(W, H, a, v, s_wf, p->d_band, p->d_band_base, p->d_band_count,
+                                     p->d_band_scale, grad_bands, s));
     }
     return conv;
 }

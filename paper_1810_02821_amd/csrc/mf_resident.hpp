@@ -26,7 +26,30 @@ struct ResidentArgs {
     int32_t chains;
 };
 
+// Deterministic messenger solve (Wiener filter / adjoint) of one problem per
+// workgroup, cooling levels and the residual test on the device.
+struct SolveArgs {
+    const ProbDev* probs;
+    const ItemDev* items;     // one per problem
+    int32_t n_items;
+    const float* src;         // concatenated d (kSrcData) or g (kSrcGrad)
+    int32_t src_kind;
+    const float* s_init;      // concatenated start, or null for zero
+    float* s_out;             // concatenated result
+    const float* nbar;        // concatenated Nbar (+inf missing)
+    const float* nP;          // concatenated n P(|k|)
+    const float2* tw;         // W_N^r, r < N
+    const double* lambda;     // [n_levels] cooling levels
+    const int32_t* sweeps;    // [n_levels] sweeps per level
+    int32_t n_levels;
+    double tol;               // residual tolerance of the final level (<= 0: none)
+    int32_t max_sweeps;
+    int32_t check_every;
+    double* info;             // [item][3]: sweeps run, converged flag, last residual (NaN if none)
+};
+
 bool resident_supported(int H, int W);
+hipError_t launch_resident_solve(int N, const SolveArgs& a, hipStream_t s);
 hipError_t launch_resident_sample(int N, const ResidentArgs& a, hipStream_t s);
 // Build the sampler's per-call coefficient tables (lambda = 1) for every problem.
 hipError_t launch_sampler_coefs(const ProbDev* probs, int n_problems, const float* d, const float* nbar,

@@ -372,7 +372,7 @@ __global__ void copy_out_pairs_kernel(SweepArgs a, int H, int W, float2* out) {
     }
 }
 
-__global__ void grad_d_kernel(SweepArgs a, int H, int W, float* grad_d) {
+__global__ void grad_d_kernel(SweepArgs a, int H, int W, const float* v, float* grad_d) {
     const int64_t n = (int64_t)H * W;
     const int64_t total = (int64_t)a.n_items * n;
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
@@ -383,7 +383,7 @@ __global__ void grad_d_kernel(SweepArgs a, int H, int W, float* grad_d) {
         const ProbDev pr = a.probs[it.prob];
         const float nb = a.nbar[pr.pix_off + i];
         // N^-1 v with N = Nbar + tau; 0 on missing pixels (Nbar = +inf)
-        grad_d[pr.pix_off + i] = a.field[it.field_off + i].x * __builtin_amdgcn_rcpf(nb + pr.tau);
+        grad_d[pr.pix_off + i] = v[pr.pix_off + i] * __builtin_amdgcn_rcpf(nb + pr.tau);
     }
 }
 
@@ -621,8 +621,8 @@ hipError_t launch_copy_out_pairs(int W, int H, const SweepArgs& a, float2* out, 
     return hipGetLastError();
 }
 
-hipError_t launch_grad_d(int W, int H, const SweepArgs& a, float* grad_d, hipStream_t s) {
-    hipLaunchKernelGGL(grad_d_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a, H, W,
+hipError_t launch_grad_d(int W, int H, const SweepArgs& a, const float* v, float* grad_d, hipStream_t s) {
+    hipLaunchKernelGGL(grad_d_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a, H, W, v,
                        grad_d);
     return hipGetLastError();
 }

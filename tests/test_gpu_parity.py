@@ -71,12 +71,13 @@ def test_thousand_sweeps_per_sample_parity(torch_cuda, form):
     assert worst < REL_TOL
 
 
-@pytest.mark.parametrize("size", [32, 128, 512])
-def test_wiener_fixed_schedule_matches_oracle(torch_cuda, size):
+@pytest.mark.parametrize("size,solve", [(32, "persistent"), (32, "streamed"), (64, "persistent"),
+                                        (128, "persistent"), (128, "streamed"), (512, "streamed")])
+def test_wiener_fixed_schedule_matches_oracle(torch_cuda, size, solve):
     mf = _mf()
-    banner(f"wiener fixed schedule {size}")
+    banner(f"wiener fixed schedule {size} {solve}")
     prob = synth.config_128(1, size) if size >= 64 else synth.config_small(1, size)
-    plan = mf.Plan([prob])
+    plan = mf.Plan([prob], streamed_solve=solve == "streamed")
     d = plan.concat([prob.d])
     levels = [(30.0, 5), (5.0, 5), (1.0, 40)]
     sch = mf.Schedule([l for l, _ in levels], [k for _, k in levels])
@@ -87,15 +88,16 @@ def test_wiener_fixed_schedule_matches_oracle(torch_cuda, size):
     assert r < REL_TOL
 
 
-def test_wiener_converges_to_dense_solve_32(torch_cuda):
+@pytest.mark.parametrize("solve", ["persistent", "streamed"])
+def test_wiener_converges_to_dense_solve_32(torch_cuda, solve):
     """Cooling 1e4 -> 1 over 100 levels, then sweeps at lambda = 1 down to the
     FP32 floor of the residual (about 3e-6 here; the Wiener error is ~100x the
     residual, so a residual tolerance cannot certify 1e-4 in FP32); the result
     is compared with the dense solve of Eq. 2."""
     mf = _mf()
-    banner("wiener converged vs dense 32")
+    banner(f"wiener converged vs dense 32 {solve}")
     prob = synth.config_small(0, 32)
-    plan = mf.Plan([prob])
+    plan = mf.Plan([prob], streamed_solve=solve == "streamed")
     d = plan.concat([prob.d])
     sch = mf.Schedule.geometric(1e4, 1.0, 100, 10, tol=1e-8, max_sweeps=6000, check_every=10)
     s, info = plan.wiener(d, sch, allow_not_converged=True)
@@ -107,12 +109,13 @@ def test_wiener_converges_to_dense_solve_32(torch_cuda):
     assert r < REL_TOL
 
 
-def test_residual_tracks_oracle(torch_cuda):
+@pytest.mark.parametrize("solve", ["persistent", "streamed"])
+def test_residual_tracks_oracle(torch_cuda, solve):
     """Residual test sweeps and the returned residual agree with the oracle."""
     mf = _mf()
-    banner("residual parity")
+    banner(f"residual parity {solve}")
     prob = synth.config_small(2, 32)
-    plan = mf.Plan([prob])
+    plan = mf.Plan([prob], streamed_solve=solve == "streamed")
     d = plan.concat([prob.d])
     s, info = plan.wiener(d, mf.Schedule([1.0], [0], 1e-3, 5000, 10))
     ref, rinfo = om.wiener(prob, om.Schedule((1.0,), (0,), 1e-3, 5000, 10))
@@ -180,12 +183,13 @@ def test_dispersed_init_matches_oracle(torch_cuda):
         assert rel(got[0, k], ref[0, k]) < REL_TOL and rel(got[1, k], ref[1, k]) < REL_TOL
 
 
-@pytest.mark.parametrize("size", [32, 64])
-def test_backward_matches_oracle_vjp(torch_cuda, size):
+@pytest.mark.parametrize("size,solve", [(32, "persistent"), (32, "streamed"), (64, "persistent"),
+                                        (64, "streamed")])
+def test_backward_matches_oracle_vjp(torch_cuda, size, solve):
     mf = _mf()
-    banner(f"backward {size}")
+    banner(f"backward {size} {solve}")
     prob = synth.config_bands(1, size, 32)
-    plan = mf.Plan([prob])
+    plan = mf.Plan([prob], streamed_solve=solve == "streamed")
     d = plan.concat([prob.d])
     sch_o = om.Schedule((1.0,), (0,), 1e-10, 100000, 10)
     s_ref, _ = om.wiener(prob, sch_o)
@@ -201,6 +205,47 @@ def test_backward_matches_oracle_vjp(torch_cuda, size):
     rb = float(np.max(np.abs(gb - gt_ref)) / np.max(np.abs(gt_ref)))
     print(f"info {info[0]} rel v {rv:.2e} grad_d {rd:.2e} bands {rb:.2e}")
     assert rv < 1e-3 and rd < 1e-3 and rb < 1e-3
+
+
+def test_persistent_solve_batch_levels_and_residuals(torch_cuda):
+    """Many problems of the persistent sizes (and one streamed size) in one plan,
+    a cooling schedule with a convergence phase: every problem's sweep count,
+    residual and image agree with the oracle's, so the per-problem stopping rule
+    runs independently in each workgroup."""
+    mf = _mf()
+    banner("persistent solve batch")
+    probs = synth.config_uneven(9, n_problems=10, sizes=(16, 32, 64, 128), weights=(0.1, 0.3, 0.3, 0.3))
+    plan = mf.Plan(probs)
+    d = plan.concat([p.d for p in probs])
+    levels = ((20.0, 3), (4.0, 3), (1.0, 4))
+    sch = mf.Schedule([l for l, _ in levels], [k for _, k in levels], 2e-3, 3000, 5)
+    s, info = plan.wiener(d, sch)
+    for i, p in enumerate(probs):
+        ref, rinfo = om.wiener(p, om.Schedule(tuple(l for l, _ in levels), tuple(k for _, k in levels),
+                                              2e-3, 3000, 5))
+        r = rel(plan.split(s)[i], ref)
+        print(f"problem {i} {p.H}: sweeps {info[i].sweeps}/{rinfo.sweeps} "
+              f"residual {info[i].residual:.4e}/{rinfo.residual:.4e} rel {r:.2e}")
+        assert info[i].converged and info[i].sweeps == rinfo.sweeps
+        assert abs(info[i].residual - rinfo.residual) < 1e-3 * rinfo.residual + 1e-6
+        assert r < REL_TOL
+
+
+@pytest.mark.parametrize("solve", ["persistent", "streamed"])
+def test_wiener_in_place_resume(torch_cuda, solve):
+    """s_init may be the output array: 20 sweeps, then 25 more started from
+    the first result, equal 45 sweeps of the oracle."""
+    mf = _mf()
+    banner(f"wiener resume in place {solve}")
+    prob = synth.config_128(4, 128)
+    plan = mf.Plan([prob], streamed_solve=solve == "streamed")
+    d = plan.concat([prob.d])
+    s, _ = plan.wiener(d, mf.Schedule.fixed(20))
+    s2, _ = plan.wiener(d, mf.Schedule.fixed(25), s_init=s, out=s)
+    ref, _ = om.wiener(prob, om.Schedule.fixed(45))
+    r = rel(plan.split(s2)[0], ref)
+    print(f"rel {r:.2e}")
+    assert s2.data_ptr() == s.data_ptr() and r < REL_TOL
 
 
 def test_band_power_matches_numpy(torch_cuda):
