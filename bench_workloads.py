@@ -3,9 +3,15 @@
 large  : 2048x2048 map (P=(k+1)^-2.2, smooth noise, disk footprint with 5%
          holes), 64 chains x 200 sweeps on the streamed path, every 20th state
          emitted; reports chain-sweeps/s and HBM GB/s of the sweep kernels.
+         Then the same map with the spectrum as 32 log bands: the unrolled
+         gradient of a 200-sweep cooled Wiener iteration (10 levels x 20) with
+         respect to d and the bands, a checkpoint every 20 sweeps, timed against
+         the forward iteration alone.
 uneven : 4096 problems of sizes {64,128,256,512}^2 at weights {.4,.3,.2,.1},
          per-problem spectra, noise and masks; one chain (pair) per problem,
-         500 sweeps, final states written; reports pixel-sweeps/s per class.
+         500 sweeps, final states written, column tiles picked by the
+         autotuner and the streamed sweep loops replayed as HIP graphs;
+         reports pixel-sweeps/s.
 grad   : 256x256 band-spectrum Wiener filter (32 bands) and its gradient
          (one adjoint solve); reports the gradient/forward time ratio.
 """
@@ -29,6 +35,7 @@ def _timed(fn, reps=1):
 
 
 def large(args):
+    import torch
     import paper_1810_02821_amd as mf
     from paper_1810_02821_amd import synth
     N, chains, sweeps, thin = 2048, 64, 200, 20
@@ -53,10 +60,27 @@ def large(args):
     sample_bytes = pairs * n_samples * 8 * n
     table_bytes = 12 * n
     gbps = (field_bytes + sample_bytes + table_bytes) / t / 1e9
+    del out, st, plan
+    print("[bench] large: unrolled gradient, 32 bands", file=sys.stderr, flush=True)
+    bprob = synth.config_large(0, N, n_bands=32)
+    bplan = mf.Plan([bprob])
+    bd = bplan.concat([bprob.d])
+    sch = mf.Schedule(list(np.geomspace(100.0, 1.0, 10)), [20] * 10)
+    g = bplan.concat([np.random.default_rng(8).standard_normal((N, N))])
+    s_out = torch.empty_like(bd)
+    fwd = lambda: bplan.wiener(bd, sch, out=s_out)
+    bwd = lambda: bplan.wiener_backward_unrolled(bd, g, sch, 20)
+    fwd()
+    bwd()
+    t_f = _timed(fwd, 2)
+    t_b = _timed(bwd, 2)
     print(json.dumps({"workload": "large", "metric": "chain-sweeps/s at 2048^2 (streamed, 64 chains)",
                       "value": chains * sweeps / t, "unit": "chain-sweeps/s", "seconds": t,
                       "hbm_algorithmic_GBps": gbps, "hbm_frac": gbps / 8000.0,
-                      "samples_per_s": chains * n_samples / t}), flush=True)
+                      "samples_per_s": chains * n_samples / t,
+                      "unrolled_gradient": {"sweeps": 200, "checkpoint_every": 20, "bands": 32,
+                                            "forward_s": t_f, "gradient_s": t_b,
+                                            "ratio": t_b / t_f}}), flush=True)
 
 
 def uneven(args):
@@ -67,7 +91,7 @@ def uneven(args):
     probs = synth.config_uneven(0, n_problems=4096)
     t_gen = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plan = mf.Plan(probs)
+    plan = mf.Plan(probs, autotune=True, graph=True)
     t_plan = time.perf_counter() - t0
     d = plan.concat([p.d for p in probs])
     st = plan.state_buffer(1)
@@ -83,7 +107,10 @@ def uneven(args):
     print(json.dumps({"workload": "uneven", "metric": "pixel-sweeps/s, 4096 uneven problems, 500 sweeps",
                       "value": total_px * sweeps / t, "unit": "pixel-sweeps/s (one chain per problem)",
                       "seconds": t, "problems_per_size": {int(s): int(np.sum(sizes == s)) for s in np.unique(sizes)},
-                      "plan_seconds": t_plan, "generate_seconds": t_gen}), flush=True)
+                      "plan_seconds": t_plan, "generate_seconds": t_gen,
+                      "graph": True, "autotune": True,
+                      "tile_shapes": {f"{s}x{s}": list(plan.tile_shape(int(s), int(s)))
+                                      for s in np.unique(sizes) if s >= 256}}), flush=True)
 
 
 def grad(args):

@@ -224,6 +224,12 @@ mf_status mf_wiener_backward_unrolled(mf_plan plan, const float* d, const mf_sch
 mf_status mf_band_power(mf_plan plan, const float* x, const float* y, double* out,
                         mf_stream stream);
 
+/* Column-kernel tile of the streamed size class H x W in use by the plan (the
+ * autotuner's choice under MF_FLAG_AUTOTUNE, else the default): *cols columns
+ * per workgroup of *threads threads.  MF_ERR_INVALID_ARG if the plan has no
+ * problem of that size. */
+mf_status mf_plan_tile_shape(mf_plan plan, int32_t H, int32_t W, int32_t* cols, int32_t* threads);
+
 /* Number of bands over all band-spectrum problems (length of grad_bands). */
 int32_t mf_plan_total_bands(mf_plan plan);
 

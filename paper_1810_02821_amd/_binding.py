@@ -67,7 +67,8 @@ class _SampleArgs(C.Structure):
 
 EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_plan_pixel_offset",
            "mf_plan_tau", "mf_plan_total_bands", "mf_wiener", "mf_sample", "mf_wiener_backward",
-           "mf_wiener_backward_unrolled", "mf_band_power", "mf_status_string", "mf_last_error"]
+           "mf_wiener_backward_unrolled", "mf_band_power", "mf_plan_tile_shape", "mf_status_string",
+           "mf_last_error"]
 
 _lib = None
 
@@ -100,11 +101,13 @@ def lib():
     L.mf_wiener_backward.argtypes = [vp, vp, vp, C.POINTER(_Schedule), vp, vp, vp, C.POINTER(Info), vp]
     L.mf_band_power.argtypes = [vp, vp, vp, vp, vp]
     L.mf_wiener_backward_unrolled.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_int32, vp, vp, vp, vp, vp]
+    L.mf_plan_tile_shape.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.mf_status_string.argtypes = [C.c_int]
     L.mf_status_string.restype = C.c_char_p
     L.mf_last_error.restype = C.c_char_p
     for name in ("mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_wiener",
-                 "mf_sample", "mf_wiener_backward", "mf_wiener_backward_unrolled", "mf_band_power"):
+                 "mf_sample", "mf_wiener_backward", "mf_wiener_backward_unrolled", "mf_band_power",
+                 "mf_plan_tile_shape"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -277,6 +280,20 @@ class Plan:
         import torch
         pairs = (chains + 1) // 2
         return torch.zeros(2 * pairs * self.total_pixels, dtype=torch.float32, device=device)
+
+    def tile_shape(self, H: int, W: int):
+        """(columns, threads) of the column-kernel tile used for size class H x W."""
+        c, t = C.c_int32(), C.c_int32()
+        _check(lib().mf_plan_tile_shape(self._h, int(H), int(W), C.byref(c), C.byref(t)))
+        return c.value, t.value
+
+    def state_view(self, flat, problem: int, chains: int):
+        """Complex pair states [pairs, H, W] of one problem in a state buffer."""
+        import torch
+        p = self.problems[problem]
+        pairs = (chains + 1) // 2
+        off = 2 * pairs * self.offsets[problem]
+        return torch.view_as_complex(flat[off:off + 2 * pairs * p.H * p.W].view(pairs, p.H, p.W, 2))
 
     def wiener_backward(self, s_wf, grad_s, schedule: Schedule, want_bands=True, want_v=False,
                         allow_not_converged=False):

@@ -859,6 +859,15 @@ double mf_plan_tau(mf_plan p, int32_t problem) {
 
 int32_t mf_plan_total_bands(mf_plan p) { return p ? p->total_bands : -1; }
 
+mf_status mf_plan_tile_shape(mf_plan p, int32_t H, int32_t W, int32_t* cols, int32_t* threads) {
+    if (!p || !cols || !threads) return fail(MF_ERR_INVALID_ARG, "plan, cols and threads are required");
+    if (!p->classes.count({H, W})) return fail(MF_ERR_INVALID_ARG, "the plan has no problem of that size");
+    const auto sh = class_shape(p, H, W);
+    *cols = sh.first;
+    *threads = sh.second;
+    return MF_OK;
+}
+
 mf_status mf_wiener(mf_plan p, const float* d, const mf_schedule* schedule, const float* s_init, float* s_out,
                     mf_info* info, mf_stream stream) {
     if (!p || !d || !s_out) return fail(MF_ERR_INVALID_ARG, "plan, d and s_out are required");

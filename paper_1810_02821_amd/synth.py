@@ -187,33 +187,42 @@ def config_uneven(seed: int = 0, n_problems: int = 4096,
     return out
 
 
-def config_bands(seed: int = 0, size: int = 256, n_bands: int = 32) -> Problem:
-    """Band-amplitude spectrum for differentiation: 32 log bands seeded from
-    P(k)=(k+1)^-2 at the mean |k| of each band, times U[0.8,1.2];
-    sigma~U[0.5,2]; 30% masked tiles."""
-    rng = np.random.default_rng(seed)
-    edges = log_band_edges(size, size, n_bands)
-    km = _kmag(size, size)
+def bands_from_powerlaw(H: int, W: int, n_bands: int, k0: float, n: float) -> Spectrum:
+    """Log bands (log_band_edges) with amplitude (k + k0)^-n at the mean |k|
+    of the modes in each band (the band midpoint for an empty band)."""
+    edges = log_band_edges(H, W, n_bands)
+    km = _kmag(H, W)
     idx = np.clip(np.searchsorted(edges, km, side="right") - 1, 0, n_bands - 1)
     amps = np.empty(n_bands)
     for b in range(n_bands):
         sel = km[idx == b]
         kc = sel.mean() if sel.size else 0.5 * (edges[b] + edges[b + 1])
-        amps[b] = (kc + 1.0) ** (-2.0)
-    amps *= rng.uniform(0.8, 1.2, size=n_bands)
-    spec = spectrum_bands(edges, amps)
+        amps[b] = (kc + k0) ** (-n)
+    return spectrum_bands(edges, amps)
+
+
+def config_bands(seed: int = 0, size: int = 256, n_bands: int = 32) -> Problem:
+    """Band-amplitude spectrum for differentiation: 32 log bands seeded from
+    P(k)=(k+1)^-2 at the mean |k| of each band, times U[0.8,1.2];
+    sigma~U[0.5,2]; 30% masked tiles."""
+    rng = np.random.default_rng(seed)
+    base = bands_from_powerlaw(size, size, n_bands, 1.0, 2.0)
+    spec = spectrum_bands(base.edges, base.amps * rng.uniform(0.8, 1.2, size=n_bands))
     sigma = _uniform_sigma(size, size, 0.5, 2.0, rng)
     mask = tile_mask(size, size, 0.30, rng)
     return make_problem(size, size, spec, sigma, mask, rng)
 
 
-def config_large(seed: int = 0, size: int = 2048) -> Problem:
+def config_large(seed: int = 0, size: int = 2048, n_bands: int = 0) -> Problem:
     """Large map: P=(k+1)^-2.2; sigma = 2^(cos(2 pi x/N) cos(2 pi y/N)) in
     [0.5, 2]; observed central disk of radius 0.45 N (outside masked) with
-    random radius-3 holes until 5% of the disk is masked."""
+    random radius-3 holes until 5% of the disk is masked.  n_bands > 0 gives
+    the spectrum as that many log bands of the same power law (for gradients
+    with respect to band amplitudes)."""
     rng = np.random.default_rng(seed)
     N = size
-    spec = spectrum_powerlaw(1.0, 1.0, 2.2)
+    spec = (bands_from_powerlaw(N, N, n_bands, 1.0, 2.2) if n_bands > 0
+            else spectrum_powerlaw(1.0, 1.0, 2.2))
     y, x = np.mgrid[0:N, 0:N].astype(np.float64)
     sigma = 2.0 ** (np.cos(2 * np.pi * x / N) * np.cos(2 * np.pi * y / N))
     c = (N - 1) / 2.0

@@ -141,6 +141,12 @@ def test_autotuned_shapes_give_identical_samples(torch_cuda):
     d = base.concat([p.d for p in probs])
     a, _ = base.sample(d, 5, chains=2, burn_in=1, n_samples=2, form="streamed")
     b, _ = tuned.sample(d, 5, chains=2, burn_in=1, n_samples=2, form="streamed")
+    shapes = {p.H: (base.tile_shape(p.H, p.W), tuned.tile_shape(p.H, p.W)) for p in probs}
+    print("default / tuned column tiles:", shapes)
+    defaults = {256: (16, 256), 512: (16, 512), 1024: (16, 1024), 2048: (8, 1024)}
+    for H, (dflt, tuned_shape) in shapes.items():
+        assert dflt == defaults[H]
+        assert tuned_shape[0] in (4, 8, 16) and tuned_shape[1] in (256, 512, 1024)
     assert torch.equal(a, b)
 
 
