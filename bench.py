@@ -38,14 +38,14 @@ PEAK_FP32_TFLOPS = 157.3
 # FETCH_SIZE / WRITE_SIZE runs scaled by the same counters on a 1 GiB copy, and
 # the hash of the kernel sources it was measured on (traffic is reported only
 # while the sources are unchanged).
-TRAFFIC_BYTES = int((81173.75 * 2.0 + 6492839.0 * 1.0) * 1024)  # FETCH x2.0 + WRITE x1.0 (copy-calibrated)
-TRAFFIC_SOURCES_SHA = "6680614397d08baf"
+TRAFFIC_BYTES = int((19319.8125 * 2.0 + 6488199.125 * 1.0) * 1024)  # FETCH x2.0 + WRITE x1.0 (copy-calibrated)
+TRAFFIC_SOURCES_SHA = "8ff5f83433d0a592"
 
 
 def kernel_sources_sha() -> str:
     import hashlib
     h = hashlib.sha256()
-    for f in ("mf_resident.hip", "mf_device.hpp", "mf_resident.hpp"):
+    for f in ("mf_resident.hip", "mf_resident_fft.hpp", "mf_device.hpp", "mf_resident.hpp"):
         with open(os.path.join(ROOT, "paper_1810_02821_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="paper", choices=["paper", "large", "uneven", "grad"],
+    ap.add_argument("--workload", default="paper", choices=["paper", "large", "uneven", "grad", "solve"],
                     help="paper (default, the headline line) or one of the other measured workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to scale HBM counters)")

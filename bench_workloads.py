@@ -14,6 +14,10 @@ uneven : 4096 problems of sizes {64,128,256,512}^2 at weights {.4,.3,.2,.1},
          reports pixel-sweeps/s.
 grad   : 256x256 band-spectrum Wiener filter (32 bands) and its gradient
          (one adjoint solve); reports the gradient/forward time ratio.
+solve  : Wiener filters of 256 independent 128x128 images (the paper-size
+         recipe, one seed each): 20 cooling levels x 10 sweeps, then sweeps at
+         lambda = 1 to a residual of 1e-5 tested every 10 sweeps; the persistent
+         solve kernel against the streamed kernels (host-side residual test).
 """
 from __future__ import annotations
 
@@ -138,5 +142,34 @@ def grad(args):
                       "loss_and_grad_s": t_all, "sweeps_per_solve": 3300}), flush=True)
 
 
+def solve(args):
+    import torch
+    import paper_1810_02821_amd as mf
+    from paper_1810_02821_amd import synth
+    n_problems = 256
+    print("[bench] solve: generating 256 problems", file=sys.stderr, flush=True)
+    probs = [synth.config_128(i, 128) for i in range(n_problems)]
+    sch = mf.Schedule(list(np.geomspace(1e3, 1.0, 20)) + [1.0], [10] * 20 + [0], tol=1e-5, max_sweeps=4000,
+                      check_every=10)
+    res = {}
+    for form in ("persistent", "streamed"):
+        plan = mf.Plan(probs, streamed_solve=form == "streamed")
+        d = plan.concat([p.d for p in probs])
+        out = torch.empty_like(d)
+        run = lambda: plan.wiener(d, sch, out=out, allow_not_converged=True)
+        _, info = run()
+        print(f"[bench] solve: timing {form}", file=sys.stderr, flush=True)
+        t = _timed(run, 2)
+        sweeps = sum(i.sweeps for i in info)
+        res[form] = {"seconds": t, "problem_sweeps": sweeps, "pixel_sweeps_per_s": sweeps * 128 * 128 / t,
+                     "converged": sum(i.converged for i in info), "mean_sweeps": sweeps / n_problems}
+        del plan
+    print(json.dumps({"workload": "solve", "metric": "Wiener-filter pixel-sweeps/s, 256 x 128^2, to residual 1e-5",
+                      "value": res["persistent"]["pixel_sweeps_per_s"], "unit": "pixel-sweeps/s",
+                      "persistent": res["persistent"], "streamed": res["streamed"],
+                      "speedup_vs_streamed": res["streamed"]["seconds"] / res["persistent"]["seconds"]}),
+          flush=True)
+
+
 def run(args):
-    {"large": large, "uneven": uneven, "grad": grad}[args.workload](args)
+    {"large": large, "uneven": uneven, "grad": grad, "solve": solve}[args.workload](args)

@@ -66,7 +66,7 @@ typedef enum {
     MF_ERR_OUT_OF_MEMORY = 3,    /* a plan table or workspace could not be allocated */
     MF_ERR_DEVICE = 4,           /* a HIP runtime call failed */
     MF_ERR_NOT_CONVERGED = 5,    /* tol > 0 not reached within max_sweeps (result still written) */
-    MF_ERR_NONFINITE = 6         /* a NaN/Inf appeared in an output */
+    MF_ERR_NONFINITE = 6         /* a solve's residual test saw NaN/Inf (that problem stops; outputs written) */
 } mf_status;
 
 /* Power spectrum P(|k|) of the signal (Eq. 9). */
@@ -172,7 +172,8 @@ double mf_plan_tau(mf_plan plan, int32_t problem);
  * check_every sweeps (never on the first sweep of the phase), the residual
  * ||t_k - t_{k-1}|| / (T ||b||) of Sec. 2.2 in FP64, b = N_eff^-1 d at that level.
  * Returns MF_ERR_NOT_CONVERGED if any problem missed tol (s_out still holds the
- * last iterate). */
+ * last iterate), MF_ERR_NONFINITE if a tested residual was NaN or Inf (NaN in
+ * the data of an observed pixel, say); that problem's iteration stops there. */
 mf_status mf_wiener(mf_plan plan, const float* d, const mf_schedule* schedule,
                     const float* s_init, float* s_out, mf_info* info, mf_stream stream);
 

@@ -345,11 +345,14 @@ mf_status solve_class(mf_plan p, const std::vector<int>& pids, int H, int W, con
                 for (int y = 0; y < H; ++y) acc += part[(size_t)y * a.n_items + i];
                 const int pid = live[i].prob;
                 const double T = lam * p->probs[pid].tau;
-                const double r = bnorm2[pid] > 0 ? std::sqrt(acc) / (T * std::sqrt(bnorm2[pid])) : 0.0;
+                const double r = bnorm2[pid] == 0.0 ? 0.0 : std::sqrt(acc) / (T * std::sqrt(bnorm2[pid]));
                 info[pid].residual = r;
                 info[pid].sweeps = total;
                 if (r <= sch->tol) {
                     info[pid].converged = 1;
+                    conv.push_back(live[i]);
+                } else if (!std::isfinite(r)) {
+                    info[pid].converged = -1;  // non-finite: stop iterating this problem
                     conv.push_back(live[i]);
                 } else {
                     keep.push_back(live[i]);
@@ -520,12 +523,19 @@ mf_status run_solve(mf_plan p, const float* src, int src_kind, const mf_schedule
         if ((st = solve_class(p, kv.second, H, W, src, src_kind, sch, s_init, bn, info, s)) != MF_OK) return st;
         if ((st = copy_class_real(p, kv.second, H, W, out, s)) != MF_OK) return st;
     }
-    bool all = true;
-    for (auto& i : info) all = all && i.converged;
+    bool all = true, finite = true;
+    for (auto& i : info) {
+        if (i.converged < 0) {
+            finite = false;
+            i.converged = 0;
+        }
+        all = all && i.converged;
+    }
     if (info_out) {
         MF_HIP(hipStreamSynchronize(s));
         std::copy(info.begin(), info.end(), info_out);
     }
+    if (!finite) return fail(MF_ERR_NONFINITE, "the residual test saw a non-finite value");
     if (!all) return fail(MF_ERR_NOT_CONVERGED, "tolerance not reached within max_sweeps");
     return MF_OK;
 }

@@ -45,7 +45,7 @@ struct SolveArgs {
     double tol;               // residual tolerance of the final level (<= 0: none)
     int32_t max_sweeps;
     int32_t check_every;
-    double* info;             // [item][3]: sweeps run, converged flag, last residual (NaN if none)
+    double* info;             // [item][3]: sweeps run, converged (1, 0, or -1 non-finite), last residual
 };
 
 bool resident_supported(int H, int W);

@@ -248,6 +248,28 @@ def test_wiener_in_place_resume(torch_cuda, solve):
     assert s2.data_ptr() == s.data_ptr() and r < REL_TOL
 
 
+@pytest.mark.parametrize("solve", ["persistent", "streamed"])
+def test_nonfinite_data_is_reported(torch_cuda, solve):
+    """NaN in the data of an observed pixel: the residual test stops that
+    problem and the call returns MF_ERR_NONFINITE; a clean problem in the same
+    batch still converges to the oracle's result."""
+    mf = _mf()
+    banner(f"non-finite data {solve}")
+    probs = [synth.config_small(3, 32), synth.config_small(4, 32)]
+    plan = mf.Plan(probs, streamed_solve=solve == "streamed")
+    bad = probs[0].d.copy()
+    y, x = np.argwhere(~probs[0].mask)[5]
+    bad[y, x] = np.nan
+    d = plan.concat([bad, probs[1].d])
+    sch = mf.Schedule([1.0], [0], 1e-3, 2000, 10)
+    out = torch_cuda.empty_like(d)
+    with pytest.raises(mf.MFError) as e:
+        plan.wiener(d, sch, out=out)
+    assert e.value.status == 6
+    ref, _ = om.wiener(probs[1], om.Schedule((1.0,), (0,), 1e-3, 2000, 10))
+    assert rel(plan.split(out)[1], ref) < REL_TOL
+
+
 def test_band_power_matches_numpy(torch_cuda):
     mf = _mf()
     prob = synth.config_bands(2, 64, 32)
