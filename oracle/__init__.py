@@ -17,11 +17,14 @@ Data with Dataflow Engines"):
                   stationary law of the Gibbs chain;
 * ``adjoint``   - gradients of the Wiener-filter map with respect to the data
                   and to band amplitudes of the power spectrum (implicit
-                  differentiation of the normal equations of Eq. 7).
+                  differentiation of the normal equations of Eq. 7);
+* ``spectrum``  - the power-spectrum Gibbs step of Sec. 5 (inverse-gamma band
+                  amplitudes given the signal) and the hierarchical sampler
+                  that alternates it with Algorithm 1.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import it.  It shares no code with the GPU path and never
 imports it; the two meet only through the seeded inputs of
 ``paper_1810_02821_amd.synth``.
 """
-from . import philox, messenger, dense, adjoint  # noqa: F401
+from . import philox, messenger, dense, adjoint, spectrum  # noqa: F401

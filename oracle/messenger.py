@@ -64,7 +64,7 @@ def power_spectrum(spectrum, H: int, W: int) -> np.ndarray:
     if spectrum.kind == "bands":
         edges = np.asarray(spectrum.edges, dtype=np.float64)
         amps = np.asarray(spectrum.amps, dtype=np.float64)
-        out = np.empty_like(k)
+        out = np.zeros_like(k)  # a mode outside every band has no signal power
         for b in range(len(amps)):
             lo, hi = edges[b], edges[b + 1]
             sel = (k >= lo) & ((k < hi) | ((b == len(amps) - 1) & (k <= hi)))

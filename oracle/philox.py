@@ -21,8 +21,10 @@ Stream layout (one Philox call per two elements):
     counter = (elem >> 1, sweep, (problem << 8) | stage, pair)
     words (x0, x1) -> (z0, z1) of element 2j, words (x2, x3) -> element 2j+1
 where `elem` is the row-major index of a pixel (stage 0, messenger draw) or
-of a Fourier mode in unshifted FFT order (stage 1, signal draw), and stage 2
-is the dispersed initial state.  For a chain pair, z0 feeds chain 2*pair and
+of a Fourier mode in unshifted FFT order (stage 1, signal draw), stage 2
+is the dispersed initial state, and stage 3 holds the chi-square variates of
+the power-spectrum draw (elem = flat index over the bands' degrees of
+freedom, sweep = the Gibbs iteration).  For a chain pair, z0 feeds chain 2*pair and
 z1 chain 2*pair+1 (stage 0, 2) or the real and imaginary parts of the mode's
 complex variate (stage 1).
 """
@@ -42,6 +44,7 @@ ROUNDS = 10
 STAGE_PIXEL = 0
 STAGE_HARMONIC = 1
 STAGE_INIT = 2
+STAGE_SPECTRUM = 3
 
 
 def philox4x32(ctr, key, rounds: int = ROUNDS):
