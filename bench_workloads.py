@@ -14,6 +14,10 @@ uneven : 4096 problems of sizes {64,128,256,512}^2 at weights {.4,.3,.2,.1},
          reports pixel-sweeps/s.
 grad   : 256x256 band-spectrum Wiener filter (32 bands) and its gradient
          (one adjoint solve); reports the gradient/forward time ratio.
+spectrum: the hierarchical sampler (signal + 32 band amplitudes) on the
+         128x128 band-spectrum recipe: 1024 chains, 100 iterations of one
+         messenger sweep and one amplitude draw each; reports chain-iterations/s
+         next to the fixed-spectrum sampler's chain-sweeps/s on the same image.
 solve  : Wiener filters of 256 independent 128x128 images (the paper-size
          recipe, one seed each): 20 cooling levels x 10 sweeps, then sweeps at
          lambda = 1 to a residual of 1e-5 tested every 10 sweeps; the persistent
@@ -171,5 +175,29 @@ def solve(args):
           flush=True)
 
 
+def spectrum(args):
+    import torch
+    import paper_1810_02821_amd as mf
+    from paper_1810_02821_amd import synth
+    prob = synth.config_bands(0, 128, 32)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    chains, iters = 1024, 100
+    st = plan.state_buffer(chains)
+    run_h = lambda: plan.sample_spectrum(d, 1000, chains, 0, iters, 1, 1, state_out=st)
+    run_s = lambda: plan.sample(d, 1000, chains=chains, burn_in=iters, n_samples=0, form="persistent",
+                                state_out=st, samples=False)
+    run_h()
+    run_s()
+    print("[bench] spectrum: timing", file=sys.stderr, flush=True)
+    t_h = _timed(run_h, max(1, args.steps // 2))
+    t_s = _timed(run_s, max(1, args.steps // 2))
+    print(json.dumps({"workload": "spectrum",
+                      "metric": "chain-iterations/s, hierarchical sampler at 128^2 (32 bands, 1024 chains)",
+                      "value": chains * iters / t_h, "unit": "chain-iterations/s", "seconds": t_h,
+                      "fixed_spectrum_chain_sweeps_per_s": chains * iters / t_s,
+                      "cost_ratio_vs_fixed_spectrum": t_h / t_s}), flush=True)
+
+
 def run(args):
-    {"large": large, "uneven": uneven, "grad": grad, "solve": solve}[args.workload](args)
+    {"large": large, "uneven": uneven, "grad": grad, "solve": solve, "spectrum": spectrum}[args.workload](args)

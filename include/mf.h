@@ -143,6 +143,20 @@ typedef struct {
     int32_t form;              /* MF_FORM_* */
 } mf_sample_args;
 
+/* Arguments of mf_sample_spectrum. */
+typedef struct {
+    uint64_t seed;             /* Philox key */
+    int32_t chains_per_problem;/* >= 1; pairs = ceil(chains / 2) */
+    int32_t burn_in;           /* iterations before the first sample (>= 0) */
+    int32_t n_samples;         /* samples per chain (>= 0) */
+    int32_t thin;              /* iterations per sample after burn-in (>= 1) */
+    int32_t sweeps_per_draw;   /* messenger sweeps per iteration, before each spectrum draw (>= 1) */
+    int32_t prior_dof;         /* nu_0: inverse-gamma prior of shape nu_0/2 on each band amplitude */
+    double prior_beta;         /* beta_0 >= 0: its scale (nu_0 = beta_0 = 0: Jeffreys' 1/theta) */
+    int64_t iteration_offset;  /* global index of the first iteration (for resuming a chain) */
+    float init_scale;          /* > 0: dispersed start as in mf_sample (ignored if state_in) */
+} mf_spectrum_args;
+
 /* Create a plan for n_problems problems (Algorithm 1's definitions: tau, Nbar,
  * n P(|k|) evaluated in FP64 and stored in FP32, FFT twiddles evaluated in FP64).
  * Copies all tables to the current device.  *out receives the plan. */
@@ -187,6 +201,33 @@ mf_status mf_wiener(mf_plan plan, const float* d, const mf_schedule* schedule,
 mf_status mf_sample(mf_plan plan, const float* d, const mf_sample_args* args,
                     const float* state_in, float* state_out, float* samples_out,
                     mf_stream stream);
+
+/* Hierarchical sampler (Sec. 5): samples of the signal and of the band
+ * amplitudes theta_b of the power spectrum.  Every problem needs a band
+ * spectrum and H = W in {32, 64, 128}.  Iteration i (global g = iteration_offset
+ * + i) runs sweeps_per_draw sweeps of Algorithm 1 (global sweep indices
+ * g * sweeps_per_draw + k) with the current amplitudes, then draws each band
+ * amplitude from its conditional given the signal,
+ *     theta_b | s ~ InvGamma((m_b + nu_0)/2, beta_0 + sigma_b / (2 n^2)),
+ * m_b the modes of band b, sigma_b = sum_{k in b} |s_k|^2 (unnormalised DFT);
+ * the draw is (2 beta_0 + sigma_b / n^2) / x with x the sum of m_b + nu_0
+ * squared normals from stream stage 3 (a band with no degrees of freedom, or
+ * a zero sum, keeps its amplitude).  Each chain has its own amplitudes.  A
+ * sample is (s, theta) after iteration i when i >= burn_in and (i - burn_in +
+ * 1) is a multiple of thin.
+ *   d                  device, concatenated float32 data
+ *   state_in/out       device, pair states as in mf_sample, or NULL
+ *   theta_in/out       device float64 [problem][2 * pairs][band] (problem p starts at
+ *                      2 * pairs * band_base(p), band_base = the problem's first band
+ *                      in plan order), or NULL; theta_in NULL starts from the plan's
+ *                      amplitudes
+ *   samples_out        device float32, as in mf_sample, or NULL
+ *   theta_samples_out  device float64 [problem][chain][sample][band] (problem p starts at
+ *                      chains * n_samples * band_base(p)), or NULL */
+mf_status mf_sample_spectrum(mf_plan plan, const float* d, const mf_spectrum_args* args,
+                             const float* state_in, const double* theta_in, float* state_out,
+                             double* theta_out, float* samples_out, double* theta_samples_out,
+                             mf_stream stream);
 
 /* Vector-Jacobian product of the Wiener-filter map (d, P) -> s_W by implicit
  * differentiation of the normal equations (S^-1 + N^-1) s_W = N^-1 d read off

@@ -65,9 +65,17 @@ class _SampleArgs(C.Structure):
                 ("init_scale", C.c_float), ("form", C.c_int32)]
 
 
+class _SpectrumArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("chains_per_problem", C.c_int32), ("burn_in", C.c_int32),
+                ("n_samples", C.c_int32), ("thin", C.c_int32), ("sweeps_per_draw", C.c_int32),
+                ("prior_dof", C.c_int32), ("prior_beta", C.c_double), ("iteration_offset", C.c_int64),
+                ("init_scale", C.c_float)]
+
+
 EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_plan_pixel_offset",
            "mf_plan_tau", "mf_plan_total_bands", "mf_wiener", "mf_sample", "mf_wiener_backward",
-           "mf_wiener_backward_unrolled", "mf_band_power", "mf_plan_tile_shape", "mf_status_string",
+           "mf_wiener_backward_unrolled", "mf_band_power", "mf_plan_tile_shape", "mf_sample_spectrum",
+           "mf_status_string",
            "mf_last_error"]
 
 _lib = None
@@ -102,12 +110,13 @@ def lib():
     L.mf_band_power.argtypes = [vp, vp, vp, vp, vp]
     L.mf_wiener_backward_unrolled.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_int32, vp, vp, vp, vp, vp]
     L.mf_plan_tile_shape.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.mf_sample_spectrum.argtypes = [vp, vp, C.POINTER(_SpectrumArgs), vp, vp, vp, vp, vp, vp, vp]
     L.mf_status_string.argtypes = [C.c_int]
     L.mf_status_string.restype = C.c_char_p
     L.mf_last_error.restype = C.c_char_p
     for name in ("mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_wiener",
                  "mf_sample", "mf_wiener_backward", "mf_wiener_backward_unrolled", "mf_band_power",
-                 "mf_plan_tile_shape"):
+                 "mf_plan_tile_shape", "mf_sample_spectrum"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -280,6 +289,46 @@ class Plan:
         import torch
         pairs = (chains + 1) // 2
         return torch.zeros(2 * pairs * self.total_pixels, dtype=torch.float32, device=device)
+
+    @property
+    def band_offsets(self):
+        """First band of each problem in concatenated band arrays (plan order)."""
+        out, o = [], 0
+        for p in self.problems:
+            out.append(o)
+            if p.spectrum.kind == "bands":
+                o += len(p.spectrum.amps)
+        return out + [o]
+
+    def sample_spectrum(self, d, seed: int, chains: int, burn_in: int, n_samples: int, thin: int = 1,
+                        sweeps_per_draw: int = 1, prior_dof: int = 0, prior_beta: float = 0.0,
+                        iteration_offset: int = 0, init_scale: float = 0.0, state_in=None, theta_in=None,
+                        state_out=None, theta_out=None, samples=False, theta_samples=True):
+        """Hierarchical sampler (signal and band amplitudes).  Returns
+        (theta samples [concat over problems of chains*n_samples*bands] float64 or
+        None, signal samples or None, state_out, theta_out)."""
+        import torch
+        dev = d.device
+        pairs = (chains + 1) // 2
+        if theta_out is None:
+            theta_out = torch.empty(2 * pairs * self.total_bands, dtype=torch.float64, device=dev)
+        ts = None
+        if theta_samples and n_samples > 0:
+            ts = torch.empty(chains * n_samples * self.total_bands, dtype=torch.float64, device=dev)
+        smp = self.samples_buffer(chains, n_samples, dev) if samples and n_samples > 0 else None
+        args = _SpectrumArgs(int(seed), int(chains), int(burn_in), int(n_samples), int(thin),
+                             int(sweeps_per_draw), int(prior_dof), float(prior_beta), int(iteration_offset),
+                             float(init_scale))
+        _check(lib().mf_sample_spectrum(self._h, _ptr(d), C.byref(args), _ptr(state_in), _ptr(theta_in),
+                                        _ptr(state_out), _ptr(theta_out), _ptr(smp), _ptr(ts), _stream()))
+        return ts, smp, state_out, theta_out
+
+    def theta_view(self, flat, problem: int, chains: int, n_samples: int):
+        """Band-amplitude samples [chains, n_samples, bands] of one problem."""
+        b0, b1 = self.band_offsets[problem], self.band_offsets[problem + 1]
+        nb = b1 - b0
+        off = chains * n_samples * b0
+        return flat[off:off + chains * n_samples * nb].view(chains, n_samples, nb)
 
     def tile_shape(self, H: int, W: int):
         """(columns, threads) of the column-kernel tile used for size class H x W."""

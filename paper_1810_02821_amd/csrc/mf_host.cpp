@@ -43,6 +43,7 @@ struct HostProblem {
     int n_bands = 0;
     int band_base = 0;
     std::vector<double> edges, amps;
+    std::vector<int32_t> band_modes;  // modes per band (band spectra)
     double amp = 1, k0 = 1, n = 2;
 };
 
@@ -90,6 +91,7 @@ struct mf_plan_s {
     DevBuf items, field, t_save, partials, aux, coef;
     DevBuf field_adj, ckpt, tstore, slots;  // unrolled-gradient workspaces
     DevBuf sched;                           // persistent solve: levels, sweeps, per-item outcome
+    DevBuf spec;                            // hierarchical sampler: dof and start amplitudes per band
     std::vector<mf::ItemDev> items_cached;  // what items[0..] holds (skip re-uploads)
     // column-kernel tile shape per size class: (H, W) -> (tc, nth)
     std::map<std::pair<int, int>, std::pair<int, int>> col_shape;
@@ -122,6 +124,7 @@ struct mf_plan_s {
         tstore.release();
         slots.release();
         sched.release();
+        spec.release();
         for (auto& g : graphs) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
             if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -182,7 +185,8 @@ mf_status copy_spectrum(HostProblem& hp, const mf_spectrum& s, int pidx) {
 
 // Upload n P(|k|) (FP64 -> FP32) for one problem; also its band map and scales.
 mf_status upload_spectrum(mf_plan p, int i) {
-    const HostProblem& hp = p->probs[i];
+    HostProblem& hp = p->probs[i];
+    hp.band_modes.assign(hp.n_bands, 0);
     const int H = hp.H, W = hp.W;
     const double n = (double)H * W;
     std::vector<float> nP((size_t)H * W);
@@ -194,7 +198,11 @@ mf_status upload_spectrum(mf_plan p, int i) {
             if (!(P > 0) || !std::isfinite(n * P))
                 return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": P(k) must be finite and > 0 on every mode");
             nP[(size_t)ky * W + kx] = (float)(n * P);
-            if (hp.kind == MF_PK_BANDS) band[(size_t)ky * W + kx] = (int16_t)band_of(hp, k);
+            if (hp.kind == MF_PK_BANDS) {
+                const int b = band_of(hp, k);
+                band[(size_t)ky * W + kx] = (int16_t)b;
+                if (b >= 0) ++hp.band_modes[b];
+            }
         }
     MF_HIP(hipMemcpy(p->d_nP + hp.pix_off, nP.data(), nP.size() * sizeof(float), hipMemcpyHostToDevice));
     MF_HIP(hipMemcpy(p->d_band + hp.pix_off, band.data(), band.size() * sizeof(int16_t), hipMemcpyHostToDevice));
@@ -1144,6 +1152,103 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
                 st = sample_streamed(p, di + i, 1, H, W, d, g, work, sin, samples_out, s);
         }
         if (st != MF_OK) return st;
+    }
+    return MF_OK;
+}
+
+mf_status mf_sample_spectrum(mf_plan p, const float* d, const mf_spectrum_args* g, const float* state_in,
+                             const double* theta_in, float* state_out, double* theta_out, float* samples_out,
+                             double* theta_samples_out, mf_stream stream) {
+    if (!p || !d || !g) return fail(MF_ERR_INVALID_ARG, "plan, d and args are required");
+    if (g->chains_per_problem < 1 || g->burn_in < 0 || g->n_samples < 0 || g->thin < 1 || g->sweeps_per_draw < 1 ||
+        g->iteration_offset < 0 || !(g->prior_beta >= 0) || !std::isfinite(g->prior_beta))
+        return fail(MF_ERR_INVALID_ARG,
+                    "need chains >= 1, burn_in >= 0, n_samples >= 0, thin >= 1, sweeps_per_draw >= 1, "
+                    "iteration_offset >= 0, prior_beta >= 0");
+    const int64_t iters = (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin;
+    if ((g->iteration_offset + iters) * (int64_t)g->sweeps_per_draw > 0xffffffffLL)
+        return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
+    for (size_t i = 0; i < p->probs.size(); ++i) {
+        const HostProblem& hp = p->probs[i];
+        if (hp.kind != MF_PK_BANDS)
+            return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + " has no band spectrum");
+        if (!mf::resident_supported(hp.H, hp.W))
+            return fail(MF_ERR_UNSUPPORTED_SIZE, "the hierarchical sampler needs H = W in {32, 64, 128}");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const int pairs = (g->chains_per_problem + 1) / 2;
+    float2* work;
+    if (state_out) {
+        work = reinterpret_cast<float2*>(state_out);
+    } else {
+        MF_HIP(p->field.ensure((size_t)p->total_px * pairs * sizeof(float2)));
+        work = p->field.as<float2>();
+    }
+    // per-band degrees of freedom and start amplitudes
+    const int nbt = p->total_bands;
+    std::vector<int32_t> dof(nbt);
+    std::vector<double> th0(nbt);
+    for (const HostProblem& hp : p->probs)
+        for (int b = 0; b < hp.n_bands; ++b) {
+            dof[hp.band_base + b] = std::max(0, hp.band_modes[b] + g->prior_dof);
+            th0[hp.band_base + b] = hp.amps[b];
+        }
+    MF_HIP(p->spec.ensure((size_t)nbt * (sizeof(double) + sizeof(int32_t))));
+    double* d_th0 = p->spec.as<double>();
+    int32_t* d_dof = reinterpret_cast<int32_t*>(d_th0 + nbt);
+    MF_HIP(hipMemcpyAsync(d_th0, th0.data(), (size_t)nbt * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP(hipMemcpyAsync(d_dof, dof.data(), (size_t)nbt * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    // pixel tables of the sampler (the pixel step does not depend on the spectrum)
+    const size_t half = (size_t)p->total_px / 2;
+    MF_HIP(p->coef.ensure(half * (sizeof(float4) + sizeof(float2) + sizeof(float4))));
+    float4* pcoef = p->coef.as<float4>();
+    float2* psrc = reinterpret_cast<float2*>(pcoef + half);
+    float4* mcoef = reinterpret_cast<float4*>(psrc + half);
+    MF_HIP(mf::launch_sampler_coefs(p->d_probs, (int)p->probs.size(), d, p->d_nbar, p->d_nP, pcoef, psrc, mcoef, s));
+    size_t max_items = 0;
+    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size() * (size_t)pairs);
+    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
+    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
+    MF_HIP(hipStreamSynchronize(s));  // the host staging vectors die on return
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first;
+        std::vector<mf::ItemDev> items;
+        for (int pid : kv.second)
+            for (int q = 0; q < pairs; ++q)
+                items.push_back({pid, q, (int64_t)pairs * p->probs[pid].pix_off + (int64_t)q * H * H});
+        mf::ItemDev* di = nullptr;
+        mf_status st = put_items(p, items, 0, s, &di);
+        if (st != MF_OK) return st;
+        mf::SpectrumArgs r{};
+        r.probs = p->d_probs;
+        r.items = di;
+        r.n_items = (int)items.size();
+        r.field = work;
+        r.state_in = reinterpret_cast<const float2*>(state_in);
+        r.init_scale = g->init_scale;
+        r.pcoef = pcoef;
+        r.psrc = psrc;
+        r.tw = p->d_tw.at(H);
+        r.key0 = (uint32_t)(g->seed & 0xffffffffu);
+        r.key1 = (uint32_t)(g->seed >> 32);
+        r.iter0 = (uint32_t)g->iteration_offset;
+        r.sweeps = g->sweeps_per_draw;
+        r.burn_in = g->burn_in;
+        r.n_samples = g->n_samples;
+        r.thin = g->thin;
+        r.samples = samples_out;
+        r.chains = g->chains_per_problem;
+        r.chains_pad = 2 * pairs;
+        r.band = p->d_band;
+        r.band_base = p->d_band_base;
+        r.band_count = p->d_band_count;
+        r.dof = d_dof;
+        r.theta0 = d_th0;
+        r.theta_in = theta_in;
+        r.theta_out = theta_out;
+        r.theta_samples = theta_samples_out;
+        r.prior_beta = g->prior_beta;
+        MF_HIP(mf::launch_resident_spectrum(H, r, s));
     }
     return MF_OK;
 }
