@@ -15,6 +15,7 @@
 #include "../../include/mf.h"
 #include "mf_kernels.hpp"
 #include "mf_resident.hpp"
+#include "mf_spectrum.hpp"
 
 namespace {
 

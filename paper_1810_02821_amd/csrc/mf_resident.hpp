@@ -48,37 +48,7 @@ struct SolveArgs {
     double* info;             // [item][3]: sweeps run, converged (1, 0, or -1 non-finite), last residual
 };
 
-// Hierarchical sampler: Algorithm 1 alternated with the band-amplitude draw.
-struct SpectrumArgs {
-    const ProbDev* probs;
-    const ItemDev* items;     // one per (problem, pair)
-    int32_t n_items;
-    float2* field;            // final pair states
-    const float2* state_in;   // start states or null
-    float init_scale;
-    const float4* pcoef;      // sampler pixel tables (lambda = 1)
-    const float2* psrc;
-    const float2* tw;         // W_N^r, r < N
-    uint32_t key0, key1;
-    uint32_t iter0;           // global index of the first iteration
-    int32_t sweeps;           // messenger sweeps per iteration
-    int32_t burn_in, n_samples, thin;
-    float* samples;           // [problem][chain][sample][H][W] or null
-    int32_t chains;           // chains per problem
-    int32_t chains_pad;       // 2 * pairs: chain slots of theta_in / theta_out
-    const int16_t* band;      // per-mode band index (concatenated)
-    const int32_t* band_base; // first band of each problem
-    const int32_t* band_count;// bands of each problem
-    const int32_t* dof;       // degrees of freedom per band (concatenated)
-    const double* theta0;     // plan amplitudes per band (start when theta_in is null)
-    const double* theta_in;   // [problem][chain_pad][band] or null
-    double* theta_out;        // [problem][chain_pad][band] or null
-    double* theta_samples;    // [problem][chain][sample][band] or null
-    double prior_beta;
-};
-
 bool resident_supported(int H, int W);
-hipError_t launch_resident_spectrum(int N, const SpectrumArgs& a, hipStream_t s);
 hipError_t launch_resident_solve(int N, const SolveArgs& a, hipStream_t s);
 hipError_t launch_resident_sample(int N, const ResidentArgs& a, hipStream_t s);
 // Build the sampler's per-call coefficient tables (lambda = 1) for every problem.

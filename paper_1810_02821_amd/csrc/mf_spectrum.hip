@@ -19,6 +19,7 @@
 #include "mf_device.hpp"
 #include "mf_resident.hpp"
 #include "mf_resident_fft.hpp"
+#include "mf_spectrum.hpp"
 
 namespace mf {
 
