@@ -33,7 +33,7 @@ def adjoint_solve(problem, gbar, schedule: messenger.Schedule, nP=None):
     """v = (S^-1 + N^-1)^-1 gbar by the messenger iteration."""
     g = np.asarray(gbar, dtype=np.float64)
     return messenger.solve(problem.noise_var, problem.spectrum, lambda c: g,
-                           schedule, None, nP)
+                           schedule, None, nP, messenger.response_of(problem))
 
 
 def band_cross_power(x, y, edges, H, W):
@@ -53,8 +53,8 @@ def wiener_vjp(problem, s_wf, gbar, schedule: messenger.Schedule = None, solver:
         info = it
     else:
         v, info = adjoint_solve(problem, gbar, schedule)
-    c = messenger.coefficients(problem.noise_var, problem.spectrum, 1.0)
-    grad_d = c.ninv * v
+    c = messenger.coefficients(problem.noise_var, problem.spectrum, 1.0, None, messenger.response_of(problem))
+    grad_d = c.ninv * v  # A^T N^-1 v
     grad_theta = None
     if problem.spectrum.kind == "bands":
         H, W = problem.H, problem.W
@@ -89,7 +89,7 @@ def unrolled_vjp(problem, schedule: messenger.Schedule, gbar):
     s = np.zeros((H, W))
     tape = []
     for lam in level_sequence(schedule):
-        c = messenger.coefficients(problem.noise_var, problem.spectrum, lam)
+        c = messenger.coefficients(problem.noise_var, problem.spectrum, lam, None, messenger.response_of(problem))
         s_new, t = messenger.sweep(s, c.ninv * d, c)
         tape.append((t, c))
         s = s_new
@@ -107,7 +107,7 @@ def unrolled_vjp(problem, schedule: messenger.Schedule, gbar):
             contrib = np.real(np.conj(F_sbar) * np.fft.fft2(t)) * c.T / (c.nP + c.T) ** 2
             gtheta += np.array([contrib[idx == b].sum() for b in range(nb)])
         tbar = np.fft.ifft2(c.f * F_sbar).real
-        dbar += c.a * tbar
+        dbar += c.T * c.ninv * tbar  # dt/dd = T A^T N_eff^-1 (= a when A = I)
         sbar = (1.0 - c.a) * tbar
     return s, dbar, (gtheta if bands else None)
 
@@ -144,7 +144,9 @@ def unrolled_vjp_torch(problem, schedule: messenger.Schedule, gbar):
 
 def loss_terms(problem, s_wf, s_true):
     """L = 1/2 s^T S^-1 s + 1/2 (d-s)^T N^-1 (d-s) + 1/2 sum_k ln(n P_k)
-           + 1/2 ||s - s_true||^2  at s = s_wf."""
+           + 1/2 ||s - s_true||^2  at s = s_wf (A = I)."""
+    if messenger.response_of(problem) is not None:
+        raise ValueError("the loss is defined for A = I")
     c = messenger.coefficients(problem.noise_var, problem.spectrum, 1.0)
     d = np.where(problem.mask, 0.0, problem.d)
     prior = 0.5 * float(np.sum(s_wf * messenger.apply_S_inverse(s_wf, c)))
@@ -159,6 +161,8 @@ def loss_grad(problem, s_wf, s_true, schedule: messenger.Schedule = None, solver
 
     At the Wiener solution the prior + likelihood part is stationary in s, so
     only the L2 term sends a gradient through s*: gbar = s* - s_true."""
+    if messenger.response_of(problem) is not None:
+        raise ValueError("the loss is defined for A = I")
     H, W = problem.H, problem.W
     n = H * W
     c = messenger.coefficients(problem.noise_var, problem.spectrum, 1.0)

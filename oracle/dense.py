@@ -63,30 +63,44 @@ def signal_covariance(spectrum, H: int, W: int) -> np.ndarray:
     return c[dy, dx]
 
 
-def effective_noise(noise_var: np.ndarray, lam: float = 1.0, tau: float = None) -> np.ndarray:
-    """N + (lam - 1) tau on observed pixels (the noise a cooling level sees)."""
-    obs = np.isfinite(noise_var)
+def _observed_rows(noise_var, response):
+    nv = noise_var.ravel()
+    obs = np.isfinite(nv)
+    A = np.ones_like(nv) if response is None else np.asarray(response, dtype=np.float64).ravel()
+    obs = obs & (A != 0)
+    return nv, obs, A
+
+
+def effective_noise(noise_var: np.ndarray, lam: float = 1.0, tau: float = None,
+                    response=None) -> np.ndarray:
+    """N + (lam - 1) tau A^2 on observed pixels (the noise a cooling level sees,
+    tau = min N / A^2)."""
+    nv, obs, A = _observed_rows(noise_var, response)
+    obs = obs.reshape(noise_var.shape)
+    A = A.reshape(noise_var.shape)
     if tau is None:
-        tau = float(np.min(noise_var[obs])) if obs.any() else 1.0
-    return np.where(obs, noise_var + (lam - 1.0) * tau, np.inf)
+        tau = float(np.min(noise_var[obs] / A[obs] ** 2)) if obs.any() else 1.0
+    return np.where(obs, noise_var + (lam - 1.0) * tau * A * A, np.inf)
 
 
-def wiener_dense(S: np.ndarray, noise_var: np.ndarray, d: np.ndarray) -> np.ndarray:
-    """Eq. 2-3 with A = selector of observed pixels."""
-    nv = noise_var.ravel()
-    obs = np.isfinite(nv)
-    So = S[np.ix_(obs, obs)] + np.diag(nv[obs])
+def wiener_dense(S: np.ndarray, noise_var: np.ndarray, d: np.ndarray, response=None) -> np.ndarray:
+    """Eq. 2-3, s_W = S A^T (A S A^T + N)^-1 d over the observed rows of the
+    diagonal response A (identity when None; missing pixels drop out)."""
+    nv, obs, A = _observed_rows(noise_var, response)
+    Ao = A[obs]
+    So = Ao[:, None] * S[np.ix_(obs, obs)] * Ao[None, :] + np.diag(nv[obs])
     x = scipy.linalg.solve(So, d.ravel()[obs], assume_a="pos")
-    return (S[:, obs] @ x).reshape(noise_var.shape)
+    return (S[:, obs] @ (Ao * x)).reshape(noise_var.shape)
 
 
-def posterior_covariance(S: np.ndarray, noise_var: np.ndarray) -> np.ndarray:
+def posterior_covariance(S: np.ndarray, noise_var: np.ndarray, response=None) -> np.ndarray:
     """(S^-1 + A^T N_o^-1 A)^-1 = S - S A^T (A S A^T + N_o)^-1 A S  (Eq. 7)."""
-    nv = noise_var.ravel()
-    obs = np.isfinite(nv)
-    So = S[np.ix_(obs, obs)] + np.diag(nv[obs])
-    X = scipy.linalg.solve(So, S[obs, :], assume_a="pos")
-    C = S - S[:, obs] @ X
+    nv, obs, A = _observed_rows(noise_var, response)
+    Ao = A[obs]
+    So = Ao[:, None] * S[np.ix_(obs, obs)] * Ao[None, :] + np.diag(nv[obs])
+    SA = S[:, obs] * Ao[None, :]
+    X = scipy.linalg.solve(So, SA.T, assume_a="pos")
+    C = S - SA @ X
     return 0.5 * (C + C.T)
 
 

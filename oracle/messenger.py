@@ -99,26 +99,46 @@ class Coefficients:
     vk: np.ndarray       # nP T/(nP+T), eigenvalues of (S^-1 + T^-1)^-1
 
 
-def messenger_tau(noise_var: np.ndarray) -> float:
-    """tau = min over observed pixels of N_i (T = min(N) I); 1.0 when every
-    pixel is missing (any T works then: the chain samples the prior)."""
+def observed(noise_var: np.ndarray, response: Optional[np.ndarray] = None) -> np.ndarray:
+    """Pixels that carry data: finite noise and, with a response A, A_i != 0."""
     obs = np.isfinite(noise_var)
+    if response is not None:
+        obs = obs & (np.asarray(response) != 0)
+    return obs
+
+
+def messenger_tau(noise_var: np.ndarray, response: Optional[np.ndarray] = None) -> float:
+    """tau = min over observed pixels of N_i / A_i^2, the diagonal of
+    (A^-1)^dagger N A^-1 (T = tau I under Algorithm 1); 1.0 when every pixel
+    is missing (any T works then: the chain samples the prior)."""
+    obs = observed(noise_var, response)
     if not obs.any():
         return 1.0
-    return float(np.min(noise_var[obs]))
+    A2 = 1.0 if response is None else np.asarray(response, dtype=np.float64)[obs] ** 2
+    return float(np.min(noise_var[obs] / A2))
 
 
 def coefficients(noise_var: np.ndarray, spectrum, lam: float = 1.0,
-                 nP: Optional[np.ndarray] = None) -> Coefficients:
+                 nP: Optional[np.ndarray] = None,
+                 response: Optional[np.ndarray] = None) -> Coefficients:
+    """Coefficients of Algorithm 1's definitions with a diagonal A (identity
+    when `response` is None): Nbar_i = N_i - tau A_i^2, and on observed pixels
+        mu_i^t = T A_i d_i / (T A_i^2 + Nbar_i) + Nbar_i s_i / (T A_i^2 + Nbar_i),
+        (sigma_i^t)^2 = T Nbar_i / (T A_i^2 + Nbar_i),
+    i.e. a = T A^2 / (T A^2 + Nbar), mu = (1 - a) s + T b with
+    b = A d / (T A^2 + Nbar) = A^T N_eff^-1 d, sigma_t^2 = T (1 - a)."""
     H, W = noise_var.shape
     n = H * W
-    tau = messenger_tau(noise_var)
+    obs = observed(noise_var, response)
+    A = np.ones((H, W)) if response is None else np.asarray(response, dtype=np.float64)
+    tau = messenger_tau(noise_var, response)
     T = float(lam) * tau
-    nbar = np.where(np.isfinite(noise_var), noise_var - tau, np.inf)
-    with np.errstate(invalid="ignore"):
-        a = np.where(np.isfinite(nbar), T / (T + nbar), 0.0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        nbar = np.where(obs, noise_var - tau * A * A, np.inf)
+        den = np.where(obs, T * A * A + nbar, np.inf)
+        a = np.where(obs, T * A * A / den, 0.0)
+        ninv = np.where(obs, A / den, 0.0)
     sig_t = np.sqrt(T * (1.0 - a))
-    ninv = a / T
     if nP is None:
         nP = n * power_spectrum(spectrum, H, W)
     f = nP / (nP + T)
@@ -126,6 +146,10 @@ def coefficients(noise_var: np.ndarray, spectrum, lam: float = 1.0,
     w = np.sqrt(n * vk)
     return Coefficients(tau=tau, T=T, a=a, sig_t=sig_t, ninv=ninv, nP=nP,
                         f=f, w=w, vk=vk)
+
+
+def response_of(problem) -> Optional[np.ndarray]:
+    return getattr(problem, "response", None)
 
 
 def pixel_step(s, b, c: Coefficients, xi=None):
@@ -205,7 +229,7 @@ def _norm(x) -> float:
 
 
 def solve(noise_var, spectrum, rhs_of, schedule: Schedule, s0=None,
-          nP: Optional[np.ndarray] = None):
+          nP: Optional[np.ndarray] = None, response: Optional[np.ndarray] = None):
     """Deterministic messenger iteration with right-hand side b = rhs_of(c)
     at each cooling level.  Returns (s, WienerInfo)."""
     H, W = noise_var.shape
@@ -213,7 +237,7 @@ def solve(noise_var, spectrum, rhs_of, schedule: Schedule, s0=None,
     total = 0
     c = None
     for lam, k in zip(schedule.lambdas, schedule.sweeps):
-        c = coefficients(noise_var, spectrum, lam, nP)
+        c = coefficients(noise_var, spectrum, lam, nP, response)
         b = rhs_of(c)
         for _ in range(int(k)):
             s, _ = sweep(s, b, c)
@@ -221,7 +245,7 @@ def solve(noise_var, spectrum, rhs_of, schedule: Schedule, s0=None,
     residual = float("nan")
     converged = schedule.tol <= 0
     if schedule.tol > 0:
-        c = coefficients(noise_var, spectrum, schedule.lambdas[-1], nP)
+        c = coefficients(noise_var, spectrum, schedule.lambdas[-1], nP, response)
         b = rhs_of(c)
         bnorm = _norm(b)
         t_prev = None
@@ -242,16 +266,17 @@ def wiener(problem, schedule: Schedule, s0=None, nP=None):
     """Wiener filter of one problem by the messenger iteration."""
     d = np.where(problem.mask, 0.0, problem.d)
     return solve(problem.noise_var, problem.spectrum, lambda c: c.ninv * d,
-                 schedule, s0, nP)
+                 schedule, s0, nP, response_of(problem))
 
 
 def residual(problem, s, lam: float = 1.0) -> float:
     """Relative residual ||(S^-1 + N_eff^-1) s - N_eff^-1 d|| / ||N_eff^-1 d||
     of the normal equations (Eq. 7) at cooling level lam, by definition."""
-    c = coefficients(problem.noise_var, problem.spectrum, lam)
+    c = coefficients(problem.noise_var, problem.spectrum, lam, None, response_of(problem))
     d = np.where(problem.mask, 0.0, problem.d)
     b = c.ninv * d
-    r = apply_S_inverse(s, c) + c.ninv * s - b
+    A = 1.0 if response_of(problem) is None else response_of(problem)
+    r = apply_S_inverse(s, c) + c.ninv * A * s - b
     return _norm(r) / _norm(b)
 
 
@@ -261,16 +286,18 @@ def wiener_cg(problem, tol: float = 1e-12, max_iter: int = 20000, lam: float = 1
     gradients on the S-preconditioned form (I + S^1/2 N^-1 S^1/2) x = S^1/2 b,
     s = S^1/2 x.  A second, independent route to the same fixed point for images
     too large for dense algebra; S^1/2 is diagonal in Fourier space."""
-    c = coefficients(problem.noise_var, problem.spectrum, lam)
+    c = coefficients(problem.noise_var, problem.spectrum, lam, None, response_of(problem))
     d = np.where(problem.mask, 0.0, problem.d)
     b = c.ninv * d if rhs is None else np.asarray(rhs, dtype=np.float64)
+    A = 1.0 if response_of(problem) is None else response_of(problem)
+    prec = c.ninv * A  # A^T N_eff^-1 A
     sq = np.sqrt(c.nP)
 
     def half(x):  # S^1/2 x
         return np.fft.ifft2(sq * np.fft.fft2(x)).real
 
     def op(x):
-        return x + half(c.ninv * half(x))
+        return x + half(prec * half(x))
 
     rhs_x = half(b)
     x = np.zeros_like(rhs_x)
@@ -323,7 +350,7 @@ def sample_pair(problem, seed: int, problem_index: int, pair: int,
     k >= burn_in and (k - burn_in + 1) is a multiple of thin."""
     H, W = problem.H, problem.W
     if c is None:
-        c = coefficients(problem.noise_var, problem.spectrum, 1.0)
+        c = coefficients(problem.noise_var, problem.spectrum, 1.0, None, response_of(problem))
     d = np.where(problem.mask, 0.0, problem.d)
     b = c.ninv * d
     s = np.zeros((H, W), dtype=np.complex128) if s0 is None else np.array(s0, dtype=np.complex128)
@@ -348,7 +375,7 @@ def sample(problem, seed: int, problem_index: int, n_chains: int,
     """Samples [n_chains, n_samples, H, W]; chain 2p / 2p+1 = Re / Im of pair p."""
     H, W = problem.H, problem.W
     n_pairs = (n_chains + 1) // 2
-    c = coefficients(problem.noise_var, problem.spectrum, 1.0)
+    c = coefficients(problem.noise_var, problem.spectrum, 1.0, None, response_of(problem))
     out = np.empty((n_chains, n_samples, H, W))
     for p in (range(n_pairs) if pairs is None else pairs):
         s0 = initial_state(seed, problem_index, p, H, W, init_scale)

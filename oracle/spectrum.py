@@ -93,7 +93,7 @@ def chain_coefficients(problem, theta: np.ndarray) -> messenger.Coefficients:
     H, W = problem.H, problem.W
     spec = type("S", (), {"kind": "bands", "edges": np.asarray(problem.spectrum.edges),
                           "amps": np.asarray(theta, dtype=np.float64)})()
-    return messenger.coefficients(problem.noise_var, spec, 1.0)
+    return messenger.coefficients(problem.noise_var, spec, 1.0, None, messenger.response_of(problem))
 
 
 def chain_sweep(sA, sB, d, cA: messenger.Coefficients, cB: messenger.Coefficients, xi, eta):

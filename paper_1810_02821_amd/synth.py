@@ -121,6 +121,7 @@ class Problem:
     mask: np.ndarray         # bool (H, W), True = missing
     spectrum: Spectrum
     s_true: np.ndarray       # float64 (H, W), the generating field
+    response: Optional[np.ndarray] = None  # float64 (H, W) diagonal A of d = A s + n, None = identity
 
     @property
     def n(self) -> int:
@@ -135,6 +136,24 @@ def make_problem(H: int, W: int, spectrum: Spectrum, sigma: np.ndarray,
     nv = np.where(mask, np.inf, sigma ** 2)
     return Problem(H=H, W=W, d=d, noise_var=nv, mask=mask.copy(),
                    spectrum=spectrum, s_true=s)
+
+
+def config_response(seed: int = 0, size: int = 128, dead: float = 0.01) -> Problem:
+    """The paper-size recipe seen through a diagonal instrument response:
+    d = A s + n with A_i ~ U[0.5, 1.5] (gain / exposure variation), a fraction
+    `dead` of pixels with A_i = 0 (no response), and 25% masked 4x4 tiles."""
+    rng = np.random.default_rng(seed)
+    spec = spectrum_powerlaw(1.0, 2.0, 2.5)
+    sigma = _uniform_sigma(size, size, 0.3, 3.0, rng)
+    mask = tile_mask(size, size, 0.25, rng)
+    A = rng.uniform(0.5, 1.5, size=(size, size))
+    A[rng.random((size, size)) < dead] = 0.0
+    s = grf(size, size, spec, rng)
+    noise = sigma * rng.standard_normal((size, size))
+    missing = mask | (A == 0.0)
+    d = np.where(missing, 0.0, A * s + noise)
+    nv = np.where(mask, np.inf, sigma ** 2)
+    return Problem(H=size, W=size, d=d, noise_var=nv, mask=missing, spectrum=spec, s_true=s, response=A)
 
 
 def philox_seed(data_seed: int) -> int:
