@@ -79,11 +79,16 @@ typedef struct {
     const double* band_amps;   /* host, n_bands values > 0 */
 } mf_spectrum;
 
-/* One image problem. */
+/* One image problem, d = A s + n (Eq. 1) with a diagonal A. */
 typedef struct {
     int32_t H, W;              /* image size; each a power of two in [16, 2048] */
     const float* noise_var;    /* host, H*W: N_i > 0, +INFINITY marks a missing pixel */
     mf_spectrum spectrum;
+    const float* response;     /* host, H*W: the diagonal of A (finite; 0 = a pixel without
+                                  response), or NULL for A = I.  Algorithm 1's definitions
+                                  then use tau = min N_i / A_i^2 and Nbar_i = N_i - tau A_i^2;
+                                  every entry point takes d and returns dL/dd in the units of
+                                  the data, and the plan works with d_i / A_i and N_i / A_i^2 */
 } mf_problem;
 
 /* Cooling schedule of the Wiener filter (zero-variate Algorithm 1).
@@ -233,7 +238,7 @@ mf_status mf_sample_spectrum(mf_plan plan, const float* d, const mf_spectrum_arg
  * differentiation of the normal equations (S^-1 + N^-1) s_W = N^-1 d read off
  * Eq. 7: v solves (S^-1 + N^-1) v = grad_s by the messenger iteration (pixel
  * step t = (1 - a) v + T grad_s), then
- *   grad_d     = N^-1 v (0 on missing pixels)                     device, concatenated
+ *   grad_d     = A^T N^-1 v (0 on missing pixels; N^-1 v when A = I) device, concatenated
  *   grad_bands = sum_{k in b} Re(conj(v_k) s_k) / (n^2 theta_b^2)  device float64,
  *                bands of every band-spectrum problem concatenated (NULL allowed)
  * with v_k, s_k the unnormalised DFTs of v and s_wf.  grad_bands needs s_wf.

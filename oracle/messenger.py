@@ -134,7 +134,8 @@ def coefficients(noise_var: np.ndarray, spectrum, lam: float = 1.0,
     tau = messenger_tau(noise_var, response)
     T = float(lam) * tau
     with np.errstate(invalid="ignore", divide="ignore"):
-        nbar = np.where(obs, noise_var - tau * A * A, np.inf)
+        # Nbar >= 0 by the choice of tau; the clamp removes the rounding of (N/A^2) A^2
+        nbar = np.where(obs, np.maximum(noise_var - tau * A * A, 0.0), np.inf)
         den = np.where(obs, T * A * A + nbar, np.inf)
         a = np.where(obs, T * A * A / den, 0.0)
         ninv = np.where(obs, A / den, 0.0)

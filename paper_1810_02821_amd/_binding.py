@@ -43,7 +43,7 @@ class _Spectrum(C.Structure):
 
 class _Problem(C.Structure):
     _fields_ = [("H", C.c_int32), ("W", C.c_int32), ("noise_var", C.POINTER(C.c_float)),
-                ("spectrum", _Spectrum)]
+                ("spectrum", _Spectrum), ("response", C.POINTER(C.c_float))]
 
 
 class _Schedule(C.Structure):
@@ -195,7 +195,13 @@ class Plan:
             nv = np.ascontiguousarray(p.noise_var, dtype=np.float32)
             spec, k = _spectrum_c(p.spectrum)
             keep += [nv, k]
-            arr[i] = _Problem(int(p.H), int(p.W), nv.ctypes.data_as(C.POINTER(C.c_float)), spec)
+            resp = getattr(p, "response", None)
+            rp = None
+            if resp is not None:
+                r = np.ascontiguousarray(resp, dtype=np.float32)
+                keep.append(r)
+                rp = r.ctypes.data_as(C.POINTER(C.c_float))
+            arr[i] = _Problem(int(p.H), int(p.W), nv.ctypes.data_as(C.POINTER(C.c_float)), spec, rp)
         h = C.c_void_p()
         flags = ((MF_FLAG_AUTOTUNE if autotune else 0) | (MF_FLAG_GRAPH if graph else 0)
                  | (MF_FLAG_STREAMED_SOLVE if streamed_solve else 0))

@@ -105,6 +105,9 @@ struct mf_plan_s {
     std::vector<GraphEntry> graphs;
     hipStream_t cap_stream = nullptr;
     std::vector<float> host_nbar;    // for residual norms
+    bool has_response = false;       // some problem has a diagonal A != I
+    float* d_rinv = nullptr;         // 1 / A_i per pixel (0 without response), when has_response
+    DevBuf dprime;                   // d / A of the current call
     ~mf_plan_s() {
         (void)hipFree(d_probs);
         (void)hipFree(d_nbar);
@@ -113,6 +116,8 @@ struct mf_plan_s {
         (void)hipFree(d_band_base);
         (void)hipFree(d_band_count);
         (void)hipFree(d_band_scale);
+        (void)hipFree(d_rinv);
+        dprime.release();
         for (auto& kv : d_tw) (void)hipFree(kv.second);
         items.release();
         field.release();
@@ -431,6 +436,23 @@ mf_status rhs_norms(mf_plan p, const float* src, int src_kind, double lam, std::
         }
         out[i] = acc;
     }
+    return MF_OK;
+}
+
+// The data the kernels see: d itself, or d / A when some problem has a response.
+mf_status plan_data(mf_plan p, const float* d, hipStream_t s, const float** out) {
+    *out = d;
+    if (!p->has_response) return MF_OK;
+    MF_HIP(p->dprime.ensure((size_t)p->total_px * sizeof(float)));
+    MF_HIP(mf::launch_scale(d, p->d_rinv, p->dprime.as<float>(), p->total_px, s));
+    *out = p->dprime.as<float>();
+    return MF_OK;
+}
+
+// dL/dd from dL/d(d/A): multiply by 1/A in place.
+mf_status data_gradient(mf_plan p, float* g, hipStream_t s) {
+    if (!p->has_response || !g) return MF_OK;
+    MF_HIP(mf::launch_scale(g, p->d_rinv, g, p->total_px, s));
     return MF_OK;
 }
 
@@ -773,25 +795,40 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
     p->total_bands = bands;
     p->host_nbar.resize(off);
     std::vector<mf::ProbDev> pd(n_problems);
+    std::vector<float> rinv;
+    for (int i = 0; i < n_problems; ++i) p->has_response = p->has_response || problems[i].response;
+    if (p->has_response) rinv.assign(off, 1.0f);
+    std::vector<double> neff;
     for (int i = 0; i < n_problems; ++i) {
         HostProblem& hp = p->probs[i];
         const float* nv = problems[i].noise_var;
+        const float* A = problems[i].response;
         double tau = INFINITY;
         const int64_t n = (int64_t)hp.H * hp.W;
+        // with a response, the plan holds the A = I problem for d/A and N/A^2
+        neff.assign(n, INFINITY);
         for (int64_t e = 0; e < n; ++e) {
             const float v = nv[e];
             if (std::isnan(v) || v <= 0.f) {
                 delete p;
                 return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": noise variances must be > 0 (+inf = missing)");
             }
-            if (std::isfinite(v)) tau = std::min(tau, (double)v);
+            double a = 1.0;
+            if (A) {
+                a = A[e];
+                if (!std::isfinite(a)) {
+                    delete p;
+                    return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + ": response values must be finite");
+                }
+                rinv[hp.pix_off + e] = a != 0.0 ? (float)(1.0 / a) : 0.0f;
+            }
+            if (std::isfinite(v) && a != 0.0) neff[e] = (double)v / (a * a);
+            if (std::isfinite(neff[e])) tau = std::min(tau, neff[e]);
         }
         if (!std::isfinite(tau)) tau = 1.0;  // every pixel missing: any T samples the prior
         hp.tau = tau;
-        for (int64_t e = 0; e < n; ++e) {
-            const float v = nv[e];
-            p->host_nbar[hp.pix_off + e] = std::isfinite(v) ? (float)((double)v - tau) : INFINITY;
-        }
+        for (int64_t e = 0; e < n; ++e)
+            p->host_nbar[hp.pix_off + e] = std::isfinite(neff[e]) ? (float)(neff[e] - tau) : INFINITY;
         pd[i] = {hp.H, hp.W, hp.pix_off, (float)tau, i};
     }
     std::vector<int32_t> bb(n_problems), bc(n_problems);
@@ -819,6 +856,10 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
     MF_TRY(hipMemcpy(p->d_nbar, p->host_nbar.data(), off * sizeof(float), hipMemcpyHostToDevice));
     MF_TRY(hipMemcpy(p->d_band_base, bb.data(), n_problems * sizeof(int32_t), hipMemcpyHostToDevice));
     MF_TRY(hipMemcpy(p->d_band_count, bc.data(), n_problems * sizeof(int32_t), hipMemcpyHostToDevice));
+    if (p->has_response) {
+        MF_TRY(hipMalloc(&p->d_rinv, off * sizeof(float)));
+        MF_TRY(hipMemcpy(p->d_rinv, rinv.data(), off * sizeof(float), hipMemcpyHostToDevice));
+    }
 #undef MF_TRY
     for (int i = 0; i < n_problems; ++i) {
         mf_status st = upload_spectrum(p, i);
@@ -890,7 +931,10 @@ mf_status mf_plan_tile_shape(mf_plan p, int32_t H, int32_t W, int32_t* cols, int
 mf_status mf_wiener(mf_plan p, const float* d, const mf_schedule* schedule, const float* s_init, float* s_out,
                     mf_info* info, mf_stream stream) {
     if (!p || !d || !s_out) return fail(MF_ERR_INVALID_ARG, "plan, d and s_out are required");
-    return run_solve(p, d, mf::kSrcData, schedule, s_init, s_out, info, (hipStream_t)stream);
+    const float* dd = nullptr;
+    mf_status st = plan_data(p, d, (hipStream_t)stream, &dd);
+    if (st != MF_OK) return st;
+    return run_solve(p, dd, mf::kSrcData, schedule, s_init, s_out, info, (hipStream_t)stream);
 }
 
 mf_status mf_wiener_backward(mf_plan p, const float* s_wf, const float* grad_s, const mf_schedule* schedule,
@@ -933,6 +977,7 @@ mf_status mf_wiener_backward(mf_plan p, const float* s_wf, const float* grad_s, 
         MF_HIP(mf::launch_band_power(W, H, a, v, s_wf, p->d_band, p->d_band_base, p->d_band_count,
                                      p->d_band_scale, grad_bands, s));
     }
+    if ((st = data_gradient(p, grad_d, s)) != MF_OK) return st;
     return conv;
 }
 
@@ -945,6 +990,7 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
     if (sch->tol > 0) return fail(MF_ERR_INVALID_ARG, "the unrolled gradient needs a fixed sweep count (tol <= 0)");
     if (C < 1) return fail(MF_ERR_INVALID_ARG, "checkpoint_every must be >= 1");
     hipStream_t s = (hipStream_t)stream;
+    if ((st = plan_data(p, d, s, &d)) != MF_OK) return st;
     std::vector<double> lam;
     for (int j = 0; j < sch->n_levels; ++j)
         for (int k = 0; k < sch->sweeps[j]; ++k) lam.push_back(sch->lambda[j]);
@@ -1044,7 +1090,7 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
         if (grad_bands && p->total_bands > 0)
             MF_HIP(mf::launch_band_slots_reduce(W, H, sh.first, r, p->d_band_base, p->d_band_count, grad_bands, s));
     }
-    return MF_OK;
+    return data_gradient(p, grad_d, s);
 }
 
 mf_status mf_band_power(mf_plan p, const float* x, const float* y, double* out, mf_stream stream) {
@@ -1081,6 +1127,10 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
     if (g->n_samples > 0 && !samples_out && !state_out)
         return fail(MF_ERR_INVALID_ARG, "nothing to write: samples_out and state_out are NULL");
     hipStream_t s = (hipStream_t)stream;
+    {
+        const mf_status st0 = plan_data(p, d, s, &d);
+        if (st0 != MF_OK) return st0;
+    }
     const int pairs = (g->chains_per_problem + 1) / 2;
     const size_t field_elems = (size_t)p->total_px * pairs;
     float2* work;
@@ -1177,6 +1227,10 @@ mf_status mf_sample_spectrum(mf_plan p, const float* d, const mf_spectrum_args* 
             return fail(MF_ERR_UNSUPPORTED_SIZE, "the hierarchical sampler needs H = W in {32, 64, 128}");
     }
     hipStream_t s = (hipStream_t)stream;
+    {
+        const mf_status st0 = plan_data(p, d, s, &d);
+        if (st0 != MF_OK) return st0;
+    }
     const int pairs = (g->chains_per_problem + 1) / 2;
     float2* work;
     if (state_out) {

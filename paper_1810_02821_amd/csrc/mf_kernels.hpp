@@ -88,6 +88,8 @@ hipError_t launch_init_items(int W, int H, const SweepArgs& a, const float2* sta
                              hipStream_t s);
 hipError_t launch_copy_out_real(int W, int H, const SweepArgs& a, float* out, hipStream_t s);
 hipError_t launch_copy_out_pairs(int W, int H, const SweepArgs& a, float2* out, hipStream_t s);
+// y[i] = x[i] * r[i] for i < n (y may be x).
+hipError_t launch_scale(const float* x, const float* r, float* y, int64_t n, hipStream_t s);
 hipError_t launch_grad_d(int W, int H, const SweepArgs& a, const float* v, float* grad_d, hipStream_t s);
 hipError_t launch_load_real(int W, int H, const SweepArgs& a, const float* s_init, hipStream_t s);
 // Band cross-power of two real fields per item (a.partials must hold

@@ -387,6 +387,11 @@ __global__ void grad_d_kernel(SweepArgs a, int H, int W, const float* v, float* 
     }
 }
 
+__global__ void scale_kernel(const float* x, const float* r, float* y, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] = x[e] * r[e];
+}
+
 // Pack z = x + i y into the field so one complex FFT gives both spectra.
 __global__ void pack_pair_kernel(SweepArgs a, int H, int W, const float* x, const float* y) {
     const int64_t n = (int64_t)H * W;
@@ -618,6 +623,11 @@ hipError_t launch_copy_out_real(int W, int H, const SweepArgs& a, float* out, hi
 hipError_t launch_copy_out_pairs(int W, int H, const SweepArgs& a, float2* out, hipStream_t s) {
     hipLaunchKernelGGL(copy_out_pairs_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a,
                        H, W, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_scale(const float* x, const float* r, float* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(scale_kernel, elementwise_grid(n), dim3(256), 0, s, x, r, y, n);
     return hipGetLastError();
 }
 
