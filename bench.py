@@ -190,6 +190,16 @@ def main():
     traffic = TRAFFIC_BYTES if TRAFFIC_SOURCES_SHA == kernel_sources_sha() else None
 
     extra = {}
+    # per-pixel mean and variance of the step's samples (the maps of Fig. 3)
+    plan.sample_moments(out, CHAINS, N_SAMPLES)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    plan.sample_moments(out, CHAINS, N_SAMPLES)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    mom_ms = e0.elapsed_time(e1)
+    extra["sample_moments"] = {"ms": mom_ms, "GBps": samples_per_step * n_pix * 4 / (mom_ms / 1000.0) / 1e9}
     if not args.no_plain:
         # plain form: one chain pair per launch sequence, field in HBM between kernels
         sub_chains = 8

@@ -234,6 +234,17 @@ mf_status mf_sample_spectrum(mf_plan plan, const float* d, const mf_spectrum_arg
                              double* theta_out, float* samples_out, double* theta_samples_out,
                              mf_stream stream);
 
+/* Per-pixel mean and variance of posterior samples (the maps of Sec. 4.1,
+ * Fig. 3) over all chains and samples of every problem.
+ *   samples    device float32 [problem][chain][sample][H][W], as written by mf_sample
+ *              or mf_sample_spectrum with the same chains and n_samples
+ *   mean_out   device float64, concatenated images
+ *   var_out    device float64, concatenated images (unbiased, over chains * n_samples
+ *              values; 0 when there is one value), or NULL
+ * Sums are shifted by each pixel's first sample and accumulated in FP64. */
+mf_status mf_sample_moments(mf_plan plan, const float* samples, int32_t chains, int32_t n_samples,
+                            double* mean_out, double* var_out, mf_stream stream);
+
 /* Vector-Jacobian product of the Wiener-filter map (d, P) -> s_W by implicit
  * differentiation of the normal equations (S^-1 + N^-1) s_W = N^-1 d read off
  * Eq. 7: v solves (S^-1 + N^-1) v = grad_s by the messenger iteration (pixel

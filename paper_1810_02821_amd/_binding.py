@@ -75,6 +75,7 @@ class _SpectrumArgs(C.Structure):
 EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_plan_pixel_offset",
            "mf_plan_tau", "mf_plan_total_bands", "mf_wiener", "mf_sample", "mf_wiener_backward",
            "mf_wiener_backward_unrolled", "mf_band_power", "mf_plan_tile_shape", "mf_sample_spectrum",
+           "mf_sample_moments",
            "mf_status_string",
            "mf_last_error"]
 
@@ -111,12 +112,13 @@ def lib():
     L.mf_wiener_backward_unrolled.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_int32, vp, vp, vp, vp, vp]
     L.mf_plan_tile_shape.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.mf_sample_spectrum.argtypes = [vp, vp, C.POINTER(_SpectrumArgs), vp, vp, vp, vp, vp, vp, vp]
+    L.mf_sample_moments.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
     L.mf_status_string.argtypes = [C.c_int]
     L.mf_status_string.restype = C.c_char_p
     L.mf_last_error.restype = C.c_char_p
     for name in ("mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_wiener",
                  "mf_sample", "mf_wiener_backward", "mf_wiener_backward_unrolled", "mf_band_power",
-                 "mf_plan_tile_shape", "mf_sample_spectrum"):
+                 "mf_plan_tile_shape", "mf_sample_spectrum", "mf_sample_moments"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -328,6 +330,15 @@ class Plan:
         _check(lib().mf_sample_spectrum(self._h, _ptr(d), C.byref(args), _ptr(state_in), _ptr(theta_in),
                                         _ptr(state_out), _ptr(theta_out), _ptr(smp), _ptr(ts), _stream()))
         return ts, smp, state_out, theta_out
+
+    def sample_moments(self, samples, chains: int, n_samples: int, want_var: bool = True):
+        """Per-pixel (mean, variance) over chains and samples, float64, concatenated."""
+        import torch
+        mean = torch.empty(self.total_pixels, dtype=torch.float64, device=samples.device)
+        var = torch.empty_like(mean) if want_var else None
+        _check(lib().mf_sample_moments(self._h, _ptr(samples), int(chains), int(n_samples), _ptr(mean), _ptr(var),
+                                       _stream()))
+        return mean, var
 
     def theta_view(self, flat, problem: int, chains: int, n_samples: int):
         """Band-amplitude samples [chains, n_samples, bands] of one problem."""

@@ -1093,6 +1093,17 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
     return data_gradient(p, grad_d, s);
 }
 
+mf_status mf_sample_moments(mf_plan p, const float* samples, int32_t chains, int32_t n_samples, double* mean_out,
+                            double* var_out, mf_stream stream) {
+    if (!p || !samples || !mean_out) return fail(MF_ERR_INVALID_ARG, "plan, samples and mean_out are required");
+    if (chains < 1 || n_samples < 1) return fail(MF_ERR_INVALID_ARG, "need chains >= 1 and n_samples >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    MF_HIP(p->aux.ensure((size_t)p->total_px * 2 * sizeof(double)));
+    MF_HIP(mf::launch_moments(p->d_probs, (int)p->probs.size(), p->total_px, samples, (int64_t)chains * n_samples,
+                              p->aux.as<double2>(), mean_out, var_out, s));
+    return MF_OK;
+}
+
 mf_status mf_band_power(mf_plan p, const float* x, const float* y, double* out, mf_stream stream) {
     if (!p || !x || !y || !out) return fail(MF_ERR_INVALID_ARG, "plan, x, y and out are required");
     hipStream_t s = (hipStream_t)stream;

@@ -88,6 +88,11 @@ hipError_t launch_init_items(int W, int H, const SweepArgs& a, const float2* sta
                              hipStream_t s);
 hipError_t launch_copy_out_real(int W, int H, const SweepArgs& a, float* out, hipStream_t s);
 hipError_t launch_copy_out_pairs(int W, int H, const SweepArgs& a, float2* out, hipStream_t s);
+// Per-pixel mean and unbiased variance over the m = chains * n_samples values
+// of every pixel in a sample array [problem][chain][sample][H][W]; acc is a
+// 16-byte-per-pixel workspace.
+hipError_t launch_moments(const ProbDev* probs, int n_problems, int64_t total_px, const float* samples, int64_t m,
+                          double2* acc, double* mean, double* var, hipStream_t s);
 // y[i] = x[i] * r[i] for i < n (y may be x).
 hipError_t launch_scale(const float* x, const float* r, float* y, int64_t n, hipStream_t s);
 hipError_t launch_grad_d(int W, int H, const SweepArgs& a, const float* v, float* grad_d, hipStream_t s);

@@ -392,6 +392,58 @@ __global__ void scale_kernel(const float* x, const float* r, float* y, int64_t n
         y[e] = x[e] * r[e];
 }
 
+// ------------------------------------------------------ sample moments --
+// Problem of a concatenated pixel index (problems are in pix_off order).
+__device__ __forceinline__ int problem_of(const ProbDev* probs, int n_problems, int64_t g) {
+    int lo = 0, hi = n_problems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) / 2;
+        if (probs[mid].pix_off <= g) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Shifted sums over one slice of the chain-sample axis: with K the pixel's
+// first sample, acc = (sum (x - K), sum (x - K)^2) in FP64 (accumulated
+// across slices with atomics).
+__global__ void moments_kernel(const ProbDev* probs, int n_problems, int64_t total_px, const float* samples,
+                               int64_t m, int64_t slice, double2* acc) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= total_px) return;
+    const ProbDev pr = probs[problem_of(probs, n_problems, g)];
+    const int64_t n = (int64_t)pr.H * pr.W;
+    const float* x = samples + m * pr.pix_off + (g - pr.pix_off);
+    const double K = x[0];
+    const int64_t k0 = (int64_t)blockIdx.y * slice, k1 = min(m, k0 + slice);
+    double s1 = 0.0, s2 = 0.0;
+#pragma unroll 4
+    for (int64_t k = k0; k < k1; ++k) {
+        const double d = (double)x[k * n] - K;
+        s1 += d;
+        s2 = fma(d, d, s2);
+    }
+    atomicAdd(&acc[g].x, s1);
+    atomicAdd(&acc[g].y, s2);
+}
+
+__global__ void moments_finish_kernel(const float* samples, const ProbDev* probs, int n_problems, int64_t total_px,
+                                      int64_t m, const double2* acc, double* mean, double* var) {
+    for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < total_px;
+         g += (int64_t)gridDim.x * blockDim.x) {
+        const ProbDev pr = probs[problem_of(probs, n_problems, g)];
+        const double K = samples[m * pr.pix_off + (g - pr.pix_off)];
+        const double2 a = acc[g];
+        mean[g] = K + a.x / (double)m;
+        if (var) var[g] = m > 1 ? (a.y - a.x * a.x / (double)m) / (double)(m - 1) : 0.0;
+    }
+}
+
+__global__ void zero_kernel(double2* p, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = make_double2(0.0, 0.0);
+}
+
 // Pack z = x + i y into the field so one complex FFT gives both spectra.
 __global__ void pack_pair_kernel(SweepArgs a, int H, int W, const float* x, const float* y) {
     const int64_t n = (int64_t)H * W;
@@ -623,6 +675,22 @@ hipError_t launch_copy_out_real(int W, int H, const SweepArgs& a, float* out, hi
 hipError_t launch_copy_out_pairs(int W, int H, const SweepArgs& a, float2* out, hipStream_t s) {
     hipLaunchKernelGGL(copy_out_pairs_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a,
                        H, W, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const ProbDev* probs, int n_problems, int64_t total_px, const float* samples, int64_t m,
+                          double2* acc, double* mean, double* var, hipStream_t s) {
+    hipLaunchKernelGGL(zero_kernel, elementwise_grid(total_px), dim3(256), 0, s, acc, total_px);
+    // enough slices of the chain-sample axis to keep about 2^18 threads reading
+    int64_t slices = ((int64_t)1 << 18) / total_px;
+    slices = slices < 1 ? 1 : (slices > m ? m : slices);
+    if (slices > 65535) slices = 65535;
+    const int64_t slice = (m + slices - 1) / slices;
+    slices = (m + slice - 1) / slice;
+    const dim3 grid((unsigned)((total_px + 255) / 256), (unsigned)slices);
+    hipLaunchKernelGGL(moments_kernel, grid, dim3(256), 0, s, probs, n_problems, total_px, samples, m, slice, acc);
+    hipLaunchKernelGGL(moments_finish_kernel, elementwise_grid(total_px), dim3(256), 0, s, samples, probs, n_problems,
+                       total_px, m, acc, mean, var);
     return hipGetLastError();
 }
 

@@ -270,6 +270,27 @@ def test_nonfinite_data_is_reported(torch_cuda, solve):
     assert rel(plan.split(out)[1], ref) < REL_TOL
 
 
+def test_sample_moments_match_numpy(torch_cuda):
+    """Per-pixel mean and variance over chains and samples of a two-size batch,
+    against numpy on the same samples (FP64 both sides)."""
+    mf = _mf()
+    banner("sample moments")
+    probs = [synth.config_small(1, 32), synth.config_128(2, 64)]
+    plan = mf.Plan(probs)
+    d = plan.concat([p.d for p in probs])
+    chains, n_samples = 5, 40
+    flat, _ = plan.sample(d, 3, chains=chains, burn_in=5, n_samples=n_samples)
+    mean, var = plan.sample_moments(flat, chains, n_samples)
+    for i, p in enumerate(probs):
+        x = plan.sample_view(flat, i, chains, n_samples).cpu().numpy().astype(np.float64)
+        x = x.reshape(chains * n_samples, p.H, p.W)
+        m_ref, v_ref = x.mean(axis=0), x.var(axis=0, ddof=1)
+        m = plan.split(mean)[i]
+        v = plan.split(var)[i]
+        assert np.max(np.abs(m - m_ref)) < 1e-12 * np.max(np.abs(m_ref)) + 1e-12
+        assert np.max(np.abs(v - v_ref) / v_ref) < 1e-10
+
+
 def test_band_power_matches_numpy(torch_cuda):
     mf = _mf()
     prob = synth.config_bands(2, 64, 32)
