@@ -1,0 +1,93 @@
+"""Distribution checks of the GPU samplers against the plain definitions,
+independent of the oracle's stream: many independent chains, their per-pixel
+mean against the Wiener filter of Eq. 2 and their variance against the
+diagonal of the posterior covariance of Eq. 7 (Sec. 4.1, Fig. 3), and the
+hierarchical sampler's amplitudes against their exact marginal without data.
+Standard errors come from independent groups of chains; the bound on the
+largest z over all pixels (or bands) is the Student-t quantile of a
+family-wise two-sided level of 1e-3."""
+import numpy as np
+import pytest
+from scipy import special, stats
+
+from gpu_common import banner
+from oracle import dense
+from paper_1810_02821_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1810_02821_amd as mf
+    mf.lib()
+    return torch
+
+
+def _posterior_check(mf, prob, chains=2048, burn_in=3000, n_samples=24, thin=8, groups=32):
+    """The chain mean follows the deterministic messenger iteration from s = 0,
+    so the burn-in must bring that iteration to its fixed point (3000 sweeps
+    leave less than 0.5% of a posterior standard deviation at 32^2)."""
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    flat, _ = plan.sample(d, 4242, chains=chains, burn_in=burn_in, n_samples=n_samples, thin=thin)
+    x = plan.sample_view(flat, 0, chains, n_samples).cpu().numpy().astype(np.float64)
+    x = x.reshape(chains, n_samples, -1)
+    S = dense.signal_covariance(prob.spectrum, prob.H, prob.W)
+    resp = getattr(prob, "response", None)
+    sw = dense.wiener_dense(S, prob.noise_var, prob.d, resp).ravel()
+    cv = np.diag(dense.posterior_covariance(S, prob.noise_var, resp))
+    g = x.reshape(groups, -1, x.shape[-1])                     # groups of whole chains
+    gm = g.mean(axis=1)
+    z_mean = np.abs(gm.mean(axis=0) - sw) / (gm.std(axis=0, ddof=1) / np.sqrt(groups))
+    gv = ((g - sw) ** 2).mean(axis=1)                           # variance about the exact mean
+    z_var = np.abs(gv.mean(axis=0) - cv) / (gv.std(axis=0, ddof=1) / np.sqrt(groups))
+    # the device reduction agrees with the host one
+    mean, var = plan.sample_moments(flat, chains, n_samples)
+    m_host = x.reshape(-1, x.shape[-1]).mean(axis=0)
+    assert np.max(np.abs(mean.cpu().numpy() - m_host)) < 1e-9 * (1 + np.max(np.abs(m_host)))
+    bound = stats.t.ppf(1 - 1e-3 / (2 * 2 * x.shape[-1]), groups - 1)
+    return z_mean.max(), z_var.max(), bound
+
+
+def test_samples_have_the_posterior_mean_and_variance_32(torch_cuda):
+    import paper_1810_02821_amd as mf
+    banner("posterior moments 32x32, 2048 chains")
+    zm, zv, bound = _posterior_check(mf, synth.config_small(0, 32))
+    print(f"max z mean {zm:.2f}, max z var {zv:.2f}, bound {bound:.2f}")
+    assert zm < bound and zv < bound
+
+
+def test_samples_with_response_have_the_posterior_moments_32(torch_cuda):
+    import paper_1810_02821_amd as mf
+    banner("posterior moments with response 32x32")
+    zm, zv, bound = _posterior_check(mf, synth.config_response(2, 32, dead=0.05))
+    print(f"max z mean {zm:.2f}, max z var {zv:.2f}, bound {bound:.2f}")
+    assert zm < bound and zv < bound
+
+
+def test_hierarchical_amplitudes_follow_the_prior_without_data(torch_cuda):
+    """Every pixel missing: the amplitudes' stationary marginal is the
+    inverse-gamma prior, E log theta = log beta_0 - digamma(nu_0 / 2).  The
+    prior scale keeps n theta well below T (the signal step then mixes within
+    the five sweeps of an iteration), and the chains start at the prior mean."""
+    import paper_1810_02821_amd as mf
+    banner("hierarchical prior recovery 32x32")
+    p = synth.config_bands(1, 32, 6)
+    nu0, beta0 = 6, 2e-4
+    p.noise_var = np.full((32, 32), np.inf)
+    p.mask = np.ones((32, 32), dtype=bool)
+    p.d = np.zeros((32, 32))
+    p.spectrum = synth.spectrum_bands(p.spectrum.edges, np.full(6, beta0 / 2.0))
+    plan = mf.Plan([p])
+    chains = 4096
+    ts, _, _, _ = plan.sample_spectrum(plan.concat([p.d]), 77, chains, 400, 1, 1, 5, nu0, beta0)
+    th = plan.theta_view(ts, 0, chains, 1).cpu().numpy()[:, 0, :]
+    lt = np.log(th)
+    target = np.log(beta0) - special.digamma(nu0 / 2.0)
+    z = np.abs(lt.mean(axis=0) - target) / (lt.std(axis=0, ddof=1) / np.sqrt(chains))
+    bound = stats.norm.ppf(1 - 1e-3 / (2 * lt.shape[1]))
+    print(f"E log theta per band {lt.mean(axis=0)}, target {target:.4f}, max z {z.max():.2f}, bound {bound:.2f}")
+    assert z.max() < bound
