@@ -20,11 +20,13 @@ Data with Dataflow Engines"):
                   differentiation of the normal equations of Eq. 7);
 * ``spectrum``  - the power-spectrum Gibbs step of Sec. 5 (inverse-gamma band
                   amplitudes given the signal) and the hierarchical sampler
-                  that alternates it with Algorithm 1.
+                  that alternates it with Algorithm 1;
+* ``shear``     - mass mapping (Sec. 5): the messenger filter and sampler for
+                  complex shear data and the spin-2 operator A = F^-1 D F.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import it.  It shares no code with the GPU path and never
 imports it; the two meet only through the seeded inputs of
 ``paper_1810_02821_amd.synth``.
 """
-from . import philox, messenger, dense, adjoint, spectrum  # noqa: F401
+from . import philox, messenger, dense, adjoint, spectrum, shear  # noqa: F401

@@ -122,6 +122,7 @@ class Problem:
     spectrum: Spectrum
     s_true: np.ndarray       # float64 (H, W), the generating field
     response: Optional[np.ndarray] = None  # float64 (H, W) diagonal A of d = A s + n, None = identity
+    gamma: Optional[np.ndarray] = None     # complex128 (H, W) shear data of a mass-mapping problem
 
     @property
     def n(self) -> int:
@@ -154,6 +155,37 @@ def config_response(seed: int = 0, size: int = 128, dead: float = 0.01) -> Probl
     d = np.where(missing, 0.0, A * s + noise)
     nv = np.where(mask, np.inf, sigma ** 2)
     return Problem(H=size, W=size, d=d, noise_var=nv, mask=missing, spectrum=spec, s_true=s, response=A)
+
+
+def shear_from_convergence(kappa: np.ndarray) -> np.ndarray:
+    """The weak-lensing shear of a convergence map (Kaiser & Squires 1993):
+    gamma_hat = (k_1 + i k_2)^2 / |k|^2 kappa_hat, with no shear from k = 0."""
+    H, W = kappa.shape
+    ky = (np.fft.fftfreq(H) * H)[:, None]
+    kx = (np.fft.fftfreq(W) * W)[None, :]
+    k2 = kx * kx + ky * ky
+    k2[0, 0] = 1.0
+    kernel = (kx + 1j * ky) ** 2 / k2
+    kernel[0, 0] = 0.0
+    return np.fft.ifft2(kernel * np.fft.fft2(kappa))
+
+
+def config_shear(seed: int = 0, size: int = 128, b_ratio: float = 0.0) -> Problem:
+    """Mass mapping: convergence kappa = kappa_E + i kappa_B with
+    P_E = (k+1)^-2 and P_B = b_ratio P_E, shear gamma = A kappa + n with
+    sigma ~ U[0.3, 1.0] per component, 20% masked 4x4 tiles.  `spectrum` is P_E."""
+    rng = np.random.default_rng(seed)
+    spec = spectrum_powerlaw(1.0, 1.0, 2.0)
+    sigma = _uniform_sigma(size, size, 0.3, 1.0, rng)
+    mask = tile_mask(size, size, 0.20, rng)
+    kE = grf(size, size, spec, rng)
+    kB = np.sqrt(b_ratio) * grf(size, size, spec, rng) if b_ratio > 0 else np.zeros((size, size))
+    kappa = kE + 1j * kB
+    noise = sigma * (rng.standard_normal((size, size)) + 1j * rng.standard_normal((size, size)))
+    g = np.where(mask, 0.0, shear_from_convergence(kappa) + noise)
+    nv = np.where(mask, np.inf, sigma ** 2)
+    return Problem(H=size, W=size, d=np.zeros((size, size)), noise_var=nv, mask=mask, spectrum=spec,
+                   s_true=kE, gamma=g)
 
 
 def philox_seed(data_seed: int) -> int:
