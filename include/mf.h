@@ -234,6 +234,38 @@ mf_status mf_sample_spectrum(mf_plan plan, const float* d, const mf_spectrum_arg
                              double* theta_out, float* samples_out, double* theta_samples_out,
                              mf_stream stream);
 
+/* Arguments of mf_shear_sample. */
+typedef struct {
+    uint64_t seed;             /* Philox key */
+    int32_t chains_per_problem;/* >= 1; one chain per stream index (no pairing) */
+    int32_t burn_in;           /* sweeps before the first sample (>= 0) */
+    int32_t n_samples;         /* samples per chain (>= 0) */
+    int32_t thin;              /* sweeps per sample after burn-in (>= 1) */
+    int64_t sweep_offset;      /* global sweep index of the first sweep */
+    float b_ratio;             /* P_B / P_E >= 0 (0: no B modes) */
+} mf_shear_args;
+
+/* Mass mapping (Sec. 5): complex shear data gamma = A kappa + n with the
+ * spin-2 operator A = F^-1 D F, D_k = (k_1 + i k_2)^2 / |k|^2 (k_1 along x,
+ * integer frequencies in FFT order; D_0 = 0), convergence kappa = kappa_E + i
+ * kappa_B with the problem's spectrum as P_E and P_B = b_ratio P_E, noise
+ * variance noise_var per component.  The messenger field lives in shear
+ * space (T = tau I, tau = min N); the Fourier step removes D and applies the
+ * Wiener step of each real field (E = real part, B = imaginary part of
+ * kappa); k = 0 is drawn from the prior.  Every problem needs H = W in
+ * {32, 64, 128} and no response.
+ *   gamma       device, concatenated complex shear (float2 per pixel)
+ *   kappa_out   device, concatenated complex convergence (float2 per pixel)
+ * mf_shear_wiener runs the schedule's sweeps from kappa = 0 (tol must be <= 0)
+ * and writes kappa after the last sweep.  mf_shear_sample draws samples of
+ * kappa, float2 [problem][chain][sample][H][W] (problem p starts at chains *
+ * n_samples * pixel_offset(p)); its state is the model shear A kappa per
+ * chain, float2 [problem][chain][H][W]. */
+mf_status mf_shear_wiener(mf_plan plan, const float* gamma, const mf_schedule* schedule, float b_ratio,
+                          float* kappa_out, mf_stream stream);
+mf_status mf_shear_sample(mf_plan plan, const float* gamma, const mf_shear_args* args,
+                          const float* state_in, float* state_out, float* samples_out, mf_stream stream);
+
 /* Per-pixel mean and variance of posterior samples (the maps of Sec. 4.1,
  * Fig. 3) over all chains and samples of every problem.
  *   samples    device float32 [problem][chain][sample][H][W], as written by mf_sample

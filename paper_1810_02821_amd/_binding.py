@@ -72,10 +72,16 @@ class _SpectrumArgs(C.Structure):
                 ("init_scale", C.c_float)]
 
 
+class _ShearArgs(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("chains_per_problem", C.c_int32), ("burn_in", C.c_int32),
+                ("n_samples", C.c_int32), ("thin", C.c_int32), ("sweep_offset", C.c_int64),
+                ("b_ratio", C.c_float)]
+
+
 EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_plan_pixel_offset",
            "mf_plan_tau", "mf_plan_total_bands", "mf_wiener", "mf_sample", "mf_wiener_backward",
            "mf_wiener_backward_unrolled", "mf_band_power", "mf_plan_tile_shape", "mf_sample_spectrum",
-           "mf_sample_moments",
+           "mf_sample_moments", "mf_shear_wiener", "mf_shear_sample",
            "mf_status_string",
            "mf_last_error"]
 
@@ -113,12 +119,15 @@ def lib():
     L.mf_plan_tile_shape.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.mf_sample_spectrum.argtypes = [vp, vp, C.POINTER(_SpectrumArgs), vp, vp, vp, vp, vp, vp, vp]
     L.mf_sample_moments.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
+    L.mf_shear_wiener.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_float, vp, vp]
+    L.mf_shear_sample.argtypes = [vp, vp, C.POINTER(_ShearArgs), vp, vp, vp, vp]
     L.mf_status_string.argtypes = [C.c_int]
     L.mf_status_string.restype = C.c_char_p
     L.mf_last_error.restype = C.c_char_p
     for name in ("mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_wiener",
                  "mf_sample", "mf_wiener_backward", "mf_wiener_backward_unrolled", "mf_band_power",
-                 "mf_plan_tile_shape", "mf_sample_spectrum", "mf_sample_moments"):
+                 "mf_plan_tile_shape", "mf_sample_spectrum", "mf_sample_moments", "mf_shear_wiener",
+                 "mf_shear_sample"):
         getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -330,6 +339,42 @@ class Plan:
         _check(lib().mf_sample_spectrum(self._h, _ptr(d), C.byref(args), _ptr(state_in), _ptr(theta_in),
                                         _ptr(state_out), _ptr(theta_out), _ptr(smp), _ptr(ts), _stream()))
         return ts, smp, state_out, theta_out
+
+    # ---- mass mapping (complex shear data, spin-2 operator)
+    def concat_complex(self, arrays, device="cuda"):
+        """Concatenate complex images into one complex64 device tensor."""
+        import torch
+        flat = np.concatenate([np.asarray(a, dtype=np.complex64).ravel() for a in arrays])
+        return torch.from_numpy(flat).to(device)
+
+    def split_complex(self, flat):
+        x = flat.detach().cpu().numpy()
+        return [x[self.offsets[i]:self.offsets[i + 1]].reshape(p.H, p.W) for i, p in enumerate(self.problems)]
+
+    def shear_wiener(self, gamma, schedule: Schedule, b_ratio: float = 0.0, out=None):
+        """Convergence Wiener filter (complex, concatenated) of complex shear data."""
+        import torch
+        out = torch.empty_like(gamma) if out is None else out
+        sch = schedule._c()
+        _check(lib().mf_shear_wiener(self._h, _ptr(gamma), C.byref(sch), float(b_ratio), _ptr(out), _stream()))
+        return out
+
+    def shear_state_buffer(self, chains: int, device="cuda"):
+        import torch
+        return torch.zeros(chains * self.total_pixels, dtype=torch.complex64, device=device)
+
+    def shear_sample(self, gamma, seed: int, chains: int, burn_in: int, n_samples: int, thin: int = 1,
+                     sweep_offset: int = 0, b_ratio: float = 0.0, state_in=None, state_out=None, samples=True):
+        """Samples of the convergence, complex [concat over problems of chains*n_samples*H*W]."""
+        import torch
+        out = None
+        if samples and n_samples > 0:
+            out = torch.empty(chains * n_samples * self.total_pixels, dtype=torch.complex64, device=gamma.device)
+        args = _ShearArgs(int(seed), int(chains), int(burn_in), int(n_samples), int(thin), int(sweep_offset),
+                          float(b_ratio))
+        _check(lib().mf_shear_sample(self._h, _ptr(gamma), C.byref(args), _ptr(state_in), _ptr(state_out),
+                                     _ptr(out), _stream()))
+        return out, state_out
 
     def sample_moments(self, samples, chains: int, n_samples: int, want_var: bool = True):
         """Per-pixel (mean, variance) over chains and samples, float64, concatenated."""

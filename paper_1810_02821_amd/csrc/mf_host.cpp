@@ -16,6 +16,7 @@
 #include "mf_kernels.hpp"
 #include "mf_resident.hpp"
 #include "mf_spectrum.hpp"
+#include "mf_shear.hpp"
 
 namespace {
 
@@ -453,6 +454,68 @@ mf_status plan_data(mf_plan p, const float* d, hipStream_t s, const float** out)
 mf_status data_gradient(mf_plan p, float* g, hipStream_t s) {
     if (!p->has_response || !g) return MF_OK;
     MF_HIP(mf::launch_scale(g, p->d_rinv, g, p->total_px, s));
+    return MF_OK;
+}
+
+// Shear problems: every problem H = W in {32, 64, 128}, no response.
+mf_status shear_check(mf_plan p) {
+    if (p->has_response) return fail(MF_ERR_INVALID_ARG, "shear problems take no response");
+    for (const HostProblem& hp : p->probs)
+        if (!mf::resident_supported(hp.H, hp.W))
+            return fail(MF_ERR_UNSUPPORTED_SIZE, "mass mapping needs H = W in {32, 64, 128}");
+    return MF_OK;
+}
+
+mf_status launch_shear(mf_plan p, const float* gamma, float b_ratio, int chains, const std::vector<double>& lam,
+                       const std::vector<int32_t>& sweeps, int stochastic, uint64_t seed, int64_t sweep_offset,
+                       int burn_in, int n_samples, int thin, const float* state_in, float* state_out,
+                       float* samples, float* kappa_out, hipStream_t s) {
+    const int L = (int)lam.size();
+    MF_HIP(p->sched.ensure((size_t)L * (sizeof(double) + sizeof(int32_t))));
+    char* base = p->sched.as<char>();
+    MF_HIP(hipMemcpyAsync(base, lam.data(), (size_t)L * sizeof(double), hipMemcpyHostToDevice, s));
+    MF_HIP(hipMemcpyAsync(base + (size_t)L * sizeof(double), sweeps.data(), (size_t)L * sizeof(int32_t),
+                          hipMemcpyHostToDevice, s));
+    size_t max_items = 0;
+    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size() * (size_t)chains);
+    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
+    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
+    MF_HIP(hipStreamSynchronize(s));  // the host vectors must outlive the copies
+    for (auto& kv : p->classes) {
+        const int N = kv.first.first;
+        std::vector<mf::ItemDev> items;
+        for (int pid : kv.second)
+            for (int c = 0; c < chains; ++c)
+                items.push_back({pid, c, (int64_t)chains * p->probs[pid].pix_off + (int64_t)c * N * N});
+        mf::ItemDev* di = nullptr;
+        mf_status st = put_items(p, items, 0, s, &di);
+        if (st != MF_OK) return st;
+        mf::ShearArgs r{};
+        r.probs = p->d_probs;
+        r.items = di;
+        r.n_items = (int)items.size();
+        r.gamma = reinterpret_cast<const float2*>(gamma);
+        r.nbar = p->d_nbar;
+        r.nP = p->d_nP;
+        r.b_ratio = b_ratio;
+        r.tw = p->d_tw.at(N);
+        r.key0 = (uint32_t)(seed & 0xffffffffu);
+        r.key1 = (uint32_t)(seed >> 32);
+        r.sweep0 = (uint32_t)sweep_offset;
+        r.stochastic = stochastic;
+        r.lambda = reinterpret_cast<const double*>(base);
+        r.level_sweeps = reinterpret_cast<const int32_t*>(base + (size_t)L * sizeof(double));
+        r.n_levels = L;
+        r.burn_in = burn_in;
+        r.n_samples = n_samples;
+        r.thin = thin;
+        r.samples = reinterpret_cast<float2*>(samples);
+        r.chains = chains;
+        r.state_in = reinterpret_cast<const float2*>(state_in);
+        r.state_out = reinterpret_cast<float2*>(state_out);
+        r.kappa_out = reinterpret_cast<float2*>(kappa_out);
+        MF_HIP(mf::launch_resident_shear(N, r, s));
+    }
     return MF_OK;
 }
 
@@ -1091,6 +1154,41 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
             MF_HIP(mf::launch_band_slots_reduce(W, H, sh.first, r, p->d_band_base, p->d_band_count, grad_bands, s));
     }
     return data_gradient(p, grad_d, s);
+}
+
+mf_status mf_shear_wiener(mf_plan p, const float* gamma, const mf_schedule* sch, float b_ratio, float* kappa_out,
+                          mf_stream stream) {
+    if (!p || !gamma || !kappa_out) return fail(MF_ERR_INVALID_ARG, "plan, gamma and kappa_out are required");
+    mf_status st = validate_schedule(sch);
+    if (st != MF_OK) return st;
+    if (sch->tol > 0) return fail(MF_ERR_INVALID_ARG, "the shear filter runs a fixed schedule (tol <= 0)");
+    if (!(b_ratio >= 0.f) || !std::isfinite(b_ratio)) return fail(MF_ERR_INVALID_ARG, "b_ratio must be >= 0");
+    if ((st = shear_check(p)) != MF_OK) return st;
+    std::vector<double> lam(sch->lambda, sch->lambda + sch->n_levels);
+    std::vector<int32_t> sw(sch->sweeps, sch->sweeps + sch->n_levels);
+    int total = 0;
+    for (int k : sw) total += k;
+    if (total < 1) return fail(MF_ERR_INVALID_ARG, "the schedule runs no sweep");
+    return launch_shear(p, gamma, b_ratio, 1, lam, sw, 0, 0, 0, 0, 0, 1, nullptr, nullptr, nullptr, kappa_out,
+                        (hipStream_t)stream);
+}
+
+mf_status mf_shear_sample(mf_plan p, const float* gamma, const mf_shear_args* g, const float* state_in,
+                          float* state_out, float* samples_out, mf_stream stream) {
+    if (!p || !gamma || !g) return fail(MF_ERR_INVALID_ARG, "plan, gamma and args are required");
+    if (g->chains_per_problem < 1 || g->burn_in < 0 || g->n_samples < 0 || g->thin < 1 || g->sweep_offset < 0 ||
+        !(g->b_ratio >= 0.f) || !std::isfinite(g->b_ratio))
+        return fail(MF_ERR_INVALID_ARG,
+                    "need chains >= 1, burn_in >= 0, n_samples >= 0, thin >= 1, sweep_offset >= 0, b_ratio >= 0");
+    const int64_t K = (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin;
+    if (g->sweep_offset + K > 0xffffffffLL || K > 0x7fffffffLL)
+        return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
+    mf_status st = shear_check(p);
+    if (st != MF_OK) return st;
+    if (K == 0) return MF_OK;
+    return launch_shear(p, gamma, g->b_ratio, g->chains_per_problem, {1.0}, {(int32_t)K}, 1, g->seed,
+                        g->sweep_offset, g->burn_in, g->n_samples, g->thin, state_in, state_out, samples_out,
+                        nullptr, (hipStream_t)stream);
 }
 
 mf_status mf_sample_moments(mf_plan p, const float* samples, int32_t chains, int32_t n_samples, double* mean_out,
