@@ -4,7 +4,9 @@
  *
  * The method (Jeffrey, Heavens & Fortio, "Fast Sampling from Wiener Posteriors
  * for Image Data with Dataflow Engines"):
- *   data model d = A s + n with A = I (Sec. 1.1, Eq. 1); diagonal pixel noise
+ *   data model d = A s + n with A = I or a diagonal response (Sec. 1.1, Eq. 1,
+ *   and Algorithm 1's A_i terms; mass mapping uses the spin-2 operator of
+ *   Sec. 5, see mf_shear_wiener); diagonal pixel noise
  *   covariance N, missing pixels having infinite variance (Sec. 1.1); a
  *   statistically homogeneous signal whose covariance S is diagonal in Fourier
  *   space with an isotropic power spectrum P(|k|) (Eq. 8-9).  The Wiener filter
@@ -31,16 +33,21 @@
  *     u2 = (x>>8) 2^-24, z0 = sqrt(-2 ln u1) cos(2 pi u2), z1 = ... sin(...).
  *     stage 0 = pixel draw of t (elem = row-major pixel), stage 1 = Fourier
  *     draw of s (elem = row-major mode index in unshifted FFT order), stage 2 =
- *     dispersed initial state.  The stream does not depend on how the work is
- *     tiled or batched, so every execution form yields the same samples.
+ *     dispersed initial state, stage 3 = chi-square variates of the
+ *     power-spectrum draw (mf_sample_spectrum).  The stream does not depend on
+ *     how the work is tiled or batched, so every execution form yields the
+ *     same samples.
  *
  * Memory: every pointer argument documented "device" is memory on the current
  * HIP device owned by the caller; the plan owns its own tables and workspaces
- * and frees them in mf_plan_destroy.  "host" pointers are read during the
- * call only.  All entry points enqueue work on `stream` (a hipStream_t; NULL
- * is the null stream) and return once it is enqueued, except where a result is
- * returned to the host (mf_info, convergence tests), which synchronises the
- * stream.  A plan must not be used from two streams at once.
+ * and frees them in mf_plan_destroy.  Workspaces are allocated on the first
+ * call that needs them (and grown when a later call needs more), so a first
+ * call may allocate device memory.  "host" pointers are read during the call
+ * only.  All entry points enqueue their kernels on `stream` (a hipStream_t;
+ * NULL is the null stream); they synchronise the stream when they upload a
+ * new work list or schedule from host memory and when a result returns to the
+ * host (mf_info, convergence tests).  A plan must not be used from two
+ * streams or threads at once.
  *
  * Errors: every entry point returns an mf_status; no C++ exception crosses the
  * boundary.  mf_last_error() returns a thread-local message for the last
