@@ -94,6 +94,7 @@ struct mf_plan_s {
     DevBuf field_adj, ckpt, tstore, slots;  // unrolled-gradient workspaces
     DevBuf sched;                           // persistent solve: levels, sweeps, per-item outcome
     DevBuf spec;                            // hierarchical sampler: dof and start amplitudes per band
+    DevBuf hier;                            // streamed hierarchical sampler: per-item amplitudes and sums
     std::vector<mf::ItemDev> items_cached;  // what items[0..] holds (skip re-uploads)
     // column-kernel tile shape per size class: (H, W) -> (tc, nth)
     std::map<std::pair<int, int>, std::pair<int, int>> col_shape;
@@ -132,6 +133,7 @@ struct mf_plan_s {
         slots.release();
         sched.release();
         spec.release();
+        hier.release();
         for (auto& g : graphs) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
             if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -718,6 +720,84 @@ mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, in
     }
     p->graphs.push_back({key, graph, exec});
     MF_HIP(hipGraphLaunch(exec, s));
+    return MF_OK;
+}
+
+// The hierarchical sampler on the streamed kernels for one size class: per
+// iteration, sweeps_per_draw sweeps (row kernel, mirror-paired column kernel;
+// the last one adds the band powers), then the chi-square sums and the new
+// amplitudes.  Samples are emitted by the next row kernel's inverse pass.
+mf_status spectrum_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H, int W, int max_dof, const float* d,
+                            const mf_spectrum_args* g, float2* work, const float2* state_in, const double* theta_in,
+                            double* theta_out, float* samples, double* theta_samples, const int32_t* d_dof,
+                            const double* d_th0, hipStream_t s) {
+    constexpr int kNB = mf::kMaxBandsPerProblem;
+    const size_t nd = (size_t)n_items * 2 * kNB;
+    MF_HIP(p->hier.ensure(3 * nd * sizeof(double) + (size_t)n_items * kNB * sizeof(float4)));
+    double* theta = p->hier.as<double>();
+    mf::SweepArgs a = base_args(p, H, W);
+    a.items = di;
+    a.n_items = n_items;
+    a.field = work;
+    a.src = d;
+    a.src_kind = mf::kSrcData;
+    a.stochastic = 1;
+    a.key0 = (uint32_t)(g->seed & 0xffffffffu);
+    a.key1 = (uint32_t)(g->seed >> 32);
+    a.samples = samples;
+    a.chains = g->chains_per_problem;
+    a.n_samples = g->n_samples;
+    mf::SpectrumStreamArgs r{};
+    r.probs = p->d_probs;
+    r.items = di;
+    r.n_items = n_items;
+    r.field = work;
+    r.tw_col = p->d_tw.at(H);
+    r.band = p->d_band;
+    r.band_base = p->d_band_base;
+    r.band_count = p->d_band_count;
+    r.dof = d_dof;
+    r.theta0 = d_th0;
+    r.theta_in = theta_in;
+    r.theta_out = theta_out;
+    r.theta_samples = theta_samples;
+    r.theta = theta;
+    r.pw = theta + nd;
+    r.chi = theta + 2 * nd;
+    r.coef = reinterpret_cast<float4*>(theta + 3 * nd);
+    r.key0 = a.key0;
+    r.key1 = a.key1;
+    r.chains = g->chains_per_problem;
+    r.chains_pad = 2 * ((g->chains_per_problem + 1) / 2);
+    r.n_samples = g->n_samples;
+    r.prior_beta = g->prior_beta;
+    if (state_in != work)  // copy the given states, or make zero / dispersed starts
+        MF_HIP(mf::launch_init_items(W, H, a, state_in, state_in ? 0.f : g->init_scale, s));
+    MF_HIP(mf::launch_spectrum_init(r, s));
+    const int64_t iters = (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin;
+    const int K = g->sweeps_per_draw;
+    auto slot_of = [&](int64_t i) -> int64_t {
+        if (i < g->burn_in) return -1;
+        const int64_t q = i - g->burn_in + 1;
+        return (q % g->thin == 0) ? q / g->thin - 1 : -1;
+    };
+    for (int64_t i = 0; i < iters; ++i) {
+        const int64_t gi = g->iteration_offset + i;
+        for (int k = 0; k < K; ++k) {
+            a.sweep = (uint32_t)(gi * K + k);
+            a.emit_index = (samples && k == 0 && i > 0) ? (int)slot_of(i - 1) : -1;
+            MF_HIP(mf::launch_row(W, H, (i == 0 && k == 0) ? mf::kRowFwd : mf::kRowInvFwd, a, s));
+            r.sweep = a.sweep;
+            r.add_power = k == K - 1;
+            MF_HIP(mf::launch_spectrum_col(W, H, r, s));
+        }
+        r.iteration = (uint32_t)gi;
+        MF_HIP(mf::launch_spectrum_draw(r, max_dof, slot_of(i), s));
+    }
+    if (iters > 0) {
+        a.emit_index = samples ? (int)slot_of(iters - 1) : -1;
+        MF_HIP(mf::launch_row(W, H, mf::kRowInv, a, s));
+    }
     return MF_OK;
 }
 
@@ -1332,8 +1412,6 @@ mf_status mf_sample_spectrum(mf_plan p, const float* d, const mf_spectrum_args* 
         const HostProblem& hp = p->probs[i];
         if (hp.kind != MF_PK_BANDS)
             return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + " has no band spectrum");
-        if (!mf::resident_supported(hp.H, hp.W))
-            return fail(MF_ERR_UNSUPPORTED_SIZE, "the hierarchical sampler needs H = W in {32, 64, 128}");
     }
     hipStream_t s = (hipStream_t)stream;
     {
@@ -1375,14 +1453,27 @@ mf_status mf_sample_spectrum(mf_plan p, const float* d, const mf_spectrum_args* 
     MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
     MF_HIP(hipStreamSynchronize(s));  // the host staging vectors die on return
     for (auto& kv : p->classes) {
-        const int H = kv.first.first;
+        const int H = kv.first.first, W = kv.first.second;
         std::vector<mf::ItemDev> items;
         for (int pid : kv.second)
             for (int q = 0; q < pairs; ++q)
-                items.push_back({pid, q, (int64_t)pairs * p->probs[pid].pix_off + (int64_t)q * H * H});
+                items.push_back({pid, q, (int64_t)pairs * p->probs[pid].pix_off + (int64_t)q * H * W});
         mf::ItemDev* di = nullptr;
         mf_status st = put_items(p, items, 0, s, &di);
         if (st != MF_OK) return st;
+        if (!mf::resident_supported(H, W)) {
+            int max_dof = 0;
+            for (int pid : kv.second) {
+                int tot = 0;
+                for (int b = 0; b < p->probs[pid].n_bands; ++b) tot += dof[p->probs[pid].band_base + b];
+                max_dof = std::max(max_dof, tot);
+            }
+            st = spectrum_streamed(p, di, (int)items.size(), H, W, max_dof, d, g, work,
+                                   reinterpret_cast<const float2*>(state_in), theta_in, theta_out, samples_out,
+                                   theta_samples_out, d_dof, d_th0, s);
+            if (st != MF_OK) return st;
+            continue;
+        }
         mf::SpectrumArgs r{};
         r.probs = p->d_probs;
         r.items = di;

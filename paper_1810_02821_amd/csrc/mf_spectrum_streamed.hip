@@ -1,0 +1,293 @@
+// Streamed form of the hierarchical sampler (Sec. 5) for size classes the
+// persistent kernel does not hold: the streamed sampler's row kernel does the
+// pixel step; the column kernel below does the Fourier step with each chain's
+// own band amplitudes, and two small kernels draw the amplitudes.
+//
+// The Fourier step of a pair whose chains have different spectra combines
+// every mode k with its mirror -k (mf_spectrum.hip derives the update).
+// Column tiles are therefore made of mirror pairs of columns: tile j of an
+// item holds columns c = j TC/2 + i (i < TC/2) in its first TC/2 slots and
+// their mirrors W - c in the others, with the two self-mirror columns 0 and
+// W/2 both in tile 0.  After the column transforms a tile holds both modes of
+// every pair it updates.
+//
+// On the last sweep of an iteration the tile also adds the band powers of
+// both chains (FP64) to per-item sums; the draw then needs only those sums and
+// the chi-square variates, as in the persistent kernel.
+#include "mf_device.hpp"
+#include "mf_kernels.hpp"
+#include "mf_spectrum.hpp"
+
+namespace mf {
+
+namespace {
+
+constexpr int kNB = kMaxBandsPerProblem;
+constexpr uint32_t kStageSpectrum = 3;
+
+template <int L>
+struct PairShape {
+    static constexpr int TC = L >= 2048 ? 8 : 16;
+    static constexpr int NTH = L >= 1024 ? 1024 : (L >= 512 ? 512 : 256);
+    static constexpr int TPC = NTH / TC;
+    static constexpr int SEG = L + 32 / TC;
+};
+
+// Opaque copies: the compiler cannot keep values derived from them live across
+// the transforms (which would raise register pressure).
+__device__ __forceinline__ unsigned opaque(unsigned v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+__device__ __forceinline__ const float2* opaque(const float2* p) {
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
+// Column held by slot s of tile j.
+__device__ __forceinline__ int pair_column(int j, int s, int half, int W) {
+    if (s < half) return j * half + s;
+    const int c = j * half + (s - half);
+    return c == 0 ? W / 2 : W - c;
+}
+
+// Harmonic-stage normal of mode index e (same element mapping as the other
+// samplers: the pair call j = e / 2 gives .a to even e and .b to odd e).
+__device__ __forceinline__ float2 mode_normal(uint32_t e, uint32_t sweep, uint32_t pid, uint32_t pair, uint32_t k0,
+                                              uint32_t k1) {
+    const Normals2 z = pair_normals(e >> 1, sweep, pid, kStageHarmonic, pair, k0, k1);
+    return (e & 1u) ? z.b : z.a;
+}
+
+template <int L>
+__global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStreamArgs a, int W) {
+    constexpr int TC = PairShape<L>::TC, NTH = PairShape<L>::NTH, TPC = PairShape<L>::TPC, SEG = PairShape<L>::SEG;
+    constexpr int H = L;
+    constexpr int half = TC / 2;
+    __shared__ float2 lds[TC * SEG];
+    __shared__ double pw[2][kNB];
+    const unsigned tid = threadIdx.x;
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x);
+    const int item = (int)(t % a.n_items);
+    const int j = (int)(t / a.n_items);
+    const ItemDev it = a.items[item];
+    const ProbDev pr = a.probs[it.prob];
+    float2* fld = a.field + it.field_off;
+
+    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+        const int s = (int)(e % TC), y = (int)(e / TC);
+        lds[s * SEG + swz(y)] = fld[(int64_t)y * W + pair_column(j, s, half, W)];
+    }
+    for (unsigned u = tid; u < 2 * kNB; u += NTH) pw[u / kNB][u % kNB] = 0.0;
+    __syncthreads();
+    const unsigned cid = tid / TPC, lane = tid % TPC;
+    stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
+
+    // one job per mode pair {k, -k}: a first-half slot with its partner slot;
+    // in tile 0 the self-mirror columns 0 (slot 0) and W/2 (slot half) take
+    // the rows ky <= H/2, whose partners -ky lie in the same column
+    const float4* coef = a.coef + (int64_t)item * kNB;
+    const int16_t* band = a.band + pr.pix_off;
+    const uint32_t pid = (uint32_t)pr.pid, pair = (uint32_t)it.pair;
+    const int jobs = half * H + (j == 0 ? H / 2 + 1 : 0);
+#pragma unroll 1
+    for (int q = opaque(tid); q < jobs; q += NTH) {
+        int s, ky;
+        if (q < half * H) {
+            s = q / H;
+            ky = q % H;
+            if (j == 0 && s == 0 && ky > H / 2) continue;
+        } else {
+            s = half;
+            ky = q - half * H;
+        }
+        const bool self_col = j == 0 && (s == 0 || s == half);
+        const int p = self_col ? s : s + half;
+        const int my = (H - ky) & (H - 1);
+        const bool self = self_col && my == ky;
+        const int ck = pair_column(j, s, half, W), cm = pair_column(j, p, half, W);
+        float2& zk = lds[s * SEG + swz(ky)];
+        float2& zm = lds[p * SEG + swz(my)];
+        const float2 Zk = zk, Zm = zm;
+        const uint32_t ek = (uint32_t)(ky * W + ck), em = (uint32_t)(my * W + cm);
+        const int b = band[ek];  // band(-k) = band(k): same |k|
+        const float4 c = coef[b];
+        const float fp = 0.5f * (c.x + c.z), fm = 0.5f * (c.x - c.z);
+        const float wp = 0.5f * (c.y + c.w), wm = 0.5f * (c.y - c.w);
+        const float2 hk = mode_normal(ek, a.sweep, pid, pair, a.key0, a.key1);
+        const float2 hm = self ? hk : mode_normal(em, a.sweep, pid, pair, a.key0, a.key1);
+        // S(k) = f_+ Z(k) + f_- conj Z(-k) + w_+ eta(k) + w_- conj eta(-k), and with k, -k swapped
+        const float2 Sk = make_float2(fmaf(fp, Zk.x, fm * Zm.x) + fmaf(wp, hk.x, wm * hm.x),
+                                      fmaf(fp, Zk.y, -fm * Zm.y) + fmaf(wp, hk.y, -wm * hm.y));
+        const float2 Sm = make_float2(fmaf(fp, Zm.x, fm * Zk.x) + fmaf(wp, hm.x, wm * hk.x),
+                                      fmaf(fp, Zm.y, -fm * Zk.y) + fmaf(wp, hm.y, -wm * hk.y));
+        zk = Sk;
+        if (!self) zm = Sm;
+        if (a.add_power) {
+            // X_A(k) = (S(k) + conj S(-k))/2, X_B(k) = (S(k) - conj S(-k))/(2i); |X(-k)| = |X(k)|
+            const double ar = 0.5 * ((double)Sk.x + Sm.x), ai = 0.5 * ((double)Sk.y - Sm.y);
+            const double br = 0.5 * ((double)Sk.y + Sm.y), bi = 0.5 * ((double)Sk.x - Sm.x);
+            const double wgt = self ? 1.0 : 2.0;
+            atomicAdd(&pw[0][b], wgt * (ar * ar + ai * ai));
+            atomicAdd(&pw[1][b], wgt * (br * br + bi * bi));
+        }
+    }
+    __syncthreads();
+    if (a.add_power)
+        for (unsigned u = tid; u < 2 * kNB; u += NTH) {
+            const double v = pw[u / kNB][u % kNB];
+            if (v != 0.0) atomicAdd(&a.pw[((int64_t)item * 2 + u / kNB) * kNB + u % kNB], v);
+        }
+    stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
+
+    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+        const int s = (int)(e % TC), y = (int)(e / TC);
+        fld[(int64_t)y * W + pair_column(j, s, half, W)] = lds[s * SEG + swz(y)];
+    }
+}
+
+// Chi-square sums of one iteration.  Block (x, item): variates [x chunk,
+// (x + 1) chunk) of the item's flat index over its bands' degrees of freedom;
+// each thread sums an even-length contiguous run in registers and flushes at
+// band boundaries.
+constexpr int kChiThreads = 256;
+constexpr int kChiChunk = 4096;
+
+__global__ __launch_bounds__(kChiThreads) void spectrum_chi_kernel(SpectrumStreamArgs a) {
+    __shared__ double acc[2][kNB];
+    __shared__ int32_t pre[kNB + 1];
+    const int item = blockIdx.y;
+    const ItemDev it = a.items[item];
+    const ProbDev pr = a.probs[it.prob];
+    const int nb = a.band_count[it.prob], bbase = a.band_base[it.prob];
+    for (int u = threadIdx.x; u < 2 * kNB; u += blockDim.x) acc[u / kNB][u % kNB] = 0.0;
+    if (threadIdx.x == 0) {
+        int s = 0;
+        for (int b = 0; b < nb; ++b) {
+            pre[b] = s;
+            s += a.dof[bbase + b];
+        }
+        pre[nb] = s;
+    }
+    __syncthreads();
+    constexpr int per = kChiChunk / kChiThreads;  // even
+    const int e0 = (int)blockIdx.x * kChiChunk + (int)threadIdx.x * per;
+    const int e1 = min(pre[nb], e0 + per);
+    if (e0 < e1) {
+        int b = 0;
+        while (pre[b + 1] <= e0) ++b;
+        double sa = 0.0, sb = 0.0;
+        for (int e = e0; e < e1; e += 2) {
+            const Normals2 z = pair_normals((uint32_t)(e >> 1), a.iteration, (uint32_t)pr.pid, kStageSpectrum,
+                                            (uint32_t)it.pair, a.key0, a.key1);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int ee = e + h;
+                if (ee >= e1) break;
+                if (ee >= pre[b + 1]) {
+                    atomicAdd(&acc[0][b], sa);
+                    atomicAdd(&acc[1][b], sb);
+                    sa = sb = 0.0;
+                    while (pre[b + 1] <= ee) ++b;
+                }
+                const float2 zz = h ? z.b : z.a;
+                sa += (double)zz.x * zz.x;
+                sb += (double)zz.y * zz.y;
+            }
+        }
+        atomicAdd(&acc[0][b], sa);
+        atomicAdd(&acc[1][b], sb);
+    }
+    __syncthreads();
+    for (int u = threadIdx.x; u < 2 * nb; u += blockDim.x) {
+        const double v = acc[u / nb][u % nb];
+        if (v != 0.0) atomicAdd(&a.chi[((int64_t)item * 2 + u / nb) * kNB + u % nb], v);
+    }
+}
+
+// draw = 1: new amplitudes theta = (2 beta_0 + sigma/n^2) / x from the sums,
+// written to the theta samples (slot >= 0); the sums cleared.  Always: the
+// coefficient table for the next sweeps and theta_out.  One block per item.
+__global__ void spectrum_theta_kernel(SpectrumStreamArgs a, int draw, int64_t slot) {
+    const int item = blockIdx.x;
+    const ItemDev it = a.items[item];
+    const ProbDev pr = a.probs[it.prob];
+    const int nb = a.band_count[it.prob], bbase = a.band_base[it.prob];
+    const double n = (double)pr.H * pr.W, T = pr.tau;
+    for (int u = threadIdx.x; u < 2 * nb; u += blockDim.x) {
+        const int ch = u / nb, b = u % nb;
+        const int64_t k = ((int64_t)item * 2 + ch) * kNB + b;
+        const int c = 2 * it.pair + ch;
+        double th = a.theta[k];
+        if (draw) {
+            const double x = a.chi[k];
+            if (a.dof[bbase + b] > 0 && x > 0.0) th = (2.0 * a.prior_beta + a.pw[k]) / x;
+            a.theta[k] = th;
+            a.pw[k] = 0.0;
+            a.chi[k] = 0.0;
+            if (slot >= 0 && a.theta_samples && c < a.chains)
+                a.theta_samples[(int64_t)a.chains * a.n_samples * bbase + ((int64_t)c * a.n_samples + slot) * nb + b] =
+                    th;
+        }
+        if (a.theta_out) a.theta_out[(int64_t)a.chains_pad * bbase + (int64_t)c * nb + b] = th;
+    }
+    __syncthreads();
+    float4* coef = a.coef + (int64_t)item * kNB;
+    for (int b = threadIdx.x; b < nb; b += blockDim.x) {
+        float c[4];
+#pragma unroll
+        for (int ch = 0; ch < 2; ++ch) {
+            const double nP = n * a.theta[((int64_t)item * 2 + ch) * kNB + b];
+            c[2 * ch] = (float)(nP / (nP + T) / n);
+            c[2 * ch + 1] = (float)(sqrt(n * nP * T / (nP + T)) / n);
+        }
+        coef[b] = make_float4(c[0], c[1], c[2], c[3]);
+    }
+}
+
+// Start amplitudes (theta_in or the plan's) and cleared sums.
+__global__ void spectrum_init_kernel(SpectrumStreamArgs a) {
+    const int item = blockIdx.x;
+    const ItemDev it = a.items[item];
+    const int nb = a.band_count[it.prob], bbase = a.band_base[it.prob];
+    for (int u = threadIdx.x; u < 2 * nb; u += blockDim.x) {
+        const int ch = u / nb, b = u % nb;
+        const int64_t k = ((int64_t)item * 2 + ch) * kNB + b;
+        const int c = 2 * it.pair + ch;
+        a.theta[k] = a.theta_in ? a.theta_in[(int64_t)a.chains_pad * bbase + (int64_t)c * nb + b] : a.theta0[bbase + b];
+        a.pw[k] = 0.0;
+        a.chi[k] = 0.0;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_spectrum_init(const SpectrumStreamArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(spectrum_init_kernel, dim3((unsigned)a.n_items), dim3(128), 0, s, a);
+    hipLaunchKernelGGL(spectrum_theta_kernel, dim3((unsigned)a.n_items), dim3(128), 0, s, a, 0, (int64_t)-1);
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum_col(int W, int H, const SpectrumStreamArgs& a, hipStream_t s) {
+    switch (H) {
+#define MF_CASE(LL)                                                                                    \
+    case LL:                                                                                           \
+        if (W < PairShape<LL>::TC) return hipErrorInvalidValue;                                        \
+        hipLaunchKernelGGL(col_pair_kernel<LL>, dim3((unsigned)((int64_t)a.n_items * (W / PairShape<LL>::TC))), \
+                           dim3(PairShape<LL>::NTH), 0, s, a, W);                                      \
+        break;
+        MF_CASE(16) MF_CASE(32) MF_CASE(64) MF_CASE(128) MF_CASE(256) MF_CASE(512) MF_CASE(1024) MF_CASE(2048)
+#undef MF_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_spectrum_draw(const SpectrumStreamArgs& a, int max_total_dof, int64_t slot, hipStream_t s) {
+    const int blocks = max_total_dof > 0 ? (max_total_dof + kChiChunk - 1) / kChiChunk : 1;
+    hipLaunchKernelGGL(spectrum_chi_kernel, dim3((unsigned)blocks, (unsigned)a.n_items), dim3(kChiThreads), 0, s, a);
+    hipLaunchKernelGGL(spectrum_theta_kernel, dim3((unsigned)a.n_items), dim3(128), 0, s, a, 1, slot);
+    return hipGetLastError();
+}
+
+}  // namespace mf

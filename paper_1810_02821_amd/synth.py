@@ -252,16 +252,17 @@ def bands_from_powerlaw(H: int, W: int, n_bands: int, k0: float, n: float) -> Sp
     return spectrum_bands(edges, amps)
 
 
-def config_bands(seed: int = 0, size: int = 256, n_bands: int = 32) -> Problem:
+def config_bands(seed: int = 0, size: int = 256, n_bands: int = 32, width: Optional[int] = None) -> Problem:
     """Band-amplitude spectrum for differentiation: 32 log bands seeded from
     P(k)=(k+1)^-2 at the mean |k| of each band, times U[0.8,1.2];
-    sigma~U[0.5,2]; 30% masked tiles."""
+    sigma~U[0.5,2]; 30% masked tiles.  size x size, or size x width."""
     rng = np.random.default_rng(seed)
-    base = bands_from_powerlaw(size, size, n_bands, 1.0, 2.0)
+    H, W = size, (size if width is None else width)
+    base = bands_from_powerlaw(H, W, n_bands, 1.0, 2.0)
     spec = spectrum_bands(base.edges, base.amps * rng.uniform(0.8, 1.2, size=n_bands))
-    sigma = _uniform_sigma(size, size, 0.5, 2.0, rng)
-    mask = tile_mask(size, size, 0.30, rng)
-    return make_problem(size, size, spec, sigma, mask, rng)
+    sigma = _uniform_sigma(H, W, 0.5, 2.0, rng)
+    mask = tile_mask(H, W, 0.30, rng)
+    return make_problem(H, W, spec, sigma, mask, rng)
 
 
 def config_large(seed: int = 0, size: int = 2048, n_bands: int = 0) -> Problem:
