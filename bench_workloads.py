@@ -17,7 +17,10 @@ grad   : 256x256 band-spectrum Wiener filter (32 bands) and its gradient
 spectrum: the hierarchical sampler (signal + 32 band amplitudes) on the
          128x128 band-spectrum recipe: 1024 chains, 100 iterations of one
          messenger sweep and one amplitude draw each; reports chain-iterations/s
-         next to the fixed-spectrum sampler's chain-sweeps/s on the same image.
+         next to the fixed-spectrum sampler's chain-sweeps/s on the same image;
+         then the streamed form on the 2048^2 large map with 32 log bands (64
+         chains, 20 iterations of 5 sweeps) against the streamed fixed-spectrum
+         sampler over the same 100 sweeps.
 solve  : Wiener filters of 256 independent 128x128 images (the paper-size
          recipe, one seed each): 20 cooling levels x 10 sweeps, then sweeps at
          lambda = 1 to a residual of 1e-5 tested every 10 sweeps; the persistent
@@ -192,11 +195,30 @@ def spectrum(args):
     print("[bench] spectrum: timing", file=sys.stderr, flush=True)
     t_h = _timed(run_h, max(1, args.steps // 2))
     t_s = _timed(run_s, max(1, args.steps // 2))
+    del st, plan
+    # streamed form: the 2048^2 large map with its spectrum as 32 log bands
+    print("[bench] spectrum: 2048^2 streamed", file=sys.stderr, flush=True)
+    N, lchains, liters, lsweeps = 2048, 64, 20, 5
+    lprob = synth.config_large(0, N, n_bands=32)
+    lplan = mf.Plan([lprob])
+    ld = lplan.concat([lprob.d])
+    lst = lplan.state_buffer(lchains)
+    run_lh = lambda: lplan.sample_spectrum(ld, 1000, lchains, 0, liters, 1, lsweeps, state_out=lst)
+    run_ls = lambda: lplan.sample(ld, 1000, chains=lchains, burn_in=liters * lsweeps, n_samples=0,
+                                  form="streamed", state_out=lst, samples=False)
+    run_lh()
+    run_ls()
+    t_lh = _timed(run_lh, 2)
+    t_ls = _timed(run_ls, 2)
     print(json.dumps({"workload": "spectrum",
                       "metric": "chain-iterations/s, hierarchical sampler at 128^2 (32 bands, 1024 chains)",
                       "value": chains * iters / t_h, "unit": "chain-iterations/s", "seconds": t_h,
                       "fixed_spectrum_chain_sweeps_per_s": chains * iters / t_s,
-                      "cost_ratio_vs_fixed_spectrum": t_h / t_s}), flush=True)
+                      "cost_ratio_vs_fixed_spectrum": t_h / t_s,
+                      "streamed_2048": {"chains": lchains, "iterations": liters, "sweeps_per_draw": lsweeps,
+                                        "chain_sweeps_per_s": lchains * liters * lsweeps / t_lh,
+                                        "fixed_spectrum_chain_sweeps_per_s": lchains * liters * lsweeps / t_ls,
+                                        "cost_ratio_vs_fixed_spectrum": t_lh / t_ls}}), flush=True)
 
 
 def run(args):

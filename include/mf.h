@@ -216,7 +216,11 @@ mf_status mf_sample(mf_plan plan, const float* d, const mf_sample_args* args,
 
 /* Hierarchical sampler (Sec. 5): samples of the signal and of the band
  * amplitudes theta_b of the power spectrum.  Every problem needs a band
- * spectrum and H = W in {32, 64, 128}.  Iteration i (global g = iteration_offset
+ * spectrum (MF_ERR_INVALID_ARG otherwise).  Size classes with H = W in {32,
+ * 64, 128} run one persistent kernel per call; every other size class runs
+ * the streamed kernels (one row and one column launch per sweep, two more per
+ * iteration), whose per-item amplitude sums live in a plan workspace that is
+ * allocated on first use.  Iteration i (global g = iteration_offset
  * + i) runs sweeps_per_draw sweeps of Algorithm 1 (global sweep indices
  * g * sweeps_per_draw + k) with the current amplitudes, then draws each band
  * amplitude from its conditional given the signal,

@@ -66,10 +66,13 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
     constexpr int half = TC / 2;
     __shared__ float2 lds[TC * SEG];
     __shared__ double pw[2][kNB];
+    __shared__ float4 coef[kNB];
     const unsigned tid = threadIdx.x;
+    // tile fastest: an XCD runs neighbouring tiles of one item together, so
+    // the cache lines they share meet in its L2
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);
-    const int item = (int)(t % a.n_items);
-    const int j = (int)(t / a.n_items);
+    const int item = (int)(t / (W / TC));
+    const int j = (int)(t % (W / TC));
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
     float2* fld = a.field + it.field_off;
@@ -79,14 +82,16 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
         lds[s * SEG + swz(y)] = fld[(int64_t)y * W + pair_column(j, s, half, W)];
     }
     for (unsigned u = tid; u < 2 * kNB; u += NTH) pw[u / kNB][u % kNB] = 0.0;
+    for (unsigned u = tid; u < kNB; u += NTH) coef[u] = a.coef[(int64_t)item * kNB + u];
     __syncthreads();
     const unsigned cid = tid / TPC, lane = tid % TPC;
     stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
 
-    // one job per mode pair {k, -k}: a first-half slot with its partner slot;
-    // in tile 0 the self-mirror columns 0 (slot 0) and W/2 (slot half) take
-    // the rows ky <= H/2, whose partners -ky lie in the same column
-    const float4* coef = a.coef + (int64_t)item * kNB;
+    // one job per mode pair {k, -k}: a first-half slot with its partner slot
+    // (consecutive lanes take consecutive slots of a row, so the band-index
+    // reads of a wave cover a few short row segments); in tile 0 the
+    // self-mirror columns 0 (slot 0) and W/2 (slot half) take the rows
+    // ky <= H/2, whose partners -ky lie in the same column
     const int16_t* band = a.band + pr.pix_off;
     const uint32_t pid = (uint32_t)pr.pid, pair = (uint32_t)it.pair;
     const int jobs = half * H + (j == 0 ? H / 2 + 1 : 0);
@@ -94,8 +99,8 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
     for (int q = opaque(tid); q < jobs; q += NTH) {
         int s, ky;
         if (q < half * H) {
-            s = q / H;
-            ky = q % H;
+            s = q % half;
+            ky = q / half;
             if (j == 0 && s == 0 && ky > H / 2) continue;
         } else {
             s = half;

@@ -217,10 +217,12 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     constexpr int H = L;
     __shared__ float2 lds[TC * SEG];
     const unsigned tid = threadIdx.x;
-    // tiles enumerated with the item fastest: t = tile * n_items + item
+    // tiles enumerated with the tile fastest: t = item * (W / TC) + tile.  An
+    // XCD then runs neighbouring tiles of one item together, and the cache
+    // lines they share (a 128-byte line spans 16 columns) meet in its L2.
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);
-    const int item = (int)(t % a.n_items);
-    const int x0 = (int)(t / a.n_items) * TC;
+    const int item = (int)(t / (W / TC));
+    const int x0 = (int)(t % (W / TC)) * TC;
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
     float2* fld = a.field + it.field_off + x0;
@@ -305,14 +307,15 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     }
 }
 
-__global__ void band_slots_reduce_kernel(SweepArgs a, int n_tiles, const int32_t* band_base,
+__global__ void band_slots_reduce_kernel(SweepArgs a, int tiles_per_item, const int32_t* band_base,
                                          const int32_t* band_count, double* out) {
     const int item = blockIdx.x;
     const ItemDev it = a.items[item];
     const int cnt = band_count[it.prob];
     for (int b = threadIdx.x; b < cnt; b += blockDim.x) {
         double s = 0.0;
-        for (int t = item; t < n_tiles; t += a.n_items) s += a.band_slots[(int64_t)t * kMaxBandsPerProblem + b];
+        for (int64_t t = (int64_t)item * tiles_per_item; t < (int64_t)(item + 1) * tiles_per_item; ++t)
+            s += a.band_slots[t * kMaxBandsPerProblem + b];
         out[band_base[it.prob] + b] = s;
     }
 }
@@ -653,8 +656,7 @@ hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s) {
 hipError_t launch_band_slots_reduce(int W, int H, int tc, const SweepArgs& a, const int32_t* band_base,
                                     const int32_t* band_count, double* out, hipStream_t s) {
     (void)H;
-    const int n_tiles = a.n_items * (W / tc);
-    hipLaunchKernelGGL(band_slots_reduce_kernel, dim3(a.n_items), dim3(64), 0, s, a, n_tiles, band_base, band_count,
+    hipLaunchKernelGGL(band_slots_reduce_kernel, dim3(a.n_items), dim3(64), 0, s, a, W / tc, band_base, band_count,
                        out);
     return hipGetLastError();
 }
