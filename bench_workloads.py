@@ -21,6 +21,12 @@ spectrum: the hierarchical sampler (signal + 32 band amplitudes) on the
          then the streamed form on the 2048^2 large map with 32 log bands (64
          chains, 20 iterations of 5 sweeps) against the streamed fixed-spectrum
          sampler over the same 100 sweeps.
+storage: the large-map sampling loop with the streamed field stored as FP32,
+         FP16 and BF16 (chain-sweeps/s each); then a drift study: 2048 chains
+         on a 64x64 image (6000 burn-in sweeps, 24 samples 8 apart) per
+         storage, the shift of their per-pixel posterior mean and standard
+         deviation from the FP32 run on the same stream, in posterior standard
+         deviations.
 solve  : Wiener filters of 256 independent 128x128 images (the paper-size
          recipe, one seed each): 20 cooling levels x 10 sweeps, then sweeps at
          lambda = 1 to a residual of 1e-5 tested every 10 sweeps; the persistent
@@ -221,5 +227,62 @@ def spectrum(args):
                                         "cost_ratio_vs_fixed_spectrum": t_lh / t_ls}}), flush=True)
 
 
+def storage(args):
+    import torch
+    import paper_1810_02821_amd as mf
+    from paper_1810_02821_amd import synth
+    # speed: the large-map sampling loop with the field stored in FP32, FP16, BF16
+    N, chains, sweeps, thin = 2048, 64, 200, 20
+    print("[bench] storage: generating 2048^2 problem", file=sys.stderr, flush=True)
+    prob = synth.config_large(0, N)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    n_samples = sweeps // thin
+    out = plan.samples_buffer(chains, n_samples)
+    st = plan.state_buffer(chains)
+    speed = {}
+    for stg in ("fp32", "fp16", "bf16"):
+        run = lambda: plan.sample(d, 1000, chains=chains, burn_in=0, n_samples=n_samples, thin=thin,
+                                  form="streamed", state_out=st, out=out, storage=stg)
+        run()
+        print(f"[bench] storage: timing {stg}", file=sys.stderr, flush=True)
+        t = _timed(run, max(1, args.steps // 2))
+        speed[stg] = {"chain_sweeps_per_s": chains * sweeps / t, "seconds": t}
+    del out, st, plan
+    # drift: per-pixel posterior mean and standard deviation of many chains on a
+    # 64^2 image, FP16 / BF16 storage against the FP32 run on the same stream,
+    # in units of the posterior standard deviation (the exact-posterior checks
+    # of the same samplers are GPU tests)
+    print("[bench] storage: drift study 64^2", file=sys.stderr, flush=True)
+    sp = synth.config_small(0, 64)
+    splan = mf.Plan([sp])
+    sd_d = splan.concat([sp.d])
+    dchains, burn, ns, dthin = 2048, 6000, 24, 8
+    moments = {}
+    for stg in ("fp32", "fp16", "bf16"):
+        flat, _ = splan.sample(sd_d, 4242, chains=dchains, burn_in=burn, n_samples=ns, thin=dthin,
+                               form="streamed", storage=stg)
+        m, v = splan.sample_moments(flat, dchains, ns)
+        moments[stg] = (m.cpu().numpy(), v.cpu().numpy())
+    m32, v32 = moments["fp32"]
+    sd32 = np.sqrt(v32)
+    drift = {}
+    for stg in ("fp16", "bf16"):
+        m, v = moments[stg]
+        dm = np.abs(m - m32) / sd32
+        drift[stg] = {"max_mean_shift_over_sd": float(dm.max()), "mean_mean_shift_over_sd": float(dm.mean()),
+                      "max_sd_ratio_minus_1": float(np.max(np.abs(np.sqrt(v / v32) - 1)))}
+    print(json.dumps({"workload": "storage",
+                      "metric": "chain-sweeps/s at 2048^2 (streamed, 64 chains) by field storage",
+                      "value": speed["fp16"]["chain_sweeps_per_s"], "unit": "chain-sweeps/s (fp16 storage)",
+                      "speed": speed,
+                      "speedup_fp16": speed["fp32"]["seconds"] / speed["fp16"]["seconds"],
+                      "speedup_bf16": speed["fp32"]["seconds"] / speed["bf16"]["seconds"],
+                      "drift_64": {"chains": dchains, "burn_in": burn, "samples": ns, "thin": dthin,
+                                   "mc_standard_error_over_sd": float(1.0 / np.sqrt(dchains * ns)),
+                                   "vs_fp32_same_stream": drift}}), flush=True)
+
+
 def run(args):
-    {"large": large, "uneven": uneven, "grad": grad, "solve": solve, "spectrum": spectrum}[args.workload](args)
+    {"large": large, "uneven": uneven, "grad": grad, "solve": solve, "spectrum": spectrum,
+     "storage": storage}[args.workload](args)

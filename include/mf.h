@@ -143,6 +143,23 @@ enum {
                                   test on the device, no host synchronisation per check) */
 };
 
+/* Storage of the streamed sampler's pair field in HBM between its two kernels
+ * per sweep (the reduced-bitwidth trade-off of Sec. 3.2).  Arithmetic
+ * stays FP32: each kernel widens what it loads and rounds (to nearest even)
+ * what it stores, so a sweep adds two roundings of the field, one after the
+ * row transforms and one after the column transforms.  Applies to the streamed
+ * and plain forms; the persistent form keeps the field in registers and
+ * ignores it.  state_in / state_out and the samples stay FP32.  FP16 holds
+ * magnitudes up to 65504: the row-transformed field reaches W times the
+ * largest |t| of a row, so data and signal must be scaled well inside that
+ * (values of order 1 are fine up to 2048 columns); BF16 has FP32's range and
+ * an 8-bit significand. */
+enum {
+    MF_STORAGE_FP32 = 0,       /* 8 bytes per pixel per chain pair (default) */
+    MF_STORAGE_FP16 = 1,       /* 4 bytes: IEEE binary16 pairs, unit roundoff 2^-11 */
+    MF_STORAGE_BF16 = 2        /* 4 bytes: bfloat16 pairs, unit roundoff 2^-8 */
+};
+
 /* Arguments of mf_sample. */
 typedef struct {
     uint64_t seed;             /* Philox key */
@@ -153,6 +170,7 @@ typedef struct {
     int64_t sweep_offset;      /* global sweep index of the first sweep (for resuming a chain) */
     float init_scale;          /* > 0: start from init_scale * stage-2 normals (ignored if state_in) */
     int32_t form;              /* MF_FORM_* */
+    int32_t storage;           /* MF_STORAGE_*: precision of the streamed field between kernels */
 } mf_sample_args;
 
 /* Arguments of mf_sample_spectrum. */

@@ -22,11 +22,14 @@ Data with Dataflow Engines"):
                   amplitudes given the signal) and the hierarchical sampler
                   that alternates it with Algorithm 1;
 * ``shear``     - mass mapping (Sec. 5): the messenger filter and sampler for
-                  complex shear data and the spin-2 operator A = F^-1 D F.
+                  complex shear data and the spin-2 operator A = F^-1 D F;
+* ``storage``   - the sampler with its field stored in 16-bit formats between
+                  the row and column transforms (the bit-width trade-off of
+                  Sec. 3.2), with the formats' rounding written out.
 
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import it.  It shares no code with the GPU path and never
 imports it; the two meet only through the seeded inputs of
 ``paper_1810_02821_amd.synth``.
 """
-from . import philox, messenger, dense, adjoint, spectrum, shear  # noqa: F401
+from . import philox, messenger, dense, adjoint, spectrum, shear, storage  # noqa: F401

@@ -95,6 +95,7 @@ struct mf_plan_s {
     DevBuf sched;                           // persistent solve: levels, sweeps, per-item outcome
     DevBuf spec;                            // hierarchical sampler: dof and start amplitudes per band
     DevBuf hier;                            // streamed hierarchical sampler: per-item amplitudes and sums
+    DevBuf hfield;                          // streamed sampler field in FP16 / BF16 storage
     std::vector<mf::ItemDev> items_cached;  // what items[0..] holds (skip re-uploads)
     // column-kernel tile shape per size class: (H, W) -> (tc, nth)
     std::map<std::pair<int, int>, std::pair<int, int>> col_shape;
@@ -134,6 +135,7 @@ struct mf_plan_s {
         sched.release();
         spec.release();
         hier.release();
+        hfield.release();
         for (auto& g : graphs) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
             if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -655,6 +657,7 @@ mf_status enqueue_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, i
     a.samples = samples;
     a.chains = g->chains_per_problem;
     a.n_samples = g->n_samples;
+    a.storage = g->storage;
     if (state_in != work)  // copy the given states, or make zero / dispersed starts
         MF_HIP(mf::launch_init_items(W, H, a, state_in, state_in ? 0.f : g->init_scale, s));
     const int64_t K = (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin;
@@ -691,7 +694,7 @@ mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, in
                                        (uint64_t)(uintptr_t)state_in, (uint64_t)(uintptr_t)samples, g->seed,
                                        (uint64_t)g->sweep_offset, (uint64_t)g->burn_in, (uint64_t)g->n_samples,
                                        (uint64_t)g->thin, (uint64_t)g->chains_per_problem, (uint64_t)init_bits,
-                                       (uint64_t)sh.first, (uint64_t)sh.second};
+                                       (uint64_t)sh.first, (uint64_t)sh.second, (uint64_t)g->storage};
     for (auto& e : p->graphs)
         if (e.key == key) {
             MF_HIP(hipGraphLaunch(e.exec, s));
@@ -1313,6 +1316,7 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
     if (g->sweep_offset + (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin > 0xffffffffLL)
         return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
     if (g->form < MF_FORM_AUTO || g->form > MF_FORM_PLAIN) return fail(MF_ERR_INVALID_ARG, "unknown form");
+    if (g->storage < MF_STORAGE_FP32 || g->storage > MF_STORAGE_BF16) return fail(MF_ERR_INVALID_ARG, "unknown storage");
     if (g->n_samples > 0 && !samples_out && !state_out)
         return fail(MF_ERR_INVALID_ARG, "nothing to write: samples_out and state_out are NULL");
     hipStream_t s = (hipStream_t)stream;
@@ -1339,6 +1343,12 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
     }
     if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
     MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
+    // reduced-precision storage: the streamed classes work in a 4-byte-per-element field
+    float2* hwork = nullptr;
+    if (g->storage != MF_STORAGE_FP32) {
+        MF_HIP(p->hfield.ensure(field_elems * 4));
+        hwork = p->hfield.as<float2>();
+    }
     float4* pcoef = nullptr;
     float2* psrc = nullptr;
     float4* mcoef = nullptr;
@@ -1385,11 +1395,22 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
             r.samples = samples_out;
             r.chains = g->chains_per_problem;
             MF_HIP(mf::launch_resident_sample(H, r, s));
-        } else if (form == MF_FORM_STREAMED) {
-            st = sample_streamed(p, di, (int)items.size(), H, W, d, g, work, sin, samples_out, s);
-        } else {  // plain: one chain pair per launch sequence
-            for (size_t i = 0; i < items.size() && st == MF_OK; ++i)
-                st = sample_streamed(p, di + i, 1, H, W, d, g, work, sin, samples_out, s);
+        } else {
+            float2* w = hwork ? hwork : work;
+            if (form == MF_FORM_STREAMED) {
+                st = sample_streamed(p, di, (int)items.size(), H, W, d, g, w, sin, samples_out, s);
+            } else {  // plain: one chain pair per launch sequence
+                for (size_t i = 0; i < items.size() && st == MF_OK; ++i)
+                    st = sample_streamed(p, di + i, 1, H, W, d, g, w, sin, samples_out, s);
+            }
+            if (st == MF_OK && hwork && state_out) {  // final states widened to FP32
+                mf::SweepArgs a = base_args(p, H, W);
+                a.items = di;
+                a.n_items = (int)items.size();
+                a.field = hwork;
+                a.storage = g->storage;
+                MF_HIP(mf::launch_copy_out_pairs(W, H, a, work, s));
+            }
         }
         if (st != MF_OK) return st;
     }

@@ -61,7 +61,12 @@ struct SweepArgs {
     const float2* t_load;     // col kernel: stored transform to pair with for band sums, or null
     double* band_slots;       // col kernel: per-tile band sums [tile][kMaxBandsPerProblem], accumulated
     const int16_t* band;      // per-mode band index (concatenated), -1 = none
+    int32_t storage;          // kStoreF32 / kStoreF16 / kStoreBF16: element type of `field`
 };
+
+// Element type of the work field (row, column, init and copy-out kernels of
+// the sampler): FP32 pairs, or FP16 / BF16 pairs of 4 bytes.
+enum Storage : int32_t { kStoreF32 = 0, kStoreF16 = 1, kStoreBF16 = 2 };
 
 enum PixMode : int32_t {
     kPixUpdate = 0,    // messenger step t = (1 - a) s + src (+ sigma xi)

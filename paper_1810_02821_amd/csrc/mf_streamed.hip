@@ -29,6 +29,40 @@ __device__ __forceinline__ const float2* fresh(const float2* p) {
     return p;
 }
 
+// Work-field elements: FP32 pairs, or FP16 / BF16 pairs (4 bytes) when the
+// sampler stores the field in reduced precision.  Arithmetic is FP32: loads
+// widen, stores round to nearest even (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32).
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ float2 widen(float2 e) { return e; }
+__device__ __forceinline__ float2 widen(f16x2 e) { return make_float2((float)e.x, (float)e.y); }
+__device__ __forceinline__ float2 widen(bf16x2 e) { return make_float2((float)e.x, (float)e.y); }
+__device__ __forceinline__ void narrow_to(float2& e, float2 v) { e = v; }
+__device__ __forceinline__ void narrow_to(f16x2& e, float2 v) {
+    e.x = (_Float16)v.x;
+    e.y = (_Float16)v.y;
+}
+__device__ __forceinline__ void narrow_to(bf16x2& e, float2 v) {
+    e.x = (__bf16)v.x;
+    e.y = (__bf16)v.y;
+}
+template <typename E>
+__device__ __forceinline__ E narrow(float2 v) {
+    E e;
+    narrow_to(e, v);
+    return e;
+}
+
+// Runs fn with a value of the field's element type (the storage flag is
+// uniform, so this is one scalar branch around the whole access loop).
+template <typename Fn>
+__device__ __forceinline__ void with_storage(int32_t st, Fn&& fn) {
+    if (st == kStoreF16) fn(f16x2{});
+    else if (st == kStoreBF16) fn(bf16x2{});
+    else fn(float2{});
+}
+
 __device__ __forceinline__ float pix_a(float T, float nb) {
     // a = T / (T + Nbar); Nbar = +inf on missing pixels gives a = 0
     return T * __builtin_amdgcn_rcpf(T + nb);
@@ -58,18 +92,22 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     const int64_t grow0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
 
     // ---- load ROWS rows (coalesced along x)
+    with_storage(a.storage, [&](auto e0) {
+        using E = decltype(e0);
+        const E* fld = reinterpret_cast<const E*>(a.field);
 #pragma unroll
-    for (int i = 0; i < ROWS * L / kThreads; ++i) {
-        const unsigned e = tid + i * kThreads;
-        const unsigned r = e / L, x = e % L;
-        const int64_t gr = grow0 + r;
-        float2 v = make_float2(0.f, 0.f);
-        if (gr < total_rows) {
-            const ItemDev it = a.items[gr % a.n_items];
-            v = a.field[it.field_off + (gr / a.n_items) * W + x];
+        for (int i = 0; i < ROWS * L / kThreads; ++i) {
+            const unsigned e = tid + i * kThreads;
+            const unsigned r = e / L, x = e % L;
+            const int64_t gr = grow0 + r;
+            float2 v = make_float2(0.f, 0.f);
+            if (gr < total_rows) {
+                const ItemDev it = a.items[gr % a.n_items];
+                v = widen(fld[it.field_off + (gr / a.n_items) * W + x]);
+            }
+            lds[r * L + swz(x)] = v;
         }
-        lds[r * L + swz(x)] = v;
-    }
+    });
     __syncthreads();
 
     const int64_t gr = grow0 + rid;
@@ -110,8 +148,11 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
                 }
             }
             if (valid)
-                for (unsigned x = lane; x < (unsigned)L; x += TPR)
-                    a.field[it.field_off + (int64_t)y * W + x] = row[swz(x)];
+                with_storage(a.storage, [&](auto e0) {
+                    using E = decltype(e0);
+                    E* fld = reinterpret_cast<E*>(a.field) + it.field_off + (int64_t)y * W;
+                    for (unsigned x = lane; x < (unsigned)L; x += TPR) fld[x] = narrow<E>(row[swz(x)]);
+                });
             return;
         }
     }
@@ -191,8 +232,11 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
       }
         stockham_fft<L, 1, TPR, false>(row, fresh(lane), fresh(a.tw_row));
         if (valid)
-            for (unsigned x = lane; x < (unsigned)L; x += TPR)
-                a.field[it.field_off + (int64_t)y * W + x] = row[swz(x)];
+            with_storage(a.storage, [&](auto e0) {
+                using E = decltype(e0);
+                E* fld = reinterpret_cast<E*>(a.field) + it.field_off + (int64_t)y * W;
+                for (unsigned x = lane; x < (unsigned)L; x += TPR) fld[x] = narrow<E>(row[swz(x)]);
+            });
     }
 }
 
@@ -225,13 +269,17 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     const int x0 = (int)(t % (W / TC)) * TC;
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
-    float2* fld = a.field + it.field_off + x0;
+    const int64_t f0 = it.field_off + x0;
 
+    with_storage(a.storage, [&](auto e0) {
+        using E = decltype(e0);
+        const E* fld = reinterpret_cast<const E*>(a.field) + f0;
 #pragma unroll 4
-    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
-        const unsigned c = e % TC, y = e / TC;
-        lds[c * SEG + swz(y)] = fld[(int64_t)y * W + c];
-    }
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const unsigned c = e % TC, y = e / TC;
+            lds[c * SEG + swz(y)] = widen(fld[(int64_t)y * W + c]);
+        }
+    });
     __syncthreads();
     const unsigned cid = tid / TPC, lane = tid % TPC;
     stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
@@ -300,11 +348,15 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     __syncthreads();
     stockham_fft<L, 1, TPC, true>(lds + fresh(cid) * SEG, fresh(lane), fresh(a.tw_col));
 
+    with_storage(a.storage, [&](auto e0) {
+        using E = decltype(e0);
+        E* fld = reinterpret_cast<E*>(a.field) + f0;
 #pragma unroll 4
-    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
-        const unsigned c = e % TC, y = e / TC;
-        fld[(int64_t)y * W + c] = lds[c * SEG + swz(y)];
-    }
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const unsigned c = e % TC, y = e / TC;
+            fld[(int64_t)y * W + c] = narrow<E>(lds[c * SEG + swz(y)]);
+        }
+    });
 }
 
 __global__ void band_slots_reduce_kernel(SweepArgs a, int tiles_per_item, const int32_t* band_base,
@@ -346,8 +398,12 @@ __global__ void init_kernel(SweepArgs a, int H, int W, const float2* state_in, f
             v0 = cscale(nz.a, init_scale);
             v1 = cscale(nz.b, init_scale);
         }
-        a.field[it.field_off + i] = v0;
-        a.field[it.field_off + i + 1] = v1;
+        with_storage(a.storage, [&](auto e0) {
+            using E = decltype(e0);
+            E* fld = reinterpret_cast<E*>(a.field) + it.field_off + i;
+            fld[0] = narrow<E>(v0);
+            fld[1] = narrow<E>(v1);
+        });
     }
 }
 
@@ -371,7 +427,10 @@ __global__ void copy_out_pairs_kernel(SweepArgs a, int H, int W, float2* out) {
         const int item = (int)(e / n);
         const int64_t i = e % n;
         const ItemDev it = a.items[item];
-        out[it.field_off + i] = a.field[it.field_off + i];
+        with_storage(a.storage, [&](auto e0) {
+            using E = decltype(e0);
+            out[it.field_off + i] = widen(reinterpret_cast<const E*>(a.field)[it.field_off + i]);
+        });
     }
 }
 

@@ -1,8 +1,9 @@
 """Distribution checks of the GPU samplers against the plain definitions,
 independent of the oracle's stream: many independent chains, their per-pixel
 mean against the Wiener filter of Eq. 2 and their variance against the
-diagonal of the posterior covariance of Eq. 7 (Sec. 4.1, Fig. 3), and the
-hierarchical sampler's amplitudes against their exact marginal without data.
+diagonal of the posterior covariance of Eq. 7 (Sec. 4.1, Fig. 3), also with
+the streamed field stored in 16 bits, and the hierarchical sampler's
+amplitudes against their exact marginal without data.
 Standard errors come from independent groups of chains; the bound on the
 largest z over all pixels (or bands) is the Student-t quantile of a
 family-wise two-sided level of 1e-3."""
@@ -26,13 +27,13 @@ def torch_cuda():
     return torch
 
 
-def _posterior_check(mf, prob, chains=2048, burn_in=3000, n_samples=24, thin=8, groups=32):
+def _posterior_check(mf, prob, chains=2048, burn_in=3000, n_samples=24, thin=8, groups=32, **kw):
     """The chain mean follows the deterministic messenger iteration from s = 0,
     so the burn-in must bring that iteration to its fixed point (3000 sweeps
     leave less than 0.5% of a posterior standard deviation at 32^2)."""
     plan = mf.Plan([prob])
     d = plan.concat([prob.d])
-    flat, _ = plan.sample(d, 4242, chains=chains, burn_in=burn_in, n_samples=n_samples, thin=thin)
+    flat, _ = plan.sample(d, 4242, chains=chains, burn_in=burn_in, n_samples=n_samples, thin=thin, **kw)
     x = plan.sample_view(flat, 0, chains, n_samples).cpu().numpy().astype(np.float64)
     x = x.reshape(chains, n_samples, -1)
     S = dense.signal_covariance(prob.spectrum, prob.H, prob.W)
@@ -64,6 +65,18 @@ def test_samples_with_response_have_the_posterior_moments_32(torch_cuda):
     import paper_1810_02821_amd as mf
     banner("posterior moments with response 32x32")
     zm, zv, bound = _posterior_check(mf, synth.config_response(2, 32, dead=0.05))
+    print(f"max z mean {zm:.2f}, max z var {zv:.2f}, bound {bound:.2f}")
+    assert zm < bound and zv < bound
+
+
+@pytest.mark.parametrize("storage", ["fp16", "bf16"])
+def test_samples_with_16_bit_storage_have_the_posterior_moments_32(torch_cuda, storage):
+    """The streamed sampler with its field stored in 16 bits between kernels
+    (3000 burn-in sweeps, each adding two roundings) still has the exact
+    posterior mean and variance within the Monte Carlo error."""
+    import paper_1810_02821_amd as mf
+    banner(f"posterior moments 32x32, streamed, {storage} storage")
+    zm, zv, bound = _posterior_check(mf, synth.config_small(0, 32), form="streamed", storage=storage)
     print(f"max z mean {zm:.2f}, max z var {zv:.2f}, bound {bound:.2f}")
     assert zm < bound and zv < bound
 
