@@ -96,6 +96,7 @@ struct mf_plan_s {
     DevBuf spec;                            // hierarchical sampler: dof and start amplitudes per band
     DevBuf hier;                            // streamed hierarchical sampler: per-item amplitudes and sums
     DevBuf hfield;                          // streamed sampler field in FP16 / BF16 storage
+    DevBuf kfield;                          // streamed mass mapping: kappa staging field
     std::vector<mf::ItemDev> items_cached;  // what items[0..] holds (skip re-uploads)
     // column-kernel tile shape per size class: (H, W) -> (tc, nth)
     std::map<std::pair<int, int>, std::pair<int, int>> col_shape;
@@ -136,6 +137,7 @@ struct mf_plan_s {
         spec.release();
         hier.release();
         hfield.release();
+        kfield.release();
         for (auto& g : graphs) {
             if (g.exec) (void)hipGraphExecDestroy(g.exec);
             if (g.graph) (void)hipGraphDestroy(g.graph);
@@ -461,12 +463,67 @@ mf_status data_gradient(mf_plan p, float* g, hipStream_t s) {
     return MF_OK;
 }
 
-// Shear problems: every problem H = W in {32, 64, 128}, no response.
+// Shear problems: no response.
 mf_status shear_check(mf_plan p) {
     if (p->has_response) return fail(MF_ERR_INVALID_ARG, "shear problems take no response");
-    for (const HostProblem& hp : p->probs)
-        if (!mf::resident_supported(hp.H, hp.W))
-            return fail(MF_ERR_UNSUPPORTED_SIZE, "mass mapping needs H = W in {32, 64, 128}");
+    return MF_OK;
+}
+
+// Mass mapping on the streamed kernels for one size class: per sweep the row
+// kernel and the mirror-paired column kernel; on a sweep that emits kappa
+// (or the last sweep of a filter) the emission kernel after them.
+mf_status shear_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H, int W, const float* gamma,
+                         float b_ratio, int chains, const std::vector<double>& lam, const std::vector<int32_t>& sweeps,
+                         int stochastic, uint64_t seed, int64_t sweep_offset, int burn_in, int n_samples, int thin,
+                         const float* state_in, float* state_out, float* samples, float* kappa_out, hipStream_t s) {
+    float2* field;
+    if (state_out) {
+        field = reinterpret_cast<float2*>(state_out);
+    } else {
+        MF_HIP(p->field.ensure((size_t)p->total_px * chains * sizeof(float2)));
+        field = p->field.as<float2>();
+    }
+    mf::ShearStreamArgs a{};
+    if (samples || kappa_out) {
+        MF_HIP(p->kfield.ensure((size_t)p->total_px * chains * sizeof(float2)));
+        a.kfield = p->kfield.as<float2>();
+    }
+    a.probs = p->d_probs;
+    a.items = di;
+    a.n_items = n_items;
+    a.field = field;
+    a.gamma = reinterpret_cast<const float2*>(gamma);
+    a.nbar = p->d_nbar;
+    a.nP = p->d_nP;
+    a.b_ratio = b_ratio;
+    a.tw_row = p->d_tw.at(W);
+    a.tw_col = p->d_tw.at(H);
+    a.key0 = (uint32_t)(seed & 0xffffffffu);
+    a.key1 = (uint32_t)(seed >> 32);
+    a.stochastic = stochastic;
+    a.samples = reinterpret_cast<float2*>(samples);
+    a.chains = chains;
+    a.n_samples = n_samples;
+    a.kappa_out = reinterpret_cast<float2*>(kappa_out);
+    const float2* sin = reinterpret_cast<const float2*>(state_in);
+    if (sin != field) MF_HIP(mf::launch_shear_init(W, H, a, sin, s));
+    int64_t total = 0;
+    for (int32_t k : sweeps) total += k;
+    int64_t k = 0;
+    for (size_t lv = 0; lv < lam.size(); ++lv) {
+        a.lambda = (float)lam[lv];
+        for (int32_t i = 0; i < sweeps[lv]; ++i, ++k) {
+            a.sweep = (uint32_t)(sweep_offset + k);
+            const bool emit = samples && k >= burn_in && ((k - burn_in + 1) % thin) == 0;
+            const bool last_kappa = kappa_out && k == total - 1;
+            a.emit = emit || last_kappa;
+            a.slot = emit ? (int)((k - burn_in + 1) / thin - 1) : -1;
+            MF_HIP(mf::launch_shear_row(W, H, k == 0 ? mf::kShearFwd : mf::kShearInvFwd, a, s));
+            MF_HIP(mf::launch_shear_col(W, H, a, s));
+            if (a.emit) MF_HIP(mf::launch_shear_row(W, H, mf::kShearEmit, a, s));
+        }
+    }
+    if (total > 0) MF_HIP(mf::launch_shear_row(W, H, mf::kShearInv, a, s));
     return MF_OK;
 }
 
@@ -486,14 +543,20 @@ mf_status launch_shear(mf_plan p, const float* gamma, float b_ratio, int chains,
     MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
     MF_HIP(hipStreamSynchronize(s));  // the host vectors must outlive the copies
     for (auto& kv : p->classes) {
-        const int N = kv.first.first;
+        const int N = kv.first.first, W = kv.first.second;
         std::vector<mf::ItemDev> items;
         for (int pid : kv.second)
             for (int c = 0; c < chains; ++c)
-                items.push_back({pid, c, (int64_t)chains * p->probs[pid].pix_off + (int64_t)c * N * N});
+                items.push_back({pid, c, (int64_t)chains * p->probs[pid].pix_off + (int64_t)c * N * W});
         mf::ItemDev* di = nullptr;
         mf_status st = put_items(p, items, 0, s, &di);
         if (st != MF_OK) return st;
+        if (!mf::resident_supported(N, W)) {
+            st = shear_streamed(p, di, (int)items.size(), N, W, gamma, b_ratio, chains, lam, sweeps, stochastic, seed,
+                                sweep_offset, burn_in, n_samples, thin, state_in, state_out, samples, kappa_out, s);
+            if (st != MF_OK) return st;
+            continue;
+        }
         mf::ShearArgs r{};
         r.probs = p->d_probs;
         r.items = di;

@@ -170,21 +170,23 @@ def shear_from_convergence(kappa: np.ndarray) -> np.ndarray:
     return np.fft.ifft2(kernel * np.fft.fft2(kappa))
 
 
-def config_shear(seed: int = 0, size: int = 128, b_ratio: float = 0.0) -> Problem:
+def config_shear(seed: int = 0, size: int = 128, b_ratio: float = 0.0, width: Optional[int] = None) -> Problem:
     """Mass mapping: convergence kappa = kappa_E + i kappa_B with
     P_E = (k+1)^-2 and P_B = b_ratio P_E, shear gamma = A kappa + n with
-    sigma ~ U[0.3, 1.0] per component, 20% masked 4x4 tiles.  `spectrum` is P_E."""
+    sigma ~ U[0.3, 1.0] per component, 20% masked 4x4 tiles.  `spectrum` is P_E.
+    size x size, or size x width."""
     rng = np.random.default_rng(seed)
+    H, W = size, (size if width is None else width)
     spec = spectrum_powerlaw(1.0, 1.0, 2.0)
-    sigma = _uniform_sigma(size, size, 0.3, 1.0, rng)
-    mask = tile_mask(size, size, 0.20, rng)
-    kE = grf(size, size, spec, rng)
-    kB = np.sqrt(b_ratio) * grf(size, size, spec, rng) if b_ratio > 0 else np.zeros((size, size))
+    sigma = _uniform_sigma(H, W, 0.3, 1.0, rng)
+    mask = tile_mask(H, W, 0.20, rng)
+    kE = grf(H, W, spec, rng)
+    kB = np.sqrt(b_ratio) * grf(H, W, spec, rng) if b_ratio > 0 else np.zeros((H, W))
     kappa = kE + 1j * kB
-    noise = sigma * (rng.standard_normal((size, size)) + 1j * rng.standard_normal((size, size)))
+    noise = sigma * (rng.standard_normal((H, W)) + 1j * rng.standard_normal((H, W)))
     g = np.where(mask, 0.0, shear_from_convergence(kappa) + noise)
     nv = np.where(mask, np.inf, sigma ** 2)
-    return Problem(H=size, W=size, d=np.zeros((size, size)), noise_var=nv, mask=mask, spectrum=spec,
+    return Problem(H=H, W=W, d=np.zeros((H, W)), noise_var=nv, mask=mask, spectrum=spec,
                    s_true=kE, gamma=g)
 
 
