@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--workload", default="paper", choices=["paper", "large", "uneven", "grad", "solve", "spectrum", "storage"],
+    ap.add_argument("--workload", default="paper", choices=["paper", "large", "uneven", "grad", "solve", "spectrum", "storage", "shear"],
                     help="paper (default, the headline line) or one of the other measured workloads")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (to scale HBM counters)")

@@ -27,6 +27,10 @@ storage: the large-map sampling loop with the streamed field stored as FP32,
          storage, the shift of their per-pixel posterior mean and standard
          deviation from the FP32 run on the same stream, in posterior standard
          deviations.
+shear  : the mass-mapping sampler (b_ratio 0.3): 1024 chains x 200 sweeps at
+         128x128 (persistent) and 32 chains x 100 sweeps at 2048x2048
+         (streamed, mirror-paired column tiles), every 10th / 20th convergence
+         map emitted.
 solve  : Wiener filters of 256 independent 128x128 images (the paper-size
          recipe, one seed each): 20 cooling levels x 10 sweeps, then sweeps at
          lambda = 1 to a residual of 1e-5 tested every 10 sweeps; the persistent
@@ -283,6 +287,33 @@ def storage(args):
                                    "vs_fp32_same_stream": drift}}), flush=True)
 
 
+def shear(args):
+    import torch
+    import paper_1810_02821_amd as mf
+    from paper_1810_02821_amd import synth
+    res = {}
+    # one chain per complex field; 128^2 runs the persistent kernel, 2048^2 the streamed kernels
+    for N, chains, sweeps, thin in ((128, 1024, 200, 10), (2048, 32, 100, 20)):
+        print(f"[bench] shear: {N}^2", file=sys.stderr, flush=True)
+        prob = synth.config_shear(0, N, 0.3)
+        plan = mf.Plan([prob])
+        g = plan.concat_complex([prob.gamma])
+        st = plan.shear_state_buffer(chains)
+        n_samples = sweeps // thin
+        run = lambda: plan.shear_sample(g, 1000, chains, 0, n_samples, thin, b_ratio=0.3, state_out=st)
+        run()
+        t = _timed(run, max(1, args.steps // 2))
+        res[str(N)] = {"chains": chains, "sweeps": sweeps, "samples_per_chain": n_samples,
+                       "form": "persistent" if N <= 128 else "streamed",
+                       "chain_sweeps_per_s": chains * sweeps / t, "seconds": t}
+        del st, plan, g
+        torch.cuda.empty_cache()
+    print(json.dumps({"workload": "shear",
+                      "metric": "chain-sweeps/s, mass-mapping sampler (complex convergence, b_ratio 0.3)",
+                      "value": res["128"]["chain_sweeps_per_s"], "unit": "chain-sweeps/s (128^2, persistent)",
+                      "by_size": res}), flush=True)
+
+
 def run(args):
     {"large": large, "uneven": uneven, "grad": grad, "solve": solve, "spectrum": spectrum,
-     "storage": storage}[args.workload](args)
+     "storage": storage, "shear": shear}[args.workload](args)

@@ -281,8 +281,12 @@ typedef struct {
  * variance noise_var per component.  The messenger field lives in shear
  * space (T = tau I, tau = min N); the Fourier step removes D and applies the
  * Wiener step of each real field (E = real part, B = imaginary part of
- * kappa); k = 0 is drawn from the prior.  Every problem needs H = W in
- * {32, 64, 128} and no response.
+ * kappa); k = 0 is drawn from the prior.  Problems take no response
+ * (MF_ERR_INVALID_ARG).  Size classes with H = W in {32, 64, 128} run one
+ * persistent kernel per call; every other class runs the streamed kernels
+ * (a row and a mirror-paired column launch per sweep, plus one row launch per
+ * emitted kappa), whose staging field is a plan workspace allocated on first
+ * use.
  *   gamma       device, concatenated complex shear (float2 per pixel)
  *   kappa_out   device, concatenated complex convergence (float2 per pixel)
  * mf_shear_wiener runs the schedule's sweeps from kappa = 0 (tol must be <= 0)
