@@ -245,6 +245,7 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
                      "kernel": "resident_sample_kernel<128>", "kernel_ms": kern_ms,
+                     "kernel_ms_sd": float(np.std(per_call_ms, ddof=1)) if len(per_call_ms) > 1 else 0.0,
                      "flops_per_pixel_pair_sweep": algorithmic_flops_per_pixel_pair_sweep(n_pix),
                      "hbm_algorithmic_bytes": hbm_bytes,
                      "hbm_achieved_GBps": hbm_gbps, "hbm_frac": hbm_gbps / PEAK_HBM_GBPS},
