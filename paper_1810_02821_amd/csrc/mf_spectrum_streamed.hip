@@ -151,8 +151,8 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
     }
 }
 
-// Chi-square sums of one iteration.  Block (x, item): variates [x chunk,
-// (x + 1) chunk) of the item's flat index over its bands' degrees of freedom;
+// Chi-square sums of one iteration.  Block (item, y): variates [y chunk,
+// (y + 1) chunk) of the item's flat index over its bands' degrees of freedom;
 // each thread sums an even-length contiguous run in registers and flushes at
 // band boundaries.
 constexpr int kChiThreads = 256;
@@ -161,7 +161,7 @@ constexpr int kChiChunk = 4096;
 __global__ __launch_bounds__(kChiThreads) void spectrum_chi_kernel(SpectrumStreamArgs a) {
     __shared__ double acc[2][kNB];
     __shared__ int32_t pre[kNB + 1];
-    const int item = blockIdx.y;
+    const int item = blockIdx.x;
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
     const int nb = a.band_count[it.prob], bbase = a.band_base[it.prob];
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kChiThreads) void spectrum_chi_kernel(SpectrumStrea
     }
     __syncthreads();
     constexpr int per = kChiChunk / kChiThreads;  // even
-    const int e0 = (int)blockIdx.x * kChiChunk + (int)threadIdx.x * per;
+    const int e0 = (int)blockIdx.y * kChiChunk + (int)threadIdx.x * per;
     const int e1 = min(pre[nb], e0 + per);
     if (e0 < e1) {
         int b = 0;
@@ -290,7 +290,7 @@ hipError_t launch_spectrum_col(int W, int H, const SpectrumStreamArgs& a, hipStr
 
 hipError_t launch_spectrum_draw(const SpectrumStreamArgs& a, int max_total_dof, int64_t slot, hipStream_t s) {
     const int blocks = max_total_dof > 0 ? (max_total_dof + kChiChunk - 1) / kChiChunk : 1;
-    hipLaunchKernelGGL(spectrum_chi_kernel, dim3((unsigned)blocks, (unsigned)a.n_items), dim3(kChiThreads), 0, s, a);
+    hipLaunchKernelGGL(spectrum_chi_kernel, dim3((unsigned)a.n_items, (unsigned)blocks), dim3(kChiThreads), 0, s, a);
     hipLaunchKernelGGL(spectrum_theta_kernel, dim3((unsigned)a.n_items), dim3(128), 0, s, a, 1, slot);
     return hipGetLastError();
 }
