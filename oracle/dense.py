@@ -11,6 +11,10 @@ For images small enough to hold n x n matrices (n <= a few thousand pixels):
       s_W = S A^T (A S A^T + N_o)^{-1} d_o;
 * posterior covariance of Eq. 7, (S^-1 + A^T N_o^-1 A)^-1, in the equivalent
   Woodbury form S - S A^T (A S A^T + N_o)^-1 A S, which needs no S^-1;
+* the mass-mapping posterior (Sec. 5): gamma = A kappa + n with A built from
+  explicit sums over the modes (no FFT) and kappa = kappa_E + i kappa_B two
+  independent fields with spectra P and b_ratio P, as one real Gaussian
+  linear model in [kappa_E; kappa_B];
 * the exact stationary law of the Gibbs chain: one sampler sweep is an affine
   map s' = M s + c + B z of the state and of the unit normals z, so the chain
   is a discrete Lyapunov system whose stationary mean solves (I - M) m = c and
@@ -132,3 +136,38 @@ def stationary_law(M: np.ndarray, c: np.ndarray, B: np.ndarray):
     Q = B @ B.T
     Sigma = scipy.linalg.solve_discrete_lyapunov(M, Q)
     return mean, 0.5 * (Sigma + Sigma.T)
+
+
+def spin2_operator(H: int, W: int) -> np.ndarray:
+    """Complex n x n matrix of gamma = A kappa for the spin-2 shear operator:
+    A_xy = (1/n) sum_k D_k e^{2 pi i k.(x - y)}, D_k = (k_1 + i k_2)^2/|k|^2
+    (k_1 along x), D_0 = 0, summed over the integer modes directly."""
+    ky = _mode_grid(H)
+    kx = _mode_grid(W)
+    KY, KX = np.meshgrid(ky, kx, indexing="ij")
+    den = KX ** 2 + KY ** 2
+    D = np.where(den > 0, ((KX ** 2 - KY ** 2) + 2j * KX * KY) / np.where(den > 0, den, 1.0), 0.0)
+    yy, xx = np.divmod(np.arange(H * W), W)
+    ph = 2j * np.pi * (np.outer(yy, KY.ravel()) / H + np.outer(xx, KX.ravel()) / W)
+    E = np.exp(ph)
+    return (E * D.ravel()[None, :]) @ np.conj(E).T / (H * W)
+
+
+def shear_posterior(problem, b_ratio: float):
+    """Mean and covariance of [kappa_E; kappa_B] (2n) given the shear data of
+    a mass-mapping problem (missing pixels drop out of both components)."""
+    H, W = problem.H, problem.W
+    n = H * W
+    Ac = spin2_operator(H, W)
+    A = np.block([[Ac.real, -Ac.imag], [Ac.imag, Ac.real]])
+    SE = signal_covariance(problem.spectrum, H, W)
+    S = np.block([[SE, np.zeros((n, n))], [np.zeros((n, n)), b_ratio * SE]])
+    nv = np.concatenate([problem.noise_var.ravel(), problem.noise_var.ravel()])
+    obs = np.isfinite(nv)
+    g = np.concatenate([problem.gamma.real.ravel(), problem.gamma.imag.ravel()])
+    Ao = A[obs]
+    K = Ao @ S @ Ao.T + np.diag(nv[obs])
+    SA = S @ Ao.T
+    mean = SA @ np.linalg.solve(K, g[obs])
+    cov = S - SA @ np.linalg.solve(K, SA.T)
+    return mean, 0.5 * (cov + cov.T)

@@ -3,7 +3,9 @@ independent of the oracle's stream: many independent chains, their per-pixel
 mean against the Wiener filter of Eq. 2 and their variance against the
 diagonal of the posterior covariance of Eq. 7 (Sec. 4.1, Fig. 3), also with
 the streamed field stored in 16 bits, and the hierarchical sampler's
-amplitudes against their exact marginal without data.
+amplitudes against their exact marginal without data (persistent and
+streamed forms), and the mass-mapping sampler against the dense posterior of
+gamma = A kappa + n.
 Standard errors come from independent groups of chains; the bound on the
 largest z over all pixels (or bands) is the Student-t quantile of a
 family-wise two-sided level of 1e-3."""
@@ -97,6 +99,53 @@ def test_hierarchical_amplitudes_follow_the_prior_without_data(torch_cuda):
     plan = mf.Plan([p])
     chains = 4096
     ts, _, _, _ = plan.sample_spectrum(plan.concat([p.d]), 77, chains, 400, 1, 1, 5, nu0, beta0)
+    th = plan.theta_view(ts, 0, chains, 1).cpu().numpy()[:, 0, :]
+    lt = np.log(th)
+    target = np.log(beta0) - special.digamma(nu0 / 2.0)
+    z = np.abs(lt.mean(axis=0) - target) / (lt.std(axis=0, ddof=1) / np.sqrt(chains))
+    bound = stats.norm.ppf(1 - 1e-3 / (2 * lt.shape[1]))
+    print(f"E log theta per band {lt.mean(axis=0)}, target {target:.4f}, max z {z.max():.2f}, bound {bound:.2f}")
+    assert z.max() < bound
+
+
+def test_shear_samples_have_the_posterior_moments_32(torch_cuda):
+    """Mass mapping: 2048 chains of the convergence (E and B, b_ratio 0.5)
+    have the mean and variance of the dense posterior of gamma = A kappa + n."""
+    import paper_1810_02821_amd as mf
+    banner("mass-mapping posterior moments 32x32")
+    p = synth.config_shear(3, 32, 0.5)
+    mean, cov = dense.shear_posterior(p, 0.5)
+    sd2 = np.diag(cov)
+    plan = mf.Plan([p])
+    g = plan.concat_complex([p.gamma])
+    chains, burn_in, n_samples, thin, groups = 2048, 3000, 24, 8, 32
+    out, _ = plan.shear_sample(g, 91, chains, burn_in, n_samples, thin, b_ratio=0.5)
+    k = out.view(chains, n_samples, -1).cpu().numpy()
+    x = np.concatenate([k.real, k.imag], axis=2).astype(np.float64)      # [chain][sample][kE; kB]
+    gr = x.reshape(groups, -1, x.shape[-1])
+    gm = gr.mean(axis=1)
+    z_mean = np.abs(gm.mean(axis=0) - mean) / (gm.std(axis=0, ddof=1) / np.sqrt(groups))
+    gv = ((gr - mean) ** 2).mean(axis=1)
+    z_var = np.abs(gv.mean(axis=0) - sd2) / (gv.std(axis=0, ddof=1) / np.sqrt(groups))
+    bound = stats.t.ppf(1 - 1e-3 / (2 * 2 * x.shape[-1]), groups - 1)
+    print(f"max z mean {z_mean.max():.2f}, max z var {z_var.max():.2f}, bound {bound:.2f}")
+    assert z_mean.max() < bound and z_var.max() < bound
+
+
+def test_streamed_hierarchical_amplitudes_follow_the_prior_without_data(torch_cuda):
+    """The prior-recovery check of the hierarchical sampler on a 32 x 64 image,
+    which runs on the streamed kernels with mirror-paired column tiles."""
+    import paper_1810_02821_amd as mf
+    banner("hierarchical prior recovery 32x64 (streamed)")
+    p = synth.config_bands(1, 32, 6, width=64)
+    nu0, beta0 = 6, 2e-4
+    p.noise_var = np.full((32, 64), np.inf)
+    p.mask = np.ones((32, 64), dtype=bool)
+    p.d = np.zeros((32, 64))
+    p.spectrum = synth.spectrum_bands(p.spectrum.edges, np.full(6, beta0 / 2.0))
+    plan = mf.Plan([p])
+    chains = 4096
+    ts, _, _, _ = plan.sample_spectrum(plan.concat([p.d]), 78, chains, 400, 1, 1, 5, nu0, beta0)
     th = plan.theta_view(ts, 0, chains, 1).cpu().numpy()[:, 0, :]
     lt = np.log(th)
     target = np.log(beta0) - special.digamma(nu0 / 2.0)

@@ -8,35 +8,8 @@ from oracle import dense, messenger as om, shear as osh
 from paper_1810_02821_amd import synth
 
 
-def _dense_A(H, W):
-    """Complex n x n matrix of gamma = A kappa: (1/n) sum_k D_k e^{2 pi i k.(x - y)}."""
-    ky = np.arange(-(H // 2), H - H // 2, dtype=np.float64)
-    kx = np.arange(-(W // 2), W - W // 2, dtype=np.float64)
-    KY, KX = np.meshgrid(ky, kx, indexing="ij")
-    den = KX ** 2 + KY ** 2
-    D = np.where(den > 0, ((KX ** 2 - KY ** 2) + 2j * KX * KY) / np.where(den > 0, den, 1.0), 0.0)
-    yy, xx = np.divmod(np.arange(H * W), W)
-    ph = 2j * np.pi * (np.outer(yy, KY.ravel()) / H + np.outer(xx, KX.ravel()) / W)
-    E = np.exp(ph)                                  # pixel x mode
-    return (E * D.ravel()[None, :]) @ np.conj(E).T / (H * W)
-
-
-def _dense_posterior(p, b_ratio):
-    H, W = p.H, p.W
-    n = H * W
-    Ac = _dense_A(H, W)
-    A = np.block([[Ac.real, -Ac.imag], [Ac.imag, Ac.real]])       # [k_E; k_B] -> [g_1; g_2]
-    SE = dense.signal_covariance(p.spectrum, H, W)
-    S = np.block([[SE, np.zeros((n, n))], [np.zeros((n, n)), b_ratio * SE]])
-    nv = np.concatenate([p.noise_var.ravel(), p.noise_var.ravel()])
-    obs = np.isfinite(nv)
-    g = np.concatenate([p.gamma.real.ravel(), p.gamma.imag.ravel()])
-    Ao = A[obs]
-    K = Ao @ S @ Ao.T + np.diag(nv[obs])
-    SA = S @ Ao.T
-    mean = SA @ np.linalg.solve(K, g[obs])
-    cov = S - SA @ np.linalg.solve(K, SA.T)
-    return mean, 0.5 * (cov + cov.T)
+_dense_A = dense.spin2_operator
+_dense_posterior = dense.shear_posterior
 
 
 def test_kernel_is_unitary_off_zero_and_matches_the_generator():
