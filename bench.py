@@ -189,7 +189,7 @@ def main():
     hbm_gbps = hbm_bytes / (kern_ms / 1000.0) / 1e9
     traffic = TRAFFIC_BYTES if TRAFFIC_SOURCES_SHA == kernel_sources_sha() else None
 
-    extra = {}
+    extra = {"chain_sweeps_per_s": CHAINS * sweeps / (ms_per_step / 1000.0)}
     # per-pixel mean and variance of the step's samples (the maps of Fig. 3)
     plan.sample_moments(out, CHAINS, N_SAMPLES)
     torch.cuda.synchronize()
