@@ -137,10 +137,13 @@ enum {
     MF_FLAG_GRAPH = 2,         /* capture the streamed sampler's sweep loop of each size class as a HIP
                                   graph, once per launch configuration (pointers, counts, seed, sweep
                                   range), and replay it; the plan keeps up to 8 graphs */
-    MF_FLAG_STREAMED_SOLVE = 4 /* run mf_wiener / mf_wiener_backward on the streamed kernels for every size
+    MF_FLAG_STREAMED_SOLVE = 4, /* run mf_wiener / mf_wiener_backward on the streamed kernels for every size
                                   class; without it, classes with H = W in {32, 64, 128} use the persistent
                                   solve kernel (one workgroup per problem, every level and the residual
                                   test on the device, no host synchronisation per check) */
+    MF_FLAG_INF_AS_1E8 = 8     /* give missing pixels (noise +inf, or response 0) the noise variance 1e8,
+                                  the finite stand-in for infinite noise of Sec. 3.2, instead of the exact
+                                  limit a = 0; the results differ by O(T / 1e8) */
 };
 
 /* Storage of the streamed sampler's pair field in HBM between its two kernels

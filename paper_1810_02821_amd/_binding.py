@@ -24,6 +24,7 @@ STORAGES = {"fp32": 0, "fp16": 1, "bf16": 2}
 MF_FLAG_AUTOTUNE = 1
 MF_FLAG_GRAPH = 2
 MF_FLAG_STREAMED_SOLVE = 4
+MF_FLAG_INF_AS_1E8 = 8
 
 
 class MFError(RuntimeError):
@@ -198,7 +199,8 @@ class Plan:
     """A set of image problems (size, noise variance map with +inf on missing
     pixels, isotropic power spectrum) with their device tables."""
 
-    def __init__(self, problems, autotune: bool = False, graph: bool = False, streamed_solve: bool = False):
+    def __init__(self, problems, autotune: bool = False, graph: bool = False, streamed_solve: bool = False,
+                 inf_as_1e8: bool = False):
         L = lib()
         self.problems = list(problems)
         keep = []
@@ -216,7 +218,7 @@ class Plan:
             arr[i] = _Problem(int(p.H), int(p.W), nv.ctypes.data_as(C.POINTER(C.c_float)), spec, rp)
         h = C.c_void_p()
         flags = ((MF_FLAG_AUTOTUNE if autotune else 0) | (MF_FLAG_GRAPH if graph else 0)
-                 | (MF_FLAG_STREAMED_SOLVE if streamed_solve else 0))
+                 | (MF_FLAG_STREAMED_SOLVE if streamed_solve else 0) | (MF_FLAG_INF_AS_1E8 if inf_as_1e8 else 0))
         _check(L.mf_plan_create(C.byref(h), len(self.problems), arr, flags, None))
         self._h = h
         self.offsets = [L.mf_plan_pixel_offset(h, i) for i in range(len(self.problems) + 1)]

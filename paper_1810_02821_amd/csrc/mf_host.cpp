@@ -971,6 +971,10 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
         return fail(MF_ERR_INVALID_ARG, "need 1 <= n_problems < 2^24 and a problem array");
     mf_plan p = new (std::nothrow) mf_plan_s();
     if (!p) return fail(MF_ERR_OUT_OF_MEMORY, "host allocation failed");
+    if (flags & ~(uint32_t)(MF_FLAG_AUTOTUNE | MF_FLAG_GRAPH | MF_FLAG_STREAMED_SOLVE | MF_FLAG_INF_AS_1E8)) {
+        delete p;
+        return fail(MF_ERR_INVALID_ARG, "unknown plan flags");
+    }
     p->flags = flags;
     (void)hipGetDevice(&p->device);
     int64_t off = 0;
@@ -1032,6 +1036,7 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
                 rinv[hp.pix_off + e] = a != 0.0 ? (float)(1.0 / a) : 0.0f;
             }
             if (std::isfinite(v) && a != 0.0) neff[e] = (double)v / (a * a);
+            else if (flags & MF_FLAG_INF_AS_1E8) neff[e] = 1e8;
             if (std::isfinite(neff[e])) tau = std::min(tau, neff[e]);
         }
         if (!std::isfinite(tau)) tau = 1.0;  // every pixel missing: any T samples the prior

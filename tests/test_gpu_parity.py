@@ -339,3 +339,43 @@ def test_persistent_multi_problem_and_state(torch_cuda):
                     plan.sample_view(full, i, 4, 2).cpu().numpy()[c, k])
                 for i in range(4) for c in range(4) for k in range(2))
     assert worst < 1e-5
+
+
+@pytest.mark.parametrize("solve", ["persistent", "streamed"])
+def test_inf_as_1e8_flag_matches_the_finite_noise_problem(torch_cuda, solve):
+    """MF_FLAG_INF_AS_1E8 gives missing pixels the noise variance 1e8: the
+    filter and the samples equal the oracle's on the problem with 1e8 written
+    in, and the plan equals one made from that problem without the flag."""
+    import copy
+    torch = torch_cuda
+    mf = _mf()
+    banner(f"inf as 1e8, {solve}")
+    prob = synth.config_small(5, 64)
+    fin = copy.copy(prob)
+    fin.noise_var = np.where(np.isfinite(prob.noise_var), prob.noise_var, 1e8)
+    plan = mf.Plan([prob], streamed_solve=solve == "streamed", inf_as_1e8=True)
+    ref_plan = mf.Plan([fin], streamed_solve=solve == "streamed")
+    d = plan.concat([prob.d])
+    levels = [(30.0, 5), (1.0, 40)]
+    sch = mf.Schedule([l for l, _ in levels], [k for _, k in levels])
+    s, _ = plan.wiener(d, sch)
+    s2, _ = ref_plan.wiener(d, sch)
+    assert torch.equal(s, s2)
+    ref, _ = om.wiener(fin, om.Schedule(tuple(l for l, _ in levels), tuple(k for _, k in levels)))
+    r = rel(plan.split(s)[0], ref)
+    form = "persistent" if solve == "persistent" else "streamed"
+    flat, _ = plan.sample(d, 12, chains=2, burn_in=3, n_samples=2, form=form)
+    x = plan.sample_view(flat, 0, 2, 2).cpu().numpy()
+    smp, _ = om.sample_pair(fin, 12, 0, 0, 3, 2)
+    rs = max(rel(x[h, k], smp[h, k]) for h in range(2) for k in range(2))
+    print(f"filter rel {r:.2e}, samples rel {rs:.2e}")
+    assert r < REL_TOL and rs < REL_TOL
+    with pytest.raises(mf.MFError):
+        from paper_1810_02821_amd import _binding
+        import ctypes as C
+        h = C.c_void_p()
+        arr = (_binding._Problem * 1)()
+        nv = np.ascontiguousarray(prob.noise_var, dtype=np.float32)
+        spec, keep = _binding._spectrum_c(prob.spectrum)
+        arr[0] = _binding._Problem(64, 64, nv.ctypes.data_as(C.POINTER(C.c_float)), spec, None)
+        _binding._check(_binding.lib().mf_plan_create(C.byref(h), 1, arr, 1 << 20, None))
