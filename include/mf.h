@@ -174,6 +174,11 @@ typedef struct {
     float init_scale;          /* > 0: start from init_scale * stage-2 normals (ignored if state_in) */
     int32_t form;              /* MF_FORM_* */
     int32_t storage;           /* MF_STORAGE_*: precision of the streamed field between kernels */
+    const mf_schedule* cooling;/* host, or NULL: levels (lambda_j >= 1, sweeps_j) run before the burn-in,
+                                  sampling with T = lambda_j tau (the posterior for noise
+                                  N + (lambda_j - 1) tau), global sweep indices sweep_offset, ...; the
+                                  burn-in then starts at sweep_offset + sum_j sweeps_j.  tol is ignored.
+                                  These sweeps run on the streamed kernels for every form. */
 } mf_sample_args;
 
 /* Arguments of mf_sample_spectrum. */

@@ -343,18 +343,28 @@ def pair_normals(seed: int, stage: int, sweep_index: int, problem_index: int,
 def sample_pair(problem, seed: int, problem_index: int, pair: int,
                 burn_in: int, n_samples: int, thin: int = 1,
                 s0: Optional[np.ndarray] = None, sweep_offset: int = 0,
-                c: Optional[Coefficients] = None):
+                c: Optional[Coefficients] = None, cooling: Sequence = ()):
     """Run one chain pair; returns (samples [2, n_samples, H, W], last state).
 
     Sweep k (global index sweep_offset + k) draws xi from stage 0 and eta from
     stage 1 of the stream.  A sample is the state after sweep k when
-    k >= burn_in and (k - burn_in + 1) is a multiple of thin."""
+    k >= burn_in and (k - burn_in + 1) is a multiple of thin.  `cooling`
+    levels (lambda, sweeps) run first, each sweep drawn at T = lambda tau
+    (so it samples the posterior for noise N + (lambda - 1) tau), taking the
+    global sweep indices before the burn-in's."""
     H, W = problem.H, problem.W
     if c is None:
         c = coefficients(problem.noise_var, problem.spectrum, 1.0, None, response_of(problem))
     d = np.where(problem.mask, 0.0, problem.d)
-    b = c.ninv * d
     s = np.zeros((H, W), dtype=np.complex128) if s0 is None else np.array(s0, dtype=np.complex128)
+    for lam, n_lev in cooling:
+        cl = coefficients(problem.noise_var, problem.spectrum, float(lam), None, response_of(problem))
+        for _ in range(int(n_lev)):
+            xi = pair_normals(seed, philox.STAGE_PIXEL, sweep_offset, problem_index, pair, H, W)
+            eta = pair_normals(seed, philox.STAGE_HARMONIC, sweep_offset, problem_index, pair, H, W)
+            s, _ = sweep(s, cl.ninv * d, cl, xi, eta)
+            sweep_offset += 1
+    b = c.ninv * d
     out = np.empty((2, n_samples, H, W))
     emitted = 0
     total = burn_in + n_samples * thin

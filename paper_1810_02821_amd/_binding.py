@@ -64,7 +64,8 @@ class Info(C.Structure):
 class _SampleArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("chains_per_problem", C.c_int32), ("burn_in", C.c_int32),
                 ("n_samples", C.c_int32), ("thin", C.c_int32), ("sweep_offset", C.c_int64),
-                ("init_scale", C.c_float), ("form", C.c_int32), ("storage", C.c_int32)]
+                ("init_scale", C.c_float), ("form", C.c_int32), ("storage", C.c_int32),
+                ("cooling", C.POINTER(_Schedule))]
 
 
 class _SpectrumArgs(C.Structure):
@@ -286,17 +287,21 @@ class Plan:
 
     def sample(self, d, seed: int, chains: int, burn_in: int, n_samples: int, thin: int = 1,
                sweep_offset: int = 0, init_scale: float = 0.0, form: str = "auto",
-               state_in=None, state_out=None, samples=True, out=None, storage: str = "fp32"):
+               state_in=None, state_out=None, samples=True, out=None, storage: str = "fp32",
+               cooling: Optional["Schedule"] = None):
         """Returns (samples [concat over problems of chains*n_samples*H*W] or None,
         state_out or None).  `out` may hold a preallocated samples buffer.
         `storage` ("fp32", "fp16", "bf16") is the precision of the streamed
-        field between kernels (streamed and plain forms)."""
+        field between kernels (streamed and plain forms).  `cooling` levels
+        (lambda >= 1, sweeps) run before the burn-in."""
         if out is None and samples and n_samples > 0:
             out = self.samples_buffer(chains, n_samples, d.device)
         if out is not None and out.numel() < chains * n_samples * self.total_pixels:
             raise ValueError("samples buffer too small")
+        cool = cooling._c() if cooling is not None else None
         args = _SampleArgs(int(seed), int(chains), int(burn_in), int(n_samples), int(thin),
-                           int(sweep_offset), float(init_scale), FORMS[form], STORAGES[storage])
+                           int(sweep_offset), float(init_scale), FORMS[form], STORAGES[storage],
+                           C.pointer(cool) if cool is not None else None)
         st = lib().mf_sample(self._h, _ptr(d), C.byref(args), _ptr(state_in), _ptr(state_out),
                              _ptr(out), _stream())
         _check(st)

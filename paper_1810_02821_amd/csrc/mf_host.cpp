@@ -743,6 +743,34 @@ mf_status enqueue_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, i
     return MF_OK;
 }
 
+// Cooling levels before a sampler's burn-in (streamed kernels, no emission):
+// w ends holding the pair states s after the last cooling sweep.
+mf_status cool_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int H, int W, const float* d,
+                        const mf_sample_args* g, int storage, float2* w, const float2* state_in, hipStream_t s) {
+    mf::SweepArgs a = base_args(p, H, W);
+    a.items = d_items;
+    a.n_items = n_items;
+    a.field = w;
+    a.src = d;
+    a.src_kind = mf::kSrcData;
+    a.stochastic = 1;
+    a.key0 = (uint32_t)(g->seed & 0xffffffffu);
+    a.key1 = (uint32_t)(g->seed >> 32);
+    a.storage = storage;
+    if (state_in != w) MF_HIP(mf::launch_init_items(W, H, a, state_in, state_in ? 0.f : g->init_scale, s));
+    int64_t k = 0;
+    for (int j = 0; j < g->cooling->n_levels; ++j) {
+        a.lambda = (float)g->cooling->lambda[j];
+        for (int32_t i = 0; i < g->cooling->sweeps[j]; ++i, ++k) {
+            a.sweep = (uint32_t)(g->sweep_offset + k);
+            MF_HIP(mf::launch_row(W, H, k == 0 ? mf::kRowFwd : mf::kRowInvFwd, a, s));
+            MF_HIP(launch_col_class(p, W, H, a, s));
+        }
+    }
+    if (k > 0) MF_HIP(mf::launch_row(W, H, mf::kRowInv, a, s));
+    return MF_OK;
+}
+
 // The streamed sampler for one size class; with MF_FLAG_GRAPH the whole sweep
 // loop is captured once per launch configuration and replayed as one graph.
 mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int H, int W, const float* d,
@@ -1385,6 +1413,17 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
         return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
     if (g->form < MF_FORM_AUTO || g->form > MF_FORM_PLAIN) return fail(MF_ERR_INVALID_ARG, "unknown form");
     if (g->storage < MF_STORAGE_FP32 || g->storage > MF_STORAGE_BF16) return fail(MF_ERR_INVALID_ARG, "unknown storage");
+    int64_t n_cool = 0;
+    if (g->cooling) {
+        const mf_status sc = validate_schedule(g->cooling);
+        if (sc != MF_OK) return sc;
+        for (int j = 0; j < g->cooling->n_levels; ++j) n_cool += g->cooling->sweeps[j];
+        if (g->sweep_offset + n_cool + (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin > 0xffffffffLL)
+            return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
+    }
+    mf_sample_args gm = *g;  // the sampling phase after the cooling levels
+    gm.sweep_offset += n_cool;
+    gm.cooling = nullptr;
     if (g->n_samples > 0 && !samples_out && !state_out)
         return fail(MF_ERR_INVALID_ARG, "nothing to write: samples_out and state_out are NULL");
     hipStream_t s = (hipStream_t)stream;
@@ -1440,15 +1479,23 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
         mf::ItemDev* di = nullptr;
         mf_status st = put_items(p, items, 0, s, &di);
         if (st != MF_OK) return st;
+        if (form == MF_FORM_PERSISTENT && !mf::resident_supported(H, W))
+            return fail(MF_ERR_UNSUPPORTED_SIZE, "the persistent form needs H = W <= 128");
+        const float2* cin = sin;  // the state the sampling phase starts from
+        if (n_cool > 0) {
+            float2* cw = (form != MF_FORM_PERSISTENT && hwork) ? hwork : work;
+            st = cool_streamed(p, di, (int)items.size(), H, W, d, g, cw == hwork ? g->storage : MF_STORAGE_FP32, cw,
+                               sin, s);
+            if (st != MF_OK) return st;
+            cin = cw;
+        }
         if (form == MF_FORM_PERSISTENT) {
-            if (!mf::resident_supported(H, W))
-                return fail(MF_ERR_UNSUPPORTED_SIZE, "the persistent form needs H = W <= 128");
             mf::ResidentArgs r{};
             r.probs = p->d_probs;
             r.items = di;
             r.n_items = (int)items.size();
             r.field = work;
-            r.state_in = sin;
+            r.state_in = cin;
             r.init_scale = g->init_scale;
             r.pcoef = pcoef;
             r.psrc = psrc;
@@ -1456,7 +1503,7 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
             r.tw = p->d_tw.at(W);
             r.key0 = (uint32_t)(g->seed & 0xffffffffu);
             r.key1 = (uint32_t)(g->seed >> 32);
-            r.sweep0 = (uint32_t)g->sweep_offset;
+            r.sweep0 = (uint32_t)gm.sweep_offset;
             r.burn_in = g->burn_in;
             r.n_samples = g->n_samples;
             r.thin = g->thin;
@@ -1466,10 +1513,10 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
         } else {
             float2* w = hwork ? hwork : work;
             if (form == MF_FORM_STREAMED) {
-                st = sample_streamed(p, di, (int)items.size(), H, W, d, g, w, sin, samples_out, s);
+                st = sample_streamed(p, di, (int)items.size(), H, W, d, &gm, w, cin, samples_out, s);
             } else {  // plain: one chain pair per launch sequence
                 for (size_t i = 0; i < items.size() && st == MF_OK; ++i)
-                    st = sample_streamed(p, di + i, 1, H, W, d, g, w, sin, samples_out, s);
+                    st = sample_streamed(p, di + i, 1, H, W, d, &gm, w, cin, samples_out, s);
             }
             if (st == MF_OK && hwork && state_out) {  // final states widened to FP32
                 mf::SweepArgs a = base_args(p, H, W);

@@ -9,8 +9,13 @@ REL_TOL = 1e-4
 
 
 def rel(a, b):
-    """Relative L2 distance; +inf if either side holds a NaN or Inf (so a
-    max() over cases or a < comparison can never hide one)."""
+    """Relative L2 distance (complex arrays: over real and imaginary parts);
+    +inf if either side holds a NaN or Inf (so a max() over cases or a <
+    comparison can never hide one)."""
+    a, b = np.asarray(a), np.asarray(b)
+    if np.iscomplexobj(a) or np.iscomplexobj(b):
+        a = np.concatenate([np.real(a).ravel(), np.imag(a).ravel()])
+        b = np.concatenate([np.real(b).ravel(), np.imag(b).ravel()])
     a = np.asarray(a, dtype=np.float64)
     b = np.asarray(b, dtype=np.float64)
     if not (np.all(np.isfinite(a)) and np.all(np.isfinite(b))):

@@ -379,3 +379,33 @@ def test_inf_as_1e8_flag_matches_the_finite_noise_problem(torch_cuda, solve):
         spec, keep = _binding._spectrum_c(prob.spectrum)
         arr[0] = _binding._Problem(64, 64, nv.ctypes.data_as(C.POINTER(C.c_float)), spec, None)
         _binding._check(_binding.lib().mf_plan_create(C.byref(h), 1, arr, 1 << 20, None))
+
+
+@pytest.mark.parametrize("size,form", [(64, "persistent"), (64, "streamed"), (32, "plain"), (256, "auto")])
+def test_sampler_with_cooling_levels_matches_oracle(torch_cuda, size, form):
+    """Cooling levels before the burn-in (run on the streamed kernels for every
+    form, then the form's own sampling phase from the cooled state)."""
+    mf = _mf()
+    banner(f"sampler with cooling {size} {form}")
+    prob = synth.config_small(6, size)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    levels = [(20.0, 3), (4.0, 2)]
+    cool = mf.Schedule([l for l, _ in levels], [k for _, k in levels])
+    chains, burn_in, n_samples = 3, 2, 3
+    st = plan.state_buffer(chains)
+    flat, _ = plan.sample(d, 17, chains=chains, burn_in=burn_in, n_samples=n_samples, form=form, cooling=cool,
+                          state_out=st)
+    x = plan.sample_view(flat, 0, chains, n_samples).cpu().numpy()
+    worst = 0.0
+    for q in range(2):
+        ref, s_ref = om.sample_pair(prob, 17, 0, q, burn_in, n_samples, cooling=levels)
+        for h in range(2):
+            if 2 * q + h >= chains:
+                continue
+            for k in range(n_samples):
+                worst = max(worst, rel(x[2 * q + h, k], ref[h, k]))
+        pair = st.view(-1, 2)[q * size * size:(q + 1) * size * size].cpu().numpy()
+        worst = max(worst, rel(pair[:, 0] + 1j * pair[:, 1], s_ref.ravel()))
+    print(f"worst rel {worst:.2e}")
+    assert worst < REL_TOL

@@ -217,3 +217,30 @@ def test_conjugate_gradient_route_matches_dense_and_messenger(small16):
     C = dense.posterior_covariance(S, p.noise_var)
     assert _rel(v_cg.ravel(), C @ g.ravel()) < 1e-9
     assert it < 400
+
+
+@pytest.mark.parametrize("lam", [3.0, 30.0])
+def test_cooled_sweep_samples_the_posterior_with_inflated_noise(small16, lam):
+    """A sampler sweep at T = lambda tau (a cooling level before the burn-in)
+    has as its exact stationary law the posterior of Eq. 7 for the noise
+    N + (lambda - 1) tau, the law whose mean is the level's filter fixed point."""
+    p, S = small16
+    c = M.coefficients(p.noise_var, p.spectrum, lam)
+    b = c.ninv * p.d
+    fn = lambda s, xi, eta: M.sweep(s, b, c, xi, eta)[0]
+    Mm, cc, B = dense.chain_transition(fn, 16, 16)
+    mean, Sigma = dense.stationary_law(Mm, cc, B)
+    nv = dense.effective_noise(p.noise_var, lam)
+    assert _rel(mean, dense.wiener_dense(S, nv, p.d).ravel()) < 1e-10
+    assert _rel(Sigma, dense.posterior_covariance(S, nv)) < 1e-10
+
+
+def test_sampler_cooling_levels_take_the_sweep_indices_before_the_burn_in():
+    """Cooling levels at lambda = 1 are burn-in sweeps: the same chain, sample
+    for sample; a level at lambda > 1 changes it."""
+    p = synth.config_small(0, 8)
+    ref, s_ref = M.sample_pair(p, 1000, 0, 0, burn_in=7, n_samples=4)
+    got, s_got = M.sample_pair(p, 1000, 0, 0, burn_in=2, n_samples=4, cooling=[(1.0, 3), (1.0, 2)])
+    assert np.array_equal(got, ref) and np.array_equal(s_got, s_ref)
+    hot, _ = M.sample_pair(p, 1000, 0, 0, burn_in=2, n_samples=4, cooling=[(10.0, 3), (1.0, 2)])
+    assert not np.allclose(hot, ref)
