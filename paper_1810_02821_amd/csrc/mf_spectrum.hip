@@ -138,16 +138,29 @@ __device__ __forceinline__ void band_powers(const float2 (&v)[16], float2* lds, 
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) {
         const unsigned ky = k1 + P * k2;
+        int b[2];
+        double pa[2], pb[2];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const unsigned kx = 2 * jx + q;
-            const int b = band[ky * N + kx];
+            b[q] = band[ky * N + kx];
             const float2 s = v[8 * q + k2];
             const float2 m = lds[mirror<N>(ky, kx)];
             const double ar = 0.5 * ((double)s.x + m.x), ai = 0.5 * ((double)s.y - m.y);
             const double br = 0.5 * ((double)s.y + m.y), bi = 0.5 * ((double)s.x - m.x);
-            atomicAdd(&sh.pw[0][b], ar * ar + ai * ai);
-            atomicAdd(&sh.pw[1][b], br * br + bi * bi);
+            pa[q] = ar * ar + ai * ai;
+            pb[q] = br * br + bi * bi;
+        }
+        // the two modes of a thread are neighbours in k_x and mostly share a band
+        if (b[0] == b[1]) {
+            atomicAdd(&sh.pw[0][b[0]], pa[0] + pa[1]);
+            atomicAdd(&sh.pw[1][b[0]], pb[0] + pb[1]);
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+                atomicAdd(&sh.pw[0][b[q]], pa[q]);
+                atomicAdd(&sh.pw[1][b[q]], pb[q]);
+            }
         }
     }
     __syncthreads();
