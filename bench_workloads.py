@@ -11,7 +11,7 @@ uneven : 4096 problems of sizes {64,128,256,512}^2 at weights {.4,.3,.2,.1},
          per-problem spectra, noise and masks; one chain (pair) per problem,
          500 sweeps, final states written, column tiles picked by the
          autotuner and the streamed sweep loops replayed as HIP graphs;
-         reports pixel-sweeps/s.
+         reports pixel-sweeps/s, and per size class when run alone.
 grad   : 256x256 band-spectrum Wiener filter (32 bands) and its gradient
          (one adjoint solve); reports the gradient/forward time ratio.
 spectrum: the hierarchical sampler (signal + 32 band amplitudes) on the
@@ -125,9 +125,25 @@ def uneven(args):
     sizes = np.array([p.H for p in probs])
     px = {int(s): int(np.sum(sizes == s)) * int(s) * int(s) for s in np.unique(sizes)}
     total_px = sum(px.values())
+    # each size class alone (its own plan, same problems, same launch forms)
+    per_class = {}
+    for sz in np.unique(sizes):
+        sub = [p for p in probs if p.H == sz]
+        cplan = mf.Plan(sub, autotune=True, graph=True)
+        cd = cplan.concat([p.d for p in sub])
+        cst = cplan.state_buffer(1)
+        crun = lambda: cplan.sample(cd, 1000, chains=1, burn_in=sweeps, n_samples=0, form="auto",
+                                    state_out=cst, samples=False)
+        crun()
+        tc = _timed(crun, 1)
+        per_class[f"{int(sz)}x{int(sz)}"] = {"problems": len(sub), "seconds": tc,
+                                             "pixel_sweeps_per_s": px[int(sz)] * sweeps / tc,
+                                             "form": "persistent" if sz <= 128 else "streamed"}
+        del cplan, cd, cst
     print(json.dumps({"workload": "uneven", "metric": "pixel-sweeps/s, 4096 uneven problems, 500 sweeps",
                       "value": total_px * sweeps / t, "unit": "pixel-sweeps/s (one chain per problem)",
                       "seconds": t, "problems_per_size": {int(s): int(np.sum(sizes == s)) for s in np.unique(sizes)},
+                      "per_class": per_class,
                       "plan_seconds": t_plan, "generate_seconds": t_gen,
                       "graph": True, "autotune": True,
                       "tile_shapes": {f"{s}x{s}": list(plan.tile_shape(int(s), int(s)))
