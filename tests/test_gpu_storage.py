@@ -134,3 +134,22 @@ def test_unknown_storage_is_rejected(torch_cuda):
     args = _binding._SampleArgs(1, 2, 1, 0, 1, 0, 0.0, 2, 7)  # valid but for storage = 7
     st = _binding.lib().mf_sample(plan._h, _binding._ptr(d), C.byref(args), None, None, None, _binding._stream())
     assert st == 1
+
+
+def test_graph_replays_match_eager_with_16_bit_storage(torch_cuda):
+    """The captured sweep loop (MF_FLAG_GRAPH) with FP16 storage, replayed
+    several times with eager work in between, equals the eager run bit for bit."""
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("graph replays with fp16 storage")
+    prob = synth.config_small(9, 256)
+    eager = mf.Plan([prob])
+    graph = mf.Plan([prob], graph=True)
+    d = eager.concat([prob.d])
+    ref, _ = eager.sample(d, 3, chains=4, burn_in=3, n_samples=2, form="streamed", storage="fp16")
+    for _ in range(3):
+        got, _ = graph.sample(d, 3, chains=4, burn_in=3, n_samples=2, form="streamed", storage="fp16")
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
+        eager.sample(d, 4, chains=2, burn_in=1, n_samples=1, form="streamed")
+        torch.cuda.synchronize()
