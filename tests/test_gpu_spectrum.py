@@ -178,3 +178,17 @@ def test_hierarchical_rejects_unsupported_problems(torch_cuda):
     with pytest.raises(mf.MFError) as e:
         plan.sample_spectrum(d, 1, 2, 0, 1)
     assert e.value.status == 1
+
+
+def test_streamed_hierarchical_single_chain(torch_cuda):
+    """One chain (the imaginary chain of the pair is neither emitted nor
+    reported) on a streamed size class."""
+    import paper_1810_02821_amd as mf
+    banner("streamed hierarchical, one chain, 64x128")
+    prob = synth.config_bands(11, 64, 10, width=128)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    ts, smp, _, _ = plan.sample_spectrum(d, 5, 1, 1, 2, 1, 2, samples=True)
+    wt, ws = _check(plan, ts, smp, [prob], 0, 1, 2, 5, 1, 1, 2, 0, 0.0)
+    print(f"worst theta rel {wt:.2e}, worst sample rel {ws:.2e}")
+    assert wt < REL_TOL and ws < REL_TOL
