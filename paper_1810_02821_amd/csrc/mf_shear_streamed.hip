@@ -100,25 +100,30 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel(ShearStreamArgs 
     constexpr int ROWS = ShearRowShape<L>::ROWS, TPR = ShearRowShape<L>::TPR;
     constexpr int W = L;
     __shared__ float2 lds[ROWS * L];
+    __shared__ int32_t row_item[ROWS], row_y[ROWS];  // one division per row
     const unsigned tid = threadIdx.x;
     const int64_t total_rows = (int64_t)a.n_items * H;
     const int64_t grow0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
+    for (unsigned r = tid; r < (unsigned)ROWS; r += kRowThreads) {
+        const int64_t g = grow0 + r;
+        row_item[r] = g < total_rows ? (int32_t)(g % a.n_items) : -1;
+        row_y[r] = g < total_rows ? (int32_t)(g / a.n_items) : 0;
+    }
+    __syncthreads();
     const float2* src = (MODE & kShearEmit) ? a.kfield : a.field;
 #pragma unroll
     for (int i = 0; i < ROWS * L / kRowThreads; ++i) {
         const unsigned e = tid + i * kRowThreads;
         const unsigned r = e / L, x = e % L;
-        const int64_t gr = grow0 + r;
         float2 v = make_float2(0.f, 0.f);
-        if (gr < total_rows) v = src[a.items[gr % a.n_items].field_off + (gr / a.n_items) * W + x];
+        if (row_item[r] >= 0) v = src[a.items[row_item[r]].field_off + (int64_t)row_y[r] * W + x];
         lds[r * L + swz(x)] = v;
     }
     __syncthreads();
     const unsigned rid = tid / TPR, lane = tid % TPR;
-    const int64_t gr = grow0 + rid;
-    const bool valid = gr < total_rows;
-    const int item = valid ? (int)(gr % a.n_items) : 0;
-    const int y = valid ? (int)(gr / a.n_items) : 0;
+    const bool valid = row_item[rid] >= 0;
+    const int item = valid ? row_item[rid] : 0;
+    const int y = row_y[rid];
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
     float2* row = lds + rid * L;

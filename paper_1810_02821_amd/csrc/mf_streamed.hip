@@ -85,11 +85,20 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     __shared__ float2 lds[ROWS * L];
     __shared__ double red[kThreads];
 
+    // (item, row) of each of the block's rows, one division per row
+    __shared__ int32_t row_item[ROWS], row_y[ROWS];
+
     const unsigned tid = threadIdx.x;
     const unsigned rid = tid / TPR;
     const unsigned lane = tid % TPR;
     const int64_t total_rows = (int64_t)a.n_items * H;
     const int64_t grow0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
+    for (unsigned r = tid; r < (unsigned)ROWS; r += kThreads) {
+        const int64_t g = grow0 + r;
+        row_item[r] = g < total_rows ? (int32_t)(g % a.n_items) : -1;
+        row_y[r] = g < total_rows ? (int32_t)(g / a.n_items) : 0;
+    }
+    __syncthreads();
 
     // ---- load ROWS rows (coalesced along x)
     with_storage(a.storage, [&](auto e0) {
@@ -99,21 +108,17 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
         for (int i = 0; i < ROWS * L / kThreads; ++i) {
             const unsigned e = tid + i * kThreads;
             const unsigned r = e / L, x = e % L;
-            const int64_t gr = grow0 + r;
             float2 v = make_float2(0.f, 0.f);
-            if (gr < total_rows) {
-                const ItemDev it = a.items[gr % a.n_items];
-                v = widen(fld[it.field_off + (gr / a.n_items) * W + x]);
-            }
+            if (row_item[r] >= 0) v = widen(fld[a.items[row_item[r]].field_off + (int64_t)row_y[r] * W + x]);
             lds[r * L + swz(x)] = v;
         }
     });
     __syncthreads();
 
     const int64_t gr = grow0 + rid;
-    const bool valid = gr < total_rows;
-    const int item = valid ? (int)(gr % a.n_items) : 0;
-    const int y = valid ? (int)(gr / a.n_items) : 0;
+    const bool valid = row_item[rid] >= 0;
+    const int item = valid ? row_item[rid] : 0;
+    const int y = row_y[rid];
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
     float2* row = lds + rid * L;
