@@ -134,9 +134,10 @@ enum {
     MF_FLAG_AUTOTUNE = 1,      /* time the column-tile shapes of each streamed size class (>= 256) at plan
                                   creation and keep the fastest; with MF_TUNE_CACHE=<file> in the
                                   environment the choices are read from / appended to that file */
-    MF_FLAG_GRAPH = 2,         /* capture the streamed sampler's sweep loop of each size class as a HIP
-                                  graph, once per launch configuration (pointers, counts, seed, sweep
-                                  range), and replay it; the plan keeps up to 8 graphs */
+    MF_FLAG_GRAPH = 2,         /* capture the streamed sweep loops of each size class (mf_sample,
+                                  mf_sample_spectrum, mf_shear_wiener, mf_shear_sample) as HIP graphs,
+                                  once per launch configuration (pointers, counts, seeds, sweep range,
+                                  schedule), and replay them; the plan keeps up to 8 graphs */
     MF_FLAG_STREAMED_SOLVE = 4, /* run mf_wiener / mf_wiener_backward on the streamed kernels for every size
                                   class; without it, classes with H = W in {32, 64, 128} use the persistent
                                   solve kernel (one workgroup per problem, every level and the residual

@@ -279,6 +279,49 @@ mf::SweepArgs base_args(mf_plan p, int H, int W) {
     return a;
 }
 
+// Launch the graph cached under `key`, or capture `enqueue` (on the plan's
+// capture stream) as a new graph, cache it and launch it.  The plan keeps up
+// to 8 graphs; keys begin with a tag for the loop they capture.
+template <typename Fn>
+mf_status run_graph(mf_plan p, const std::vector<uint64_t>& key, hipStream_t s, Fn&& enqueue) {
+    for (auto& e : p->graphs)
+        if (e.key == key) {
+            MF_HIP(hipGraphLaunch(e.exec, s));
+            return MF_OK;
+        }
+    if (!p->cap_stream) MF_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
+    MF_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+    mf_status st = enqueue(p->cap_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
+    if (st != MF_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(MF_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return fail(MF_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
+    }
+    if (p->graphs.size() >= 8) {  // keep the cache small
+        (void)hipGraphExecDestroy(p->graphs.front().exec);
+        (void)hipGraphDestroy(p->graphs.front().graph);
+        p->graphs.erase(p->graphs.begin());
+    }
+    p->graphs.push_back({key, graph, exec});
+    MF_HIP(hipGraphLaunch(exec, s));
+    return MF_OK;
+}
+
+template <typename T>
+uint64_t bits_of(T v) {
+    uint64_t b = 0;
+    std::memcpy(&b, &v, sizeof(T));
+    return b;
+}
+
 // Upload a work list at element offset `slot` of the items workspace.
 mf_status put_items(mf_plan p, const std::vector<mf::ItemDev>& it, size_t slot, hipStream_t s,
                     mf::ItemDev** out) {
@@ -506,25 +549,40 @@ mf_status shear_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H, i
     a.n_samples = n_samples;
     a.kappa_out = reinterpret_cast<float2*>(kappa_out);
     const float2* sin = reinterpret_cast<const float2*>(state_in);
-    if (sin != field) MF_HIP(mf::launch_shear_init(W, H, a, sin, s));
     int64_t total = 0;
     for (int32_t k : sweeps) total += k;
-    int64_t k = 0;
-    for (size_t lv = 0; lv < lam.size(); ++lv) {
-        a.lambda = (float)lam[lv];
-        for (int32_t i = 0; i < sweeps[lv]; ++i, ++k) {
-            a.sweep = (uint32_t)(sweep_offset + k);
-            const bool emit = samples && k >= burn_in && ((k - burn_in + 1) % thin) == 0;
-            const bool last_kappa = kappa_out && k == total - 1;
-            a.emit = emit || last_kappa;
-            a.slot = emit ? (int)((k - burn_in + 1) / thin - 1) : -1;
-            MF_HIP(mf::launch_shear_row(W, H, k == 0 ? mf::kShearFwd : mf::kShearInvFwd, a, s));
-            MF_HIP(mf::launch_shear_col(W, H, a, s));
-            if (a.emit) MF_HIP(mf::launch_shear_row(W, H, mf::kShearEmit, a, s));
+    auto enqueue = [&](hipStream_t cs) -> mf_status {
+        mf::ShearStreamArgs aa = a;
+        if (sin != field) MF_HIP(mf::launch_shear_init(W, H, aa, sin, cs));
+        int64_t k = 0;
+        for (size_t lv = 0; lv < lam.size(); ++lv) {
+            aa.lambda = (float)lam[lv];
+            for (int32_t i = 0; i < sweeps[lv]; ++i, ++k) {
+                aa.sweep = (uint32_t)(sweep_offset + k);
+                const bool emit = samples && k >= burn_in && ((k - burn_in + 1) % thin) == 0;
+                const bool last_kappa = kappa_out && k == total - 1;
+                aa.emit = emit || last_kappa;
+                aa.slot = emit ? (int)((k - burn_in + 1) / thin - 1) : -1;
+                MF_HIP(mf::launch_shear_row(W, H, k == 0 ? mf::kShearFwd : mf::kShearInvFwd, aa, cs));
+                MF_HIP(mf::launch_shear_col(W, H, aa, cs));
+                if (aa.emit) MF_HIP(mf::launch_shear_row(W, H, mf::kShearEmit, aa, cs));
+            }
         }
+        if (total > 0) MF_HIP(mf::launch_shear_row(W, H, mf::kShearInv, aa, cs));
+        return MF_OK;
+    };
+    if (!(p->flags & MF_FLAG_GRAPH)) return enqueue(s);
+    std::vector<uint64_t> key = {3, (uint64_t)H, (uint64_t)W, (uint64_t)n_items, (uint64_t)(uintptr_t)di,
+                                 (uint64_t)(uintptr_t)gamma, (uint64_t)(uintptr_t)field,
+                                 (uint64_t)(uintptr_t)a.kfield, (uint64_t)(uintptr_t)sin,
+                                 (uint64_t)(uintptr_t)samples, (uint64_t)(uintptr_t)kappa_out, bits_of(b_ratio),
+                                 (uint64_t)chains, (uint64_t)stochastic, seed, (uint64_t)sweep_offset,
+                                 (uint64_t)burn_in, (uint64_t)n_samples, (uint64_t)thin, lam.size()};
+    for (size_t lv = 0; lv < lam.size(); ++lv) {
+        key.push_back(bits_of(lam[lv]));
+        key.push_back((uint64_t)sweeps[lv]);
     }
-    if (total > 0) MF_HIP(mf::launch_shear_row(W, H, mf::kShearInv, a, s));
-    return MF_OK;
+    return run_graph(p, key, s, enqueue);
 }
 
 mf_status launch_shear(mf_plan p, const float* gamma, float b_ratio, int chains, const std::vector<double>& lam,
@@ -777,44 +835,16 @@ mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, in
                           const mf_sample_args* g, float2* work, const float2* state_in, float* samples,
                           hipStream_t s) {
     if (!(p->flags & MF_FLAG_GRAPH)) return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, s);
-    uint32_t init_bits;
-    std::memcpy(&init_bits, &g->init_scale, sizeof(init_bits));
     const auto sh = class_shape(p, H, W);
-    const std::vector<uint64_t> key = {(uint64_t)H, (uint64_t)W, (uint64_t)n_items, (uint64_t)(uintptr_t)d_items,
+    const std::vector<uint64_t> key = {1, (uint64_t)H, (uint64_t)W, (uint64_t)n_items, (uint64_t)(uintptr_t)d_items,
                                        (uint64_t)(uintptr_t)d, (uint64_t)(uintptr_t)work,
                                        (uint64_t)(uintptr_t)state_in, (uint64_t)(uintptr_t)samples, g->seed,
                                        (uint64_t)g->sweep_offset, (uint64_t)g->burn_in, (uint64_t)g->n_samples,
-                                       (uint64_t)g->thin, (uint64_t)g->chains_per_problem, (uint64_t)init_bits,
+                                       (uint64_t)g->thin, (uint64_t)g->chains_per_problem, bits_of(g->init_scale),
                                        (uint64_t)sh.first, (uint64_t)sh.second, (uint64_t)g->storage};
-    for (auto& e : p->graphs)
-        if (e.key == key) {
-            MF_HIP(hipGraphLaunch(e.exec, s));
-            return MF_OK;
-        }
-    if (!p->cap_stream) MF_HIP(hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking));
-    MF_HIP(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
-    mf_status st = enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, p->cap_stream);
-    hipGraph_t graph = nullptr;
-    hipError_t e = hipStreamEndCapture(p->cap_stream, &graph);
-    if (st != MF_OK) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return st;
-    }
-    if (e != hipSuccess) return fail(MF_ERR_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(e));
-    hipGraphExec_t exec = nullptr;
-    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-        (void)hipGraphDestroy(graph);
-        return fail(MF_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e));
-    }
-    if (p->graphs.size() >= 8) {  // keep the cache small
-        (void)hipGraphExecDestroy(p->graphs.front().exec);
-        (void)hipGraphDestroy(p->graphs.front().graph);
-        p->graphs.erase(p->graphs.begin());
-    }
-    p->graphs.push_back({key, graph, exec});
-    MF_HIP(hipGraphLaunch(exec, s));
-    return MF_OK;
+    return run_graph(p, key, s, [&](hipStream_t cs) {
+        return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, cs);
+    });
 }
 
 // The hierarchical sampler on the streamed kernels for one size class: per
@@ -865,9 +895,6 @@ mf_status spectrum_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H
     r.chains_pad = 2 * ((g->chains_per_problem + 1) / 2);
     r.n_samples = g->n_samples;
     r.prior_beta = g->prior_beta;
-    if (state_in != work)  // copy the given states, or make zero / dispersed starts
-        MF_HIP(mf::launch_init_items(W, H, a, state_in, state_in ? 0.f : g->init_scale, s));
-    MF_HIP(mf::launch_spectrum_init(r, s));
     const int64_t iters = (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin;
     const int K = g->sweeps_per_draw;
     auto slot_of = [&](int64_t i) -> int64_t {
@@ -875,24 +902,43 @@ mf_status spectrum_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H
         const int64_t q = i - g->burn_in + 1;
         return (q % g->thin == 0) ? q / g->thin - 1 : -1;
     };
-    for (int64_t i = 0; i < iters; ++i) {
-        const int64_t gi = g->iteration_offset + i;
-        for (int k = 0; k < K; ++k) {
-            a.sweep = (uint32_t)(gi * K + k);
-            a.emit_index = (samples && k == 0 && i > 0) ? (int)slot_of(i - 1) : -1;
-            MF_HIP(mf::launch_row(W, H, (i == 0 && k == 0) ? mf::kRowFwd : mf::kRowInvFwd, a, s));
-            r.sweep = a.sweep;
-            r.add_power = k == K - 1;
-            MF_HIP(mf::launch_spectrum_col(W, H, r, s));
+    auto enqueue = [&](hipStream_t cs) -> mf_status {
+        mf::SweepArgs aa = a;
+        mf::SpectrumStreamArgs rr = r;
+        if (state_in != work)  // copy the given states, or make zero / dispersed starts
+            MF_HIP(mf::launch_init_items(W, H, aa, state_in, state_in ? 0.f : g->init_scale, cs));
+        MF_HIP(mf::launch_spectrum_init(rr, cs));
+        for (int64_t i = 0; i < iters; ++i) {
+            const int64_t gi = g->iteration_offset + i;
+            for (int k = 0; k < K; ++k) {
+                aa.sweep = (uint32_t)(gi * K + k);
+                aa.emit_index = (samples && k == 0 && i > 0) ? (int)slot_of(i - 1) : -1;
+                MF_HIP(mf::launch_row(W, H, (i == 0 && k == 0) ? mf::kRowFwd : mf::kRowInvFwd, aa, cs));
+                rr.sweep = aa.sweep;
+                rr.add_power = k == K - 1;
+                MF_HIP(mf::launch_spectrum_col(W, H, rr, cs));
+            }
+            rr.iteration = (uint32_t)gi;
+            MF_HIP(mf::launch_spectrum_draw(rr, max_dof, slot_of(i), cs));
         }
-        r.iteration = (uint32_t)gi;
-        MF_HIP(mf::launch_spectrum_draw(r, max_dof, slot_of(i), s));
-    }
-    if (iters > 0) {
-        a.emit_index = samples ? (int)slot_of(iters - 1) : -1;
-        MF_HIP(mf::launch_row(W, H, mf::kRowInv, a, s));
-    }
-    return MF_OK;
+        if (iters > 0) {
+            aa.emit_index = samples ? (int)slot_of(iters - 1) : -1;
+            MF_HIP(mf::launch_row(W, H, mf::kRowInv, aa, cs));
+        }
+        return MF_OK;
+    };
+    if (!(p->flags & MF_FLAG_GRAPH)) return enqueue(s);
+    const std::vector<uint64_t> key = {2, (uint64_t)H, (uint64_t)W, (uint64_t)n_items, (uint64_t)(uintptr_t)di,
+                                       (uint64_t)(uintptr_t)d, (uint64_t)(uintptr_t)work,
+                                       (uint64_t)(uintptr_t)state_in, (uint64_t)(uintptr_t)theta_in,
+                                       (uint64_t)(uintptr_t)theta_out, (uint64_t)(uintptr_t)samples,
+                                       (uint64_t)(uintptr_t)theta_samples, (uint64_t)(uintptr_t)d_dof,
+                                       (uint64_t)(uintptr_t)d_th0, (uint64_t)(uintptr_t)theta, g->seed,
+                                       (uint64_t)g->iteration_offset, (uint64_t)g->burn_in, (uint64_t)g->n_samples,
+                                       (uint64_t)g->thin, (uint64_t)K, (uint64_t)g->chains_per_problem,
+                                       (uint64_t)g->prior_dof, bits_of(g->prior_beta), bits_of(g->init_scale),
+                                       (uint64_t)max_dof};
+    return run_graph(p, key, s, enqueue);
 }
 
 // Time every column-tile shape of each streamed size class on a scratch field

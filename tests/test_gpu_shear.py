@@ -136,3 +136,25 @@ def test_streamed_shear_resume(torch_cuda):
     rest, _ = plan.shear_sample(g, 5, 2, 0, 3, 1, sweep_offset=2, b_ratio=0.2, state_in=st, state_out=st)
     assert torch.equal(st, st_full)
     assert torch.equal(rest.view(2, 3, -1), full.view(2, 5, -1)[:, 2:])
+
+
+def test_streamed_shear_graph_replays_match_eager(torch_cuda):
+    """MF_FLAG_GRAPH captures the streamed mass-mapping loops; replays with
+    eager work in between equal the eager runs bit for bit."""
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("streamed shear graph replays")
+    prob = synth.config_shear(12, 256, 0.4)
+    eager = mf.Plan([prob])
+    graph = mf.Plan([prob], graph=True)
+    g = eager.concat_complex([prob.gamma])
+    sch = mf.Schedule([10.0, 1.0], [3, 4])
+    ref_k = eager.shear_wiener(g, sch, 0.4)
+    ref_s, _ = eager.shear_sample(g, 9, 2, 1, 2, 1, b_ratio=0.4)
+    for _ in range(3):
+        k = graph.shear_wiener(g, sch, 0.4)
+        smp, _ = graph.shear_sample(g, 9, 2, 1, 2, 1, b_ratio=0.4)
+        torch.cuda.synchronize()
+        assert torch.equal(k, ref_k) and torch.equal(smp, ref_s)
+        eager.shear_sample(g, 10, 1, 1, 1, 1, b_ratio=0.4)
+        torch.cuda.synchronize()

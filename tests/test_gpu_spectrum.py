@@ -192,3 +192,24 @@ def test_streamed_hierarchical_single_chain(torch_cuda):
     wt, ws = _check(plan, ts, smp, [prob], 0, 1, 2, 5, 1, 1, 2, 0, 0.0)
     print(f"worst theta rel {wt:.2e}, worst sample rel {ws:.2e}")
     assert wt < REL_TOL and ws < REL_TOL
+
+
+def test_streamed_hierarchical_graph_replays_match_eager(torch_cuda):
+    """MF_FLAG_GRAPH captures the streamed hierarchical loop; replays with
+    eager work in between agree with the eager run (band sums are FP64
+    atomics, so amplitudes agree to FP64 rounding and samples to FP32)."""
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("streamed hierarchical graph replays")
+    prob = synth.config_bands(13, 256, 12)
+    eager = mf.Plan([prob])
+    graph = mf.Plan([prob], graph=True)
+    d = eager.concat([prob.d])
+    ts0, sm0, _, th0 = eager.sample_spectrum(d, 4, 2, 1, 2, 1, 2, samples=True)
+    for _ in range(3):
+        ts, sm, _, th = graph.sample_spectrum(d, 4, 2, 1, 2, 1, 2, samples=True)
+        torch.cuda.synchronize()
+        assert torch.allclose(ts, ts0, rtol=1e-9, atol=0) and torch.allclose(th, th0, rtol=1e-9, atol=0)
+        assert rel(sm.cpu().numpy(), sm0.cpu().numpy()) < 1e-6
+        eager.sample_spectrum(d, 5, 2, 0, 1, 1, 1)
+        torch.cuda.synchronize()
