@@ -244,3 +244,36 @@ def test_sampler_cooling_levels_take_the_sweep_indices_before_the_burn_in():
     assert np.array_equal(got, ref) and np.array_equal(s_got, s_ref)
     hot, _ = M.sample_pair(p, 1000, 0, 0, burn_in=2, n_samples=4, cooling=[(10.0, 3), (1.0, 2)])
     assert not np.allclose(hot, ref)
+
+
+@pytest.mark.parametrize("H,W", [(16, 16), (32, 32), (24, 24), (12, 18)])
+def test_library_fft_equals_the_naive_dft(H, W):
+    """The oracle's 2D transforms (numpy, unnormalised forward e^{-i}) equal the
+    O(n^2) sum of the definition, also at sizes with factors of 3."""
+    rng = np.random.default_rng(H * 100 + W)
+    x = rng.standard_normal((H, W)) + 1j * rng.standard_normal((H, W))
+    ky = np.arange(H)[:, None]
+    kx = np.arange(W)[None, :]
+    Fy = np.exp(-2j * np.pi * np.outer(np.arange(H), np.arange(H)) / H)
+    Fx = np.exp(-2j * np.pi * np.outer(np.arange(W), np.arange(W)) / W)
+    naive = np.empty((H, W), dtype=np.complex128)
+    for a in range(H):
+        for b in range(W):
+            naive[a, b] = np.sum(x * np.exp(-2j * np.pi * (a * ky / H + b * kx / W)))
+    assert np.allclose(np.fft.fft2(x), naive, atol=1e-9 * np.abs(naive).max())
+    assert np.allclose(Fy @ x @ Fx.T, naive, atol=1e-9 * np.abs(naive).max())
+    assert np.allclose(np.fft.ifft2(naive), x, atol=1e-12 * np.abs(x).max())
+
+
+def test_gibbs_chain_stationary_law_at_24x24():
+    """The exact stationary law of the sweep equals Eq. 7 at a size with a
+    factor of 3 (radix-3 transforms in the oracle's library FFT)."""
+    p = synth.config_small(3, 24)
+    S = dense.signal_covariance(p.spectrum, 24, 24)
+    c = M.coefficients(p.noise_var, p.spectrum)
+    b = c.ninv * p.d
+    fn = lambda s, xi, eta: M.sweep(s, b, c, xi, eta)[0]
+    Mm, cc, B = dense.chain_transition(fn, 24, 24)
+    mean, Sigma = dense.stationary_law(Mm, cc, B)
+    assert _rel(mean, dense.wiener_dense(S, p.noise_var, p.d).ravel()) < 1e-10
+    assert _rel(Sigma, dense.posterior_covariance(S, p.noise_var)) < 1e-10
