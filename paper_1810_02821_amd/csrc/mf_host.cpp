@@ -84,6 +84,7 @@ struct mf_plan_s {
     mf::ProbDev* d_probs = nullptr;
     float* d_nbar = nullptr;
     float* d_nP = nullptr;
+    float2* d_nPt = nullptr;  // column-pair copy of nP for the streamed column kernel
     int16_t* d_band = nullptr;
     int32_t* d_band_base = nullptr;
     int32_t* d_band_count = nullptr;
@@ -116,6 +117,7 @@ struct mf_plan_s {
         (void)hipFree(d_probs);
         (void)hipFree(d_nbar);
         (void)hipFree(d_nP);
+        (void)hipFree(d_nPt);
         (void)hipFree(d_band);
         (void)hipFree(d_band_base);
         (void)hipFree(d_band_count);
@@ -218,6 +220,12 @@ mf_status upload_spectrum(mf_plan p, int i) {
             }
         }
     MF_HIP(hipMemcpy(p->d_nP + hp.pix_off, nP.data(), nP.size() * sizeof(float), hipMemcpyHostToDevice));
+    // column pairs: entry (kx/2) H + ky holds (nP(ky, kx), nP(ky, kx + 1)) for even kx
+    std::vector<float2> nPt((size_t)H * W / 2);
+    for (int kx = 0; kx < W; kx += 2)
+        for (int ky = 0; ky < H; ++ky)
+            nPt[(size_t)(kx / 2) * H + ky] = make_float2(nP[(size_t)ky * W + kx], nP[(size_t)ky * W + kx + 1]);
+    MF_HIP(hipMemcpy(p->d_nPt + hp.pix_off / 2, nPt.data(), nPt.size() * sizeof(float2), hipMemcpyHostToDevice));
     MF_HIP(hipMemcpy(p->d_band + hp.pix_off, band.data(), band.size() * sizeof(int16_t), hipMemcpyHostToDevice));
     if (hp.kind == MF_PK_BANDS) {
         std::vector<double> sc(hp.n_bands);
@@ -272,6 +280,7 @@ mf::SweepArgs base_args(mf_plan p, int H, int W) {
     a.probs = p->d_probs;
     a.nbar = p->d_nbar;
     a.nP = p->d_nP;
+    a.nPt = p->d_nPt;
     a.tw_row = p->d_tw.at(W);
     a.tw_col = p->d_tw.at(H);
     a.lambda = 1.0f;
@@ -1136,6 +1145,7 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
     MF_TRY(hipMalloc(&p->d_probs, n_problems * sizeof(mf::ProbDev)));
     MF_TRY(hipMalloc(&p->d_nbar, off * sizeof(float)));
     MF_TRY(hipMalloc(&p->d_nP, off * sizeof(float)));
+    MF_TRY(hipMalloc(&p->d_nPt, off / 2 * sizeof(float2)));
     MF_TRY(hipMalloc(&p->d_band, off * sizeof(int16_t)));
     MF_TRY(hipMalloc(&p->d_band_base, n_problems * sizeof(int32_t)));
     MF_TRY(hipMalloc(&p->d_band_count, n_problems * sizeof(int32_t)));
@@ -1313,6 +1323,10 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
         float2* ck = p->ckpt.as<float2>();
         float2* ts = p->tstore.as<float2>();
         mf::SweepArgs a = base_args(p, H, W);
+        // the recomputed and reverse sweeps store and load transforms, which only
+        // col_kernel_t does: the first forward pass runs on it too, so that the
+        // recomputed states repeat the checkpointed ones bit for bit
+        a.nPt = nullptr;
         a.items = di;
         a.n_items = n_items;
         a.src = d;

@@ -36,6 +36,7 @@ struct SweepArgs {
     int32_t src_kind;
     const float* nbar;        // concatenated Nbar (+inf missing)
     const float* nP;          // concatenated n P(|k|) per mode (unshifted order)
+    const float2* nPt;        // column-pair table: [pix_off/2 + (kx/2) H + ky] = (nP(ky,kx), nP(ky,kx+1)), or null
     const float2* tw_row;     // twiddles W_W^r
     const float2* tw_col;     // twiddles W_H^r
     float lambda;             // cooling level: T = lambda * tau

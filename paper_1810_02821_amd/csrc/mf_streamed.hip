@@ -364,6 +364,193 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     });
 }
 
+// Radix of the last forward pass (and of the first inverse pass) of a
+// length-L transform planned as radix-16 passes plus one remainder pass.
+template <int L>
+constexpr int last_radix() {
+    int r = L;
+    while (r > 16) r /= 16;
+    return r;
+}
+
+// Radix-16 Stockham passes over LDS with NS = NS0, 16 NS0, ... while
+// NS * 16 * TAIL < L, i.e. all passes before a final pass of radix TAIL.
+template <int L, int NS, int TAIL, int TPG, bool INV>
+__device__ __forceinline__ void passes_before(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    if constexpr (NS * 16 * TAIL <= L && NS * TAIL < L) {
+        stockham_pass<L, 16, NS, TPG, INV>(buf, lane, tw);
+        passes_before<L, NS * 16, TAIL, TPG, INV>(buf, lane, tw);
+    }
+}
+
+// Column kernel of the sampler and the Wiener iteration for H >= 512, with
+// half the LDS traffic and barriers of col_kernel_t:
+//   A. the first forward radix-16 pass reads its inputs from HBM into
+//      registers (a wave covers TC columns of 64/TC rows, as the tile load
+//      does) and writes its outputs to LDS;
+//   B. the middle forward passes run in LDS;
+//   C. the last forward pass, the Fourier-space update and the first inverse
+//      pass run in registers, one thread owning the same rows of a column
+//      pair (2p, 2p+1), so one Philox call serves both modes of a pair and
+//      the column-pair table nPt gives both coefficients in one coalesced load;
+//   D. the middle inverse passes run in LDS and the last one writes its
+//      outputs, in natural order, straight to HBM.
+// Same arithmetic per mode as col_kernel_t; the inverse transform runs its
+// radices in the opposite order (remainder pass first).
+template <int L, int TC_, int NTH_>
+__global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
+    constexpr int TC = TC_;
+    constexpr int NTH = NTH_;
+    constexpr int TPC = NTH / TC;
+    constexpr int SEG = L + 32 / TC;
+    constexpr int H = L;
+    constexpr int RL = last_radix<L>();
+    constexpr int NT16 = L / 16;                            // radix-16 butterflies per column
+    constexpr int IT16 = (TC * NT16 + NTH - 1) / NTH;       // per thread in phases A and D
+    constexpr int NTL = L / RL;                             // last-radix butterflies per column
+    constexpr int TPP = NTH / (TC / 2);                     // threads per column pair in phase C
+    constexpr int ITL = (NTL + TPP - 1) / TPP;
+    static_assert(L >= 512 && TC % 2 == 0 && NTH % (TC / 2) == 0, "col_kernel_f shape");
+    __shared__ float2 lds[TC * SEG];
+    const unsigned tid = threadIdx.x;
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x);
+    const int item = (int)(t / (W / TC));
+    const int x0 = (int)(t % (W / TC)) * TC;
+    const ItemDev it = a.items[item];
+    const ProbDev pr = a.probs[it.prob];
+    const int64_t f0 = it.field_off + x0;
+
+    // ---- A: first forward pass (NS = 1), inputs from HBM
+    with_storage(a.storage, [&](auto e0) {
+        using E = decltype(e0);
+        const E* fld = reinterpret_cast<const E*>(a.field) + f0;
+        float2 v[IT16][16];
+#pragma unroll
+        for (int i = 0; i < IT16; ++i) {
+            const unsigned b = tid + i * NTH;
+            if ((TC * NT16) % NTH == 0 || b < (unsigned)(TC * NT16)) {
+                const unsigned c = b % TC, j = b / TC;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[i][r] = widen(fld[(int64_t)(j + r * NT16) * W + c]);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < IT16; ++i) {
+            const unsigned b = tid + i * NTH;
+            if ((TC * NT16) % NTH == 0 || b < (unsigned)(TC * NT16)) {
+                const unsigned c = b % TC, j = b / TC;
+                dft<16, false>(v[i]);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) lds[c * SEG + swz(j * 16 + r)] = v[i][r];
+            }
+        }
+    });
+    __syncthreads();
+
+    // ---- B: middle forward passes
+    {
+        const unsigned cid = tid / TPC, lane = tid % TPC;
+        passes_before<L, 16, RL, TPC, false>(lds + cid * SEG, lane, a.tw_col);
+    }
+
+    // ---- C: last forward pass + Fourier-space update + first inverse pass
+    {
+        const float T = a.lambda * pr.tau;
+        const float inv_n = 1.0f / ((float)H * (float)W);
+        const unsigned pp = tid / TPP, lane = tid % TPP;
+        const int kx0 = x0 + 2 * (int)pp;
+        const float2* npt = a.nPt + pr.pix_off / 2 + (int64_t)(kx0 / 2) * H;
+        float2 v[ITL][2][RL];
+#pragma unroll
+        for (int i = 0; i < ITL; ++i) {
+            const unsigned j = lane + i * TPP;
+            if (NTL % TPP == 0 || j < (unsigned)NTL) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int r = 0; r < RL; ++r) v[i][q][r] = lds[(2 * pp + q) * SEG + swz(j + r * NTL)];
+#pragma unroll
+                for (int r = 1; r < RL; ++r) {
+                    const float2 w = a.tw_col[r * j];
+                    v[i][0][r] = cmul(v[i][0][r], w);
+                    v[i][1][r] = cmul(v[i][1][r], w);
+                }
+                dft<RL, false>(v[i][0]);
+                dft<RL, false>(v[i][1]);
+                // v[i][q][r] now holds mode (ky, kx0 + q), ky = j + r NTL
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    const unsigned ky = j + r * NTL;
+                    const float2 np = npt[ky];
+                    float2 z[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+                    if (a.stochastic) {
+                        const int64_t mode = (int64_t)ky * W + kx0;
+                        const Normals2 nz = pair_normals((uint32_t)(mode >> 1), a.sweep, (uint32_t)pr.pid,
+                                                         kStageHarmonic, (uint32_t)it.pair, a.key0, a.key1);
+                        z[0] = nz.a;
+                        z[1] = nz.b;
+                    }
+                    const float npv[2] = {np.x, np.y};
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        const float P = npv[q];
+                        const float rden = __builtin_amdgcn_rcpf(P + T);
+                        const float f = P * rden * inv_n;
+                        float2 o = cscale(v[i][q][r], f);
+                        if (a.stochastic) {
+                            const float w = __builtin_amdgcn_sqrtf(P * T * rden * inv_n);
+                            o.x = fmaf(w, z[q].x, o.x);
+                            o.y = fmaf(w, z[q].y, o.y);
+                        }
+                        v[i][q][r] = o;
+                    }
+                }
+                dft<RL, true>(v[i][0]);
+                dft<RL, true>(v[i][1]);
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITL; ++i) {
+            const unsigned j = lane + i * TPP;
+            if (NTL % TPP == 0 || j < (unsigned)NTL) {
+#pragma unroll
+                for (int q = 0; q < 2; ++q)
+#pragma unroll
+                    for (int r = 0; r < RL; ++r) lds[(2 * pp + q) * SEG + swz(j * RL + r)] = v[i][q][r];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- D: middle inverse passes, then the last one (NS = L/16) to HBM
+    {
+        const unsigned cid = fresh(tid) / TPC, lane = fresh(tid) % TPC;
+        passes_before<L, RL, 16, TPC, true>(lds + cid * SEG, lane, fresh(a.tw_col));
+    }
+    with_storage(a.storage, [&](auto e0) {
+        using E = decltype(e0);
+        E* fld = reinterpret_cast<E*>(a.field) + f0;
+        const unsigned tid2 = fresh(tid);
+        const float2* tw = fresh(a.tw_col);
+        float2 v[IT16][16];
+#pragma unroll
+        for (int i = 0; i < IT16; ++i) {
+            const unsigned b = tid2 + i * NTH;
+            if ((TC * NT16) % NTH == 0 || b < (unsigned)(TC * NT16)) {
+                const unsigned c = b % TC, j = b / TC;
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[i][r] = lds[c * SEG + swz(j + r * NT16)];
+#pragma unroll
+                for (int r = 1; r < 16; ++r) v[i][r] = cmulc(v[i][r], tw[r * j]);
+                dft<16, true>(v[i]);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) fld[(int64_t)(j + r * NT16) * W + c] = narrow<E>(v[i][r]);
+            }
+        }
+    });
+}
+
 __global__ void band_slots_reduce_kernel(SweepArgs a, int tiles_per_item, const int32_t* band_base,
                                          const int32_t* band_count, double* out) {
     const int item = blockIdx.x;
@@ -652,6 +839,7 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Shape of ColShape<H> (the column-FFT kernel's tile).
 int col_tc(int H) { return H >= 2048 ? 8 : 16; }
 int col_threads(int H) { return H >= 1024 ? 1024 : (H >= 512 ? 512 : 256); }
 
@@ -684,25 +872,39 @@ hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_
         hipLaunchKernelGGL((col_kernel_t<LL, TCC, NN>), dim3((unsigned)(cols / TCC)), dim3(NN), 0, s, a, W); \
         return hipGetLastError();                                                              \
     }
+// H >= 512 without the gradient's stored transforms: the fused kernel (at 256
+// its 16-point last pass holds two columns of 16 values per thread: 163 VGPRs)
+#define MF_COL_CASE_F(LL, TCC, NN)                                                            \
+    if (H == LL && tc == TCC && nth == NN) {                                                   \
+        if (fused)                                                                             \
+            hipLaunchKernelGGL((col_kernel_f<LL, TCC, NN>), dim3((unsigned)(cols / TCC)), dim3(NN), 0, s, a, W); \
+        else                                                                                   \
+            hipLaunchKernelGGL((col_kernel_t<LL, TCC, NN>), dim3((unsigned)(cols / TCC)), dim3(NN), 0, s, a, W); \
+        return hipGetLastError();                                                              \
+    }
 
 hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, hipStream_t s) {
     if (tc > W || tc < 2) return hipErrorInvalidValue;
     const int64_t cols = (int64_t)a.n_items * W;
+    const bool fused = !a.t_store && !a.t_load && a.nPt;
     MF_COL_CASE(16, 16, 256) MF_COL_CASE(32, 16, 256) MF_COL_CASE(64, 16, 256) MF_COL_CASE(128, 16, 256)
     MF_COL_CASE(256, 16, 256) MF_COL_CASE(256, 8, 256) MF_COL_CASE(256, 16, 512) MF_COL_CASE(256, 8, 512)
-    MF_COL_CASE(512, 16, 512) MF_COL_CASE(512, 8, 512) MF_COL_CASE(512, 16, 256) MF_COL_CASE(512, 16, 1024)
-    MF_COL_CASE(1024, 16, 1024) MF_COL_CASE(1024, 8, 1024) MF_COL_CASE(1024, 8, 512) MF_COL_CASE(1024, 16, 512)
-    MF_COL_CASE(2048, 8, 1024) MF_COL_CASE(2048, 8, 512) MF_COL_CASE(2048, 4, 512) MF_COL_CASE(2048, 4, 256)
+    MF_COL_CASE_F(512, 16, 512) MF_COL_CASE_F(512, 8, 512) MF_COL_CASE_F(512, 16, 256) MF_COL_CASE_F(512, 16, 1024)
+    MF_COL_CASE_F(1024, 16, 1024) MF_COL_CASE_F(1024, 8, 1024) MF_COL_CASE_F(1024, 8, 512) MF_COL_CASE_F(1024, 16, 512)
+    MF_COL_CASE_F(2048, 8, 1024) MF_COL_CASE_F(2048, 8, 512) MF_COL_CASE_F(2048, 4, 512) MF_COL_CASE_F(2048, 4, 256)
     return hipErrorInvalidValue;
 }
 #undef MF_COL_CASE
+#undef MF_COL_CASE_F
 
+// Tile shapes per column length; the first one for a length is its default
+// (the autotuner's choice on MI355X for the sampler's column kernel).
 int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
     static const int table[][3] = {{16, 16, 256}, {32, 16, 256}, {64, 16, 256}, {128, 16, 256},
                                    {256, 16, 256}, {256, 8, 256}, {256, 16, 512}, {256, 8, 512},
                                    {512, 16, 512}, {512, 8, 512}, {512, 16, 256}, {512, 16, 1024},
-                                   {1024, 16, 1024}, {1024, 8, 1024}, {1024, 8, 512}, {1024, 16, 512},
-                                   {2048, 8, 1024}, {2048, 8, 512}, {2048, 4, 512}, {2048, 4, 256}};
+                                   {1024, 8, 512}, {1024, 16, 1024}, {1024, 8, 1024}, {1024, 16, 512},
+                                   {2048, 8, 512}, {2048, 8, 1024}, {2048, 4, 512}, {2048, 4, 256}};
     int n = 0;
     for (const auto& r : table)
         if (r[0] == H && n < max_n) {
@@ -714,7 +916,9 @@ int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
 }
 
 hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s) {
-    return launch_col_shape(W, H, col_tc(H), col_threads(H), a, s);
+    int tc[8], nth[8];
+    if (col_shape_candidates(H, tc, nth, 8) < 1) return hipErrorInvalidValue;
+    return launch_col_shape(W, H, tc[0], nth[0], a, s);  // the first candidate is the default
 }
 
 hipError_t launch_band_slots_reduce(int W, int H, int tc, const SweepArgs& a, const int32_t* band_base,

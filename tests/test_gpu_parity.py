@@ -51,6 +51,23 @@ def test_samples_match_oracle(torch_cuda, size, form):
     _check_samples(plan, flat, prob, 0, 4, n, seed, 2)
 
 
+@pytest.mark.parametrize("H,W", [(512, 512), (1024, 32), (512, 64), (2048, 16)])
+def test_long_column_samples_match_oracle(torch_cuda, H, W):
+    """Columns of 512 rows and more (the column kernel that reads its first
+    transform pass from HBM and fuses the last forward pass, the Fourier step
+    and the first inverse pass), square and rectangular, every chain of every
+    sample against the oracle."""
+    mf = _mf()
+    banner(f"samples streamed {H}x{W}")
+    prob = synth.config_128(4, H) if H == W else synth.config_bands(4, H, 8, width=W)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    seed = synth.philox_seed(4)
+    flat, _ = plan.sample(d, seed, chains=3, burn_in=2, n_samples=3, form="streamed")
+    torch_cuda.cuda.synchronize()
+    _check_samples(plan, flat, prob, 0, 3, 3, seed, 2)
+
+
 @pytest.mark.parametrize("form", ["streamed", "persistent"])
 def test_thousand_sweeps_per_sample_parity(torch_cuda, form):
     """Samples after 1, 10, 100 and 1000 sweeps on the same Philox stream."""

@@ -143,7 +143,7 @@ def test_autotuned_shapes_give_identical_samples(torch_cuda):
     b, _ = tuned.sample(d, 5, chains=2, burn_in=1, n_samples=2, form="streamed")
     shapes = {p.H: (base.tile_shape(p.H, p.W), tuned.tile_shape(p.H, p.W)) for p in probs}
     print("default / tuned column tiles:", shapes)
-    defaults = {256: (16, 256), 512: (16, 512), 1024: (16, 1024), 2048: (8, 1024)}
+    defaults = {256: (16, 256), 512: (16, 512), 1024: (8, 512), 2048: (8, 512)}
     for H, (dflt, tuned_shape) in shapes.items():
         assert dflt == defaults[H]
         assert tuned_shape[0] in (4, 8, 16) and tuned_shape[1] in (256, 512, 1024)
