@@ -1324,9 +1324,9 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
         float2* ts = p->tstore.as<float2>();
         mf::SweepArgs a = base_args(p, H, W);
         // the recomputed and reverse sweeps store and load transforms, which only
-        // col_kernel_t does: the first forward pass runs on it too, so that the
-        // recomputed states repeat the checkpointed ones bit for bit
-        a.nPt = nullptr;
+        // the plain kernels do: the first forward pass runs on them too, so that
+        // the recomputed states repeat the checkpointed ones bit for bit
+        a.plain_kernels = 1;
         a.items = di;
         a.n_items = n_items;
         a.src = d;

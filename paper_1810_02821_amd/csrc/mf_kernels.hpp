@@ -63,6 +63,7 @@ struct SweepArgs {
     double* band_slots;       // col kernel: per-tile band sums [tile][kMaxBandsPerProblem], accumulated
     const int16_t* band;      // per-mode band index (concatenated), -1 = none
     int32_t storage;          // kStoreF32 / kStoreF16 / kStoreBF16: element type of `field`
+    int32_t plain_kernels;    // 1: row_kernel / col_kernel_t only (no fused variants)
 };
 
 // Element type of the work field (row, column, init and copy-out kernels of

@@ -245,6 +245,224 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     }
 }
 
+// Radix of the last pass of a length-L transform planned as radix-16 passes
+// plus one remainder pass.
+template <int L>
+constexpr int last_radix() {
+    int r = L;
+    while (r > 16) r /= 16;
+    return r;
+}
+
+// Radix-16 Stockham passes over LDS with NS = NS0, 16 NS0, ... while
+// NS * 16 * TAIL <= L and NS * TAIL < L: all passes before a final pass of radix TAIL.
+template <int L, int NS, int TAIL, int TPG, bool INV>
+__device__ __forceinline__ void passes_before(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    if constexpr (NS * 16 * TAIL <= L && NS * TAIL < L) {
+        stockham_pass<L, 16, NS, TPG, INV>(buf, lane, tw);
+        passes_before<L, NS * 16, TAIL, TPG, INV>(buf, lane, tw);
+    }
+}
+
+// Value of the neighbouring lane (lane ^ 1) in one DPP move (quad_perm 1,0,3,2).
+__device__ __forceinline__ float swap_lanes(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+// Row kernel of a middle sweep (inverse row FFT, emission, pixel-space update,
+// forward row FFT) for rows of 512 pixels and more, with half the LDS traffic
+// and barriers of row_kernel:
+//   A. the first inverse radix-16 pass reads the row from HBM into registers;
+//   B. the middle inverse passes run in LDS;
+//   C. the last inverse pass (radix RL) leaves pixels x = j + r L/RL in
+//      registers, which are emitted, updated and fed to the first forward pass
+//      (radix RL, the same pixels) without touching LDS.  A pixel pair
+//      (x, x + 1) sits in neighbouring lanes: each lane draws half of the
+//      pair's Philox calls and swaps the other half's normals with DPP;
+//   D. the middle forward passes run in LDS and the last one writes the
+//      natural-order row straight to HBM.
+// Same arithmetic per pixel as row_kernel; the forward transform runs its
+// radices remainder-first.
+template <int L>
+__global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
+    constexpr int ROWS = RowShape<L>::ROWS;
+    constexpr int TPR = RowShape<L>::TPR;
+    constexpr int W = L;
+    constexpr int RL = last_radix<L>();
+    constexpr int NT16 = L / 16;                    // radix-16 butterflies per row
+    constexpr int IT16 = (NT16 + TPR - 1) / TPR;
+    constexpr int NTL = L / RL;                     // last-radix butterflies per row
+    constexpr int ITL = NTL / TPR;
+    static_assert(L >= 512 && NTL % TPR == 0 && RL % 2 == 0, "row_kernel_f shape");
+    __shared__ float2 lds[ROWS * L];
+    __shared__ double red[kThreads];
+    __shared__ int32_t row_item[ROWS], row_y[ROWS];
+
+    const unsigned tid = threadIdx.x;
+    const unsigned rid = tid / TPR;
+    const unsigned lane = tid % TPR;
+    const int64_t total_rows = (int64_t)a.n_items * H;
+    const int64_t grow0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
+    for (unsigned r = tid; r < (unsigned)ROWS; r += kThreads) {
+        const int64_t g = grow0 + r;
+        row_item[r] = g < total_rows ? (int32_t)(g % a.n_items) : -1;
+        row_y[r] = g < total_rows ? (int32_t)(g / a.n_items) : 0;
+    }
+    __syncthreads();
+    const int64_t gr = grow0 + rid;
+    const bool valid = row_item[rid] >= 0;
+    const int item = valid ? row_item[rid] : 0;
+    const int y = row_y[rid];
+    const ItemDev it = a.items[item];
+    const ProbDev pr = a.probs[it.prob];
+    float2* row = lds + rid * L;
+    const int64_t frow = it.field_off + (int64_t)y * W;
+
+    // ---- A: first inverse pass (NS = 1), inputs from HBM
+    with_storage(a.storage, [&](auto e0) {
+        using E = decltype(e0);
+        const E* fld = reinterpret_cast<const E*>(a.field) + frow;
+        float2 v[IT16][16];
+#pragma unroll
+        for (int i = 0; i < IT16; ++i) {
+            const unsigned j = lane + i * TPR;
+            if (NT16 % TPR == 0 || j < (unsigned)NT16) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    v[i][r] = valid ? widen(fld[j + r * NT16]) : make_float2(0.f, 0.f);
+                dft<16, true>(v[i]);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) row[swz(j * 16 + r)] = v[i][r];
+            }
+        }
+    });
+    __syncthreads();
+
+    // ---- B: middle inverse passes
+    passes_before<L, 16, RL, TPR, true>(row, lane, a.tw_row);
+
+    // ---- C: last inverse pass, emission, pixel update, first forward pass
+    {
+        const float T = a.lambda * pr.tau;
+        const bool odd = lane & 1u;
+        double acc = 0.0;
+        float2 v[ITL][RL];
+#pragma unroll
+        for (int i = 0; i < ITL; ++i) {
+            const unsigned j = lane + i * TPR;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) v[i][r] = row[swz(j + r * NTL)];
+#pragma unroll
+            for (int r = 1; r < RL; ++r) v[i][r] = cmulc(v[i][r], a.tw_row[r * j]);
+            dft<RL, true>(v[i]);
+            // v[i][r] is now the state at pixel x = j + r NTL
+            if (a.emit_index >= 0 && valid) {
+                const int64_t base = (int64_t)a.chains * a.n_samples * pr.pix_off;
+                const int64_t n = (int64_t)pr.H * pr.W;
+                const int c0 = 2 * it.pair, c1 = 2 * it.pair + 1;
+                float* o0 = a.samples + base + ((int64_t)c0 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
+                float* o1 = a.samples + base + ((int64_t)c1 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
+#pragma unroll
+                for (int r = 0; r < RL; ++r) {
+                    o0[j + r * NTL] = v[i][r].x;
+                    if (c1 < a.chains) o1[j + r * NTL] = v[i][r].y;
+                }
+            }
+            // normals: the even lane draws the pairs of r < RL/2, the odd lane
+            // those of r >= RL/2; each passes its partner the half it needs
+            float2 z[RL];
+#pragma unroll
+            for (int r = 0; r < RL; ++r) z[r] = make_float2(0.f, 0.f);
+            if (a.stochastic) {
+#pragma unroll
+                for (int h = 0; h < RL / 2; ++h) {
+                    const int rr = odd ? h + RL / 2 : h;
+                    const unsigned xe = (j & ~1u) + rr * NTL;
+                    const uint32_t pj = (uint32_t)(((int64_t)y * W + xe) >> 1);
+                    const Normals2 nz = pair_normals(pj, a.sweep, (uint32_t)pr.pid, kStagePixel,
+                                                     (uint32_t)it.pair, a.key0, a.key1);
+                    const float2 send = odd ? nz.a : nz.b;
+                    const float2 recv = make_float2(swap_lanes(send.x), swap_lanes(send.y));
+                    if (odd) {
+                        z[h + RL / 2] = nz.b;
+                        z[h] = recv;
+                    } else {
+                        z[h] = nz.a;
+                        z[h + RL / 2] = recv;
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const unsigned x = j + r * NTL;
+                const int64_t pix = pr.pix_off + (int64_t)y * W + x;
+                const float aa = pix_a(T, a.nbar[pix]);
+                const float sr = a.src[pix];
+                const float oma = 1.0f - aa;
+                float src;
+                if (a.src_kind == kSrcData) src = aa > 0.f ? aa * sr : 0.f;
+                else src = T * sr;
+                const float sig = a.stochastic ? __builtin_amdgcn_sqrtf(fmaxf(T * oma, 0.f)) : 0.f;
+                float2 t;
+                t.x = fmaf(oma, v[i][r].x, fmaf(sig, z[r].x, src));
+                t.y = a.real_only ? 0.f : fmaf(oma, v[i][r].y, fmaf(sig, z[r].y, src));
+                if (valid) {
+                    const int64_t f = frow + x;
+                    if (a.check_t) {
+                        const float2 p0 = a.t_save[f];
+                        const double d0 = (double)t.x - p0.x, e0 = (double)t.y - p0.y;
+                        acc += d0 * d0 + e0 * e0;
+                    }
+                    if (a.save_t) a.t_save[f] = t;
+                }
+                v[i][r] = t;
+            }
+            dft<RL, false>(v[i]);
+        }
+        if (a.check_t) {
+            red[tid] = acc;
+            __syncthreads();
+            if (lane == 0 && valid) {
+                double sum = 0.0;
+                for (int k = 0; k < TPR; ++k) sum += red[rid * TPR + k];
+                a.partials[gr] = sum;  // indexed y * n_items + item
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITL; ++i) {
+            const unsigned j = lane + i * TPR;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) row[swz(j * RL + r)] = v[i][r];
+        }
+        __syncthreads();
+    }
+
+    // ---- D: middle forward passes, then the last one (NS = L/16) to HBM
+    passes_before<L, RL, 16, TPR, false>(row, fresh(lane), fresh(a.tw_row));
+    if (valid)
+        with_storage(a.storage, [&](auto e0) {
+            using E = decltype(e0);
+            E* fld = reinterpret_cast<E*>(a.field) + frow;
+            const unsigned lane2 = fresh(lane);
+            const float2* tw = fresh(a.tw_row);
+            float2 v[IT16][16];
+#pragma unroll
+            for (int i = 0; i < IT16; ++i) {
+                const unsigned j = lane2 + i * TPR;
+                if (NT16 % TPR == 0 || j < (unsigned)NT16) {
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) v[i][r] = row[swz(j + r * NT16)];
+#pragma unroll
+                    for (int r = 1; r < 16; ++r) v[i][r] = cmul(v[i][r], tw[r * j]);
+                    dft<16, false>(v[i]);
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) fld[j + r * NT16] = narrow<E>(v[i][r]);
+                }
+            }
+        });
+}
+
 // Column tiles: TC columns of one item per block of NTH threads; each column
 // is its own LDS segment of L + 32/TC elements (the tile load then hits
 // distinct banks).  The default shape fills at most ~128 KiB of LDS; the
@@ -362,25 +580,6 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
             fld[(int64_t)y * W + c] = narrow<E>(lds[c * SEG + swz(y)]);
         }
     });
-}
-
-// Radix of the last forward pass (and of the first inverse pass) of a
-// length-L transform planned as radix-16 passes plus one remainder pass.
-template <int L>
-constexpr int last_radix() {
-    int r = L;
-    while (r > 16) r /= 16;
-    return r;
-}
-
-// Radix-16 Stockham passes over LDS with NS = NS0, 16 NS0, ... while
-// NS * 16 * TAIL < L, i.e. all passes before a final pass of radix TAIL.
-template <int L, int NS, int TAIL, int TPG, bool INV>
-__device__ __forceinline__ void passes_before(float2* buf, unsigned lane, const float2* __restrict__ tw) {
-    if constexpr (NS * 16 * TAIL <= L && NS * TAIL < L) {
-        stockham_pass<L, 16, NS, TPG, INV>(buf, lane, tw);
-        passes_before<L, NS * 16, TAIL, TPG, INV>(buf, lane, tw);
-    }
 }
 
 // Column kernel of the sampler and the Wiener iteration for H >= 512, with
@@ -829,6 +1028,17 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
     if (rows < 1) rows = 1;
     const int64_t total = (int64_t)a.n_items * H;
     dim3 grid((unsigned)((total + rows - 1) / rows));
+    // middle sweeps of the sampler and the Wiener iteration on rows of 512 and more
+    const bool fused = MODE == kRowInvFwd && W >= 512 && a.pix_mode == kPixUpdate && !a.s_save && !a.plain_kernels;
+    if (fused) {
+        switch (W) {
+            case 512: hipLaunchKernelGGL((row_kernel_f<512>), grid, dim3(kThreads), 0, s, a, H); break;
+            case 1024: hipLaunchKernelGGL((row_kernel_f<1024>), grid, dim3(kThreads), 0, s, a, H); break;
+            case 2048: hipLaunchKernelGGL((row_kernel_f<2048>), grid, dim3(kThreads), 0, s, a, H); break;
+            default: return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     switch (W) {
 #define MF_CASE(N) \
     case N: hipLaunchKernelGGL((row_kernel<N, MODE>), grid, dim3(kThreads), 0, s, a, H); break;
@@ -886,7 +1096,7 @@ hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_
 hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, hipStream_t s) {
     if (tc > W || tc < 2) return hipErrorInvalidValue;
     const int64_t cols = (int64_t)a.n_items * W;
-    const bool fused = !a.t_store && !a.t_load && a.nPt;
+    const bool fused = !a.t_store && !a.t_load && a.nPt && !a.plain_kernels;
     MF_COL_CASE(16, 16, 256) MF_COL_CASE(32, 16, 256) MF_COL_CASE(64, 16, 256) MF_COL_CASE(128, 16, 256)
     MF_COL_CASE(256, 16, 256) MF_COL_CASE(256, 8, 256) MF_COL_CASE(256, 16, 512) MF_COL_CASE(256, 8, 512)
     MF_COL_CASE_F(512, 16, 512) MF_COL_CASE_F(512, 8, 512) MF_COL_CASE_F(512, 16, 256) MF_COL_CASE_F(512, 16, 1024)

@@ -51,12 +51,13 @@ def test_samples_match_oracle(torch_cuda, size, form):
     _check_samples(plan, flat, prob, 0, 4, n, seed, 2)
 
 
-@pytest.mark.parametrize("H,W", [(512, 512), (1024, 32), (512, 64), (2048, 16)])
-def test_long_column_samples_match_oracle(torch_cuda, H, W):
-    """Columns of 512 rows and more (the column kernel that reads its first
-    transform pass from HBM and fuses the last forward pass, the Fourier step
-    and the first inverse pass), square and rectangular, every chain of every
-    sample against the oracle."""
+@pytest.mark.parametrize("H,W", [(512, 512), (1024, 32), (512, 64), (2048, 16), (64, 1024), (16, 2048)])
+def test_long_axis_samples_match_oracle(torch_cuda, H, W):
+    """Columns or rows of 512 and more (the streamed kernels that read their
+    first transform pass from HBM, keep the last pass of one transform, the
+    update and the first pass of the next in registers, and write their last
+    pass to HBM), square and rectangular, every chain of every sample against
+    the oracle."""
     mf = _mf()
     banner(f"samples streamed {H}x{W}")
     prob = synth.config_128(4, H) if H == W else synth.config_bands(4, H, 8, width=W)
@@ -126,12 +127,12 @@ def test_wiener_converges_to_dense_solve_32(torch_cuda, solve):
     assert r < REL_TOL
 
 
-@pytest.mark.parametrize("solve", ["persistent", "streamed"])
-def test_residual_tracks_oracle(torch_cuda, solve):
+@pytest.mark.parametrize("solve,size", [("persistent", 32), ("streamed", 32), ("streamed", 512)])
+def test_residual_tracks_oracle(torch_cuda, solve, size):
     """Residual test sweeps and the returned residual agree with the oracle."""
     mf = _mf()
-    banner(f"residual parity {solve}")
-    prob = synth.config_small(2, 32)
+    banner(f"residual parity {solve} {size}")
+    prob = synth.config_small(2, size)
     plan = mf.Plan([prob], streamed_solve=solve == "streamed")
     d = plan.concat([prob.d])
     s, info = plan.wiener(d, mf.Schedule([1.0], [0], 1e-3, 5000, 10))
