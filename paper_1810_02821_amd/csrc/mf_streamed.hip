@@ -8,6 +8,12 @@
 //
 // Each 1D transform is a Stockham FFT staged in LDS.  Rows (columns) of all
 // work items of one launch are flattened, so small images still fill a block.
+// Floating-point contraction only within a source expression: the fused and
+// the plain row kernels then round every butterfly alike (with contraction
+// across inlined calls, whether a product meets its sum in one basic block,
+// and so becomes an FMA, depends on the kernel), and a run split into several
+// calls reproduces the uninterrupted run bit for bit.
+#pragma clang fp contract(on)
 #include "mf_device.hpp"
 #include "mf_kernels.hpp"
 
@@ -68,6 +74,57 @@ __device__ __forceinline__ float pix_a(float T, float nb) {
     return T * __builtin_amdgcn_rcpf(T + nb);
 }
 
+// Transform plan of the fused streamed kernels: a radix-16 pass at one end,
+// a radix-RL pass at the other, radix-RM passes between them.  L = 256 uses
+// 16 x 4 x 4, so that its RL pass has enough butterflies for every lane and
+// holds few values per thread; longer transforms use radix 16 and the
+// remainder (2048 = 16 x 16 x 8).
+template <int L>
+constexpr int last_radix() {
+    if (L == 256) return 4;
+    int r = L;
+    while (r > 16) r /= 16;
+    return r;
+}
+template <int L>
+constexpr int middle_radix() { return L == 256 ? 4 : 16; }
+
+// Radix-RM Stockham passes over LDS with NS = NS0, RM NS0, ... while
+// NS * RM * TAIL <= L and NS * TAIL < L: all passes before a final pass of radix TAIL.
+template <int L, int RM, int NS, int TAIL, int TPG, bool INV>
+__device__ __forceinline__ void passes_before(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    if constexpr (NS * RM * TAIL <= L && NS * TAIL < L) {
+        stockham_pass<L, RM, NS, TPG, INV>(buf, lane, tw);
+        passes_before<L, RM, NS * RM, TAIL, TPG, INV>(buf, lane, tw);
+    }
+}
+
+// One plan per transform length for every row kernel (so that the fused and
+// the plain row kernels, and hence split and resumed runs, round alike):
+// inverse 16, RM..., RL and forward RL, RM..., 16 from 256 points up.
+template <int L, int TPG>
+__device__ __forceinline__ void row_inverse(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    if constexpr (L >= 256) {
+        constexpr int RL = last_radix<L>();
+        stockham_pass<L, 16, 1, TPG, true>(buf, lane, tw);
+        passes_before<L, middle_radix<L>(), 16, RL, TPG, true>(buf, lane, tw);
+        stockham_pass<L, RL, L / RL, TPG, true>(buf, lane, tw);
+    } else {
+        stockham_fft<L, 1, TPG, true>(buf, lane, tw);
+    }
+}
+template <int L, int TPG>
+__device__ __forceinline__ void row_forward(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    if constexpr (L >= 256) {
+        constexpr int RL = last_radix<L>();
+        stockham_pass<L, RL, 1, TPG, false>(buf, lane, tw);
+        passes_before<L, middle_radix<L>(), RL, 16, TPG, false>(buf, lane, tw);
+        stockham_pass<L, 16, L / 16, TPG, false>(buf, lane, tw);
+    } else {
+        stockham_fft<L, 1, TPG, false>(buf, lane, tw);
+    }
+}
+
 template <int L>
 struct RowShape {
     static constexpr int ROWS = (2048 / L) < 1 ? 1 : (2048 / L);  // rows per block
@@ -124,7 +181,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     float2* row = lds + rid * L;
 
     if constexpr (MODE & kRowInv) {
-        stockham_fft<L, 1, TPR, true>(row, lane, a.tw_row);
+        row_inverse<L, TPR>(row, lane, a.tw_row);
         if (a.s_save && valid)
             for (unsigned x = lane; x < (unsigned)L; x += TPR)
                 a.s_save[it.field_off + (int64_t)y * W + x] = row[swz(x)];
@@ -235,7 +292,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
         }
         __syncthreads();
       }
-        stockham_fft<L, 1, TPR, false>(row, fresh(lane), fresh(a.tw_row));
+        row_forward<L, TPR>(row, fresh(lane), fresh(a.tw_row));
         if (valid)
             with_storage(a.storage, [&](auto e0) {
                 using E = decltype(e0);
@@ -245,32 +302,13 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     }
 }
 
-// Radix of the last pass of a length-L transform planned as radix-16 passes
-// plus one remainder pass.
-template <int L>
-constexpr int last_radix() {
-    int r = L;
-    while (r > 16) r /= 16;
-    return r;
-}
-
-// Radix-16 Stockham passes over LDS with NS = NS0, 16 NS0, ... while
-// NS * 16 * TAIL <= L and NS * TAIL < L: all passes before a final pass of radix TAIL.
-template <int L, int NS, int TAIL, int TPG, bool INV>
-__device__ __forceinline__ void passes_before(float2* buf, unsigned lane, const float2* __restrict__ tw) {
-    if constexpr (NS * 16 * TAIL <= L && NS * TAIL < L) {
-        stockham_pass<L, 16, NS, TPG, INV>(buf, lane, tw);
-        passes_before<L, NS * 16, TAIL, TPG, INV>(buf, lane, tw);
-    }
-}
-
 // Value of the neighbouring lane (lane ^ 1) in one DPP move (quad_perm 1,0,3,2).
 __device__ __forceinline__ float swap_lanes(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
 
 // Row kernel of a middle sweep (inverse row FFT, emission, pixel-space update,
-// forward row FFT) for rows of 512 pixels and more, with half the LDS traffic
+// forward row FFT) for rows of 256 pixels and more, with half the LDS traffic
 // and barriers of row_kernel:
 //   A. the first inverse radix-16 pass reads the row from HBM into registers;
 //   B. the middle inverse passes run in LDS;
@@ -293,7 +331,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     constexpr int IT16 = (NT16 + TPR - 1) / TPR;
     constexpr int NTL = L / RL;                     // last-radix butterflies per row
     constexpr int ITL = NTL / TPR;
-    static_assert(L >= 512 && NTL % TPR == 0 && RL % 2 == 0, "row_kernel_f shape");
+    static_assert(L >= 256 && NTL % TPR == 0 && RL % 2 == 0, "row_kernel_f shape");
     __shared__ float2 lds[ROWS * L];
     __shared__ double red[kThreads];
     __shared__ int32_t row_item[ROWS], row_y[ROWS];
@@ -339,7 +377,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     __syncthreads();
 
     // ---- B: middle inverse passes
-    passes_before<L, 16, RL, TPR, true>(row, lane, a.tw_row);
+    passes_before<L, middle_radix<L>(), 16, RL, TPR, true>(row, lane, a.tw_row);
 
     // ---- C: last inverse pass, emission, pixel update, first forward pass
     {
@@ -439,7 +477,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     }
 
     // ---- D: middle forward passes, then the last one (NS = L/16) to HBM
-    passes_before<L, RL, 16, TPR, false>(row, fresh(lane), fresh(a.tw_row));
+    passes_before<L, middle_radix<L>(), RL, 16, TPR, false>(row, fresh(lane), fresh(a.tw_row));
     if (valid)
         with_storage(a.storage, [&](auto e0) {
             using E = decltype(e0);
@@ -582,7 +620,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     });
 }
 
-// Column kernel of the sampler and the Wiener iteration for H >= 512, with
+// Column kernel of the sampler and the Wiener iteration for H >= 256, with
 // half the LDS traffic and barriers of col_kernel_t:
 //   A. the first forward radix-16 pass reads its inputs from HBM into
 //      registers (a wave covers TC columns of 64/TC rows, as the tile load
@@ -609,7 +647,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     constexpr int NTL = L / RL;                             // last-radix butterflies per column
     constexpr int TPP = NTH / (TC / 2);                     // threads per column pair in phase C
     constexpr int ITL = (NTL + TPP - 1) / TPP;
-    static_assert(L >= 512 && TC % 2 == 0 && NTH % (TC / 2) == 0, "col_kernel_f shape");
+    static_assert(L >= 256 && TC % 2 == 0 && NTH % (TC / 2) == 0, "col_kernel_f shape");
     __shared__ float2 lds[TC * SEG];
     const unsigned tid = threadIdx.x;
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);
@@ -649,7 +687,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     // ---- B: middle forward passes
     {
         const unsigned cid = tid / TPC, lane = tid % TPC;
-        passes_before<L, 16, RL, TPC, false>(lds + cid * SEG, lane, a.tw_col);
+        passes_before<L, middle_radix<L>(), 16, RL, TPC, false>(lds + cid * SEG, lane, a.tw_col);
     }
 
     // ---- C: last forward pass + Fourier-space update + first inverse pass
@@ -725,7 +763,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     // ---- D: middle inverse passes, then the last one (NS = L/16) to HBM
     {
         const unsigned cid = fresh(tid) / TPC, lane = fresh(tid) % TPC;
-        passes_before<L, RL, 16, TPC, true>(lds + cid * SEG, lane, fresh(a.tw_col));
+        passes_before<L, middle_radix<L>(), RL, 16, TPC, true>(lds + cid * SEG, lane, fresh(a.tw_col));
     }
     with_storage(a.storage, [&](auto e0) {
         using E = decltype(e0);
@@ -1028,10 +1066,11 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
     if (rows < 1) rows = 1;
     const int64_t total = (int64_t)a.n_items * H;
     dim3 grid((unsigned)((total + rows - 1) / rows));
-    // middle sweeps of the sampler and the Wiener iteration on rows of 512 and more
-    const bool fused = MODE == kRowInvFwd && W >= 512 && a.pix_mode == kPixUpdate && !a.s_save && !a.plain_kernels;
+    // middle sweeps of the sampler and the Wiener iteration on rows of 256 and more
+    const bool fused = MODE == kRowInvFwd && W >= 256 && a.pix_mode == kPixUpdate && !a.s_save && !a.plain_kernels;
     if (fused) {
         switch (W) {
+            case 256: hipLaunchKernelGGL((row_kernel_f<256>), grid, dim3(kThreads), 0, s, a, H); break;
             case 512: hipLaunchKernelGGL((row_kernel_f<512>), grid, dim3(kThreads), 0, s, a, H); break;
             case 1024: hipLaunchKernelGGL((row_kernel_f<1024>), grid, dim3(kThreads), 0, s, a, H); break;
             case 2048: hipLaunchKernelGGL((row_kernel_f<2048>), grid, dim3(kThreads), 0, s, a, H); break;
@@ -1082,8 +1121,7 @@ hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_
         hipLaunchKernelGGL((col_kernel_t<LL, TCC, NN>), dim3((unsigned)(cols / TCC)), dim3(NN), 0, s, a, W); \
         return hipGetLastError();                                                              \
     }
-// H >= 512 without the gradient's stored transforms: the fused kernel (at 256
-// its 16-point last pass holds two columns of 16 values per thread: 163 VGPRs)
+// H >= 256 without the gradient's stored transforms: the fused kernel
 #define MF_COL_CASE_F(LL, TCC, NN)                                                            \
     if (H == LL && tc == TCC && nth == NN) {                                                   \
         if (fused)                                                                             \
@@ -1098,7 +1136,7 @@ hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, h
     const int64_t cols = (int64_t)a.n_items * W;
     const bool fused = !a.t_store && !a.t_load && a.nPt && !a.plain_kernels;
     MF_COL_CASE(16, 16, 256) MF_COL_CASE(32, 16, 256) MF_COL_CASE(64, 16, 256) MF_COL_CASE(128, 16, 256)
-    MF_COL_CASE(256, 16, 256) MF_COL_CASE(256, 8, 256) MF_COL_CASE(256, 16, 512) MF_COL_CASE(256, 8, 512)
+    MF_COL_CASE_F(256, 16, 256) MF_COL_CASE_F(256, 8, 256) MF_COL_CASE_F(256, 16, 512) MF_COL_CASE_F(256, 8, 512)
     MF_COL_CASE_F(512, 16, 512) MF_COL_CASE_F(512, 8, 512) MF_COL_CASE_F(512, 16, 256) MF_COL_CASE_F(512, 16, 1024)
     MF_COL_CASE_F(1024, 16, 1024) MF_COL_CASE_F(1024, 8, 1024) MF_COL_CASE_F(1024, 8, 512) MF_COL_CASE_F(1024, 16, 512)
     MF_COL_CASE_F(2048, 8, 1024) MF_COL_CASE_F(2048, 8, 512) MF_COL_CASE_F(2048, 4, 512) MF_COL_CASE_F(2048, 4, 256)

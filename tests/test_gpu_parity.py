@@ -51,9 +51,10 @@ def test_samples_match_oracle(torch_cuda, size, form):
     _check_samples(plan, flat, prob, 0, 4, n, seed, 2)
 
 
-@pytest.mark.parametrize("H,W", [(512, 512), (1024, 32), (512, 64), (2048, 16), (64, 1024), (16, 2048)])
+@pytest.mark.parametrize("H,W", [(512, 512), (1024, 32), (512, 64), (2048, 16), (64, 1024), (16, 2048),
+                                 (256, 32), (32, 256)])
 def test_long_axis_samples_match_oracle(torch_cuda, H, W):
-    """Columns or rows of 512 and more (the streamed kernels that read their
+    """Columns or rows of 256 and more (the streamed kernels that read their
     first transform pass from HBM, keep the last pass of one transform, the
     update and the first pass of the next in registers, and write their last
     pass to HBM), square and rectangular, every chain of every sample against
@@ -170,10 +171,14 @@ def test_plain_form_equals_streamed(torch_cuda):
     assert torch_cuda.equal(a, b)
 
 
-def test_resume_is_exact_and_odd_chain_count(torch_cuda):
+@pytest.mark.parametrize("size", [32, 256, 512])
+def test_resume_is_exact_and_odd_chain_count(torch_cuda, size):
+    """A run split at sweep 8 and resumed from its state equals the
+    uninterrupted run bit for bit (its first sweep takes the plain row kernel,
+    the uninterrupted run the fused one at 256 and up)."""
     mf = _mf()
-    banner("resume")
-    prob = synth.config_small(6, 32)
+    banner(f"resume {size}")
+    prob = synth.config_small(6, size)
     plan = mf.Plan([prob])
     d = plan.concat([prob.d])
     full, _ = plan.sample(d, 9, chains=3, burn_in=0, n_samples=20, form="streamed")
