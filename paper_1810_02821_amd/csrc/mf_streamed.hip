@@ -365,9 +365,11 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
         for (int i = 0; i < IT16; ++i) {
             const unsigned j = lane + i * TPR;
             if (NT16 % TPR == 0 || j < (unsigned)NT16) {
+                // unconditional loads (a row past the end reads row 0 of item 0,
+                // whose results are never stored), so that all 16 are in flight
+                // at once instead of each behind its own branch
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    v[i][r] = valid ? widen(fld[j + r * NT16]) : make_float2(0.f, 0.f);
+                for (int r = 0; r < 16; ++r) v[i][r] = widen(fld[j + r * NT16]);
                 dft<16, true>(v[i]);
 #pragma unroll
                 for (int r = 0; r < 16; ++r) row[swz(j * 16 + r)] = v[i][r];
