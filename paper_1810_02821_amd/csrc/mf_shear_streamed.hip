@@ -9,9 +9,14 @@
 // kernel uses mirror-paired tiles as the streamed hierarchical sampler does:
 // tile j of an item holds columns c = j TC/2 + i and their mirrors W - c,
 // with the self-mirror columns 0 and W/2 both in tile 0.
+// Contraction within a source expression only, as in mf_streamed.hip: the
+// fused and the plain row kernels round alike, so split runs repeat
+// uninterrupted ones bit for bit.
+#pragma clang fp contract(on)
 #include "mf_device.hpp"
 #include "mf_kernels.hpp"
 #include "mf_shear.hpp"
+#include "mf_streamed_fft.hpp"
 
 namespace mf {
 
@@ -128,7 +133,7 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel(ShearStreamArgs 
     const ProbDev pr = a.probs[it.prob];
     float2* row = lds + rid * L;
 
-    if constexpr ((MODE & kShearInv) || (MODE & kShearEmit)) stockham_fft<L, 1, TPR, true>(row, lane, a.tw_row);
+    if constexpr ((MODE & kShearInv) || (MODE & kShearEmit)) row_inverse<L, TPR>(row, lane, a.tw_row);
     if constexpr (MODE & kShearEmit) {
         if (valid) {
             const int64_t n = (int64_t)H * W;
@@ -169,9 +174,144 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel(ShearStreamArgs 
         row[swz(x + 1)] = s1;
     }
     __syncthreads();
-    stockham_fft<L, 1, TPR, false>(row, opaque(lane), opaque(a.tw_row));
+    row_forward<L, TPR>(row, opaque(lane), opaque(a.tw_row));
     if (valid)
         for (unsigned x = lane; x < (unsigned)L; x += TPR) a.field[it.field_off + (int64_t)y * W + x] = row[swz(x)];
+}
+
+// Middle sweeps' row step for rows of 256 and more, arranged as the sampler's
+// row_kernel_f: the first inverse pass reads the row from HBM, the last
+// inverse pass, the shear-space pixel step and the first forward pass run in
+// registers (pixel pairs split across neighbouring lanes, normals swapped with
+// DPP), and the last forward pass writes the row to HBM.
+template <int L>
+__global__ __launch_bounds__(kRowThreads) void shear_row_kernel_f(ShearStreamArgs a, int H) {
+    constexpr int ROWS = ShearRowShape<L>::ROWS, TPR = ShearRowShape<L>::TPR;
+    constexpr int W = L;
+    constexpr int RL = last_radix<L>();
+    constexpr int NT16 = L / 16;
+    constexpr int IT16 = (NT16 + TPR - 1) / TPR;
+    constexpr int NTL = L / RL;
+    constexpr int ITL = NTL / TPR;
+    static_assert(L >= 256 && NTL % TPR == 0 && RL % 2 == 0, "shear_row_kernel_f shape");
+    __shared__ float2 lds[ROWS * L];
+    __shared__ int32_t row_item[ROWS], row_y[ROWS];
+    const unsigned tid = threadIdx.x;
+    const int64_t total_rows = (int64_t)a.n_items * H;
+    const int64_t grow0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
+    for (unsigned r = tid; r < (unsigned)ROWS; r += kRowThreads) {
+        const int64_t g = grow0 + r;
+        row_item[r] = g < total_rows ? (int32_t)(g % a.n_items) : -1;
+        row_y[r] = g < total_rows ? (int32_t)(g / a.n_items) : 0;
+    }
+    __syncthreads();
+    const unsigned rid = tid / TPR, lane = tid % TPR;
+    const bool valid = row_item[rid] >= 0;
+    const int item = valid ? row_item[rid] : 0;
+    const int y = row_y[rid];
+    const ItemDev it = a.items[item];
+    const ProbDev pr = a.probs[it.prob];
+    float2* row = lds + rid * L;
+    float2* frow = a.field + it.field_off + (int64_t)y * W;
+
+    // first inverse pass from HBM (a row past the end reads row 0 of item 0,
+    // whose results are never stored)
+#pragma unroll
+    for (int i = 0; i < IT16; ++i) {
+        const unsigned j = lane + i * TPR;
+        if (NT16 % TPR == 0 || j < (unsigned)NT16) {
+            float2 v[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = frow[j + r * NT16];
+            dft<16, true>(v);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) row[swz(j * 16 + r)] = v[r];
+        }
+    }
+    __syncthreads();
+    passes_before<L, middle_radix<L>(), 16, RL, TPR, true>(row, lane, a.tw_row);
+
+    // last inverse pass, pixel step t = (1 - a) s + a gamma (+ sqrt(T (1 - a)) xi),
+    // first forward pass
+    {
+        const float T = a.lambda * pr.tau;
+        const bool odd = lane & 1u;
+        float2 v[ITL][RL];
+#pragma unroll
+        for (int i = 0; i < ITL; ++i) {
+            const unsigned j = lane + i * TPR;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) v[i][r] = row[swz(j + r * NTL)];
+#pragma unroll
+            for (int r = 1; r < RL; ++r) v[i][r] = cmulc(v[i][r], a.tw_row[r * j]);
+            dft<RL, true>(v[i]);
+            float2 z[RL];
+#pragma unroll
+            for (int r = 0; r < RL; ++r) z[r] = make_float2(0.f, 0.f);
+            if (a.stochastic) {
+#pragma unroll
+                for (int h = 0; h < RL / 2; ++h) {
+                    const int rr = odd ? h + RL / 2 : h;
+                    const unsigned xe = (j & ~1u) + rr * NTL;
+                    const uint32_t pj = (uint32_t)(((int64_t)y * W + xe) >> 1);
+                    const Normals2 nz = pair_normals(pj, a.sweep, (uint32_t)pr.pid, kStagePixel,
+                                                     (uint32_t)it.pair, a.key0, a.key1);
+                    const float2 send = odd ? nz.a : nz.b;
+                    const float2 recv = make_float2(swap_lanes(send.x), swap_lanes(send.y));
+                    if (odd) {
+                        z[h + RL / 2] = nz.b;
+                        z[h] = recv;
+                    } else {
+                        z[h] = nz.a;
+                        z[h + RL / 2] = recv;
+                    }
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const int64_t px = pr.pix_off + (int64_t)y * W + j + r * NTL;
+                const float a0 = T * __builtin_amdgcn_rcpf(T + a.nbar[px]);
+                const float2 g = a.gamma[px];
+                const float2 g0 = a0 > 0.f ? make_float2(a0 * g.x, a0 * g.y) : make_float2(0.f, 0.f);
+                float2 s0 = make_float2(fmaf(1.f - a0, v[i][r].x, g0.x), fmaf(1.f - a0, v[i][r].y, g0.y));
+                if (a.stochastic && valid) {
+                    const float sg0 = __builtin_amdgcn_sqrtf(fmaxf(T * (1.f - a0), 0.f));
+                    s0 = make_float2(fmaf(sg0, z[r].x, s0.x), fmaf(sg0, z[r].y, s0.y));
+                }
+                v[i][r] = s0;
+            }
+            dft<RL, false>(v[i]);
+        }
+        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < ITL; ++i) {
+            const unsigned j = lane + i * TPR;
+#pragma unroll
+            for (int r = 0; r < RL; ++r) row[swz(j * RL + r)] = v[i][r];
+        }
+        __syncthreads();
+    }
+
+    // middle forward passes, then the last one (NS = L/16) to HBM
+    passes_before<L, middle_radix<L>(), RL, 16, TPR, false>(row, opaque(lane), opaque(a.tw_row));
+    if (valid) {
+        const unsigned lane2 = opaque(lane);
+        const float2* tw = opaque(a.tw_row);
+#pragma unroll
+        for (int i = 0; i < IT16; ++i) {
+            const unsigned j = lane2 + i * TPR;
+            if (NT16 % TPR == 0 || j < (unsigned)NT16) {
+                float2 v[16];
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[r] = row[swz(j + r * NT16)];
+#pragma unroll
+                for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw[r * j]);
+                dft<16, false>(v);
+#pragma unroll
+                for (int r = 0; r < 16; ++r) frow[j + r * NT16] = v[r];
+            }
+        }
+    }
 }
 
 template <int L>
@@ -284,6 +424,8 @@ hipError_t launch_shear_row(int W, int H, int mode, const ShearStreamArgs& a, hi
     case LL: {                                                                                               \
         const dim3 grid((unsigned)((rows + ShearRowShape<LL>::ROWS - 1) / ShearRowShape<LL>::ROWS));         \
         if (mode == kShearFwd) hipLaunchKernelGGL((shear_row_kernel<LL, kShearFwd>), grid, dim3(kRowThreads), 0, s, a, H); \
+        else if (mode == kShearInvFwd && LL >= 256)                                                          \
+            hipLaunchKernelGGL((shear_row_kernel_f<(LL >= 256 ? LL : 256)>), grid, dim3(kRowThreads), 0, s, a, H); \
         else if (mode == kShearInvFwd)                                                                       \
             hipLaunchKernelGGL((shear_row_kernel<LL, kShearInvFwd>), grid, dim3(kRowThreads), 0, s, a, H);   \
         else if (mode == kShearInv) hipLaunchKernelGGL((shear_row_kernel<LL, kShearInv>), grid, dim3(kRowThreads), 0, s, a, H); \

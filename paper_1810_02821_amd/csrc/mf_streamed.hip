@@ -16,6 +16,7 @@
 #pragma clang fp contract(on)
 #include "mf_device.hpp"
 #include "mf_kernels.hpp"
+#include "mf_streamed_fft.hpp"
 
 namespace mf {
 
@@ -72,57 +73,6 @@ __device__ __forceinline__ void with_storage(int32_t st, Fn&& fn) {
 __device__ __forceinline__ float pix_a(float T, float nb) {
     // a = T / (T + Nbar); Nbar = +inf on missing pixels gives a = 0
     return T * __builtin_amdgcn_rcpf(T + nb);
-}
-
-// Transform plan of the fused streamed kernels: a radix-16 pass at one end,
-// a radix-RL pass at the other, radix-RM passes between them.  L = 256 uses
-// 16 x 4 x 4, so that its RL pass has enough butterflies for every lane and
-// holds few values per thread; longer transforms use radix 16 and the
-// remainder (2048 = 16 x 16 x 8).
-template <int L>
-constexpr int last_radix() {
-    if (L == 256) return 4;
-    int r = L;
-    while (r > 16) r /= 16;
-    return r;
-}
-template <int L>
-constexpr int middle_radix() { return L == 256 ? 4 : 16; }
-
-// Radix-RM Stockham passes over LDS with NS = NS0, RM NS0, ... while
-// NS * RM * TAIL <= L and NS * TAIL < L: all passes before a final pass of radix TAIL.
-template <int L, int RM, int NS, int TAIL, int TPG, bool INV>
-__device__ __forceinline__ void passes_before(float2* buf, unsigned lane, const float2* __restrict__ tw) {
-    if constexpr (NS * RM * TAIL <= L && NS * TAIL < L) {
-        stockham_pass<L, RM, NS, TPG, INV>(buf, lane, tw);
-        passes_before<L, RM, NS * RM, TAIL, TPG, INV>(buf, lane, tw);
-    }
-}
-
-// One plan per transform length for every row kernel (so that the fused and
-// the plain row kernels, and hence split and resumed runs, round alike):
-// inverse 16, RM..., RL and forward RL, RM..., 16 from 256 points up.
-template <int L, int TPG>
-__device__ __forceinline__ void row_inverse(float2* buf, unsigned lane, const float2* __restrict__ tw) {
-    if constexpr (L >= 256) {
-        constexpr int RL = last_radix<L>();
-        stockham_pass<L, 16, 1, TPG, true>(buf, lane, tw);
-        passes_before<L, middle_radix<L>(), 16, RL, TPG, true>(buf, lane, tw);
-        stockham_pass<L, RL, L / RL, TPG, true>(buf, lane, tw);
-    } else {
-        stockham_fft<L, 1, TPG, true>(buf, lane, tw);
-    }
-}
-template <int L, int TPG>
-__device__ __forceinline__ void row_forward(float2* buf, unsigned lane, const float2* __restrict__ tw) {
-    if constexpr (L >= 256) {
-        constexpr int RL = last_radix<L>();
-        stockham_pass<L, RL, 1, TPG, false>(buf, lane, tw);
-        passes_before<L, middle_radix<L>(), RL, 16, TPG, false>(buf, lane, tw);
-        stockham_pass<L, 16, L / 16, TPG, false>(buf, lane, tw);
-    } else {
-        stockham_fft<L, 1, TPG, false>(buf, lane, tw);
-    }
 }
 
 template <int L>
@@ -302,10 +252,6 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     }
 }
 
-// Value of the neighbouring lane (lane ^ 1) in one DPP move (quad_perm 1,0,3,2).
-__device__ __forceinline__ float swap_lanes(float v) {
-    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
-}
 
 // Row kernel of a middle sweep (inverse row FFT, emission, pixel-space update,
 // forward row FFT) for rows of 256 pixels and more, with half the LDS traffic

@@ -1,0 +1,65 @@
+// Transform plan shared by the streamed row kernels (sampler and mass
+// mapping): one radix sequence per length for the plain and the fused kernels,
+// so that both round every butterfly alike.
+#pragma once
+#include "mf_device.hpp"
+
+namespace mf {
+
+// Transform plan of the fused streamed kernels: a radix-16 pass at one end,
+// a radix-RL pass at the other, radix-RM passes between them.  L = 256 uses
+// 16 x 4 x 4, so that its RL pass has enough butterflies for every lane and
+// holds few values per thread; longer transforms use radix 16 and the
+// remainder (2048 = 16 x 16 x 8).
+template <int L>
+constexpr int last_radix() {
+    if (L == 256) return 4;
+    int r = L;
+    while (r > 16) r /= 16;
+    return r;
+}
+template <int L>
+constexpr int middle_radix() { return L == 256 ? 4 : 16; }
+
+// Radix-RM Stockham passes over LDS with NS = NS0, RM NS0, ... while
+// NS * RM * TAIL <= L and NS * TAIL < L: all passes before a final pass of radix TAIL.
+template <int L, int RM, int NS, int TAIL, int TPG, bool INV>
+__device__ __forceinline__ void passes_before(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    if constexpr (NS * RM * TAIL <= L && NS * TAIL < L) {
+        stockham_pass<L, RM, NS, TPG, INV>(buf, lane, tw);
+        passes_before<L, RM, NS * RM, TAIL, TPG, INV>(buf, lane, tw);
+    }
+}
+
+// One plan per transform length for every row kernel (the fused and the plain
+// row kernels, and hence split and resumed runs, then round alike): inverse
+// 16, RM..., RL and forward RL, RM..., 16 from 256 points up.
+template <int L, int TPG>
+__device__ __forceinline__ void row_inverse(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    if constexpr (L >= 256) {
+        constexpr int RL = last_radix<L>();
+        stockham_pass<L, 16, 1, TPG, true>(buf, lane, tw);
+        passes_before<L, middle_radix<L>(), 16, RL, TPG, true>(buf, lane, tw);
+        stockham_pass<L, RL, L / RL, TPG, true>(buf, lane, tw);
+    } else {
+        stockham_fft<L, 1, TPG, true>(buf, lane, tw);
+    }
+}
+template <int L, int TPG>
+__device__ __forceinline__ void row_forward(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    if constexpr (L >= 256) {
+        constexpr int RL = last_radix<L>();
+        stockham_pass<L, RL, 1, TPG, false>(buf, lane, tw);
+        passes_before<L, middle_radix<L>(), RL, 16, TPG, false>(buf, lane, tw);
+        stockham_pass<L, 16, L / 16, TPG, false>(buf, lane, tw);
+    } else {
+        stockham_fft<L, 1, TPG, false>(buf, lane, tw);
+    }
+}
+
+// Value of the neighbouring lane (lane ^ 1) in one DPP move (quad_perm 1,0,3,2).
+__device__ __forceinline__ float swap_lanes(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+
+}  // namespace mf
