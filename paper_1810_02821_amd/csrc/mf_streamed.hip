@@ -265,8 +265,8 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
 //      pair's Philox calls and swaps the other half's normals with DPP;
 //   D. the middle forward passes run in LDS and the last one writes the
 //      natural-order row straight to HBM.
-// Same arithmetic per pixel as row_kernel; the forward transform runs its
-// radices remainder-first.
+// The same arithmetic, pass for pass and pixel for pixel, as row_kernel with
+// the plan of row_inverse / row_forward, so the two round identically.
 template <int L>
 __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     constexpr int ROWS = RowShape<L>::ROWS;
@@ -580,8 +580,9 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
 //      the column-pair table nPt gives both coefficients in one coalesced load;
 //   D. the middle inverse passes run in LDS and the last one writes its
 //      outputs, in natural order, straight to HBM.
-// Same arithmetic per mode as col_kernel_t; the inverse transform runs its
-// radices in the opposite order (remainder pass first).
+// Same arithmetic per mode as col_kernel_t, with the plan of the row kernels
+// (forward 16, RM..., RL; inverse RL, RM..., 16).  Every sweep of a run takes
+// the same column kernel, so split runs still repeat uninterrupted ones.
 template <int L, int TC_, int NTH_>
 __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     constexpr int TC = TC_;
