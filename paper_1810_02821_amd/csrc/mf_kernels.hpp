@@ -80,7 +80,6 @@ enum PixMode : int32_t {
 // emission first; bit 2: pixel update + forward row FFT.
 enum RowMode : int32_t { kRowInv = 1, kRowFwd = 2, kRowInvFwd = 3 };
 hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_t s);
-hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s);
 // Column kernel with an explicit tile shape (TC columns, nth threads), and the
 // shapes available for a column length (returns how many were written).
 hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, hipStream_t s);

@@ -1112,12 +1112,6 @@ int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
     return n;
 }
 
-hipError_t launch_col(int W, int H, const SweepArgs& a, hipStream_t s) {
-    int tc[8], nth[8];
-    if (col_shape_candidates(H, tc, nth, 8) < 1) return hipErrorInvalidValue;
-    return launch_col_shape(W, H, tc[0], nth[0], a, s);  // the first candidate is the default
-}
-
 hipError_t launch_band_slots_reduce(int W, int H, int tc, const SweepArgs& a, const int32_t* band_base,
                                     const int32_t* band_count, double* out, hipStream_t s) {
     (void)H;
