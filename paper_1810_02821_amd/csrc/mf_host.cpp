@@ -370,6 +370,7 @@ mf_status solve_class(mf_plan p, const std::vector<int>& pids, int H, int W, con
     mf::SweepArgs a = base_args(p, H, W);
     a.items = d_items;
     a.n_items = n_items;
+    a.rows_by_item = 1;  // one item per problem
     a.field = p->field.as<float2>();
     a.src = src;
     a.src_kind = src_kind;
@@ -778,6 +779,7 @@ mf_status enqueue_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, i
     mf::SweepArgs a = base_args(p, H, W);
     a.items = d_items;
     a.n_items = n_items;
+    a.rows_by_item = g->chains_per_problem <= 2;  // one chain pair per problem
     a.field = work;
     a.src = d;
     a.src_kind = mf::kSrcData;
@@ -817,6 +819,7 @@ mf_status cool_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int 
     mf::SweepArgs a = base_args(p, H, W);
     a.items = d_items;
     a.n_items = n_items;
+    a.rows_by_item = g->chains_per_problem <= 2;  // one chain pair per problem
     a.field = w;
     a.src = d;
     a.src_kind = mf::kSrcData;

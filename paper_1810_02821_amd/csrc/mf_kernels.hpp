@@ -64,6 +64,7 @@ struct SweepArgs {
     const int16_t* band;      // per-mode band index (concatenated), -1 = none
     int32_t storage;          // kStoreF32 / kStoreF16 / kStoreBF16: element type of `field`
     int32_t plain_kernels;    // 1: row_kernel / col_kernel_t only (no fused variants)
+    int32_t rows_by_item;     // row enumeration: 1 g = item H + y (one item per problem), 0 g = y n_items + item
 };
 
 // Element type of the work field (row, column, init and copy-out kernels of

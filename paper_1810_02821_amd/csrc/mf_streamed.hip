@@ -83,7 +83,9 @@ struct RowShape {
 
 // Rows of all work items are enumerated with the item index fastest,
 // g = y * n_items + item, so that the rows one block (and one XCD) handles
-// share the rows of the problem tables.
+// share the rows of the problem tables; with one item per problem
+// (rows_by_item) they run y fastest within each item instead, so that a block
+// and its neighbours stay inside one problem's rows and pages.
 template <int L, int MODE>
 __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     constexpr int ROWS = RowShape<L>::ROWS;
@@ -102,8 +104,8 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     const int64_t grow0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
     for (unsigned r = tid; r < (unsigned)ROWS; r += kThreads) {
         const int64_t g = grow0 + r;
-        row_item[r] = g < total_rows ? (int32_t)(g % a.n_items) : -1;
-        row_y[r] = g < total_rows ? (int32_t)(g / a.n_items) : 0;
+        row_item[r] = g < total_rows ? (int32_t)(a.rows_by_item ? g / H : g % a.n_items) : -1;
+        row_y[r] = g < total_rows ? (int32_t)(a.rows_by_item ? g % H : g / a.n_items) : 0;
     }
     __syncthreads();
 
@@ -122,7 +124,6 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     });
     __syncthreads();
 
-    const int64_t gr = grow0 + rid;
     const bool valid = row_item[rid] >= 0;
     const int item = valid ? row_item[rid] : 0;
     const int y = row_y[rid];
@@ -237,7 +238,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
             if (lane == 0 && valid) {
                 double s = 0.0;
                 for (int i = 0; i < TPR; ++i) s += red[rid * TPR + i];
-                a.partials[gr] = s;  // indexed y * n_items + item
+                a.partials[(int64_t)y * a.n_items + item] = s;
             }
         }
         __syncthreads();
@@ -289,11 +290,10 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     const int64_t grow0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
     for (unsigned r = tid; r < (unsigned)ROWS; r += kThreads) {
         const int64_t g = grow0 + r;
-        row_item[r] = g < total_rows ? (int32_t)(g % a.n_items) : -1;
-        row_y[r] = g < total_rows ? (int32_t)(g / a.n_items) : 0;
+        row_item[r] = g < total_rows ? (int32_t)(a.rows_by_item ? g / H : g % a.n_items) : -1;
+        row_y[r] = g < total_rows ? (int32_t)(a.rows_by_item ? g % H : g / a.n_items) : 0;
     }
     __syncthreads();
-    const int64_t gr = grow0 + rid;
     const bool valid = row_item[rid] >= 0;
     const int item = valid ? row_item[rid] : 0;
     const int y = row_y[rid];
@@ -411,7 +411,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
             if (lane == 0 && valid) {
                 double sum = 0.0;
                 for (int k = 0; k < TPR; ++k) sum += red[rid * TPR + k];
-                a.partials[gr] = sum;  // indexed y * n_items + item
+                a.partials[(int64_t)y * a.n_items + item] = sum;
             }
         }
         __syncthreads();
