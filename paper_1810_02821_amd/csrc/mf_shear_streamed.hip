@@ -330,13 +330,21 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
     const ProbDev pr = a.probs[it.prob];
     const float2* fin = a.field + it.field_off;
 
-    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
-        const int s = (int)(e % TC), y = (int)(e / TC);
-        lds[s * SEG + swz(y)] = fin[(int64_t)y * W + pair_column(j, s, half, W)];
-    }
-    __syncthreads();
+    auto col_of = [&](int s) { return pair_column(j, s, half, W); };
     const unsigned cid = tid / TPC, lane = tid % TPC;
-    stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
+    if constexpr (L >= 256) {
+        // first forward pass straight from HBM (plan of mf_streamed_fft.hpp)
+        col_first_forward<L, TC, NTH, SEG>(lds, fin, W, tid, col_of);
+        __syncthreads();
+        col_forward_rest<L, TPC>(lds + cid * SEG, lane, a.tw_col);
+    } else {
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const int s = (int)(e % TC), y = (int)(e / TC);
+            lds[s * SEG + swz(y)] = fin[(int64_t)y * W + pair_column(j, s, half, W)];
+        }
+        __syncthreads();
+        stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
+    }
 
     // E/B Fourier step, one job per mode pair {k, -k} (see col_pair_kernel)
     const float T = a.lambda * pr.tau;
@@ -399,11 +407,17 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
         v = cmul(v, cscale(ks(y, pair_column(j, s, half, W), H, W), back));
     }
     __syncthreads();
-    stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
     float2* fout = a.field + it.field_off;
-    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
-        const int s = (int)(e % TC), y = (int)(e / TC);
-        fout[(int64_t)y * W + pair_column(j, s, half, W)] = lds[s * SEG + swz(y)];
+    if constexpr (L >= 256) {
+        // inverse transform, its last pass straight to HBM
+        col_inverse_head<L, TPC>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
+        col_last_inverse<L, TC, NTH, SEG>(lds, fout, W, opaque(tid), opaque(a.tw_col), col_of);
+    } else {
+        stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const int s = (int)(e % TC), y = (int)(e / TC);
+            fout[(int64_t)y * W + pair_column(j, s, half, W)] = lds[s * SEG + swz(y)];
+        }
     }
 }
 

@@ -17,6 +17,7 @@
 #include "mf_device.hpp"
 #include "mf_kernels.hpp"
 #include "mf_spectrum.hpp"
+#include "mf_streamed_fft.hpp"
 
 namespace mf {
 
@@ -77,15 +78,22 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
     const ProbDev pr = a.probs[it.prob];
     float2* fld = a.field + it.field_off;
 
-    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
-        const int s = (int)(e % TC), y = (int)(e / TC);
-        lds[s * SEG + swz(y)] = fld[(int64_t)y * W + pair_column(j, s, half, W)];
+    auto col_of = [&](int s) { return pair_column(j, s, half, W); };
+    if constexpr (L >= 256) {
+        // first forward pass straight from HBM (plan of mf_streamed_fft.hpp)
+        col_first_forward<L, TC, NTH, SEG>(lds, fld, W, tid, col_of);
+    } else {
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const int s = (int)(e % TC), y = (int)(e / TC);
+            lds[s * SEG + swz(y)] = fld[(int64_t)y * W + pair_column(j, s, half, W)];
+        }
     }
     for (unsigned u = tid; u < 2 * kNB; u += NTH) pw[u / kNB][u % kNB] = 0.0;
     for (unsigned u = tid; u < kNB; u += NTH) coef[u] = a.coef[(int64_t)item * kNB + u];
     __syncthreads();
     const unsigned cid = tid / TPC, lane = tid % TPC;
-    stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
+    if constexpr (L >= 256) col_forward_rest<L, TPC>(lds + cid * SEG, lane, a.tw_col);
+    else stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
 
     // one job per mode pair {k, -k}: a first-half slot with its partner slot
     // (consecutive lanes take consecutive slots of a row, so the band-index
@@ -143,11 +151,16 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
             const double v = pw[u / kNB][u % kNB];
             if (v != 0.0) atomicAdd(&a.pw[((int64_t)item * 2 + u / kNB) * kNB + u % kNB], v);
         }
-    stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
-
-    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
-        const int s = (int)(e % TC), y = (int)(e / TC);
-        fld[(int64_t)y * W + pair_column(j, s, half, W)] = lds[s * SEG + swz(y)];
+    if constexpr (L >= 256) {
+        // inverse transform, its last pass straight to HBM
+        col_inverse_head<L, TPC>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
+        col_last_inverse<L, TC, NTH, SEG>(lds, fld, W, opaque(tid), opaque(a.tw_col), col_of);
+    } else {
+        stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const int s = (int)(e % TC), y = (int)(e / TC);
+            fld[(int64_t)y * W + pair_column(j, s, half, W)] = lds[s * SEG + swz(y)];
+        }
     }
 }
 

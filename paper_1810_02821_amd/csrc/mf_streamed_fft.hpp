@@ -62,4 +62,65 @@ __device__ __forceinline__ float swap_lanes(float v) {
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
 }
 
+// Column tiles of the mirror-paired column kernels (L >= 256): TC slot columns
+// of L rows, slot c of column col_of(c), each its own LDS segment of SEG.
+// The first forward radix-16 pass reads its inputs straight from HBM (a wave
+// covers TC slots of 64/TC rows) and writes its outputs to LDS; the rest of
+// the forward transform (radix RM..., RL) runs in LDS.
+template <int L, int TC, int NTH, int SEG, typename ColOf>
+__device__ __forceinline__ void col_first_forward(float2* lds, const float2* fld, int W, unsigned tid, ColOf col_of) {
+    constexpr int NT16 = L / 16;
+    constexpr int IT16 = (TC * NT16 + NTH - 1) / NTH;
+#pragma unroll
+    for (int i = 0; i < IT16; ++i) {
+        const unsigned b = tid + i * NTH;
+        if ((TC * NT16) % NTH == 0 || b < (unsigned)(TC * NT16)) {
+            const unsigned c = b % TC, j = b / TC;
+            const int64_t col = col_of((int)c);
+            float2 v[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = fld[(int64_t)(j + r * NT16) * W + col];
+            dft<16, false>(v);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) lds[c * SEG + swz(j * 16 + r)] = v[r];
+        }
+    }
+}
+template <int L, int TPC>
+__device__ __forceinline__ void col_forward_rest(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    constexpr int RL = last_radix<L>();
+    passes_before<L, middle_radix<L>(), 16, RL, TPC, false>(buf, lane, tw);
+    stockham_pass<L, RL, L / RL, TPC, false>(buf, lane, tw);
+}
+// Inverse counterpart: radix RL, RM... in LDS, then the last radix-16 pass
+// writes natural-order rows straight to HBM.
+template <int L, int TPC>
+__device__ __forceinline__ void col_inverse_head(float2* buf, unsigned lane, const float2* __restrict__ tw) {
+    constexpr int RL = last_radix<L>();
+    stockham_pass<L, RL, 1, TPC, true>(buf, lane, tw);
+    passes_before<L, middle_radix<L>(), RL, 16, TPC, true>(buf, lane, tw);
+}
+template <int L, int TC, int NTH, int SEG, typename ColOf>
+__device__ __forceinline__ void col_last_inverse(const float2* lds, float2* fld, int W, unsigned tid,
+                                                 const float2* __restrict__ tw, ColOf col_of) {
+    constexpr int NT16 = L / 16;
+    constexpr int IT16 = (TC * NT16 + NTH - 1) / NTH;
+#pragma unroll
+    for (int i = 0; i < IT16; ++i) {
+        const unsigned b = tid + i * NTH;
+        if ((TC * NT16) % NTH == 0 || b < (unsigned)(TC * NT16)) {
+            const unsigned c = b % TC, j = b / TC;
+            const int64_t col = col_of((int)c);
+            float2 v[16];
+#pragma unroll
+            for (int r = 0; r < 16; ++r) v[r] = lds[c * SEG + swz(j + r * NT16)];
+#pragma unroll
+            for (int r = 1; r < 16; ++r) v[r] = cmulc(v[r], tw[r * j]);
+            dft<16, true>(v);
+#pragma unroll
+            for (int r = 0; r < 16; ++r) fld[(int64_t)(j + r * NT16) * W + col] = v[r];
+        }
+    }
+}
+
 }  // namespace mf
