@@ -171,78 +171,78 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     }
 
     if constexpr (MODE & kRowFwd) {
-      if (a.pix_mode == kPixAdjoint) {
-        // transpose of the pixel step: grad_d += a t, t <- (1 - a) t
-        const float T = a.lambda * pr.tau;
-        for (unsigned x = lane; x < (unsigned)L; x += TPR) {
-            const int64_t pix = pr.pix_off + (int64_t)y * W + x;
-            const float aa = pix_a(T, a.nbar[pix]);
-            const float2 tb = row[swz(x)];
-            if (valid) a.grad_d[pix] += aa * tb.x;
-            row[swz(x)] = cscale(tb, 1.0f - aa);
-        }
-        __syncthreads();
-      } else if (a.pix_mode == kPixIdentity) {
-        __syncthreads();
-      } else {
-        // ---- pixel-space messenger update t = (1 - a) s + src + sigma_t xi
-        const float T = a.lambda * pr.tau;
-        double acc = 0.0;
-#pragma unroll 2
-        for (unsigned pp = lane; pp < (unsigned)L / 2; pp += TPR) {
-            const unsigned x = 2 * pp;
-            const int64_t pix = pr.pix_off + (int64_t)y * W + x;
-            const float2 nb = *reinterpret_cast<const float2*>(a.nbar + pix);
-            const float2 sv = *reinterpret_cast<const float2*>(a.src + pix);
-            float aa[2] = {pix_a(T, nb.x), pix_a(T, nb.y)};
-            float sr[2] = {sv.x, sv.y};
-            float2 s[2] = {row[swz(x)], row[swz(x + 1)]};
-            float2 z[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
-            if (a.stochastic && valid) {
-                const uint32_t j = (uint32_t)(((int64_t)y * W + x) >> 1);
-                const Normals2 nz = pair_normals(j, a.sweep, (uint32_t)pr.pid, kStagePixel, (uint32_t)it.pair,
-                                                 a.key0, a.key1);
-                z[0] = nz.a;
-                z[1] = nz.b;
+        if (a.pix_mode == kPixAdjoint) {
+            // transpose of the pixel step: grad_d += a t, t <- (1 - a) t
+            const float T = a.lambda * pr.tau;
+            for (unsigned x = lane; x < (unsigned)L; x += TPR) {
+                const int64_t pix = pr.pix_off + (int64_t)y * W + x;
+                const float aa = pix_a(T, a.nbar[pix]);
+                const float2 tb = row[swz(x)];
+                if (valid) a.grad_d[pix] += aa * tb.x;
+                row[swz(x)] = cscale(tb, 1.0f - aa);
             }
-            float2 t[2];
-#pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                const float oma = 1.0f - aa[q];
-                float src;
-                if (a.src_kind == kSrcData) src = aa[q] > 0.f ? aa[q] * sr[q] : 0.f;
-                else src = T * sr[q];
-                const float sig = a.stochastic ? __builtin_amdgcn_sqrtf(fmaxf(T * oma, 0.f)) : 0.f;
-                t[q].x = fmaf(oma, s[q].x, fmaf(sig, z[q].x, src));
-                t[q].y = a.real_only ? 0.f : fmaf(oma, s[q].y, fmaf(sig, z[q].y, src));
-            }
-            if (valid) {
-                const int64_t f = it.field_off + (int64_t)y * W + x;
-                if (a.check_t) {
-                    const float2 p0 = a.t_save[f], p1 = a.t_save[f + 1];
-                    const double d0 = (double)t[0].x - p0.x, d1 = (double)t[1].x - p1.x;
-                    const double e0 = (double)t[0].y - p0.y, e1 = (double)t[1].y - p1.y;
-                    acc += d0 * d0 + d1 * d1 + e0 * e0 + e1 * e1;
-                }
-                if (a.save_t) {
-                    a.t_save[f] = t[0];
-                    a.t_save[f + 1] = t[1];
-                }
-            }
-            row[swz(x)] = t[0];
-            row[swz(x + 1)] = t[1];
-        }
-        if (a.check_t) {
-            red[tid] = acc;
             __syncthreads();
-            if (lane == 0 && valid) {
-                double s = 0.0;
-                for (int i = 0; i < TPR; ++i) s += red[rid * TPR + i];
-                a.partials[(int64_t)y * a.n_items + item] = s;
+        } else if (a.pix_mode == kPixIdentity) {
+            __syncthreads();
+        } else {
+            // ---- pixel-space messenger update t = (1 - a) s + src + sigma_t xi
+            const float T = a.lambda * pr.tau;
+            double acc = 0.0;
+#pragma unroll 2
+            for (unsigned pp = lane; pp < (unsigned)L / 2; pp += TPR) {
+                const unsigned x = 2 * pp;
+                const int64_t pix = pr.pix_off + (int64_t)y * W + x;
+                const float2 nb = *reinterpret_cast<const float2*>(a.nbar + pix);
+                const float2 sv = *reinterpret_cast<const float2*>(a.src + pix);
+                float aa[2] = {pix_a(T, nb.x), pix_a(T, nb.y)};
+                float sr[2] = {sv.x, sv.y};
+                float2 s[2] = {row[swz(x)], row[swz(x + 1)]};
+                float2 z[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
+                if (a.stochastic && valid) {
+                    const uint32_t j = (uint32_t)(((int64_t)y * W + x) >> 1);
+                    const Normals2 nz = pair_normals(j, a.sweep, (uint32_t)pr.pid, kStagePixel, (uint32_t)it.pair,
+                                                     a.key0, a.key1);
+                    z[0] = nz.a;
+                    z[1] = nz.b;
+                }
+                float2 t[2];
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    const float oma = 1.0f - aa[q];
+                    float src;
+                    if (a.src_kind == kSrcData) src = aa[q] > 0.f ? aa[q] * sr[q] : 0.f;
+                    else src = T * sr[q];
+                    const float sig = a.stochastic ? __builtin_amdgcn_sqrtf(fmaxf(T * oma, 0.f)) : 0.f;
+                    t[q].x = fmaf(oma, s[q].x, fmaf(sig, z[q].x, src));
+                    t[q].y = a.real_only ? 0.f : fmaf(oma, s[q].y, fmaf(sig, z[q].y, src));
+                }
+                if (valid) {
+                    const int64_t f = it.field_off + (int64_t)y * W + x;
+                    if (a.check_t) {
+                        const float2 p0 = a.t_save[f], p1 = a.t_save[f + 1];
+                        const double d0 = (double)t[0].x - p0.x, d1 = (double)t[1].x - p1.x;
+                        const double e0 = (double)t[0].y - p0.y, e1 = (double)t[1].y - p1.y;
+                        acc += d0 * d0 + d1 * d1 + e0 * e0 + e1 * e1;
+                    }
+                    if (a.save_t) {
+                        a.t_save[f] = t[0];
+                        a.t_save[f + 1] = t[1];
+                    }
+                }
+                row[swz(x)] = t[0];
+                row[swz(x + 1)] = t[1];
             }
+            if (a.check_t) {
+                red[tid] = acc;
+                __syncthreads();
+                if (lane == 0 && valid) {
+                    double s = 0.0;
+                    for (int i = 0; i < TPR; ++i) s += red[rid * TPR + i];
+                    a.partials[(int64_t)y * a.n_items + item] = s;
+                }
+            }
+            __syncthreads();
         }
-        __syncthreads();
-      }
         row_forward<L, TPR>(row, fresh(lane), fresh(a.tw_row));
         if (valid)
             with_storage(a.storage, [&](auto e0) {
