@@ -75,6 +75,15 @@ __device__ __forceinline__ float pix_a(float T, float nb) {
     return T * __builtin_amdgcn_rcpf(T + nb);
 }
 
+// Rows per block of the fused row kernel: twice row_kernel's up to 512 pixels
+// (every lane busy in the radix-16 passes: 512^2 +9%, 256^2 +2%), the same
+// from 1024 up (two rows per block ran 1024^2 8% and 2048^2 4% slower).
+template <int L>
+struct RowShapeF {
+    static constexpr int ROWS = L <= 512 ? 4096 / L : 2048 / L;
+    static constexpr int TPR = kThreads / ROWS;
+};
+
 template <int L>
 struct RowShape {
     static constexpr int ROWS = (2048 / L) < 1 ? 1 : (2048 / L);  // rows per block
@@ -270,8 +279,8 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
 // the plan of row_inverse / row_forward, so the two round identically.
 template <int L>
 __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
-    constexpr int ROWS = RowShape<L>::ROWS;
-    constexpr int TPR = RowShape<L>::TPR;
+    constexpr int ROWS = RowShapeF<L>::ROWS;
+    constexpr int TPR = RowShapeF<L>::TPR;
     constexpr int W = L;
     constexpr int RL = last_radix<L>();
     constexpr int NT16 = L / 16;                    // radix-16 butterflies per row
@@ -1018,6 +1027,8 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
     // middle sweeps of the sampler and the Wiener iteration on rows of 256 and more
     const bool fused = MODE == kRowInvFwd && W >= 256 && a.pix_mode == kPixUpdate && !a.s_save && !a.plain_kernels;
     if (fused) {
+        const int rows_f = W <= 512 ? 4096 / W : 2048 / W;
+        const dim3 grid((unsigned)((total + rows_f - 1) / rows_f));
         switch (W) {
             case 256: hipLaunchKernelGGL((row_kernel_f<256>), grid, dim3(kThreads), 0, s, a, H); break;
             case 512: hipLaunchKernelGGL((row_kernel_f<512>), grid, dim3(kThreads), 0, s, a, H); break;
