@@ -75,12 +75,13 @@ __device__ __forceinline__ float pix_a(float T, float nb) {
     return T * __builtin_amdgcn_rcpf(T + nb);
 }
 
-// Rows per block of the fused row kernel: twice row_kernel's up to 512 pixels
-// (every lane busy in the radix-16 passes: 512^2 +9%, 256^2 +2%), the same
-// from 1024 up (two rows per block ran 1024^2 8% and 2048^2 4% slower).
+// Rows per block of the fused row kernel: twice row_kernel's at 512 pixels
+// (every lane busy in the radix-16 passes: the uneven batch's 512^2 row launch
+// 14% faster), the same elsewhere (twice as many rows ran the uneven batch's
+// 256^2 rows 5%, 1024^2 8% and 2048^2 4% slower).
 template <int L>
 struct RowShapeF {
-    static constexpr int ROWS = L <= 512 ? 4096 / L : 2048 / L;
+    static constexpr int ROWS = L == 512 ? 8 : 2048 / L;
     static constexpr int TPR = kThreads / ROWS;
 };
 
@@ -1027,7 +1028,7 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
     // middle sweeps of the sampler and the Wiener iteration on rows of 256 and more
     const bool fused = MODE == kRowInvFwd && W >= 256 && a.pix_mode == kPixUpdate && !a.s_save && !a.plain_kernels;
     if (fused) {
-        const int rows_f = W <= 512 ? 4096 / W : 2048 / W;
+        const int rows_f = W == 512 ? 8 : 2048 / W;
         const dim3 grid((unsigned)((total + rows_f - 1) / rows_f));
         switch (W) {
             case 256: hipLaunchKernelGGL((row_kernel_f<256>), grid, dim3(kThreads), 0, s, a, H); break;
