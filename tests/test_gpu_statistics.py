@@ -5,7 +5,8 @@ diagonal of the posterior covariance of Eq. 7 (Sec. 4.1, Fig. 3), also with
 the streamed field stored in 16 bits, and the hierarchical sampler's
 amplitudes against their exact marginal without data (persistent and
 streamed forms), and the mass-mapping sampler against the dense posterior of
-gamma = A kappa + n.
+gamma = A kappa + n, and the convergence of dispersed chains at the paper's
+image size (Gelman-Rubin R-hat, Fig. 2).
 Standard errors come from independent groups of chains; the bound on the
 largest z over all pixels (or bands) is the Student-t quantile of a
 family-wise two-sided level of 1e-3."""
@@ -153,3 +154,41 @@ def test_streamed_hierarchical_amplitudes_follow_the_prior_without_data(torch_cu
     bound = stats.norm.ppf(1 - 1e-3 / (2 * lt.shape[1]))
     print(f"E log theta per band {lt.mean(axis=0)}, target {target:.4f}, max z {z.max():.2f}, bound {bound:.2f}")
     assert z.max() < bound
+
+
+def _rhat(x):
+    """Gelman-Rubin potential scale reduction per pixel of x [chains, samples, px]."""
+    x = x.double()
+    m = x.shape[1]
+    W = x.var(dim=1, unbiased=True).mean(dim=0)
+    B = m * x.mean(dim=1).var(dim=0, unbiased=True)
+    return ((m - 1) / m * W + B / m).div(W).sqrt()
+
+
+def test_dispersed_chains_converge_at_the_paper_size(torch_cuda):
+    """Fig. 2 at the paper's image size: 64 chains from dispersed starts
+    (Philox stage-2 normals times 30) on the 128^2 recipe.  The first 30
+    sweeps are far from converged (median per-pixel R-hat above 1.5); over
+    sweeps 400-800 the median falls below 1.06 and the worst pixels keep
+    improving from window to window.  Pixels whose noise variance is far above
+    tau move by a = T / (T + Nbar) of order 0.01 per sweep, so the tail of the
+    R-hat distribution converges slowly: this measures the method's mixing,
+    not a parity bound."""
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("R-hat from dispersed starts, 128^2, 64 chains x 800 sweeps")
+    prob = synth.config_128(0)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    chains, n = 64, 800
+    out, _ = plan.sample(d, synth.philox_seed(0), chains=chains, burn_in=0, n_samples=n, init_scale=30.0,
+                         form="persistent")
+    x = plan.sample_view(out, 0, chains, n).reshape(chains, n, -1)
+    q = torch.tensor([0.5, 0.99], device=x.device)
+    early = torch.quantile(_rhat(x[:, :30]).float(), q)
+    mid = torch.quantile(_rhat(x[:, 300:500]).float(), q)
+    late = torch.quantile(_rhat(x[:, 400:800]).float(), q)
+    print(f"R-hat median / p99: sweeps 0-30 {early.tolist()}, 300-500 {mid.tolist()}, 400-800 {late.tolist()}")
+    assert early[0] > 1.5
+    assert late[0] < 1.06
+    assert late[1] < mid[1] < early[1]
