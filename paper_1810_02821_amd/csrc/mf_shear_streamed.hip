@@ -321,6 +321,7 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
     constexpr int H = L;
     constexpr int half = TC / 2;
     __shared__ float2 lds[TC * SEG];
+    __shared__ float2 twl[L >= 256 ? L : 1];  // twiddles of the HBM-side passes
     const unsigned tid = threadIdx.x;
     // tile fastest: an XCD runs neighbouring tiles of one item together
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);
@@ -334,9 +335,10 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
     const unsigned cid = tid / TPC, lane = tid % TPC;
     if constexpr (L >= 256) {
         // first forward pass straight from HBM (plan of mf_streamed_fft.hpp)
+        for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];
         col_first_forward<L, TC, NTH, SEG>(lds, fin, W, tid, col_of);
         __syncthreads();
-        col_forward_rest<L, TPC>(lds + cid * SEG, lane, a.tw_col);
+        col_forward_rest<L, TPC>(lds + cid * SEG, lane, twl);
     } else {
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
             const int s = (int)(e % TC), y = (int)(e / TC);
@@ -410,8 +412,8 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
     float2* fout = a.field + it.field_off;
     if constexpr (L >= 256) {
         // inverse transform, its last pass straight to HBM
-        col_inverse_head<L, TPC>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
-        col_last_inverse<L, TC, NTH, SEG>(lds, fout, W, opaque(tid), opaque(a.tw_col), col_of);
+        col_inverse_head<L, TPC>(lds + opaque(cid) * SEG, opaque(lane), twl + opaque(0u));
+        col_last_inverse<L, TC, NTH, SEG>(lds, fout, W, opaque(tid), twl + opaque(0u), col_of);
     } else {
         stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {

@@ -68,6 +68,7 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
     __shared__ float2 lds[TC * SEG];
     __shared__ double pw[2][kNB];
     __shared__ float4 coef[kNB];
+    __shared__ float2 twl[L >= 256 ? L : 1];  // twiddles in LDS (hierarchical 2048^2 sweep +7%)
     const unsigned tid = threadIdx.x;
     // tile fastest: an XCD runs neighbouring tiles of one item together, so
     // the cache lines they share meet in its L2
@@ -90,9 +91,11 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
     }
     for (unsigned u = tid; u < 2 * kNB; u += NTH) pw[u / kNB][u % kNB] = 0.0;
     for (unsigned u = tid; u < kNB; u += NTH) coef[u] = a.coef[(int64_t)item * kNB + u];
+    if constexpr (L >= 256)
+        for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];
     __syncthreads();
     const unsigned cid = tid / TPC, lane = tid % TPC;
-    if constexpr (L >= 256) col_forward_rest<L, TPC>(lds + cid * SEG, lane, a.tw_col);
+    if constexpr (L >= 256) col_forward_rest<L, TPC>(lds + cid * SEG, lane, twl);
     else stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
 
     // one job per mode pair {k, -k}: a first-half slot with its partner slot
@@ -153,8 +156,8 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
         }
     if constexpr (L >= 256) {
         // inverse transform, its last pass straight to HBM
-        col_inverse_head<L, TPC>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
-        col_last_inverse<L, TC, NTH, SEG>(lds, fld, W, opaque(tid), opaque(a.tw_col), col_of);
+        col_inverse_head<L, TPC>(lds + opaque(cid) * SEG, opaque(lane), twl + opaque(0u));
+        col_last_inverse<L, TC, NTH, SEG>(lds, fld, W, opaque(tid), twl + opaque(0u), col_of);
     } else {
         stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
