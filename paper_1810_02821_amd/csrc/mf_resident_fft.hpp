@@ -69,8 +69,12 @@ __device__ __forceinline__ void dft_slice(float2* v) {
 // cache) every sweep instead of being held in registers across sweeps.
 template <typename T>
 __device__ __forceinline__ const T* per_sweep(const T* p) {
-    asm volatile("" : "+s"(p));
-    return p;
+    // an opaque zero offset (not the pointer itself), so that the pointer
+    // keeps its global address space: flat loads would also count against
+    // the LDS wait counter
+    unsigned z = 0;
+    asm volatile("" : "+s"(z));
+    return p + z;
 }
 
 template <bool INV>
