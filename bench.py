@@ -38,8 +38,8 @@ PEAK_FP32_TFLOPS = 157.3
 # FETCH_SIZE / WRITE_SIZE runs scaled by the same counters on a 1 GiB copy, and
 # the hash of the kernel sources it was measured on (traffic is reported only
 # while the sources are unchanged).
-TRAFFIC_BYTES = int((121995.9375 * 2.0 + 6497637.0625 * 1.0) * 1024)  # FETCH x2.0 + WRITE x1.0 (copy-calibrated)
-TRAFFIC_SOURCES_SHA = "cbfef67ab2ce510e"
+TRAFFIC_BYTES = int((71891.0625 * 2.0 + 6493992.5625 * 1.0) * 1024)  # FETCH x2.0 + WRITE x1.0 (copy-calibrated)
+TRAFFIC_SOURCES_SHA = "783b64e3543a92c4"
 
 
 def kernel_sources_sha() -> str:

@@ -65,6 +65,7 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_sample_kernel(Resident
     __shared__ float2 twl[N];  // twiddles: LDS latency instead of a cache hit's in every pass
     const unsigned tid = threadIdx.x;
     for (unsigned i = tid; i < (unsigned)N; i += Res<N>::NT) twl[i] = a.tw[i];
+    __syncthreads();  // the first forward pass reads twiddles before any exchange barrier
     const ItemDev it = a.items[blockIdx.x];
     const ProbDev pr = a.probs[it.prob];
     const unsigned y = tid / (P / 2), j = tid % (P / 2);
@@ -96,9 +97,7 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_sample_kernel(Resident
         ak.pcoef = per_sweep(a.pcoef);
         ak.psrc = per_sweep(a.psrc);
         ak.mcoef = per_sweep(a.mcoef);
-        unsigned tw0 = 0;
-        asm volatile("" : "+s"(tw0));
-        const float2* tw = twl + tw0;
+        const float2* tw = twl + per_sweep_zero();
         // Everything indexed by the thread id (LDS addresses, counter words of
         // the normal stream) is recomputed each sweep rather than kept live.
         // Each half of the sweep gets its own copy so that the forward pass's

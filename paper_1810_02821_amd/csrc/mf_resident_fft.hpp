@@ -67,6 +67,13 @@ __device__ __forceinline__ void dft_slice(float2* v) {
 
 // Hide a pointer from loop-invariant code motion: tables are re-read (from
 // cache) every sweep instead of being held in registers across sweeps.
+// An opaque zero, to offset an LDS table per sweep without losing its address space.
+__device__ __forceinline__ unsigned per_sweep_zero() {
+    unsigned z = 0;
+    asm volatile("" : "+s"(z));
+    return z;
+}
+
 template <typename T>
 __device__ __forceinline__ const T* per_sweep(const T* p) {
     // an opaque zero offset (not the pointer itself), so that the pointer

@@ -138,7 +138,10 @@ template <int N>
 __global__ __launch_bounds__(Res<N>::NT, 4) void resident_shear_kernel(ShearArgs a) {
     constexpr int P = Res<N>::P;
     __shared__ __align__(16) float2 lds[N * N];
+    __shared__ float2 twl[N];  // twiddles in LDS (an LDS read returns sooner than a cache hit)
     const unsigned tid = threadIdx.x;
+    for (unsigned i = tid; i < (unsigned)N; i += Res<N>::NT) twl[i] = a.tw[i];
+    __syncthreads();
     const ItemDev it = a.items[blockIdx.x];
     const ProbDev pr = a.probs[it.prob];
     const unsigned y = tid / (P / 2), j = tid % (P / 2);
@@ -157,7 +160,7 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_shear_kernel(ShearArgs
         const float T = (float)(a.lambda[lv] * (double)pr.tau);
         for (int s = 0; s < a.level_sweeps[lv]; ++s, ++k) {
             const uint32_t sweep = a.sweep0 + (uint32_t)k;
-            const float2* tw = per_sweep(a.tw);
+            const float2* tw = twl + per_sweep_zero();
             unsigned t = tid;
             asm volatile("" : "+v"(t));
             {
@@ -197,7 +200,7 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_shear_kernel(ShearArgs
                 // kappa = F^-1 kappa^, written out, then transformed back
                 unsigned t3 = tid;
                 asm volatile("" : "+v"(t3));
-                const float2* tw3 = per_sweep(a.tw);
+                const float2* tw3 = twl + per_sweep_zero();
                 inverse_fft<N>(v, lds, tw3, t3);
                 float2* o;
                 if (emit) {
@@ -222,7 +225,7 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_shear_kernel(ShearArgs
             const float back = (emit || (last && a.kappa_out)) ? 1.0f / (float)(N * N) : 1.0f;
             unsigned t5 = tid;
             asm volatile("" : "+v"(t5));
-            const float2* tw5 = per_sweep(a.tw);
+            const float2* tw5 = twl + per_sweep_zero();
             {
                 const unsigned jx = t5 % (N / 2), k1 = t5 / (N / 2);
 #pragma unroll

@@ -206,7 +206,10 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_spectrum_kernel(Spectr
     constexpr int P = Res<N>::P, NT = Res<N>::NT;
     __shared__ __align__(16) float2 lds[N * N];
     __shared__ SpecShared sh;
+    __shared__ float2 twl[N];  // twiddles in LDS (an LDS read returns sooner than a cache hit)
     const unsigned tid = threadIdx.x;
+    for (unsigned i = tid; i < (unsigned)N; i += Res<N>::NT) twl[i] = a.tw[i];
+    __syncthreads();
     const ItemDev it = a.items[blockIdx.x];
     const ProbDev pr = a.probs[it.prob];
     const unsigned y = tid / (P / 2), j = tid % (P / 2);
@@ -262,7 +265,7 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_spectrum_kernel(Spectr
             const uint32_t sweep = g * (uint32_t)a.sweeps + (uint32_t)k;
             const float4* pcoef = per_sweep(a.pcoef);
             const float2* psrc = per_sweep(a.psrc);
-            const float2* tw = per_sweep(a.tw);
+            const float2* tw = twl + per_sweep_zero();
             unsigned t = tid;
             asm volatile("" : "+v"(t));
             {
