@@ -74,7 +74,10 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_solve_kernel(SolveArgs
     constexpr int P = Res<N>::P, NT = Res<N>::NT;
     __shared__ __align__(16) float2 lds[N * N];
     __shared__ double red[NT / 64];
+    __shared__ float2 twl[N];  // twiddles in LDS (an LDS read returns sooner than a cache hit)
     const unsigned tid = threadIdx.x;
+    for (unsigned i = tid; i < (unsigned)N; i += NT) twl[i] = a.tw[i];
+    __syncthreads();
     const ItemDev it = a.items[blockIdx.x];
     const ProbDev pr = a.probs[it.prob];
     const unsigned y = tid / (P / 2), j = tid % (P / 2);
@@ -96,11 +99,11 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_solve_kernel(SolveArgs
         asm volatile("" : "+v"(t));
         double acc = 0.0;
         pixel_solve<N>(v, tprev, a, pr, t, T, save, check, acc);
-        forward_fft<N>(v, lds, a.tw, t);
+        forward_fft<N>(v, lds, twl + per_sweep_zero(), t);
         unsigned t2 = tid;
         asm volatile("" : "+v"(t2));
         harmonic_solve<N>(v, a, pr, t2, T);
-        inverse_fft<N>(v, lds, a.tw, t2);
+        inverse_fft<N>(v, lds, twl + per_sweep_zero(), t2);
         return check ? block_sum<NT>(acc, red) : 0.0;
     };
 
