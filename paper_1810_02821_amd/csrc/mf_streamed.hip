@@ -490,6 +490,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     constexpr int SEG = L + 32 / TC;
     constexpr int H = L;
     __shared__ float2 lds[TC * SEG];
+    __shared__ float2 twl[L];  // twiddles in LDS (as in col_kernel_f; identical values)
     const unsigned tid = threadIdx.x;
     // tiles enumerated with the tile fastest: t = item * (W / TC) + tile.  An
     // XCD then runs neighbouring tiles of one item together, and the cache
@@ -501,6 +502,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     const ProbDev pr = a.probs[it.prob];
     const int64_t f0 = it.field_off + x0;
 
+    for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];  // visible after the tile barrier
     with_storage(a.storage, [&](auto e0) {
         using E = decltype(e0);
         const E* fld = reinterpret_cast<const E*>(a.field) + f0;
@@ -512,7 +514,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     });
     __syncthreads();
     const unsigned cid = tid / TPC, lane = tid % TPC;
-    stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
+    stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, twl);
 
     const float T = a.lambda * pr.tau;
     if (a.t_store) {
@@ -576,7 +578,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
         }
     }
     __syncthreads();
-    stockham_fft<L, 1, TPC, true>(lds + fresh(cid) * SEG, fresh(lane), fresh(a.tw_col));
+    stockham_fft<L, 1, TPC, true>(lds + fresh(cid) * SEG, fresh(lane), twl + fresh(0u));
 
     with_storage(a.storage, [&](auto e0) {
         using E = decltype(e0);
