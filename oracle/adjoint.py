@@ -142,15 +142,26 @@ def unrolled_vjp_torch(problem, schedule: messenger.Schedule, gbar):
 # Wiener image (Eq. 5-7, up to constants) plus an L2 distance to the true field.
 # --------------------------------------------------------------------------
 
-def loss_terms(problem, s_wf, s_true):
-    """L = 1/2 s^T S^-1 s + 1/2 (d-s)^T N^-1 (d-s) + 1/2 sum_k ln(n P_k)
-           + 1/2 ||s - s_true||^2  at s = s_wf (A = I)."""
-    if messenger.response_of(problem) is not None:
-        raise ValueError("the loss is defined for A = I")
-    c = messenger.coefficients(problem.noise_var, problem.spectrum, 1.0)
+def _likelihood_residual(problem, s_wf):
+    """(d - A s) on the pixels that carry data (finite noise, A_i != 0), else 0,
+    and the noise variance there (1 elsewhere)."""
+    resp = messenger.response_of(problem)
+    A = 1.0 if resp is None else np.asarray(resp, dtype=np.float64)
+    obs = messenger.observed(problem.noise_var, resp)
     d = np.where(problem.mask, 0.0, problem.d)
+    r = np.where(obs, d - A * s_wf, 0.0)
+    return r, np.where(obs, problem.noise_var, 1.0)
+
+
+def loss_terms(problem, s_wf, s_true):
+    """L = 1/2 s^T S^-1 s + 1/2 (d - A s)^T N^-1 (d - A s) + 1/2 sum_k ln(n P_k)
+           + 1/2 ||s - s_true||^2  at s = s_wf.  The likelihood term sums over
+    the pixels that carry data (finite noise and, with a response, A_i != 0);
+    A = I when the problem has no response."""
+    c = messenger.coefficients(problem.noise_var, problem.spectrum, 1.0, None, messenger.response_of(problem))
+    r, nv = _likelihood_residual(problem, s_wf)
     prior = 0.5 * float(np.sum(s_wf * messenger.apply_S_inverse(s_wf, c)))
-    like = 0.5 * float(np.sum(c.ninv * (d - s_wf) ** 2))
+    like = 0.5 * float(np.sum(r * r / nv))
     logdet = 0.5 * float(np.sum(np.log(c.nP)))
     l2 = 0.5 * float(np.sum((s_wf - s_true) ** 2))
     return prior + like + logdet + l2
@@ -160,15 +171,13 @@ def loss_grad(problem, s_wf, s_true, schedule: messenger.Schedule = None, solver
     """Full gradient of loss_terms w.r.t. d and the band amplitudes.
 
     At the Wiener solution the prior + likelihood part is stationary in s, so
-    only the L2 term sends a gradient through s*: gbar = s* - s_true."""
-    if messenger.response_of(problem) is not None:
-        raise ValueError("the loss is defined for A = I")
+    only the L2 term sends a gradient through s*: gbar = s* - s_true.  The
+    explicit part in d is N^-1 (d - A s) on the pixels that carry data."""
     H, W = problem.H, problem.W
     n = H * W
-    c = messenger.coefficients(problem.noise_var, problem.spectrum, 1.0)
-    d = np.where(problem.mask, 0.0, problem.d)
+    r, nv = _likelihood_residual(problem, s_wf)
     gd_imp, gt_imp, v, info = wiener_vjp(problem, s_wf, s_wf - s_true, schedule, solver)
-    grad_d = c.ninv * (d - s_wf) + gd_imp
+    grad_d = r / nv + gd_imp
     theta = np.asarray(problem.spectrum.amps, dtype=np.float64)
     edges = problem.spectrum.edges
     idx = band_of_modes(edges, H, W)

@@ -131,3 +131,53 @@ def test_unrolled_vjp_with_response_matches_finite_differences():
         fp = np.sum(g * oa.unrolled_vjp(pp, sch, g)[0])
         fm = np.sum(g * oa.unrolled_vjp(pm, sch, g)[0])
         assert np.isclose((fp - fm) / (2 * h), dbar[idx], rtol=1e-6, atol=1e-10)
+
+
+def _band_problem_with_response(seed=2, size=16):
+    """A band-spectrum problem seen through a diagonal response with a few
+    pixels of zero response (the differentiation loss needs band amplitudes)."""
+    p = synth.config_bands(seed, size, 8)
+    rng = np.random.default_rng(seed + 100)
+    A = rng.uniform(0.5, 1.5, (size, size))
+    A.flat[rng.choice(size * size, 5, replace=False)] = 0.0
+    p.response = A
+    p.mask = p.mask | (A == 0)
+    p.d = np.where(p.mask, 0.0, A * p.s_true + rng.standard_normal((size, size)) * np.sqrt(
+        np.where(np.isfinite(p.noise_var), p.noise_var, 1.0)))
+    return p
+
+
+def _loss_with_response(p, theta=None, d=None):
+    spec = p.spectrum if theta is None else synth.spectrum_bands(p.spectrum.edges, theta)
+    q = synth.Problem(p.H, p.W, p.d if d is None else d, p.noise_var, p.mask, spec, p.s_true, response=p.response)
+    S = dense.signal_covariance(spec, p.H, p.W)
+    sw = dense.wiener_dense(S, p.noise_var, q.d, response=p.response)
+    return oa.loss_terms(q, sw, p.s_true)
+
+
+def test_loss_gradient_with_response_matches_central_differences():
+    """L = 1/2 s^T S^-1 s + 1/2 (d - A s)^T N^-1 (d - A s) + 1/2 sum ln(n P)
+    + 1/2 ||s - s_true||^2 at the Wiener filter with A (Eq. 2 with A, dense):
+    the oracle's gradient (explicit terms plus the implicit VJP) against
+    central differences of the dense loss, in d and in the band amplitudes."""
+    p = _band_problem_with_response()
+    S = dense.signal_covariance(p.spectrum, 16, 16)
+    sw = dense.wiener_dense(S, p.noise_var, p.d, response=p.response)
+    gd, gt = oa.loss_grad(p, sw, p.s_true, om.Schedule((1.0,), (0,), 1e-13, 400000, 10))
+    theta = np.asarray(p.spectrum.amps)
+    h = 1e-4
+    for b in range(len(theta)):
+        tp, tm = theta.copy(), theta.copy()
+        tp[b] *= 1 + h
+        tm[b] *= 1 - h
+        fd = (_loss_with_response(p, theta=tp) - _loss_with_response(p, theta=tm)) / (2 * h * theta[b])
+        assert abs(fd - gt[b]) < 5e-7 * max(1.0, abs(gt[b]))
+    rng = np.random.default_rng(0)
+    obs = np.flatnonzero((np.isfinite(p.noise_var) & (p.response != 0)).ravel())
+    for i in rng.choice(obs, 6, replace=False):
+        dp, dm = p.d.copy(), p.d.copy()
+        dp.flat[i] += 1e-3
+        dm.flat[i] -= 1e-3
+        fd = (_loss_with_response(p, d=dp) - _loss_with_response(p, d=dm)) / 2e-3
+        assert abs(fd - gd.flat[i]) < 1e-6 * max(1.0, abs(fd))
+    assert np.all(gd[p.response == 0] == 0)
