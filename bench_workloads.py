@@ -159,7 +159,7 @@ def grad(args):
     plan = mf.Plan([prob])
     d = plan.concat([prob.d])
     sch = mf.Schedule(list(np.geomspace(1e3, 1.0, 30)) + [1.0], [10] * 30 + [3000])
-    loss = BandPosteriorLoss(plan, prob.noise_var.ravel())
+    loss = BandPosteriorLoss(plan)
     theta = torch.tensor(np.asarray(prob.spectrum.amps), dtype=torch.float64, device="cuda")
     s_true = plan.concat([prob.s_true])
     fwd = lambda: plan.wiener(d, sch, allow_not_converged=True)

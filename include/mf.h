@@ -40,13 +40,24 @@
  *
  * Memory: every pointer argument documented "device" is memory on the current
  * HIP device owned by the caller; the plan owns its own tables and workspaces
- * and frees them in mf_plan_destroy.  Workspaces are allocated on the first
- * call that needs them (and grown when a later call needs more), so a first
- * call may allocate device memory.  "host" pointers are read during the call
- * only.  All entry points enqueue their kernels on `stream` (a hipStream_t;
- * NULL is the null stream); they synchronise the stream when they upload a
- * new work list or schedule from host memory and when a result returns to the
- * host (mf_info, convergence tests).  A plan must not be used from two
+ * and frees them in mf_plan_destroy.  mf_plan_create allocates the tables;
+ * mf_plan_reserve allocates the workspaces of the calls it names.  A call
+ * whose workspaces were reserved allocates nothing; a call that needs more
+ * than was reserved allocates it on first use, except on a stream that is
+ * being captured into a graph, where it fails with MF_ERR_INVALID_ARG
+ * instead.  "host" pointers are read during the call only.
+ *
+ * Asynchrony: every entry point enqueues its kernels on `stream` (a
+ * hipStream_t; NULL is the null stream).  Work lists and cooling levels are
+ * built on the device or passed in kernel arguments, so mf_sample,
+ * mf_sample_spectrum, mf_shear_sample (check_finite = 0), mf_wiener and
+ * mf_wiener_backward (tol <= 0, info NULL), mf_wiener_backward_unrolled,
+ * mf_band_power, mf_band_loss (tol <= 0, info NULL) and mf_sample_moments
+ * neither allocate (after mf_plan_reserve) nor synchronise, and can be
+ * captured into a caller's HIP graph.  A call synchronises `stream` only to
+ * return a result to the host: mf_info, a convergence test (tol > 0), the
+ * non-finite check of the samplers (check_finite = 1), and the table upload
+ * of mf_plan_create / mf_plan_set_spectrum.  A plan must not be used from two
  * streams or threads at once.
  *
  * Errors: every entry point returns an mf_status; no C++ exception crosses the
@@ -69,11 +80,13 @@ typedef void* mf_stream; /* hipStream_t */
 typedef enum {
     MF_OK = 0,
     MF_ERR_INVALID_ARG = 1,      /* a pointer, size, variance or count is invalid */
-    MF_ERR_UNSUPPORTED_SIZE = 2, /* H or W is not a power of two in [16, 2048] */
+    MF_ERR_UNSUPPORTED_SIZE = 2, /* H or W outside the supported sides (see mf_problem), or a form that the size
+                                    does not support */
     MF_ERR_OUT_OF_MEMORY = 3,    /* a plan table or workspace could not be allocated */
     MF_ERR_DEVICE = 4,           /* a HIP runtime call failed */
     MF_ERR_NOT_CONVERGED = 5,    /* tol > 0 not reached within max_sweeps (result still written) */
-    MF_ERR_NONFINITE = 6         /* a solve's residual test saw NaN/Inf (that problem stops; outputs written) */
+    MF_ERR_NONFINITE = 6         /* a solve's residual test saw NaN/Inf (that problem stops; outputs written), or
+                                    a sampler's non-finite check found a chain state holding NaN/Inf */
 } mf_status;
 
 /* Power spectrum P(|k|) of the signal (Eq. 9). */
@@ -88,7 +101,10 @@ typedef struct {
 
 /* One image problem, d = A s + n (Eq. 1) with a diagonal A. */
 typedef struct {
-    int32_t H, W;              /* image size; each a power of two in [16, 2048] */
+    int32_t H, W;              /* image size; each an even 2^a 3^b in [16, 2048] (the transforms of Eq. 8
+                                  run as radix-16/8/4/2 and radix-3 passes).  Sides with a factor 3 run on
+                                  the streamed kernels (the persistent form needs H = W in {32, 64, 128});
+                                  mf_sample_spectrum and mass mapping need powers of two */
     const float* noise_var;    /* host, H*W: N_i > 0, +INFINITY marks a missing pixel */
     mf_spectrum spectrum;
     const float* response;     /* host, H*W: the diagonal of A (finite; 0 = a pixel without
@@ -175,6 +191,10 @@ typedef struct {
     float init_scale;          /* > 0: start from init_scale * stage-2 normals (ignored if state_in) */
     int32_t form;              /* MF_FORM_* */
     int32_t storage;           /* MF_STORAGE_*: precision of the streamed field between kernels */
+    int32_t check_finite;      /* 1: after the run, synchronise and return MF_ERR_NONFINITE if a chain's final
+                                  state holds NaN or Inf (a non-finite value anywhere in a chain's history reaches
+                                  its final state: every sweep mixes all pixels through the transforms); the
+                                  samples and states are still written.  0: no check, no synchronisation */
     const mf_schedule* cooling;/* host, or NULL: levels (lambda_j >= 1, sweeps_j) run before the burn-in,
                                   sampling with T = lambda_j tau (the posterior for noise
                                   N + (lambda_j - 1) tau), global sweep indices sweep_offset, ...; the
@@ -194,6 +214,7 @@ typedef struct {
     double prior_beta;         /* beta_0 >= 0: its scale (nu_0 = beta_0 = 0: Jeffreys' 1/theta) */
     int64_t iteration_offset;  /* global index of the first iteration (for resuming a chain) */
     float init_scale;          /* > 0: dispersed start as in mf_sample (ignored if state_in) */
+    int32_t check_finite;      /* as in mf_sample_args (the chains' final signal states are checked) */
 } mf_spectrum_args;
 
 /* Create a plan for n_problems problems (Algorithm 1's definitions: tau, Nbar,
@@ -205,9 +226,35 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
 /* Release the plan and every device buffer it owns. NULL is accepted. */
 mf_status mf_plan_destroy(mf_plan plan);
 
+/* Workspace reservation: the calls named in `calls`, with at most
+ * chains_per_problem chains (samplers, moments), the given storage (mf_sample)
+ * and at most unrolled_sweeps sweeps with a checkpoint every checkpoint_every
+ * (mf_wiener_backward_unrolled), will allocate nothing.  Workspaces are sized
+ * for every problem of the plan at once (the sampler's work field included,
+ * for calls without state_out), kept until mf_plan_destroy and never shrunk;
+ * a later reservation only grows them.  Allocates synchronously (no stream). */
+enum {
+    MF_RESERVE_SOLVE = 1,      /* mf_wiener, mf_wiener_backward, mf_band_power, mf_band_loss */
+    MF_RESERVE_SAMPLE = 2,     /* mf_sample */
+    MF_RESERVE_SPECTRUM = 4,   /* mf_sample_spectrum */
+    MF_RESERVE_SHEAR = 8,      /* mf_shear_wiener, mf_shear_sample */
+    MF_RESERVE_UNROLLED = 16,  /* mf_wiener_backward_unrolled */
+    MF_RESERVE_MOMENTS = 32    /* mf_sample_moments */
+};
+typedef struct {
+    uint32_t calls;            /* MF_RESERVE_* bits */
+    int32_t chains_per_problem;/* >= 1 when a sampler or moments bit is set */
+    int32_t storage;           /* MF_STORAGE_* of the mf_sample calls */
+    int32_t unrolled_sweeps;   /* K >= 1 with MF_RESERVE_UNROLLED */
+    int32_t checkpoint_every;  /* C >= 1 with MF_RESERVE_UNROLLED */
+} mf_reserve;
+mf_status mf_plan_reserve(mf_plan plan, const mf_reserve* reserve);
+
 /* Replace the spectrum of one problem (same kind and band count for bands).
- * Used by gradient-based training loops over band amplitudes. */
-mf_status mf_plan_set_spectrum(mf_plan plan, int32_t problem, const mf_spectrum* spectrum);
+ * Used by gradient-based training loops over band amplitudes.  The new tables
+ * (n P(|k|) evaluated in FP64, Eq. 9) are copied on `stream`, after the work
+ * already queued there, and the call synchronises `stream` before it returns. */
+mf_status mf_plan_set_spectrum(mf_plan plan, int32_t problem, const mf_spectrum* spectrum, mf_stream stream);
 
 /* Element offset of problem p in concatenated image arrays (p == n_problems
  * gives the total pixel count); -1 on a bad argument. */
@@ -281,6 +328,7 @@ typedef struct {
     int32_t thin;              /* sweeps per sample after burn-in (>= 1) */
     int64_t sweep_offset;      /* global sweep index of the first sweep */
     float b_ratio;             /* P_B / P_E >= 0 (0: no B modes) */
+    int32_t check_finite;      /* as in mf_sample_args (the chains' final states A kappa are checked) */
 } mf_shear_args;
 
 /* Mass mapping (Sec. 5): complex shear data gamma = A kappa + n with the
@@ -350,6 +398,30 @@ mf_status mf_wiener_backward(mf_plan plan, const float* s_wf, const float* grad_
 mf_status mf_wiener_backward_unrolled(mf_plan plan, const float* d, const mf_schedule* schedule,
                                       int32_t checkpoint_every, const float* grad_s, float* s_out,
                                       float* grad_d, double* grad_bands, mf_stream stream);
+
+/* Loss of the differentiation workload for band-spectrum problems (every
+ * problem of the plan must have one), at the Wiener filter s = s_wf (Eq. 2-3):
+ *   L_p = 1/2 s^T S^-1 s + 1/2 (d - A s)^T N^-1 (d - A s) + 1/2 sum_k ln(n P_k)
+ *         + 1/2 ||s - s_true||^2,
+ * the negative log-posterior of Eq. 5-7 up to constants plus an L2 distance to
+ * a reference field, with the plan's own N (its response A, and 1e8 on missing
+ * pixels under MF_FLAG_INF_AS_1E8; pixels without data or response carry no
+ * likelihood term).  With P_k = theta_b on band b, s^T S^-1 s =
+ * sum_b sigma_b / (n^2 theta_b) and sum_k ln(n P_k) = sum_b m_b ln(n theta_b)
+ * (sigma_b the band power of the unnormalised DFT of s, m_b the band's modes).
+ * Gradients (NULL: not computed) with respect to d and the band amplitudes:
+ * explicit terms plus, through s_W, the implicit VJP of mf_wiener_backward for
+ * dL/ds = s - s_true (the log-posterior part is stationary at s_W), solved with
+ * adjoint_schedule.
+ *   d, s_wf, s_true  device, concatenated (s_wf from mf_wiener with the same plan)
+ *   loss_out         device float64 [n_problems]
+ *   grad_d           device, concatenated, or NULL
+ *   grad_bands       device float64 [mf_plan_total_bands], or NULL
+ *   info             host [n_problems] outcome of the adjoint solve, or NULL
+ * Returns MF_ERR_NOT_CONVERGED if the adjoint missed its tol (outputs written). */
+mf_status mf_band_loss(mf_plan plan, const float* d, const float* s_wf, const float* s_true,
+                       const mf_schedule* adjoint_schedule, double* loss_out, float* grad_d, double* grad_bands,
+                       mf_info* info, mf_stream stream);
 
 /* Band cross-power sum_{k in b} Re(conj(x_k) y_k) of two concatenated real
  * fields (unnormalised DFTs) for every band-spectrum problem; device float64 out. */

@@ -65,26 +65,34 @@ class _SampleArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("chains_per_problem", C.c_int32), ("burn_in", C.c_int32),
                 ("n_samples", C.c_int32), ("thin", C.c_int32), ("sweep_offset", C.c_int64),
                 ("init_scale", C.c_float), ("form", C.c_int32), ("storage", C.c_int32),
-                ("cooling", C.POINTER(_Schedule))]
+                ("check_finite", C.c_int32), ("cooling", C.POINTER(_Schedule))]
 
 
 class _SpectrumArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("chains_per_problem", C.c_int32), ("burn_in", C.c_int32),
                 ("n_samples", C.c_int32), ("thin", C.c_int32), ("sweeps_per_draw", C.c_int32),
                 ("prior_dof", C.c_int32), ("prior_beta", C.c_double), ("iteration_offset", C.c_int64),
-                ("init_scale", C.c_float)]
+                ("init_scale", C.c_float), ("check_finite", C.c_int32)]
 
 
 class _ShearArgs(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("chains_per_problem", C.c_int32), ("burn_in", C.c_int32),
                 ("n_samples", C.c_int32), ("thin", C.c_int32), ("sweep_offset", C.c_int64),
-                ("b_ratio", C.c_float)]
+                ("b_ratio", C.c_float), ("check_finite", C.c_int32)]
 
 
-EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_plan_pixel_offset",
+class _Reserve(C.Structure):
+    _fields_ = [("calls", C.c_uint32), ("chains_per_problem", C.c_int32), ("storage", C.c_int32),
+                ("unrolled_sweeps", C.c_int32), ("checkpoint_every", C.c_int32)]
+
+
+RESERVE = {"solve": 1, "sample": 2, "spectrum": 4, "shear": 8, "unrolled": 16, "moments": 32}
+
+
+EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_reserve", "mf_plan_set_spectrum", "mf_plan_pixel_offset",
            "mf_plan_tau", "mf_plan_total_bands", "mf_wiener", "mf_sample", "mf_wiener_backward",
            "mf_wiener_backward_unrolled", "mf_band_power", "mf_plan_tile_shape", "mf_sample_spectrum",
-           "mf_sample_moments", "mf_shear_wiener", "mf_shear_sample",
+           "mf_sample_moments", "mf_shear_wiener", "mf_shear_sample", "mf_band_loss",
            "mf_status_string",
            "mf_last_error"]
 
@@ -107,7 +115,9 @@ def lib():
     vp = C.c_void_p
     L.mf_plan_create.argtypes = [C.POINTER(vp), C.c_int32, C.POINTER(_Problem), C.c_uint32, vp]
     L.mf_plan_destroy.argtypes = [vp]
-    L.mf_plan_set_spectrum.argtypes = [vp, C.c_int32, C.POINTER(_Spectrum)]
+    L.mf_plan_set_spectrum.argtypes = [vp, C.c_int32, C.POINTER(_Spectrum), vp]
+    L.mf_plan_reserve.argtypes = [vp, C.POINTER(_Reserve)]
+    L.mf_band_loss.argtypes = [vp, vp, vp, vp, C.POINTER(_Schedule), vp, vp, vp, C.POINTER(Info), vp]
     L.mf_plan_pixel_offset.argtypes = [vp, C.c_int32]
     L.mf_plan_pixel_offset.restype = C.c_int64
     L.mf_plan_tau.argtypes = [vp, C.c_int32]
@@ -127,7 +137,8 @@ def lib():
     L.mf_status_string.argtypes = [C.c_int]
     L.mf_status_string.restype = C.c_char_p
     L.mf_last_error.restype = C.c_char_p
-    for name in ("mf_plan_create", "mf_plan_destroy", "mf_plan_set_spectrum", "mf_wiener",
+    for name in ("mf_plan_create", "mf_plan_destroy", "mf_plan_reserve", "mf_band_loss", "mf_plan_set_spectrum",
+                 "mf_wiener",
                  "mf_sample", "mf_wiener_backward", "mf_wiener_backward_unrolled", "mf_band_power",
                  "mf_plan_tile_shape", "mf_sample_spectrum", "mf_sample_moments", "mf_shear_wiener",
                  "mf_shear_sample"):
@@ -242,7 +253,18 @@ class Plan:
 
     def set_spectrum(self, i: int, spectrum):
         s, keep = _spectrum_c(spectrum)
-        _check(lib().mf_plan_set_spectrum(self._h, i, C.byref(s)))
+        _check(lib().mf_plan_set_spectrum(self._h, i, C.byref(s), _stream()))
+
+    def reserve(self, calls, chains: int = 1, storage: str = "fp32", unrolled_sweeps: int = 0,
+                checkpoint_every: int = 0):
+        """Allocate the workspaces of the named calls ("solve", "sample",
+        "spectrum", "shear", "unrolled", "moments") now, so that those calls
+        allocate nothing (and can be captured into a graph)."""
+        bits = 0
+        for c in ([calls] if isinstance(calls, str) else calls):
+            bits |= RESERVE[c]
+        r = _Reserve(bits, int(chains), STORAGES[storage], int(unrolled_sweeps), int(checkpoint_every))
+        _check(lib().mf_plan_reserve(self._h, C.byref(r)))
 
     def set_band_amplitudes(self, theta):
         """Replace the band amplitudes of every band-spectrum problem;
@@ -272,14 +294,17 @@ class Plan:
                 for i, p in enumerate(self.problems)]
 
     # ---- entry points
-    def wiener(self, d, schedule: Schedule, s_init=None, out=None, allow_not_converged=False):
+    def wiener(self, d, schedule: Schedule, s_init=None, out=None, allow_not_converged=False, want_info=True):
+        """Wiener filter (concatenated).  want_info=False passes no info array,
+        so that a fixed schedule neither synchronises nor copies to the host
+        (the call can then be captured into a graph); the info list is empty."""
         import torch
         out = torch.empty_like(d) if out is None else out
-        info = (Info * len(self.problems))()
+        info = (Info * len(self.problems))() if want_info else None
         sch = schedule._c()
         st = lib().mf_wiener(self._h, _ptr(d), C.byref(sch), _ptr(s_init), _ptr(out), info, _stream())
         _check(st, allow_not_converged)
-        return out, list(info)
+        return out, (list(info) if want_info else [])
 
     def samples_buffer(self, chains: int, n_samples: int, device="cuda"):
         import torch
@@ -288,7 +313,7 @@ class Plan:
     def sample(self, d, seed: int, chains: int, burn_in: int, n_samples: int, thin: int = 1,
                sweep_offset: int = 0, init_scale: float = 0.0, form: str = "auto",
                state_in=None, state_out=None, samples=True, out=None, storage: str = "fp32",
-               cooling: Optional["Schedule"] = None):
+               cooling: Optional["Schedule"] = None, check_finite: bool = True):
         """Returns (samples [concat over problems of chains*n_samples*H*W] or None,
         state_out or None).  `out` may hold a preallocated samples buffer.
         `storage` ("fp32", "fp16", "bf16") is the precision of the streamed
@@ -301,7 +326,7 @@ class Plan:
         cool = cooling._c() if cooling is not None else None
         args = _SampleArgs(int(seed), int(chains), int(burn_in), int(n_samples), int(thin),
                            int(sweep_offset), float(init_scale), FORMS[form], STORAGES[storage],
-                           C.pointer(cool) if cool is not None else None)
+                           int(bool(check_finite)), C.pointer(cool) if cool is not None else None)
         st = lib().mf_sample(self._h, _ptr(d), C.byref(args), _ptr(state_in), _ptr(state_out),
                              _ptr(out), _stream())
         _check(st)
@@ -330,7 +355,8 @@ class Plan:
     def sample_spectrum(self, d, seed: int, chains: int, burn_in: int, n_samples: int, thin: int = 1,
                         sweeps_per_draw: int = 1, prior_dof: int = 0, prior_beta: float = 0.0,
                         iteration_offset: int = 0, init_scale: float = 0.0, state_in=None, theta_in=None,
-                        state_out=None, theta_out=None, samples=False, theta_samples=True):
+                        state_out=None, theta_out=None, samples=False, theta_samples=True,
+                        check_finite: bool = True):
         """Hierarchical sampler (signal and band amplitudes).  Returns
         (theta samples [concat over problems of chains*n_samples*bands] float64 or
         None, signal samples or None, state_out, theta_out)."""
@@ -345,7 +371,7 @@ class Plan:
         smp = self.samples_buffer(chains, n_samples, dev) if samples and n_samples > 0 else None
         args = _SpectrumArgs(int(seed), int(chains), int(burn_in), int(n_samples), int(thin),
                              int(sweeps_per_draw), int(prior_dof), float(prior_beta), int(iteration_offset),
-                             float(init_scale))
+                             float(init_scale), int(bool(check_finite)))
         _check(lib().mf_sample_spectrum(self._h, _ptr(d), C.byref(args), _ptr(state_in), _ptr(theta_in),
                                         _ptr(state_out), _ptr(theta_out), _ptr(smp), _ptr(ts), _stream()))
         return ts, smp, state_out, theta_out
@@ -374,14 +400,15 @@ class Plan:
         return torch.zeros(chains * self.total_pixels, dtype=torch.complex64, device=device)
 
     def shear_sample(self, gamma, seed: int, chains: int, burn_in: int, n_samples: int, thin: int = 1,
-                     sweep_offset: int = 0, b_ratio: float = 0.0, state_in=None, state_out=None, samples=True):
+                     sweep_offset: int = 0, b_ratio: float = 0.0, state_in=None, state_out=None, samples=True,
+                     check_finite: bool = True):
         """Samples of the convergence, complex [concat over problems of chains*n_samples*H*W]."""
         import torch
         out = None
         if samples and n_samples > 0:
             out = torch.empty(chains * n_samples * self.total_pixels, dtype=torch.complex64, device=gamma.device)
         args = _ShearArgs(int(seed), int(chains), int(burn_in), int(n_samples), int(thin), int(sweep_offset),
-                          float(b_ratio))
+                          float(b_ratio), int(bool(check_finite)))
         _check(lib().mf_shear_sample(self._h, _ptr(gamma), C.byref(args), _ptr(state_in), _ptr(state_out),
                                      _ptr(out), _stream()))
         return out, state_out
@@ -444,6 +471,22 @@ class Plan:
         _check(lib().mf_wiener_backward_unrolled(self._h, _ptr(d), C.byref(sch), int(checkpoint_every),
                                                  _ptr(grad_s), _ptr(s_out), _ptr(grad_d), _ptr(gb), _stream()))
         return s_out, grad_d, gb
+
+    def band_loss(self, d, s_wf, s_true, adjoint_schedule: Optional[Schedule] = None, want_grad=True,
+                  allow_not_converged=False):
+        """Loss of the differentiation workload at the Wiener filter s_wf
+        (mf_band_loss): returns (loss per problem float64, grad_d or None,
+        grad_bands or None, adjoint info)."""
+        import torch
+        loss = torch.empty(len(self.problems), dtype=torch.float64, device=d.device)
+        gd = torch.empty_like(d) if want_grad else None
+        gb = torch.zeros(max(self.total_bands, 1), dtype=torch.float64, device=d.device) if want_grad else None
+        info = (Info * len(self.problems))()
+        sch = adjoint_schedule._c() if adjoint_schedule is not None else None
+        st = lib().mf_band_loss(self._h, _ptr(d), _ptr(s_wf), _ptr(s_true), C.byref(sch) if sch is not None else None,
+                                _ptr(loss), _ptr(gd), _ptr(gb), info, _stream())
+        _check(st, allow_not_converged)
+        return loss, gd, (gb[:self.total_bands] if gb is not None else None), list(info)
 
     def band_power(self, x, y):
         import torch

@@ -93,8 +93,21 @@ template <bool INV> __device__ __forceinline__ void dft16(float2 (&v)[16]) {
         for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[4 * k1 + k2];
 }
 
+// 3-point DFT: with u = v1 + v2 and the primitive root exp(-+2 pi i/3) =
+// -1/2 -+ i sqrt(3)/2, X0 = v0 + u, X1,2 = (v0 - u/2) -+ i (sqrt(3)/2) (v1 - v2).
+constexpr float kS3 = 0.86602540378443865f;  // sin(pi/3)
+template <bool INV> __device__ __forceinline__ void dft3(float2& a0, float2& a1, float2& a2) {
+    const float2 u = cadd(a1, a2);
+    const float2 m = make_float2(fmaf(-0.5f, u.x, a0.x), fmaf(-0.5f, u.y, a0.y));
+    const float2 dd = mul_mi<INV>(cscale(csub(a1, a2), kS3));
+    a0 = cadd(a0, u);
+    a1 = cadd(m, dd);
+    a2 = csub(m, dd);
+}
+
 template <int R, bool INV> __device__ __forceinline__ void dft(float2 (&v)[R]) {
     if constexpr (R == 2) dft2<INV>(v[0], v[1]);
+    else if constexpr (R == 3) dft3<INV>(v[0], v[1], v[2]);
     else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
     else if constexpr (R == 8) dft8<INV>(v);
     else if constexpr (R == 16) dft16<INV>(v);
@@ -130,7 +143,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, unsigned lane, const 
 #pragma unroll
             for (int r = 0; r < R; ++r) v[t][r] = buf[swz(j + r * NT)];
             if constexpr (NS > 1) {
-                const unsigned k = j & (NS - 1);
+                const unsigned k = j % NS;
 #pragma unroll
                 for (int r = 1; r < R; ++r) {
                     const float2 w = tw[(r * k) * (L / (NS * R))];
@@ -145,7 +158,7 @@ __device__ __forceinline__ void stockham_pass(float2* buf, unsigned lane, const 
     for (int t = 0; t < TPT; ++t) {
         const unsigned j = lane + t * TPG;
         if ((NT % TPG) == 0 || j < (unsigned)NT) {
-            const unsigned k = j & (NS - 1);
+            const unsigned k = j % NS;
             const unsigned o = (j / NS) * NS * R + k;
 #pragma unroll
             for (int r = 0; r < R; ++r) buf[swz(o + r * NS)] = v[t][r];
@@ -154,16 +167,30 @@ __device__ __forceinline__ void stockham_pass(float2* buf, unsigned lane, const 
     __syncthreads();
 }
 
-// Radix plan: radix-16 passes, then one radix-2/4/8 pass for the remainder.
+// Transform lengths: 2^a 3^b with a >= 1 (even sides).
+constexpr bool is_pow2(int L) { return L > 0 && (L & (L - 1)) == 0; }
+
+// Radix plan: radix-16 passes while 16 divides what is left, then one
+// radix-8/4/2 pass for the rest of the power of two, then radix-3 passes.
+template <int REM>
+constexpr int next_radix() {
+    return REM % 16 == 0 ? 16 : REM % 8 == 0 ? 8 : REM % 4 == 0 ? 4 : REM % 2 == 0 ? 2 : 3;
+}
 template <int L, int NS, int TPG, bool INV>
 __device__ __forceinline__ void stockham_fft(float2* buf, unsigned lane, const float2* __restrict__ tw) {
     if constexpr (NS < L) {
-        constexpr int REM = L / NS;
-        constexpr int R = REM >= 16 ? 16 : REM;
+        constexpr int R = next_radix<L / NS>();
+        static_assert((L / NS) % R == 0, "transform length must be 2^a 3^b");
         stockham_pass<L, R, NS, TPG, INV>(buf, lane, tw);
         stockham_fft<L, NS * R, TPG, INV>(buf, lane, tw);
     }
 }
+
+// Row stride in LDS of a transform of length L: the swizzle permutes within
+// 32-element blocks, so a length that is neither a power of two nor a
+// multiple of 32 takes whole blocks.
+template <int L>
+constexpr int lds_stride() { return (is_pow2(L) || L % 32 == 0) ? L : (L + 31) / 32 * 32; }
 
 // Workgroups are handed to the eight XCDs round-robin.  Renumber them so that
 // each XCD runs a contiguous range of logical blocks: neighbouring tiles that

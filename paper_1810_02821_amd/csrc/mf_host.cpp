@@ -35,7 +35,18 @@ mf_status fail(mf_status st, const std::string& msg) {
     } while (0)
 
 bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
-bool size_ok(int v) { return is_pow2(v) && v >= 16 && v <= 2048; }
+// Image sides: 2^a 3^b with a >= 1 (even, so that pixel and mode pairs stay
+// within a row) in [16, 2048]; the DFT of Eq. 8 runs as radix-16/8/4/2 and
+// radix-3 passes.
+bool size_ok(int v) {
+    if (v < 16 || v > 2048 || (v & 1)) return false;
+    while (v % 2 == 0) v /= 2;
+    while (v % 3 == 0) v /= 3;
+    return v == 1;
+}
+// The hierarchical sampler and mass mapping (the extensions of Sec. 5) run
+// on power-of-two sides only.
+mf_status pow2_sides(mf_plan p, const char* what);
 
 struct HostProblem {
     int H = 0, W = 0;
@@ -98,7 +109,6 @@ struct mf_plan_s {
     DevBuf hier;                            // streamed hierarchical sampler: per-item amplitudes and sums
     DevBuf hfield;                          // streamed sampler field in FP16 / BF16 storage
     DevBuf kfield;                          // streamed mass mapping: kappa staging field
-    std::vector<mf::ItemDev> items_cached;  // what items[0..] holds (skip re-uploads)
     // column-kernel tile shape per size class: (H, W) -> (tc, nth)
     std::map<std::pair<int, int>, std::pair<int, int>> col_shape;
     // captured sweep loops of the streamed sampler, keyed by launch configuration
@@ -113,6 +123,14 @@ struct mf_plan_s {
     bool has_response = false;       // some problem has a diagonal A != I
     float* d_rinv = nullptr;         // 1 / A_i per pixel (0 without response), when has_response
     DevBuf dprime;                   // d / A of the current call
+    // problem ids per size class (all, then the band-spectrum ones) for work
+    // lists built on the device: (H, W) -> (offset in d_class_pids, count)
+    int32_t* d_class_pids = nullptr;
+    std::map<std::pair<int, int>, std::pair<int, int>> class_all, class_band;
+    int32_t* d_band_modes = nullptr;  // modes per band, concatenated
+    double* d_band_amps = nullptr;    // the plan's band amplitudes, concatenated
+    int32_t* d_flag = nullptr;        // non-finite check: lowest problem index with a non-finite state
+    DevBuf lossbuf;                   // mf_band_loss: grad_s, explicit grad_d, partial sums, band powers
     ~mf_plan_s() {
         (void)hipFree(d_probs);
         (void)hipFree(d_nbar);
@@ -123,7 +141,12 @@ struct mf_plan_s {
         (void)hipFree(d_band_count);
         (void)hipFree(d_band_scale);
         (void)hipFree(d_rinv);
+        (void)hipFree(d_class_pids);
+        (void)hipFree(d_band_modes);
+        (void)hipFree(d_band_amps);
+        (void)hipFree(d_flag);
         dprime.release();
+        lossbuf.release();
         for (auto& kv : d_tw) (void)hipFree(kv.second);
         items.release();
         field.release();
@@ -149,6 +172,8 @@ struct mf_plan_s {
 };
 
 namespace {
+
+mf_status read_finite_flag(mf_plan p, hipStream_t s);
 
 // P(|k|) of one problem, evaluated in FP64 (Eq. 9).
 double spectrum_at(const HostProblem& p, double k) {
@@ -198,8 +223,10 @@ mf_status copy_spectrum(HostProblem& hp, const mf_spectrum& s, int pidx) {
     return MF_OK;
 }
 
-// Upload n P(|k|) (FP64 -> FP32) for one problem; also its band map and scales.
-mf_status upload_spectrum(mf_plan p, int i) {
+// Upload n P(|k|) (FP64 -> FP32) for one problem; also its band map, mode
+// counts, amplitudes and scales.  The copies are ordered on `stream` after
+// the work already queued there, and complete before the call returns.
+mf_status upload_spectrum(mf_plan p, int i, hipStream_t stream) {
     HostProblem& hp = p->probs[i];
     hp.band_modes.assign(hp.n_bands, 0);
     const int H = hp.H, W = hp.W;
@@ -219,19 +246,27 @@ mf_status upload_spectrum(mf_plan p, int i) {
                 if (b >= 0) ++hp.band_modes[b];
             }
         }
-    MF_HIP(hipMemcpy(p->d_nP + hp.pix_off, nP.data(), nP.size() * sizeof(float), hipMemcpyHostToDevice));
+    MF_HIP(hipMemcpyAsync(p->d_nP + hp.pix_off, nP.data(), nP.size() * sizeof(float), hipMemcpyHostToDevice, stream));
     // column pairs: entry (kx/2) H + ky holds (nP(ky, kx), nP(ky, kx + 1)) for even kx
     std::vector<float2> nPt((size_t)H * W / 2);
     for (int kx = 0; kx < W; kx += 2)
         for (int ky = 0; ky < H; ++ky)
             nPt[(size_t)(kx / 2) * H + ky] = make_float2(nP[(size_t)ky * W + kx], nP[(size_t)ky * W + kx + 1]);
-    MF_HIP(hipMemcpy(p->d_nPt + hp.pix_off / 2, nPt.data(), nPt.size() * sizeof(float2), hipMemcpyHostToDevice));
-    MF_HIP(hipMemcpy(p->d_band + hp.pix_off, band.data(), band.size() * sizeof(int16_t), hipMemcpyHostToDevice));
+    MF_HIP(hipMemcpyAsync(p->d_nPt + hp.pix_off / 2, nPt.data(), nPt.size() * sizeof(float2), hipMemcpyHostToDevice,
+                          stream));
+    MF_HIP(hipMemcpyAsync(p->d_band + hp.pix_off, band.data(), band.size() * sizeof(int16_t), hipMemcpyHostToDevice,
+                          stream));
+    std::vector<double> sc(hp.n_bands);
     if (hp.kind == MF_PK_BANDS) {
-        std::vector<double> sc(hp.n_bands);
         for (int b = 0; b < hp.n_bands; ++b) sc[b] = 1.0 / (n * n * hp.amps[b] * hp.amps[b]);
-        MF_HIP(hipMemcpy(p->d_band_scale + hp.band_base, sc.data(), sc.size() * sizeof(double), hipMemcpyHostToDevice));
+        MF_HIP(hipMemcpyAsync(p->d_band_scale + hp.band_base, sc.data(), sc.size() * sizeof(double),
+                              hipMemcpyHostToDevice, stream));
+        MF_HIP(hipMemcpyAsync(p->d_band_amps + hp.band_base, hp.amps.data(), hp.n_bands * sizeof(double),
+                              hipMemcpyHostToDevice, stream));
+        MF_HIP(hipMemcpyAsync(p->d_band_modes + hp.band_base, hp.band_modes.data(), hp.n_bands * sizeof(int32_t),
+                              hipMemcpyHostToDevice, stream));
     }
+    MF_HIP(hipStreamSynchronize(stream));  // the host vectors die on return
     return MF_OK;
 }
 
@@ -288,11 +323,17 @@ mf::SweepArgs base_args(mf_plan p, int H, int W) {
     return a;
 }
 
+bool capturing(hipStream_t s) {
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    return s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone;
+}
+
 // Launch the graph cached under `key`, or capture `enqueue` (on the plan's
 // capture stream) as a new graph, cache it and launch it.  The plan keeps up
 // to 8 graphs; keys begin with a tag for the loop they capture.
 template <typename Fn>
 mf_status run_graph(mf_plan p, const std::vector<uint64_t>& key, hipStream_t s, Fn&& enqueue) {
+    if (capturing(s)) return enqueue(s);  // the caller is capturing its own graph: record the launches there
     for (auto& e : p->graphs)
         if (e.key == key) {
             MF_HIP(hipGraphLaunch(e.exec, s));
@@ -331,24 +372,64 @@ uint64_t bits_of(T v) {
     return b;
 }
 
-// Upload a work list at element offset `slot` of the items workspace.
+// Grow a plan workspace to `bytes`.  A call on a stream that is being
+// captured must not allocate: its workspaces come from mf_plan_reserve.
+mf_status ws(DevBuf& b, size_t bytes, hipStream_t s) {
+    if (bytes <= b.bytes) return MF_OK;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (s && hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+        return fail(MF_ERR_INVALID_ARG, "a workspace this call needs was not reserved (mf_plan_reserve), and the "
+                                        "stream is being captured");
+    hipError_t e = b.ensure(bytes);
+    if (e != hipSuccess)
+        return fail(e == hipErrorOutOfMemory ? MF_ERR_OUT_OF_MEMORY : MF_ERR_DEVICE,
+                    std::string("workspace allocation: ") + hipGetErrorString(e));
+    return MF_OK;
+}
+
+// Items workspace for work lists of up to `per` items per problem (two
+// regions: the list and, for residual tests, the converged subset).
+mf_status ensure_items(mf_plan p, int per, hipStream_t s) {
+    size_t max_items = 0;
+    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size() * (size_t)per);
+    return ws(p->items, 2 * (max_items + 1) * sizeof(mf::ItemDev), s);
+}
+
+// Build the work list of size class `cls` on the device: `per` items per
+// problem (all problems, or only the band-spectrum ones), field offsets in
+// the concatenated layout (per * pix_off + q * H * W) or, with `local`, i * H * W.
+template <typename ItemPtr, typename Count>
+mf_status class_items_at(mf_plan p, mf::ItemDev* base, size_t cap, std::pair<int, int> cls, int per, bool local,
+                         bool bands_only, hipStream_t s, ItemPtr* out, Count* n_out) {
+    const auto& tab = bands_only ? p->class_band : p->class_all;
+    auto it = tab.find(cls);
+    const int n_pids = it == tab.end() ? 0 : it->second.second;
+    const size_t n = (size_t)n_pids * per;
+    *out = base;
+    *n_out = (Count)n;
+    if (n == 0) return MF_OK;
+    if (n > cap) return fail(MF_ERR_INVALID_ARG, "internal: items workspace too small");
+    MF_HIP(mf::launch_fill_items(base, p->d_probs, p->d_class_pids + it->second.first, n_pids, per, local ? 1 : 0,
+                                 (int64_t)cls.first * cls.second, s));
+    return MF_OK;
+}
+
+template <typename ItemPtr, typename Count>
+mf_status class_items(mf_plan p, std::pair<int, int> cls, int per, bool local, bool bands_only, hipStream_t s,
+                      ItemPtr* out, Count* n_out) {
+    return class_items_at(p, p->items.as<mf::ItemDev>(), p->items.bytes / sizeof(mf::ItemDev), cls, per, local,
+                          bands_only, s, out, n_out);
+}
+
+// Upload a host-built work list at element offset `slot` of the items
+// workspace (the residual tests' shrinking lists; those calls synchronise).
 mf_status put_items(mf_plan p, const std::vector<mf::ItemDev>& it, size_t slot, hipStream_t s,
                     mf::ItemDev** out) {
     const size_t need = (slot + it.size()) * sizeof(mf::ItemDev);
     if (need > p->items.bytes) return fail(MF_ERR_INVALID_ARG, "internal: items workspace too small");
     mf::ItemDev* d = p->items.as<mf::ItemDev>() + slot;
-    auto same = [](const mf::ItemDev& x, const mf::ItemDev& y) {
-        return x.prob == y.prob && x.pair == y.pair && x.field_off == y.field_off;
-    };
-    if (slot == 0 && p->items_cached.size() == it.size() &&
-        std::equal(it.begin(), it.end(), p->items_cached.begin(), same)) {
-        *out = d;  // already on the device
-        return MF_OK;
-    }
     MF_HIP(hipMemcpyAsync(d, it.data(), it.size() * sizeof(mf::ItemDev), hipMemcpyHostToDevice, s));
     MF_HIP(hipStreamSynchronize(s));  // the host vector may die right after
-    if (slot == 0) p->items_cached = it;
-    else p->items_cached.clear();     // slot 0 is intact, but keep the rule simple
     *out = d;
     return MF_OK;
 }
@@ -362,10 +443,11 @@ mf_status solve_class(mf_plan p, const std::vector<int>& pids, int H, int W, con
                       const mf_schedule* sch, const float* s_init, std::vector<double>& bnorm2,
                       std::vector<mf_info>& info, hipStream_t s) {
     const int n_items = (int)pids.size();
-    std::vector<mf::ItemDev> items(n_items);
+    std::vector<mf::ItemDev> items(n_items);  // host copy for the residual bookkeeping
     for (int i = 0; i < n_items; ++i) items[i] = {pids[i], 0, p->probs[pids[i]].pix_off};
     mf::ItemDev* d_items = nullptr;
-    mf_status st = put_items(p, items, 0, s, &d_items);
+    int n_dev = 0;
+    mf_status st = class_items(p, {H, W}, 1, false, false, s, &d_items, &n_dev);
     if (st != MF_OK) return st;
     mf::SweepArgs a = base_args(p, H, W);
     a.items = d_items;
@@ -460,19 +542,25 @@ mf_status solve_class(mf_plan p, const std::vector<int>& pids, int H, int W, con
     return MF_OK;
 }
 
-mf_status ensure_solve_workspace(mf_plan p, hipStream_t s) {
-    (void)s;
+// Workspaces of the deterministic solves, the adjoint, the band reductions
+// and the band loss (with_t: the residual test's messenger snapshot).
+mf_status ensure_solve_workspace(mf_plan p, bool with_t, hipStream_t s) {
     size_t max_items = 0, max_rows = 0;
     for (auto& kv : p->classes) {
         max_items = std::max(max_items, kv.second.size());
         max_rows = std::max(max_rows, kv.second.size() * (size_t)kv.first.first);
     }
-    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
-    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
-    MF_HIP(p->field.ensure((size_t)p->total_px * sizeof(float2)));
-    MF_HIP(p->t_save.ensure((size_t)p->total_px * sizeof(float2)));
+    mf_status st;
+    if ((st = ensure_items(p, 1, s)) != MF_OK) return st;
+    if ((st = ws(p->field, (size_t)p->total_px * sizeof(float2), s)) != MF_OK) return st;
+    if (with_t && (st = ws(p->t_save, (size_t)p->total_px * sizeof(float2), s)) != MF_OK) return st;
     size_t part = std::max(max_rows, max_items * mf::kBandBlocks * 64);
-    MF_HIP(p->partials.ensure(part * sizeof(double)));
+    if ((st = ws(p->partials, part * sizeof(double), s)) != MF_OK) return st;
+    // persistent solve: per-problem outcome
+    if ((st = ws(p->sched, (size_t)p->probs.size() * 3 * sizeof(double), s)) != MF_OK) return st;
+    // adjoint field v when the caller does not keep it
+    if ((st = ws(p->aux, (size_t)p->total_px * sizeof(float), s)) != MF_OK) return st;
+    if (p->has_response && (st = ws(p->dprime, (size_t)p->total_px * sizeof(float), s)) != MF_OK) return st;
     return MF_OK;
 }
 
@@ -503,7 +591,8 @@ mf_status rhs_norms(mf_plan p, const float* src, int src_kind, double lam, std::
 mf_status plan_data(mf_plan p, const float* d, hipStream_t s, const float** out) {
     *out = d;
     if (!p->has_response) return MF_OK;
-    MF_HIP(p->dprime.ensure((size_t)p->total_px * sizeof(float)));
+    mf_status st = ws(p->dprime, (size_t)p->total_px * sizeof(float), s);
+    if (st != MF_OK) return st;
     MF_HIP(mf::launch_scale(d, p->d_rinv, p->dprime.as<float>(), p->total_px, s));
     *out = p->dprime.as<float>();
     return MF_OK;
@@ -516,10 +605,19 @@ mf_status data_gradient(mf_plan p, float* g, hipStream_t s) {
     return MF_OK;
 }
 
-// Shear problems: no response.
+mf_status pow2_sides(mf_plan p, const char* what) {
+    for (auto& kv : p->classes)
+        if (!is_pow2(kv.first.first) || !is_pow2(kv.first.second))
+            return fail(MF_ERR_UNSUPPORTED_SIZE, std::string(what) + " needs power-of-two sides (a problem is " +
+                                                     std::to_string(kv.first.first) + " x " +
+                                                     std::to_string(kv.first.second) + ")");
+    return MF_OK;
+}
+
+// Shear problems: no response, power-of-two sides.
 mf_status shear_check(mf_plan p) {
     if (p->has_response) return fail(MF_ERR_INVALID_ARG, "shear problems take no response");
-    return MF_OK;
+    return pow2_sides(p, "mass mapping");
 }
 
 // Mass mapping on the streamed kernels for one size class: per sweep the row
@@ -529,18 +627,10 @@ mf_status shear_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H, i
                          float b_ratio, int chains, const std::vector<double>& lam, const std::vector<int32_t>& sweeps,
                          int stochastic, uint64_t seed, int64_t sweep_offset, int burn_in, int n_samples, int thin,
                          const float* state_in, float* state_out, float* samples, float* kappa_out, hipStream_t s) {
-    float2* field;
-    if (state_out) {
-        field = reinterpret_cast<float2*>(state_out);
-    } else {
-        MF_HIP(p->field.ensure((size_t)p->total_px * chains * sizeof(float2)));
-        field = p->field.as<float2>();
-    }
+    // workspaces sized by ensure_shear_workspace
+    float2* field = state_out ? reinterpret_cast<float2*>(state_out) : p->field.as<float2>();
     mf::ShearStreamArgs a{};
-    if (samples || kappa_out) {
-        MF_HIP(p->kfield.ensure((size_t)p->total_px * chains * sizeof(float2)));
-        a.kfield = p->kfield.as<float2>();
-    }
+    if (samples || kappa_out) a.kfield = p->kfield.as<float2>();
     a.probs = p->d_probs;
     a.items = di;
     a.n_items = n_items;
@@ -595,40 +685,59 @@ mf_status shear_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H, i
     return run_graph(p, key, s, enqueue);
 }
 
+// Workspaces of the mass-mapping calls with `chains` chains per problem
+// (field: a state field for calls without state_out, needed by the streamed
+// classes and by the non-finite check; kappa: the streamed emission staging).
+mf_status ensure_shear_workspace(mf_plan p, int chains, bool field, bool check, bool kappa, hipStream_t s) {
+    mf_status st = ensure_items(p, chains, s);
+    if (st != MF_OK) return st;
+    bool any_streamed = false;
+    for (auto& kv : p->classes) any_streamed |= !mf::resident_supported(kv.first.first, kv.first.second);
+    if (field && (any_streamed || check) &&
+        (st = ws(p->field, (size_t)p->total_px * chains * sizeof(float2), s)) != MF_OK)
+        return st;
+    if (any_streamed && kappa && (st = ws(p->kfield, (size_t)p->total_px * chains * sizeof(float2), s)) != MF_OK)
+        return st;
+    return MF_OK;
+}
+
+hipError_t shear_check_class(mf_plan p, int H, int W, const mf::ItemDev* di, int n_items, float* fin,
+                             hipStream_t s) {
+    mf::SweepArgs c = base_args(p, H, W);
+    c.items = di;
+    c.n_items = n_items;
+    c.field = reinterpret_cast<float2*>(fin);
+    return mf::launch_finite_check(W, H, c, p->d_flag, s);
+}
+
 mf_status launch_shear(mf_plan p, const float* gamma, float b_ratio, int chains, const std::vector<double>& lam,
                        const std::vector<int32_t>& sweeps, int stochastic, uint64_t seed, int64_t sweep_offset,
                        int burn_in, int n_samples, int thin, const float* state_in, float* state_out,
-                       float* samples, float* kappa_out, hipStream_t s) {
+                       float* samples, float* kappa_out, bool check, hipStream_t s) {
     const int L = (int)lam.size();
-    MF_HIP(p->sched.ensure((size_t)L * (sizeof(double) + sizeof(int32_t))));
-    char* base = p->sched.as<char>();
-    MF_HIP(hipMemcpyAsync(base, lam.data(), (size_t)L * sizeof(double), hipMemcpyHostToDevice, s));
-    MF_HIP(hipMemcpyAsync(base + (size_t)L * sizeof(double), sweeps.data(), (size_t)L * sizeof(int32_t),
-                          hipMemcpyHostToDevice, s));
-    size_t max_items = 0;
-    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size() * (size_t)chains);
-    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
-    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
-    MF_HIP(hipStreamSynchronize(s));  // the host vectors must outlive the copies
+    mf_status st = ensure_shear_workspace(p, chains, !state_out, check, samples || kappa_out, s);
+    if (st != MF_OK) return st;
+    // the chains' final states: the caller's, or the plan field (streamed classes, non-finite check)
+    float* fin = state_out ? state_out : reinterpret_cast<float*>(p->field.as<float2>());
+    if (check) MF_HIP(mf::launch_fill_int(p->d_flag, INT32_MAX, 1, s));
     for (auto& kv : p->classes) {
         const int N = kv.first.first, W = kv.first.second;
-        std::vector<mf::ItemDev> items;
-        for (int pid : kv.second)
-            for (int c = 0; c < chains; ++c)
-                items.push_back({pid, c, (int64_t)chains * p->probs[pid].pix_off + (int64_t)c * N * W});
         mf::ItemDev* di = nullptr;
-        mf_status st = put_items(p, items, 0, s, &di);
-        if (st != MF_OK) return st;
+        int n_items = 0;
+        if ((st = class_items(p, kv.first, chains, false, false, s, &di, &n_items)) != MF_OK) return st;
         if (!mf::resident_supported(N, W)) {
-            st = shear_streamed(p, di, (int)items.size(), N, W, gamma, b_ratio, chains, lam, sweeps, stochastic, seed,
+            st = shear_streamed(p, di, n_items, N, W, gamma, b_ratio, chains, lam, sweeps, stochastic, seed,
                                 sweep_offset, burn_in, n_samples, thin, state_in, state_out, samples, kappa_out, s);
             if (st != MF_OK) return st;
+            if (check) MF_HIP(shear_check_class(p, N, W, di, n_items, fin, s));
             continue;
         }
+        if (L > mf::kMaxLevels)
+            return fail(MF_ERR_INVALID_ARG, "the persistent mass-mapping kernel takes at most 128 cooling levels");
         mf::ShearArgs r{};
         r.probs = p->d_probs;
         r.items = di;
-        r.n_items = (int)items.size();
+        r.n_items = n_items;
         r.gamma = reinterpret_cast<const float2*>(gamma);
         r.nbar = p->d_nbar;
         r.nP = p->d_nP;
@@ -638,32 +747,35 @@ mf_status launch_shear(mf_plan p, const float* gamma, float b_ratio, int chains,
         r.key1 = (uint32_t)(seed >> 32);
         r.sweep0 = (uint32_t)sweep_offset;
         r.stochastic = stochastic;
-        r.lambda = reinterpret_cast<const double*>(base);
-        r.level_sweeps = reinterpret_cast<const int32_t*>(base + (size_t)L * sizeof(double));
-        r.n_levels = L;
+        r.lv.n = L;
+        for (int j = 0; j < L; ++j) {
+            r.lv.lambda[j] = lam[j];
+            r.lv.sweeps[j] = sweeps[j];
+        }
         r.burn_in = burn_in;
         r.n_samples = n_samples;
         r.thin = thin;
         r.samples = reinterpret_cast<float2*>(samples);
         r.chains = chains;
         r.state_in = reinterpret_cast<const float2*>(state_in);
-        r.state_out = reinterpret_cast<float2*>(state_out);
+        r.state_out = check ? reinterpret_cast<float2*>(fin) : reinterpret_cast<float2*>(state_out);
         r.kappa_out = reinterpret_cast<float2*>(kappa_out);
         MF_HIP(mf::launch_resident_shear(N, r, s));
+        if (check) MF_HIP(shear_check_class(p, N, W, di, n_items, fin, s));
     }
-    return MF_OK;
+    return check ? read_finite_flag(p, s) : MF_OK;
 }
 
 // Real part of the field buffer of one streamed size class into `out`.
 mf_status copy_class_real(mf_plan p, const std::vector<int>& pids, int H, int W, float* out, hipStream_t s) {
-    std::vector<mf::ItemDev> items;
-    for (int pid : pids) items.push_back({pid, 0, p->probs[pid].pix_off});
+    (void)pids;
     mf::ItemDev* d = nullptr;
-    mf_status st = put_items(p, items, 0, s, &d);
+    int n_items = 0;
+    mf_status st = class_items(p, {H, W}, 1, false, false, s, &d, &n_items);
     if (st != MF_OK) return st;
     mf::SweepArgs a = base_args(p, H, W);
     a.items = d;
-    a.n_items = (int)items.size();
+    a.n_items = n_items;
     a.field = p->field.as<float2>();
     MF_HIP(mf::launch_copy_out_real(W, H, a, out, s));
     return MF_OK;
@@ -671,52 +783,51 @@ mf_status copy_class_real(mf_plan p, const std::vector<int>& pids, int H, int W,
 
 // Deterministic solve of one size class in the persistent kernel: one
 // workgroup per problem runs every level and the residual test on the device.
+// The levels travel in the kernel arguments, at most kMaxLevels per launch; a
+// longer schedule continues in further launches from the stored result.
 mf_status solve_class_resident(mf_plan p, const std::vector<int>& pids, int N, const float* src, int src_kind,
                                const mf_schedule* sch, const float* s_init, float* out, std::vector<mf_info>& info,
                                bool want_info, hipStream_t s) {
-    const int n_items = (int)pids.size();
-    std::vector<mf::ItemDev> items(n_items);
-    for (int i = 0; i < n_items; ++i) items[i] = {pids[i], 0, p->probs[pids[i]].pix_off};
     mf::ItemDev* d_items = nullptr;
-    mf_status st = put_items(p, items, 0, s, &d_items);
+    int n_items = 0;
+    mf_status st = class_items(p, {N, N}, 1, false, false, s, &d_items, &n_items);
     if (st != MF_OK) return st;
-    const int L = sch->n_levels;
-    const size_t info_off = (size_t)L * sizeof(double) + (size_t)L * sizeof(int32_t);
-    const size_t info_at = (info_off + 255) / 256 * 256;
-    MF_HIP(p->sched.ensure(info_at + (size_t)n_items * 3 * sizeof(double)));
-    std::vector<char> stage(info_off);
-    std::memcpy(stage.data(), sch->lambda, (size_t)L * sizeof(double));
-    std::memcpy(stage.data() + (size_t)L * sizeof(double), sch->sweeps, (size_t)L * sizeof(int32_t));
-    char* base = p->sched.as<char>();
-    MF_HIP(hipMemcpyAsync(base, stage.data(), info_off, hipMemcpyHostToDevice, s));
     mf::SolveArgs a{};
     a.probs = p->d_probs;
     a.items = d_items;
     a.n_items = n_items;
     a.src = src;
     a.src_kind = src_kind;
-    a.s_init = s_init;
     a.s_out = out;
     a.nbar = p->d_nbar;
     a.nP = p->d_nP;
     a.tw = p->d_tw.at(N);
-    a.lambda = reinterpret_cast<const double*>(base);
-    a.sweeps = reinterpret_cast<const int32_t*>(base + (size_t)L * sizeof(double));
-    a.n_levels = L;
-    a.tol = sch->tol;
     a.max_sweeps = sch->max_sweeps;
     a.check_every = sch->check_every > 0 ? sch->check_every : 1;
-    a.info = reinterpret_cast<double*>(base + info_at);
-    MF_HIP(mf::launch_resident_solve(N, a, s));
+    double* d_info = p->sched.as<double>();
+    const int L = sch->n_levels;
+    int total = 0;
+    for (int j0 = 0; j0 < L; j0 += mf::kMaxLevels) {
+        const int j1 = std::min(L, j0 + mf::kMaxLevels);
+        const bool last = j1 == L;
+        a.lv.n = j1 - j0;
+        for (int j = j0; j < j1; ++j) {
+            a.lv.lambda[j - j0] = sch->lambda[j];
+            a.lv.sweeps[j - j0] = sch->sweeps[j];
+        }
+        a.total0 = total;
+        a.s_init = j0 == 0 ? s_init : out;
+        a.tol = last ? sch->tol : 0.0;
+        a.info = last && want_info ? d_info : nullptr;
+        MF_HIP(mf::launch_resident_solve(N, a, s));
+        for (int j = j0; j < j1; ++j) total += sch->sweeps[j];
+    }
     if (!want_info) {
-        int total = 0;
-        for (int j = 0; j < L; ++j) total += sch->sweeps[j];
         for (int pid : pids) info[pid] = {total, 1, std::nan("")};
-        MF_HIP(hipStreamSynchronize(s));  // the staging vector dies on return
         return MF_OK;
     }
     std::vector<double> h((size_t)n_items * 3);
-    MF_HIP(hipMemcpyAsync(h.data(), a.info, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+    MF_HIP(hipMemcpyAsync(h.data(), d_info, h.size() * sizeof(double), hipMemcpyDeviceToHost, s));
     MF_HIP(hipStreamSynchronize(s));
     for (int i = 0; i < n_items; ++i)
         info[pids[i]] = {(int32_t)h[3 * i], (int32_t)h[3 * i + 1], h[3 * i + 2]};
@@ -733,7 +844,7 @@ mf_status run_solve(mf_plan p, const float* src, int src_kind, const mf_schedule
                     float* out, mf_info* info_out, hipStream_t s) {
     mf_status st = validate_schedule(sch);
     if (st != MF_OK) return st;
-    if ((st = ensure_solve_workspace(p, s)) != MF_OK) return st;
+    if ((st = ensure_solve_workspace(p, sch->tol > 0, s)) != MF_OK) return st;
     bool any_streamed = false;
     for (auto& kv : p->classes) any_streamed = any_streamed || !solve_resident(p, kv.first.first, kv.first.second);
     std::vector<double> bn;
@@ -845,8 +956,9 @@ mf_status cool_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int 
 // loop is captured once per launch configuration and replayed as one graph.
 mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int H, int W, const float* d,
                           const mf_sample_args* g, float2* work, const float2* state_in, float* samples,
-                          hipStream_t s) {
-    if (!(p->flags & MF_FLAG_GRAPH)) return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, s);
+                          bool graphs, hipStream_t s) {
+    if (!(p->flags & MF_FLAG_GRAPH) || !graphs)
+        return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, s);
     const auto sh = class_shape(p, H, W);
     const std::vector<uint64_t> key = {1, (uint64_t)H, (uint64_t)W, (uint64_t)n_items, (uint64_t)(uintptr_t)d_items,
                                        (uint64_t)(uintptr_t)d, (uint64_t)(uintptr_t)work,
@@ -868,8 +980,7 @@ mf_status spectrum_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H
                             double* theta_out, float* samples, double* theta_samples, const int32_t* d_dof,
                             const double* d_th0, hipStream_t s) {
     constexpr int kNB = mf::kMaxBandsPerProblem;
-    const size_t nd = (size_t)n_items * 2 * kNB;
-    MF_HIP(p->hier.ensure(3 * nd * sizeof(double) + (size_t)n_items * kNB * sizeof(float4)));
+    const size_t nd = (size_t)n_items * 2 * kNB;  // hier sized by ensure_spectrum_workspace
     double* theta = p->hier.as<double>();
     mf::SweepArgs a = base_args(p, H, W);
     a.items = di;
@@ -1026,6 +1137,264 @@ mf_status autotune(mf_plan p) {
     return MF_OK;
 }
 
+// Buffers of one sampler call: plan workspaces, or any other device memory
+// of the same sizes.
+struct SampleWs {
+    mf::ItemDev* items = nullptr;  // work lists
+    size_t items_cap = 0;          // in items
+    float4* coef = nullptr;        // persistent tables: 40 bytes per pixel pair
+    float* dprime = nullptr;       // d / A (response plans)
+    float2* field = nullptr;       // work field when state_out is NULL
+    float2* hfield = nullptr;      // 16-bit work field (4 bytes per element)
+    bool graphs = true;            // MF_FLAG_GRAPH may capture and instantiate graphs (which allocates)
+};
+
+mf_status validate_sample(const mf_sample_args* g, const float* state_out, const float* samples_out) {
+    if (g->chains_per_problem < 1 || g->burn_in < 0 || g->n_samples < 0 || g->thin < 1 || g->sweep_offset < 0)
+        return fail(MF_ERR_INVALID_ARG, "need chains >= 1, burn_in >= 0, n_samples >= 0, thin >= 1, sweep_offset >= 0");
+    if (g->sweep_offset + (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin > 0xffffffffLL)
+        return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
+    if (g->form < MF_FORM_AUTO || g->form > MF_FORM_PLAIN) return fail(MF_ERR_INVALID_ARG, "unknown form");
+    if (g->storage < MF_STORAGE_FP32 || g->storage > MF_STORAGE_BF16) return fail(MF_ERR_INVALID_ARG, "unknown storage");
+    if (g->cooling) {
+        const mf_status sc = validate_schedule(g->cooling);
+        if (sc != MF_OK) return sc;
+        int64_t n_cool = 0;
+        for (int j = 0; j < g->cooling->n_levels; ++j) n_cool += g->cooling->sweeps[j];
+        if (g->sweep_offset + n_cool + (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin > 0xffffffffLL)
+            return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
+    }
+    if (g->n_samples > 0 && !samples_out && !state_out)
+        return fail(MF_ERR_INVALID_ARG, "nothing to write: samples_out and state_out are NULL");
+    return MF_OK;
+}
+
+bool sample_any_persistent(mf_plan p, int form) {
+    bool any = false;
+    for (auto& kv : p->classes)
+        any |= form == MF_FORM_PERSISTENT || (form == MF_FORM_AUTO && mf::resident_supported(kv.first.first, kv.first.second));
+    return any;
+}
+
+// Workspaces of mf_sample with `pairs` chain pairs per problem.
+mf_status ensure_sample_workspace(mf_plan p, int pairs, int storage, int form, bool need_field, hipStream_t s) {
+    mf_status st = ensure_items(p, pairs, s);
+    if (st != MF_OK) return st;
+    const size_t field_elems = (size_t)p->total_px * pairs;
+    if (need_field && (st = ws(p->field, field_elems * sizeof(float2), s)) != MF_OK) return st;
+    if (storage != MF_STORAGE_FP32 && (st = ws(p->hfield, field_elems * 4, s)) != MF_OK) return st;
+    if (sample_any_persistent(p, form) &&
+        (st = ws(p->coef, (size_t)p->total_px / 2 * (sizeof(float4) + sizeof(float2) + sizeof(float4)), s)) != MF_OK)
+        return st;
+    if (p->has_response && (st = ws(p->dprime, (size_t)p->total_px * sizeof(float), s)) != MF_OK) return st;
+    return MF_OK;
+}
+
+// Lowest problem whose chain states hold a NaN or an infinity (after a
+// synchronisation of the stream), or MF_OK.
+mf_status read_finite_flag(mf_plan p, hipStream_t s) {
+    int32_t h = 0;
+    MF_HIP(hipMemcpyAsync(&h, p->d_flag, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MF_HIP(hipStreamSynchronize(s));
+    if (h != INT32_MAX)
+        return fail(MF_ERR_NONFINITE, "problem " + std::to_string(h) + ": a chain state holds NaN or Inf");
+    return MF_OK;
+}
+
+// Algorithm 1 for every problem (mf_sample), on the buffers of `w`.
+mf_status sample_impl(mf_plan p, const float* d, const mf_sample_args* g, const float* state_in, float* state_out,
+                      float* samples_out, const SampleWs& w, hipStream_t s) {
+    int64_t n_cool = 0;
+    if (g->cooling)
+        for (int j = 0; j < g->cooling->n_levels; ++j) n_cool += g->cooling->sweeps[j];
+    mf_sample_args gm = *g;  // the sampling phase after the cooling levels
+    gm.sweep_offset += n_cool;
+    gm.cooling = nullptr;
+    if (p->has_response) {
+        MF_HIP(mf::launch_scale(d, p->d_rinv, w.dprime, p->total_px, s));
+        d = w.dprime;
+    }
+    const int pairs = (g->chains_per_problem + 1) / 2;
+    float2* work = state_out ? reinterpret_cast<float2*>(state_out) : w.field;
+    const float2* sin = reinterpret_cast<const float2*>(state_in);
+    float2* hwork = g->storage != MF_STORAGE_FP32 ? w.hfield : nullptr;
+    float4* pcoef = nullptr;
+    float2* psrc = nullptr;
+    float4* mcoef = nullptr;
+    if (sample_any_persistent(p, g->form)) {
+        const size_t half = (size_t)p->total_px / 2;
+        pcoef = w.coef;
+        psrc = reinterpret_cast<float2*>(pcoef + half);
+        mcoef = reinterpret_cast<float4*>(psrc + half);
+        MF_HIP(mf::launch_sampler_coefs(p->d_probs, (int)p->probs.size(), d, p->d_nbar, p->d_nP, pcoef, psrc, mcoef,
+                                        s));
+    }
+    if (g->check_finite) MF_HIP(mf::launch_fill_int(p->d_flag, INT32_MAX, 1, s));
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        int form = g->form;
+        if (form == MF_FORM_AUTO) form = mf::resident_supported(H, W) ? MF_FORM_PERSISTENT : MF_FORM_STREAMED;
+        if (form == MF_FORM_PERSISTENT && !mf::resident_supported(H, W))
+            return fail(MF_ERR_UNSUPPORTED_SIZE, "the persistent form needs H = W in {32, 64, 128}");
+        mf::ItemDev* di = nullptr;
+        int n_items = 0;
+        mf_status st = class_items_at(p, w.items, w.items_cap, kv.first, pairs, false, false, s, &di, &n_items);
+        if (st != MF_OK) return st;
+        const float2* cin = sin;  // the state the sampling phase starts from
+        if (n_cool > 0) {
+            float2* cw = (form != MF_FORM_PERSISTENT && hwork) ? hwork : work;
+            st = cool_streamed(p, di, n_items, H, W, d, g, cw == hwork ? g->storage : MF_STORAGE_FP32, cw, sin, s);
+            if (st != MF_OK) return st;
+            cin = cw;
+        }
+        mf::SweepArgs chk = base_args(p, H, W);
+        chk.items = di;
+        chk.n_items = n_items;
+        chk.field = work;
+        if (form == MF_FORM_PERSISTENT) {
+            mf::ResidentArgs r{};
+            r.probs = p->d_probs;
+            r.items = di;
+            r.n_items = n_items;
+            r.field = work;
+            r.state_in = cin;
+            r.init_scale = g->init_scale;
+            r.pcoef = pcoef;
+            r.psrc = psrc;
+            r.mcoef = mcoef;
+            r.tw = p->d_tw.at(W);
+            r.key0 = (uint32_t)(g->seed & 0xffffffffu);
+            r.key1 = (uint32_t)(g->seed >> 32);
+            r.sweep0 = (uint32_t)gm.sweep_offset;
+            r.burn_in = g->burn_in;
+            r.n_samples = g->n_samples;
+            r.thin = g->thin;
+            r.samples = samples_out;
+            r.chains = g->chains_per_problem;
+            MF_HIP(mf::launch_resident_sample(H, r, s));
+        } else {
+            float2* wf = hwork ? hwork : work;
+            if (form == MF_FORM_STREAMED) {
+                st = sample_streamed(p, di, n_items, H, W, d, &gm, wf, cin, samples_out, w.graphs, s);
+            } else {  // plain: one chain pair per launch sequence
+                for (int i = 0; i < n_items && st == MF_OK; ++i)
+                    st = sample_streamed(p, di + i, 1, H, W, d, &gm, wf, cin, samples_out, w.graphs, s);
+            }
+            if (st == MF_OK && hwork && state_out) {  // final states widened to FP32
+                mf::SweepArgs a = base_args(p, H, W);
+                a.items = di;
+                a.n_items = n_items;
+                a.field = hwork;
+                a.storage = g->storage;
+                MF_HIP(mf::launch_copy_out_pairs(W, H, a, work, s));
+            }
+            if (hwork) {
+                chk.field = hwork;
+                chk.storage = g->storage;
+            }
+        }
+        if (st != MF_OK) return st;
+        // a NaN or an infinity anywhere in a chain's history reaches its final
+        // state (every sweep mixes all pixels through the transforms)
+        if (g->check_finite) MF_HIP(mf::launch_finite_check(W, H, chk, p->d_flag, s));
+    }
+    return g->check_finite ? read_finite_flag(p, s) : MF_OK;
+}
+
+// Workspaces of mf_sample_spectrum with `pairs` chain pairs per problem.
+mf_status ensure_spectrum_workspace(mf_plan p, int pairs, bool need_field, hipStream_t s) {
+    mf_status st = ensure_items(p, pairs, s);
+    if (st != MF_OK) return st;
+    if (need_field && (st = ws(p->field, (size_t)p->total_px * pairs * sizeof(float2), s)) != MF_OK) return st;
+    if ((st = ws(p->spec, (size_t)std::max(1, p->total_bands) * sizeof(int32_t), s)) != MF_OK) return st;
+    if ((st = ws(p->coef, (size_t)p->total_px / 2 * (sizeof(float4) + sizeof(float2) + sizeof(float4)), s)) != MF_OK)
+        return st;
+    if (p->has_response && (st = ws(p->dprime, (size_t)p->total_px * sizeof(float), s)) != MF_OK) return st;
+    size_t max_items = 0;
+    for (auto& kv : p->classes)
+        if (!mf::resident_supported(kv.first.first, kv.first.second))
+            max_items = std::max(max_items, kv.second.size() * (size_t)pairs);
+    if (max_items > 0) {
+        constexpr int kNB = mf::kMaxBandsPerProblem;
+        const size_t nd = max_items * 2 * kNB;
+        if ((st = ws(p->hier, 3 * nd * sizeof(double) + max_items * kNB * sizeof(float4), s)) != MF_OK) return st;
+    }
+    return MF_OK;
+}
+
+// Workspaces of the unrolled gradient for K sweeps with a checkpoint every C:
+// sized for the largest size class (classes run one after another).
+mf_status ensure_unrolled_workspace(mf_plan p, int K, int C, hipStream_t s) {
+    mf_status st = ensure_items(p, 1, s);
+    if (st != MF_OK) return st;
+    if (p->has_response && (st = ws(p->dprime, (size_t)p->total_px * sizeof(float), s)) != MF_OK) return st;
+    size_t n_max = 0, tiles_max = 0;
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        n_max = std::max(n_max, kv.second.size() * (size_t)H * W);
+        const int tc = class_shape(p, H, W).first;
+        tiles_max = std::max(tiles_max, kv.second.size() * (size_t)((W + tc - 1) / tc));
+    }
+    const size_t ncp = (size_t)(K + C - 1) / C;
+    if ((st = ws(p->field, n_max * sizeof(float2), s)) != MF_OK) return st;
+    if ((st = ws(p->field_adj, n_max * sizeof(float2), s)) != MF_OK) return st;
+    if ((st = ws(p->ckpt, ncp * n_max * sizeof(float2), s)) != MF_OK) return st;
+    if ((st = ws(p->tstore, (size_t)std::min(C, K) * n_max * sizeof(float2), s)) != MF_OK) return st;
+    return ws(p->slots, tiles_max * mf::kMaxBandsPerProblem * sizeof(double), s);
+}
+
+// The implicit VJP of mf_wiener_backward: the adjoint solve, then N^-1 v and
+// the band sums per size class.
+mf_status backward_impl(mf_plan p, const float* s_wf, const float* grad_s, const mf_schedule* schedule,
+                        float* grad_d, double* grad_bands, float* v_out, mf_info* info, hipStream_t s) {
+    mf_status st = validate_schedule(schedule);
+    if (st != MF_OK) return st;
+    if ((st = ensure_solve_workspace(p, schedule->tol > 0, s)) != MF_OK) return st;
+    float* v = v_out ? v_out : p->aux.as<float>();
+    st = run_solve(p, grad_s, mf::kSrcGrad, schedule, nullptr, v, info, s);
+    if (st != MF_OK && st != MF_ERR_NOT_CONVERGED) return st;
+    const mf_status conv = st;
+    for (auto& kv : p->classes) {
+        const int H = kv.first.first, W = kv.first.second;
+        mf::SweepArgs a = base_args(p, H, W);
+        a.field = p->field.as<float2>();
+        a.partials = p->partials.as<double>();
+        if (grad_d) {
+            if ((st = class_items(p, kv.first, 1, false, false, s, &a.items, &a.n_items)) != MF_OK) return st;
+            MF_HIP(mf::launch_grad_d(W, H, a, v, grad_d, s));
+        }
+        if (!grad_bands || p->total_bands <= 0) continue;
+        if ((st = class_items(p, kv.first, 1, false, true, s, &a.items, &a.n_items)) != MF_OK) return st;
+        if (a.n_items == 0) continue;
+        MF_HIP(mf::launch_band_power(W, H, a, v, s_wf, p->d_band, p->d_band_base, p->d_band_count,
+                                     p->d_band_scale, grad_bands, s));
+    }
+    if ((st = data_gradient(p, grad_d, s)) != MF_OK) return st;
+    return conv;
+}
+
+// Workspace of mf_band_loss: grad_s and the explicit grad_d (floats per
+// pixel), FP64 partial sums per item and block, band powers.
+struct LossWs {
+    float* grad_s;
+    float* grad_d;
+    double* part;
+    double* power;
+};
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+LossWs loss_ws(mf_plan p) {
+    char* b = p->lossbuf.as<char>();
+    const size_t px = align256((size_t)p->total_px * sizeof(float));
+    const size_t part = align256(p->probs.size() * mf::kLossBlocks * 2 * sizeof(double));
+    return {reinterpret_cast<float*>(b), reinterpret_cast<float*>(b + px), reinterpret_cast<double*>(b + 2 * px),
+            reinterpret_cast<double*>(b + 2 * px + part)};
+}
+mf_status ensure_loss_workspace(mf_plan p, hipStream_t s) {
+    const size_t px = align256((size_t)p->total_px * sizeof(float));
+    const size_t part = align256(p->probs.size() * mf::kLossBlocks * 2 * sizeof(double));
+    return ws(p->lossbuf, 2 * px + part + (size_t)std::max(1, p->total_bands) * sizeof(double), s);
+}
+
 }  // namespace
 
 // =========================================================================
@@ -1050,7 +1419,6 @@ const char* mf_last_error(void) { return g_last_error.c_str(); }
 
 mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* problems, uint32_t flags,
                          mf_stream stream) {
-    (void)stream;
     if (!out) return fail(MF_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
     if (n_problems < 1 || n_problems >= (1 << 24) || !problems)
@@ -1071,7 +1439,8 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
         HostProblem& hp = p->probs[i];
         if (!size_ok(q.H) || !size_ok(q.W)) {
             delete p;
-            return fail(MF_ERR_UNSUPPORTED_SIZE, "problem " + std::to_string(i) + ": H and W must be powers of two in [16, 2048]");
+            return fail(MF_ERR_UNSUPPORTED_SIZE, "problem " + std::to_string(i) +
+                                                     ": H and W must be even 2^a 3^b in [16, 2048]");
         }
         if (!q.noise_var) {
             delete p;
@@ -1153,6 +1522,25 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
     MF_TRY(hipMalloc(&p->d_band_base, n_problems * sizeof(int32_t)));
     MF_TRY(hipMalloc(&p->d_band_count, n_problems * sizeof(int32_t)));
     MF_TRY(hipMalloc(&p->d_band_scale, std::max(bands, 1) * sizeof(double)));
+    MF_TRY(hipMalloc(&p->d_band_amps, std::max(bands, 1) * sizeof(double)));
+    MF_TRY(hipMalloc(&p->d_band_modes, std::max(bands, 1) * sizeof(int32_t)));
+    MF_TRY(hipMalloc(&p->d_flag, sizeof(int32_t)));
+    {
+        // problem ids per size class: all of them, then the band-spectrum ones
+        std::vector<int32_t> ids;
+        for (auto& kv : p->classes) {
+            p->class_all[kv.first] = {(int)ids.size(), (int)kv.second.size()};
+            ids.insert(ids.end(), kv.second.begin(), kv.second.end());
+        }
+        for (auto& kv : p->classes) {
+            const int off = (int)ids.size();
+            for (int pid : kv.second)
+                if (p->probs[pid].kind == MF_PK_BANDS) ids.push_back(pid);
+            p->class_band[kv.first] = {off, (int)ids.size() - off};
+        }
+        MF_TRY(hipMalloc(&p->d_class_pids, ids.size() * sizeof(int32_t)));
+        MF_TRY(hipMemcpy(p->d_class_pids, ids.data(), ids.size() * sizeof(int32_t), hipMemcpyHostToDevice));
+    }
     MF_TRY(hipMemcpy(p->d_probs, pd.data(), n_problems * sizeof(mf::ProbDev), hipMemcpyHostToDevice));
     MF_TRY(hipMemcpy(p->d_nbar, p->host_nbar.data(), off * sizeof(float), hipMemcpyHostToDevice));
     MF_TRY(hipMemcpy(p->d_band_base, bb.data(), n_problems * sizeof(int32_t), hipMemcpyHostToDevice));
@@ -1163,7 +1551,7 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
     }
 #undef MF_TRY
     for (int i = 0; i < n_problems; ++i) {
-        mf_status st = upload_spectrum(p, i);
+        mf_status st = upload_spectrum(p, i, (hipStream_t)stream);
         if (st != MF_OK) {
             delete p;
             return st;
@@ -1193,7 +1581,7 @@ mf_status mf_plan_destroy(mf_plan plan) {
     return MF_OK;
 }
 
-mf_status mf_plan_set_spectrum(mf_plan p, int32_t problem, const mf_spectrum* spectrum) {
+mf_status mf_plan_set_spectrum(mf_plan p, int32_t problem, const mf_spectrum* spectrum, mf_stream stream) {
     if (!p || !spectrum || problem < 0 || problem >= (int)p->probs.size())
         return fail(MF_ERR_INVALID_ARG, "bad plan, problem index or spectrum");
     HostProblem& hp = p->probs[problem];
@@ -1204,7 +1592,40 @@ mf_status mf_plan_set_spectrum(mf_plan p, int32_t problem, const mf_spectrum* sp
     if (tmp.kind != old_kind || tmp.n_bands != old_nb)
         return fail(MF_ERR_INVALID_ARG, "set_spectrum must keep the spectrum kind and band count");
     hp = tmp;
-    return upload_spectrum(p, problem);
+    return upload_spectrum(p, problem, (hipStream_t)stream);
+}
+
+mf_status mf_plan_reserve(mf_plan p, const mf_reserve* r) {
+    if (!p || !r) return fail(MF_ERR_INVALID_ARG, "plan and reserve are required");
+    const uint32_t known = MF_RESERVE_SOLVE | MF_RESERVE_SAMPLE | MF_RESERVE_SPECTRUM | MF_RESERVE_SHEAR |
+                           MF_RESERVE_UNROLLED | MF_RESERVE_MOMENTS;
+    if (r->calls & ~known) return fail(MF_ERR_INVALID_ARG, "unknown reserve bits");
+    const bool chains = r->calls & (MF_RESERVE_SAMPLE | MF_RESERVE_SPECTRUM | MF_RESERVE_SHEAR | MF_RESERVE_MOMENTS);
+    if (chains && r->chains_per_problem < 1) return fail(MF_ERR_INVALID_ARG, "chains_per_problem must be >= 1");
+    if ((r->calls & MF_RESERVE_SAMPLE) && (r->storage < MF_STORAGE_FP32 || r->storage > MF_STORAGE_BF16))
+        return fail(MF_ERR_INVALID_ARG, "unknown storage");
+    if ((r->calls & MF_RESERVE_UNROLLED) && (r->unrolled_sweeps < 1 || r->checkpoint_every < 1))
+        return fail(MF_ERR_INVALID_ARG, "the unrolled reserve needs unrolled_sweeps >= 1 and checkpoint_every >= 1");
+    const hipStream_t s = nullptr;  // allocation only
+    const int pairs = (r->chains_per_problem + 1) / 2;
+    mf_status st = MF_OK;
+    if (r->calls & MF_RESERVE_SOLVE) {
+        if ((st = ensure_solve_workspace(p, true, s)) != MF_OK) return st;
+        if ((st = ensure_loss_workspace(p, s)) != MF_OK) return st;
+    }
+    if ((r->calls & MF_RESERVE_SAMPLE) &&
+        (st = ensure_sample_workspace(p, pairs, r->storage, MF_FORM_AUTO, true, s)) != MF_OK)
+        return st;
+    if ((r->calls & MF_RESERVE_SPECTRUM) && (st = ensure_spectrum_workspace(p, pairs, true, s)) != MF_OK) return st;
+    if ((r->calls & MF_RESERVE_SHEAR) &&
+        (st = ensure_shear_workspace(p, r->chains_per_problem, true, true, true, s)) != MF_OK)
+        return st;
+    if ((r->calls & MF_RESERVE_UNROLLED) &&
+        (st = ensure_unrolled_workspace(p, r->unrolled_sweeps, r->checkpoint_every, s)) != MF_OK)
+        return st;
+    if ((r->calls & MF_RESERVE_MOMENTS) && (st = ws(p->aux, (size_t)p->total_px * 2 * sizeof(double), s)) != MF_OK)
+        return st;
+    return MF_OK;
 }
 
 int64_t mf_plan_pixel_offset(mf_plan p, int32_t problem) {
@@ -1242,44 +1663,58 @@ mf_status mf_wiener_backward(mf_plan p, const float* s_wf, const float* grad_s, 
                              float* grad_d, double* grad_bands, float* v_out, mf_info* info, mf_stream stream) {
     if (!p || !grad_s) return fail(MF_ERR_INVALID_ARG, "plan and grad_s are required");
     if (grad_bands && !s_wf) return fail(MF_ERR_INVALID_ARG, "grad_bands needs s_wf");
+    return backward_impl(p, s_wf, grad_s, schedule, grad_d, grad_bands, v_out, info, (hipStream_t)stream);
+}
+
+mf_status mf_band_loss(mf_plan p, const float* d, const float* s_wf, const float* s_true,
+                       const mf_schedule* adjoint_schedule, double* loss_out, float* grad_d, double* grad_bands,
+                       mf_info* info, mf_stream stream) {
+    if (!p || !d || !s_wf || !s_true || !loss_out)
+        return fail(MF_ERR_INVALID_ARG, "plan, d, s_wf, s_true and loss_out are required");
+    if ((grad_d || grad_bands) && !adjoint_schedule)
+        return fail(MF_ERR_INVALID_ARG, "gradients need an adjoint schedule");
+    for (size_t i = 0; i < p->probs.size(); ++i)
+        if (p->probs[i].kind != MF_PK_BANDS)
+            return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + " has no band spectrum");
     hipStream_t s = (hipStream_t)stream;
-    float* v = v_out;
-    if (!v) {
-        MF_HIP(p->aux.ensure((size_t)p->total_px * sizeof(float)));
-        v = p->aux.as<float>();
-    }
-    mf_status st = run_solve(p, grad_s, mf::kSrcGrad, schedule, nullptr, v, info, s);
-    if (st != MF_OK && st != MF_ERR_NOT_CONVERGED) return st;
-    const mf_status conv = st;
+    mf_status st = ensure_solve_workspace(p, adjoint_schedule && adjoint_schedule->tol > 0, s);
+    if (st != MF_OK) return st;
+    if ((st = ensure_loss_workspace(p, s)) != MF_OK) return st;
+    const LossWs L = loss_ws(p);
+    const float* dd = d;
+    if ((st = plan_data(p, d, s, &dd)) != MF_OK) return st;
+    // band powers sigma_b = sum_{k in b} |s_k|^2 of the filtered image
+    if ((st = mf_band_power(p, s_wf, s_wf, L.power, stream)) != MF_OK) return st;
+    // pixel terms: N_eff^-1 (d - s) and the L2 term's s - s_true (the adjoint source)
+    std::map<std::pair<int, int>, size_t> part_off;
+    size_t off = 0;
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;
-        std::vector<mf::ItemDev> items;
-        for (int pid : kv.second)
-            if (grad_d || p->probs[pid].kind == MF_PK_BANDS) items.push_back({pid, 0, p->probs[pid].pix_off});
-        if (items.empty()) continue;
-        mf::ItemDev* di = nullptr;
-        if ((st = put_items(p, items, 0, s, &di)) != MF_OK) return st;
         mf::SweepArgs a = base_args(p, H, W);
-        a.items = di;
-        a.n_items = (int)items.size();
-        a.field = p->field.as<float2>();
-        if (grad_d) MF_HIP(mf::launch_grad_d(W, H, a, v, grad_d, s));
-        if (!grad_bands || p->total_bands <= 0) continue;
-        std::vector<mf::ItemDev> band_items;
-        for (auto& it : items)
-            if (p->probs[it.prob].kind == MF_PK_BANDS) band_items.push_back(it);
-        if (band_items.empty()) continue;
-        if (band_items.size() != items.size()) {
-            if ((st = put_items(p, band_items, 0, s, &di)) != MF_OK) return st;
-            a.items = di;
-            a.n_items = (int)band_items.size();
-        }
-        a.partials = p->partials.as<double>();
-        MF_HIP(mf::launch_band_power(W, H, a, v, s_wf, p->d_band, p->d_band_base, p->d_band_count,
-                                     p->d_band_scale, grad_bands, s));
+        if ((st = class_items(p, kv.first, 1, false, false, s, &a.items, &a.n_items)) != MF_OK) return st;
+        part_off[kv.first] = off;
+        MF_HIP(mf::launch_loss_terms(W, H, a, dd, s_wf, s_true, L.grad_s, L.grad_d, L.part + off, s));
+        off += (size_t)a.n_items * mf::kLossBlocks * 2;
     }
-    if ((st = data_gradient(p, grad_d, s)) != MF_OK) return st;
-    return conv;
+    mf_status conv = MF_OK;
+    if (grad_d || grad_bands) {
+        // implicit part: only the L2 term sends a gradient through s_W (the
+        // log-posterior part is stationary there)
+        conv = backward_impl(p, s_wf, L.grad_s, adjoint_schedule, grad_d, grad_bands, nullptr, info, s);
+        if (conv != MF_OK && conv != MF_ERR_NOT_CONVERGED) return conv;
+    }
+    if (grad_d) {
+        if ((st = data_gradient(p, L.grad_d, s)) != MF_OK) return st;
+        MF_HIP(mf::launch_add(L.grad_d, grad_d, p->total_px, s));
+    }
+    for (auto& kv : p->classes) {
+        mf::SweepArgs a = base_args(p, kv.first.first, kv.first.second);
+        if ((st = class_items(p, kv.first, 1, false, false, s, &a.items, &a.n_items)) != MF_OK) return st;
+        MF_HIP(mf::launch_loss_finish(a, L.part + part_off[kv.first], L.power, p->d_band_amps, p->d_band_modes,
+                                      p->d_band_base, p->d_band_count, loss_out, grad_bands, s));
+    }
+    if (conv != MF_OK) return fail(conv, "adjoint tolerance not reached within max_sweeps");
+    return MF_OK;
 }
 
 mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedule* sch, int32_t C,
@@ -1297,30 +1732,19 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
         for (int k = 0; k < sch->sweeps[j]; ++k) lam.push_back(sch->lambda[j]);
     const int K = (int)lam.size();
     const int ncp = (K + C - 1) / C;
-    MF_HIP(hipMemsetAsync(grad_d, 0, (size_t)p->total_px * sizeof(float), s));
-    if (grad_bands && p->total_bands > 0)
-        MF_HIP(hipMemsetAsync(grad_bands, 0, (size_t)p->total_bands * sizeof(double), s));
-    if (s_out) MF_HIP(hipMemsetAsync(s_out, 0, (size_t)p->total_px * sizeof(float), s));
+    MF_HIP(mf::launch_zero_words(grad_d, p->total_px, s));
+    if (grad_bands && p->total_bands > 0) MF_HIP(mf::launch_zero_words(grad_bands, 2 * (int64_t)p->total_bands, s));
+    if (s_out) MF_HIP(mf::launch_zero_words(s_out, p->total_px, s));
     if (K == 0) return MF_OK;  // s_K = s_0 = 0 does not depend on d or P
-    size_t max_items = 0;
-    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size());
-    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
-    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
+    if ((st = ensure_unrolled_workspace(p, K, C, s)) != MF_OK) return st;
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;
-        const int n_items = (int)kv.second.size();
-        const size_t n_cls = (size_t)n_items * H * W;
-        std::vector<mf::ItemDev> items;
-        for (int i = 0; i < n_items; ++i) items.push_back({kv.second[i], 0, (int64_t)i * H * W});
+        const size_t n_cls = (size_t)kv.second.size() * H * W;
         mf::ItemDev* di = nullptr;
-        if ((st = put_items(p, items, 0, s, &di)) != MF_OK) return st;
+        int n_items = 0;
+        if ((st = class_items(p, kv.first, 1, true, false, s, &di, &n_items)) != MF_OK) return st;
         const auto sh = class_shape(p, H, W);
-        const size_t n_tiles = (size_t)n_items * (W / sh.first);
-        MF_HIP(p->field.ensure(n_cls * sizeof(float2)));
-        MF_HIP(p->field_adj.ensure(n_cls * sizeof(float2)));
-        MF_HIP(p->ckpt.ensure((size_t)ncp * n_cls * sizeof(float2)));
-        MF_HIP(p->tstore.ensure((size_t)std::min(C, K) * n_cls * sizeof(float2)));
-        MF_HIP(p->slots.ensure(n_tiles * mf::kMaxBandsPerProblem * sizeof(double)));
+        const size_t n_tiles = (size_t)n_items * ((W + sh.first - 1) / sh.first);
         float2* F = p->field.as<float2>();
         float2* FA = p->field_adj.as<float2>();
         float2* ck = p->ckpt.as<float2>();
@@ -1341,7 +1765,7 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
         // ---- forward sweeps, keeping s_{jC}
         a.field = F;
         MF_HIP(mf::launch_load_real(W, H, a, nullptr, s));
-        MF_HIP(hipMemsetAsync(ck, 0, n_cls * sizeof(float2), s));
+        MF_HIP(mf::launch_zero_words(ck, 2 * (int64_t)n_cls, s));
         for (int k = 1; k <= K; ++k) {
             a.lambda = (float)lam[k - 1];
             a.pix_mode = mf::kPixUpdate;
@@ -1353,7 +1777,7 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
         MF_HIP(mf::launch_row(W, H, mf::kRowInv, a, s));
         if (s_out) MF_HIP(mf::launch_copy_out_real(W, H, a, s_out, s));
         // ---- reverse sweeps, each segment recomputed from its checkpoint
-        MF_HIP(hipMemsetAsync(p->slots.p, 0, n_tiles * mf::kMaxBandsPerProblem * sizeof(double), s));
+        MF_HIP(mf::launch_zero_words(p->slots.p, 2 * (int64_t)n_tiles * mf::kMaxBandsPerProblem, s));
         mf::SweepArgs b = a;
         b.field = FA;
         b.band_slots = p->slots.as<double>();
@@ -1411,7 +1835,7 @@ mf_status mf_shear_wiener(mf_plan p, const float* gamma, const mf_schedule* sch,
     int total = 0;
     for (int k : sw) total += k;
     if (total < 1) return fail(MF_ERR_INVALID_ARG, "the schedule runs no sweep");
-    return launch_shear(p, gamma, b_ratio, 1, lam, sw, 0, 0, 0, 0, 0, 1, nullptr, nullptr, nullptr, kappa_out,
+    return launch_shear(p, gamma, b_ratio, 1, lam, sw, 0, 0, 0, 0, 0, 1, nullptr, nullptr, nullptr, kappa_out, false,
                         (hipStream_t)stream);
 }
 
@@ -1430,7 +1854,7 @@ mf_status mf_shear_sample(mf_plan p, const float* gamma, const mf_shear_args* g,
     if (K == 0) return MF_OK;
     return launch_shear(p, gamma, g->b_ratio, g->chains_per_problem, {1.0}, {(int32_t)K}, 1, g->seed,
                         g->sweep_offset, g->burn_in, g->n_samples, g->thin, state_in, state_out, samples_out,
-                        nullptr, (hipStream_t)stream);
+                        nullptr, g->check_finite != 0, (hipStream_t)stream);
 }
 
 mf_status mf_sample_moments(mf_plan p, const float* samples, int32_t chains, int32_t n_samples, double* mean_out,
@@ -1438,7 +1862,8 @@ mf_status mf_sample_moments(mf_plan p, const float* samples, int32_t chains, int
     if (!p || !samples || !mean_out) return fail(MF_ERR_INVALID_ARG, "plan, samples and mean_out are required");
     if (chains < 1 || n_samples < 1) return fail(MF_ERR_INVALID_ARG, "need chains >= 1 and n_samples >= 1");
     hipStream_t s = (hipStream_t)stream;
-    MF_HIP(p->aux.ensure((size_t)p->total_px * 2 * sizeof(double)));
+    mf_status st = ws(p->aux, (size_t)p->total_px * 2 * sizeof(double), s);
+    if (st != MF_OK) return st;
     MF_HIP(mf::launch_moments(p->d_probs, (int)p->probs.size(), p->total_px, samples, (int64_t)chains * n_samples,
                               p->aux.as<double2>(), mean_out, var_out, s));
     return MF_OK;
@@ -1447,19 +1872,13 @@ mf_status mf_sample_moments(mf_plan p, const float* samples, int32_t chains, int
 mf_status mf_band_power(mf_plan p, const float* x, const float* y, double* out, mf_stream stream) {
     if (!p || !x || !y || !out) return fail(MF_ERR_INVALID_ARG, "plan, x, y and out are required");
     hipStream_t s = (hipStream_t)stream;
-    mf_status st = ensure_solve_workspace(p, s);
+    mf_status st = ensure_solve_workspace(p, false, s);
     if (st != MF_OK) return st;
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;
-        std::vector<mf::ItemDev> items;
-        for (int pid : kv.second)
-            if (p->probs[pid].kind == MF_PK_BANDS) items.push_back({pid, 0, p->probs[pid].pix_off});
-        if (items.empty()) continue;
-        mf::ItemDev* di = nullptr;
-        if ((st = put_items(p, items, 0, s, &di)) != MF_OK) return st;
         mf::SweepArgs a = base_args(p, H, W);
-        a.items = di;
-        a.n_items = (int)items.size();
+        if ((st = class_items(p, kv.first, 1, false, true, s, &a.items, &a.n_items)) != MF_OK) return st;
+        if (a.n_items == 0) continue;
         a.field = p->field.as<float2>();
         a.partials = p->partials.as<double>();
         MF_HIP(mf::launch_band_power(W, H, a, x, y, p->d_band, p->d_band_base, p->d_band_count, nullptr, out, s));
@@ -1470,129 +1889,19 @@ mf_status mf_band_power(mf_plan p, const float* x, const float* y, double* out, 
 mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const float* state_in, float* state_out,
                     float* samples_out, mf_stream stream) {
     if (!p || !d || !g) return fail(MF_ERR_INVALID_ARG, "plan, d and args are required");
-    if (g->chains_per_problem < 1 || g->burn_in < 0 || g->n_samples < 0 || g->thin < 1 || g->sweep_offset < 0)
-        return fail(MF_ERR_INVALID_ARG, "need chains >= 1, burn_in >= 0, n_samples >= 0, thin >= 1, sweep_offset >= 0");
-    if (g->sweep_offset + (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin > 0xffffffffLL)
-        return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
-    if (g->form < MF_FORM_AUTO || g->form > MF_FORM_PLAIN) return fail(MF_ERR_INVALID_ARG, "unknown form");
-    if (g->storage < MF_STORAGE_FP32 || g->storage > MF_STORAGE_BF16) return fail(MF_ERR_INVALID_ARG, "unknown storage");
-    int64_t n_cool = 0;
-    if (g->cooling) {
-        const mf_status sc = validate_schedule(g->cooling);
-        if (sc != MF_OK) return sc;
-        for (int j = 0; j < g->cooling->n_levels; ++j) n_cool += g->cooling->sweeps[j];
-        if (g->sweep_offset + n_cool + (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin > 0xffffffffLL)
-            return fail(MF_ERR_INVALID_ARG, "sweep index exceeds 2^32");
-    }
-    mf_sample_args gm = *g;  // the sampling phase after the cooling levels
-    gm.sweep_offset += n_cool;
-    gm.cooling = nullptr;
-    if (g->n_samples > 0 && !samples_out && !state_out)
-        return fail(MF_ERR_INVALID_ARG, "nothing to write: samples_out and state_out are NULL");
     hipStream_t s = (hipStream_t)stream;
-    {
-        const mf_status st0 = plan_data(p, d, s, &d);
-        if (st0 != MF_OK) return st0;
-    }
+    mf_status st = validate_sample(g, state_out, samples_out);
+    if (st != MF_OK) return st;
     const int pairs = (g->chains_per_problem + 1) / 2;
-    const size_t field_elems = (size_t)p->total_px * pairs;
-    float2* work;
-    if (state_out) {
-        work = reinterpret_cast<float2*>(state_out);
-    } else {
-        MF_HIP(p->field.ensure(field_elems * sizeof(float2)));
-        work = p->field.as<float2>();
-    }
-    const float2* sin = reinterpret_cast<const float2*>(state_in);
-    size_t max_items = 0;
-    bool any_persistent = false;
-    for (auto& kv : p->classes) {
-        max_items = std::max(max_items, kv.second.size() * (size_t)pairs);
-        const bool res = mf::resident_supported(kv.first.first, kv.first.second);
-        any_persistent |= g->form == MF_FORM_PERSISTENT || (g->form == MF_FORM_AUTO && res);
-    }
-    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
-    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
-    // reduced-precision storage: the streamed classes work in a 4-byte-per-element field
-    float2* hwork = nullptr;
-    if (g->storage != MF_STORAGE_FP32) {
-        MF_HIP(p->hfield.ensure(field_elems * 4));
-        hwork = p->hfield.as<float2>();
-    }
-    float4* pcoef = nullptr;
-    float2* psrc = nullptr;
-    float4* mcoef = nullptr;
-    if (any_persistent) {
-        const size_t half = (size_t)p->total_px / 2;
-        MF_HIP(p->coef.ensure(half * (sizeof(float4) + sizeof(float2) + sizeof(float4))));
-        pcoef = p->coef.as<float4>();
-        psrc = reinterpret_cast<float2*>(pcoef + half);
-        mcoef = reinterpret_cast<float4*>(psrc + half);
-        MF_HIP(mf::launch_sampler_coefs(p->d_probs, (int)p->probs.size(), d, p->d_nbar, p->d_nP, pcoef, psrc, mcoef,
-                                        s));
-    }
-    for (auto& kv : p->classes) {
-        const int H = kv.first.first, W = kv.first.second;
-        std::vector<mf::ItemDev> items;
-        for (int pid : kv.second)
-            for (int q = 0; q < pairs; ++q)
-                items.push_back({pid, q, (int64_t)pairs * p->probs[pid].pix_off + (int64_t)q * H * W});
-        int form = g->form;
-        if (form == MF_FORM_AUTO) form = mf::resident_supported(H, W) ? MF_FORM_PERSISTENT : MF_FORM_STREAMED;
-        mf::ItemDev* di = nullptr;
-        mf_status st = put_items(p, items, 0, s, &di);
-        if (st != MF_OK) return st;
-        if (form == MF_FORM_PERSISTENT && !mf::resident_supported(H, W))
-            return fail(MF_ERR_UNSUPPORTED_SIZE, "the persistent form needs H = W <= 128");
-        const float2* cin = sin;  // the state the sampling phase starts from
-        if (n_cool > 0) {
-            float2* cw = (form != MF_FORM_PERSISTENT && hwork) ? hwork : work;
-            st = cool_streamed(p, di, (int)items.size(), H, W, d, g, cw == hwork ? g->storage : MF_STORAGE_FP32, cw,
-                               sin, s);
-            if (st != MF_OK) return st;
-            cin = cw;
-        }
-        if (form == MF_FORM_PERSISTENT) {
-            mf::ResidentArgs r{};
-            r.probs = p->d_probs;
-            r.items = di;
-            r.n_items = (int)items.size();
-            r.field = work;
-            r.state_in = cin;
-            r.init_scale = g->init_scale;
-            r.pcoef = pcoef;
-            r.psrc = psrc;
-            r.mcoef = mcoef;
-            r.tw = p->d_tw.at(W);
-            r.key0 = (uint32_t)(g->seed & 0xffffffffu);
-            r.key1 = (uint32_t)(g->seed >> 32);
-            r.sweep0 = (uint32_t)gm.sweep_offset;
-            r.burn_in = g->burn_in;
-            r.n_samples = g->n_samples;
-            r.thin = g->thin;
-            r.samples = samples_out;
-            r.chains = g->chains_per_problem;
-            MF_HIP(mf::launch_resident_sample(H, r, s));
-        } else {
-            float2* w = hwork ? hwork : work;
-            if (form == MF_FORM_STREAMED) {
-                st = sample_streamed(p, di, (int)items.size(), H, W, d, &gm, w, cin, samples_out, s);
-            } else {  // plain: one chain pair per launch sequence
-                for (size_t i = 0; i < items.size() && st == MF_OK; ++i)
-                    st = sample_streamed(p, di + i, 1, H, W, d, &gm, w, cin, samples_out, s);
-            }
-            if (st == MF_OK && hwork && state_out) {  // final states widened to FP32
-                mf::SweepArgs a = base_args(p, H, W);
-                a.items = di;
-                a.n_items = (int)items.size();
-                a.field = hwork;
-                a.storage = g->storage;
-                MF_HIP(mf::launch_copy_out_pairs(W, H, a, work, s));
-            }
-        }
-        if (st != MF_OK) return st;
-    }
-    return MF_OK;
+    if ((st = ensure_sample_workspace(p, pairs, g->storage, g->form, !state_out, s)) != MF_OK) return st;
+    SampleWs w;
+    w.items = p->items.as<mf::ItemDev>();
+    w.items_cap = p->items.bytes / sizeof(mf::ItemDev);
+    w.coef = p->coef.as<float4>();
+    w.dprime = p->dprime.as<float>();
+    w.field = p->field.as<float2>();
+    w.hfield = p->hfield.as<float2>();
+    return sample_impl(p, d, g, state_in, state_out, samples_out, w, s);
 }
 
 mf_status mf_sample_spectrum(mf_plan p, const float* d, const mf_spectrum_args* g, const float* state_in,
@@ -1612,53 +1921,35 @@ mf_status mf_sample_spectrum(mf_plan p, const float* d, const mf_spectrum_args* 
         if (hp.kind != MF_PK_BANDS)
             return fail(MF_ERR_INVALID_ARG, "problem " + std::to_string(i) + " has no band spectrum");
     }
+    mf_status st0 = pow2_sides(p, "the hierarchical sampler");
+    if (st0 != MF_OK) return st0;
     hipStream_t s = (hipStream_t)stream;
-    {
-        const mf_status st0 = plan_data(p, d, s, &d);
-        if (st0 != MF_OK) return st0;
-    }
     const int pairs = (g->chains_per_problem + 1) / 2;
-    float2* work;
-    if (state_out) {
-        work = reinterpret_cast<float2*>(state_out);
-    } else {
-        MF_HIP(p->field.ensure((size_t)p->total_px * pairs * sizeof(float2)));
-        work = p->field.as<float2>();
-    }
-    // per-band degrees of freedom and start amplitudes
+    st0 = ensure_spectrum_workspace(p, pairs, !state_out, s);
+    if (st0 != MF_OK) return st0;
+    if ((st0 = plan_data(p, d, s, &d)) != MF_OK) return st0;
+    float2* work = state_out ? reinterpret_cast<float2*>(state_out) : p->field.as<float2>();
+    // degrees of freedom per band (modes + prior_dof, at least 0) on the
+    // device; the start amplitudes are the plan's
     const int nbt = p->total_bands;
     std::vector<int32_t> dof(nbt);
-    std::vector<double> th0(nbt);
     for (const HostProblem& hp : p->probs)
-        for (int b = 0; b < hp.n_bands; ++b) {
-            dof[hp.band_base + b] = std::max(0, hp.band_modes[b] + g->prior_dof);
-            th0[hp.band_base + b] = hp.amps[b];
-        }
-    MF_HIP(p->spec.ensure((size_t)nbt * (sizeof(double) + sizeof(int32_t))));
-    double* d_th0 = p->spec.as<double>();
-    int32_t* d_dof = reinterpret_cast<int32_t*>(d_th0 + nbt);
-    MF_HIP(hipMemcpyAsync(d_th0, th0.data(), (size_t)nbt * sizeof(double), hipMemcpyHostToDevice, s));
-    MF_HIP(hipMemcpyAsync(d_dof, dof.data(), (size_t)nbt * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        for (int b = 0; b < hp.n_bands; ++b) dof[hp.band_base + b] = std::max(0, hp.band_modes[b] + g->prior_dof);
+    int32_t* d_dof = p->spec.as<int32_t>();
+    MF_HIP(mf::launch_band_dof(p->d_band_modes, g->prior_dof, d_dof, nbt, s));
+    const double* d_th0 = p->d_band_amps;
     // pixel tables of the sampler (the pixel step does not depend on the spectrum)
     const size_t half = (size_t)p->total_px / 2;
-    MF_HIP(p->coef.ensure(half * (sizeof(float4) + sizeof(float2) + sizeof(float4))));
     float4* pcoef = p->coef.as<float4>();
     float2* psrc = reinterpret_cast<float2*>(pcoef + half);
     float4* mcoef = reinterpret_cast<float4*>(psrc + half);
     MF_HIP(mf::launch_sampler_coefs(p->d_probs, (int)p->probs.size(), d, p->d_nbar, p->d_nP, pcoef, psrc, mcoef, s));
-    size_t max_items = 0;
-    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size() * (size_t)pairs);
-    if (p->items.bytes < 2 * (max_items + 1) * sizeof(mf::ItemDev)) p->items_cached.clear();
-    MF_HIP(p->items.ensure(2 * (max_items + 1) * sizeof(mf::ItemDev)));
-    MF_HIP(hipStreamSynchronize(s));  // the host staging vectors die on return
+    if (g->check_finite) MF_HIP(mf::launch_fill_int(p->d_flag, INT32_MAX, 1, s));
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;
-        std::vector<mf::ItemDev> items;
-        for (int pid : kv.second)
-            for (int q = 0; q < pairs; ++q)
-                items.push_back({pid, q, (int64_t)pairs * p->probs[pid].pix_off + (int64_t)q * H * W});
         mf::ItemDev* di = nullptr;
-        mf_status st = put_items(p, items, 0, s, &di);
+        int n_items = 0;
+        mf_status st = class_items(p, kv.first, pairs, false, false, s, &di, &n_items);
         if (st != MF_OK) return st;
         if (!mf::resident_supported(H, W)) {
             int max_dof = 0;
@@ -1667,16 +1958,15 @@ mf_status mf_sample_spectrum(mf_plan p, const float* d, const mf_spectrum_args* 
                 for (int b = 0; b < p->probs[pid].n_bands; ++b) tot += dof[p->probs[pid].band_base + b];
                 max_dof = std::max(max_dof, tot);
             }
-            st = spectrum_streamed(p, di, (int)items.size(), H, W, max_dof, d, g, work,
+            st = spectrum_streamed(p, di, n_items, H, W, max_dof, d, g, work,
                                    reinterpret_cast<const float2*>(state_in), theta_in, theta_out, samples_out,
                                    theta_samples_out, d_dof, d_th0, s);
             if (st != MF_OK) return st;
-            continue;
-        }
+        } else {
         mf::SpectrumArgs r{};
         r.probs = p->d_probs;
         r.items = di;
-        r.n_items = (int)items.size();
+        r.n_items = n_items;
         r.field = work;
         r.state_in = reinterpret_cast<const float2*>(state_in);
         r.init_scale = g->init_scale;
@@ -1703,8 +1993,16 @@ mf_status mf_sample_spectrum(mf_plan p, const float* d, const mf_spectrum_args* 
         r.theta_samples = theta_samples_out;
         r.prior_beta = g->prior_beta;
         MF_HIP(mf::launch_resident_spectrum(H, r, s));
+        }
+        if (g->check_finite) {
+            mf::SweepArgs chk = base_args(p, H, W);
+            chk.items = di;
+            chk.n_items = n_items;
+            chk.field = work;
+            MF_HIP(mf::launch_finite_check(W, H, chk, p->d_flag, s));
+        }
     }
-    return MF_OK;
+    return g->check_finite ? read_finite_flag(p, s) : MF_OK;
 }
 
 }  // extern "C"

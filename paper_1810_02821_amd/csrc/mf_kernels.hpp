@@ -21,6 +21,16 @@ struct ItemDev {
     int64_t field_off;  // float2 offset of this item's field in the work buffer
 };
 
+// Cooling levels carried by value in the kernel arguments of the persistent
+// kernels (no device table to upload), so that a call that launches them can
+// be captured into a caller's graph.  Longer schedules run in several launches.
+constexpr int kMaxLevels = 128;
+struct Levels {
+    double lambda[kMaxLevels];
+    int32_t sweeps[kMaxLevels];
+    int32_t n;
+};
+
 // What the right-hand side pointer holds.
 enum SrcKind : int32_t {
     kSrcData = 0,   // b = N_eff^-1 d, pixel source a * d
@@ -111,5 +121,34 @@ constexpr int kMaxBandsPerProblem = 64;
 hipError_t launch_band_power(int W, int H, const SweepArgs& a, const float* x, const float* y,
                              const int16_t* band, const int32_t* band_base, const int32_t* band_count,
                              const double* scale, double* out, hipStream_t s);
+
+// Work lists built on the device: item i = (pids[i / per], i % per,
+// field_off), field_off = per * pix_off + (i % per) * hw, or i * hw with
+// `local` (a field of the class's items only).
+hipError_t launch_fill_items(ItemDev* out, const ProbDev* probs, const int32_t* pids, int n_pids, int per,
+                             int local, int64_t hw, hipStream_t s);
+// Zero n 4-byte words (a kernel, so that captured graphs hold no memset node).
+hipError_t launch_zero_words(void* p, int64_t n_words, hipStream_t s);
+// flag[0] = min(flag[0], problem) for every item whose field (H x W elements
+// of the given storage) holds a NaN or an infinity.
+hipError_t launch_finite_check(int W, int H, const SweepArgs& a, int32_t* flag, hipStream_t s);
+hipError_t launch_fill_int(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// Loss terms of a band-spectrum problem at s (one item per problem, d and s
+// concatenated, d already divided by the response): per item FP64 partial
+// sums of N_eff^-1 (d - s)^2 and (s - s_true)^2 into part[item][block][2],
+// grad_s = s - s_true and grad_d = N_eff^-1 (d - s) (both concatenated).
+constexpr int kLossBlocks = 64;
+hipError_t launch_loss_terms(int W, int H, const SweepArgs& a, const float* d, const float* s_wf,
+                             const float* s_true, float* grad_s, float* grad_d, double* part, hipStream_t s);
+// loss[prob] = sum of the item's partials / 2 + the band terms
+// 1/2 sum_b (power_b / (n^2 theta_b) + m_b ln(n theta_b)); grad_bands[b] +=
+// -1/2 power_b / (n^2 theta_b^2) + m_b / (2 theta_b).
+hipError_t launch_loss_finish(const SweepArgs& a, const double* part, const double* power, const double* amps,
+                              const int32_t* band_modes, const int32_t* band_base, const int32_t* band_count,
+                              double* loss, double* grad_bands, hipStream_t s);
+// dof[b] = max(0, modes[b] + prior_dof) for b < n.
+hipError_t launch_band_dof(const int32_t* modes, int32_t prior_dof, int32_t* dof, int n, hipStream_t s);
+// y[i] += x[i] (float) for i < n.
+hipError_t launch_add(const float* x, float* y, int64_t n, hipStream_t s);
 
 }  // namespace mf

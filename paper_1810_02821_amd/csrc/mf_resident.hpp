@@ -39,10 +39,9 @@ struct SolveArgs {
     const float* nbar;        // concatenated Nbar (+inf missing)
     const float* nP;          // concatenated n P(|k|)
     const float2* tw;         // W_N^r, r < N
-    const double* lambda;     // [n_levels] cooling levels
-    const int32_t* sweeps;    // [n_levels] sweeps per level
-    int32_t n_levels;
-    double tol;               // residual tolerance of the final level (<= 0: none)
+    Levels lv;                // cooling levels of this launch
+    int32_t total0;           // sweeps run by earlier launches of the same solve
+    double tol;               // residual tolerance of the final level (<= 0: none; only in the last launch)
     int32_t max_sweeps;
     int32_t check_every;
     double* info;             // [item][3]: sweeps run, converged (1, 0, or -1 non-finite), last residual

@@ -156,9 +156,9 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_shear_kernel(ShearArgs
     }
 
     int64_t k = 0;
-    for (int lv = 0; lv < a.n_levels; ++lv) {
-        const float T = (float)(a.lambda[lv] * (double)pr.tau);
-        for (int s = 0; s < a.level_sweeps[lv]; ++s, ++k) {
+    for (int lv = 0; lv < a.lv.n; ++lv) {
+        const float T = (float)(a.lv.lambda[lv] * (double)pr.tau);
+        for (int s = 0; s < a.lv.sweeps[lv]; ++s, ++k) {
             const uint32_t sweep = a.sweep0 + (uint32_t)k;
             const float2* tw = twl + per_sweep_zero();
             unsigned t = tid;
@@ -194,7 +194,7 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_shear_kernel(ShearArgs
             unsigned t2 = tid;
             asm volatile("" : "+v"(t2));
             harmonic_shear<N>(v, lds, a, pr, T, sweep, it.pair, t2);
-            const bool last = lv == a.n_levels - 1 && s == a.level_sweeps[lv] - 1;
+            const bool last = lv == a.lv.n - 1 && s == a.lv.sweeps[lv] - 1;
             const bool emit = a.samples && k >= a.burn_in && ((k - a.burn_in + 1) % a.thin) == 0;
             if (emit || (last && a.kappa_out)) {
                 // kappa = F^-1 kappa^, written out, then transformed back

@@ -20,9 +20,7 @@ struct ShearArgs {
     uint32_t key0, key1;
     uint32_t sweep0;          // global index of the first sweep
     int32_t stochastic;       // 1: sampler, 0: Wiener filter
-    const double* lambda;     // [n_levels] cooling levels
-    const int32_t* level_sweeps;
-    int32_t n_levels;
+    Levels lv;                // cooling levels (by value)
     int32_t burn_in, n_samples, thin;
     float2* samples;          // [problem][chain][sample][H][W] kappa, or null
     int32_t chains;

@@ -107,10 +107,10 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_solve_kernel(SolveArgs
         return check ? block_sum<NT>(acc, red) : 0.0;
     };
 
-    int total = 0;
-    for (int lv = 0; lv < a.n_levels; ++lv) {
-        const float lam = (float)a.lambda[lv];
-        for (int k = 0; k < a.sweeps[lv]; ++k) {
+    int total = a.total0;
+    for (int lv = 0; lv < a.lv.n; ++lv) {
+        const float lam = (float)a.lv.lambda[lv];
+        for (int k = 0; k < a.lv.sweeps[lv]; ++k) {
             sweep(lam, false, false);
             ++total;
         }
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_solve_kernel(SolveArgs
     double residual = __builtin_nan("");
     int converged = a.tol > 0 ? 0 : 1;
     if (a.tol > 0) {
-        const double lam = a.lambda[a.n_levels - 1];
+        const double lam = a.lv.lambda[a.lv.n - 1];
         const double T = lam * (double)pr.tau;
         // ||b||^2 with b = N_eff^-1 d (data) or g (gradient) at the final level
         double bb = 0.0;

@@ -14,6 +14,8 @@
 // and so becomes an FMA, depends on the kernel), and a run split into several
 // calls reproduces the uninterrupted run bit for bit.
 #pragma clang fp contract(on)
+#include <type_traits>
+
 #include "mf_device.hpp"
 #include "mf_kernels.hpp"
 #include "mf_streamed_fft.hpp"
@@ -85,10 +87,21 @@ struct RowShapeF {
     static constexpr int TPR = kThreads / ROWS;
 };
 
+constexpr int pow2_floor(int v) {
+    int q = 1;
+    while (2 * q <= v) q *= 2;
+    return q;
+}
+// Rows per block of the plain row kernels: a power of two, about 2048 pixels.
+constexpr int rows_per_block(int L) { return L >= 2048 ? 1 : pow2_floor(2048 / L); }
+
 template <int L>
 struct RowShape {
-    static constexpr int ROWS = (2048 / L) < 1 ? 1 : (2048 / L);  // rows per block
-    static constexpr int TPR = kThreads / ROWS;                   // threads per row
+    static constexpr int ROWS = rows_per_block(L);  // rows per block
+    static constexpr int TPR = kThreads / ROWS;     // threads per row
+    static constexpr int LS = lds_stride<L>();      // LDS row stride
+    static constexpr int NE = ROWS * L;             // pixels per block
+    static constexpr int NL = (NE + kThreads - 1) / kThreads;  // load / store iterations
 };
 
 // Rows of all work items are enumerated with the item index fastest,
@@ -100,8 +113,10 @@ template <int L, int MODE>
 __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     constexpr int ROWS = RowShape<L>::ROWS;
     constexpr int TPR = RowShape<L>::TPR;
+    constexpr int LS = RowShape<L>::LS;
+    constexpr int NE = RowShape<L>::NE;
     constexpr int W = L;
-    __shared__ float2 lds[ROWS * L];
+    __shared__ float2 lds[ROWS * LS];
     __shared__ double red[kThreads];
 
     // (item, row) of each of the block's rows, one division per row
@@ -124,12 +139,13 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
         using E = decltype(e0);
         const E* fld = reinterpret_cast<const E*>(a.field);
 #pragma unroll
-        for (int i = 0; i < ROWS * L / kThreads; ++i) {
+        for (int i = 0; i < RowShape<L>::NL; ++i) {
             const unsigned e = tid + i * kThreads;
+            if (NE % kThreads != 0 && e >= (unsigned)NE) break;
             const unsigned r = e / L, x = e % L;
             float2 v = make_float2(0.f, 0.f);
             if (row_item[r] >= 0) v = widen(fld[a.items[row_item[r]].field_off + (int64_t)row_y[r] * W + x]);
-            lds[r * L + swz(x)] = v;
+            lds[r * LS + swz(x)] = v;
         }
     });
     __syncthreads();
@@ -139,7 +155,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
     const int y = row_y[rid];
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
-    float2* row = lds + rid * L;
+    float2* row = lds + rid * LS;
 
     if constexpr (MODE & kRowInv) {
         row_inverse<L, TPR>(row, lane, a.tw_row);
@@ -474,30 +490,42 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
 // is its own LDS segment of L + 32/TC elements (the tile load then hits
 // distinct banks).  The default shape fills at most ~128 KiB of LDS; the
 // autotuner may pick another feasible (TC, NTH).
+// Default tile of a column length (16 columns, 8 from 1025 rows so that the
+// tile fits in LDS) and its threads.
+constexpr int col_tc_of(int L) { return L > 1024 ? 8 : 16; }
+constexpr int col_nth_of(int L) { return L >= 1024 ? 1024 : (L >= 512 ? 512 : 256); }
+
 template <int L>
 struct ColShape {
-    static constexpr int TC = L >= 2048 ? 8 : 16;
-    static constexpr int NTH = L >= 1024 ? 1024 : (L >= 512 ? 512 : 256);
+    static constexpr int TC = col_tc_of(L);
+    static constexpr int NTH = col_nth_of(L);
     static constexpr int TPC = NTH / TC;
-    static constexpr int SEG = L + 32 / TC;
+    static constexpr int SEG = lds_stride<L>() + 32 / TC;
 };
+
+// Column tiles of an item: W / TC, or one more ragged tile when TC does not
+// divide W (sides 2^a 3^b); a ragged tile's missing columns are transformed
+// as zeros and never stored.
+__device__ __forceinline__ int tiles_per_item(int W, int tc) { return (W + tc - 1) / tc; }
 
 template <int L, int TC_, int NTH_>
 __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     constexpr int TC = TC_;
     constexpr int NTH = NTH_;
     constexpr int TPC = NTH / TC;
-    constexpr int SEG = L + 32 / TC;
+    constexpr int SEG = lds_stride<L>() + 32 / TC;
     constexpr int H = L;
     __shared__ float2 lds[TC * SEG];
     __shared__ float2 twl[L];  // twiddles in LDS (as in col_kernel_f; identical values)
     const unsigned tid = threadIdx.x;
-    // tiles enumerated with the tile fastest: t = item * (W / TC) + tile.  An
+    // tiles enumerated with the tile fastest: t = item * tiles + tile.  An
     // XCD then runs neighbouring tiles of one item together, and the cache
     // lines they share (a 128-byte line spans 16 columns) meet in its L2.
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);
-    const int item = (int)(t / (W / TC));
-    const int x0 = (int)(t % (W / TC)) * TC;
+    const int tpi = tiles_per_item(W, TC);
+    const int item = (int)(t / tpi);
+    const int x0 = (int)(t % tpi) * TC;
+    const unsigned ncol = (unsigned)min(TC, W - x0);  // columns of this tile
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
     const int64_t f0 = it.field_off + x0;
@@ -509,7 +537,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
 #pragma unroll 4
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
             const unsigned c = e % TC, y = e / TC;
-            lds[c * SEG + swz(y)] = widen(fld[(int64_t)y * W + c]);
+            lds[c * SEG + swz(y)] = c < ncol ? widen(fld[(int64_t)y * W + c]) : make_float2(0.f, 0.f);
         }
     });
     __syncthreads();
@@ -520,7 +548,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     if (a.t_store) {
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
             const unsigned c = e % TC, y = e / TC;
-            a.t_store[it.field_off + (int64_t)y * W + x0 + c] = lds[c * SEG + swz(y)];
+            if (c < ncol) a.t_store[it.field_off + (int64_t)y * W + x0 + c] = lds[c * SEG + swz(y)];
         }
     }
     if (a.t_load) {
@@ -531,6 +559,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
         __syncthreads();
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
             const unsigned c = e % TC, y = e / TC;
+            if (c >= ncol) continue;
             const int64_t mode = (int64_t)y * W + x0 + c;
             const int b = a.band[pr.pix_off + mode];
             if (b < 0) continue;
@@ -551,6 +580,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
 #pragma unroll 1
     for (unsigned e = tid; e < (unsigned)((TC / 2) * L); e += NTH) {
         const unsigned j = e % (TC / 2), ky = e / (TC / 2);
+        if (2 * j >= ncol) continue;  // W is even, so column pairs are whole
         const int kx = x0 + 2 * j;
         const int64_t mode = (int64_t)ky * W + kx;
         const float2 np = *reinterpret_cast<const float2*>(a.nP + pr.pix_off + mode);
@@ -586,7 +616,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
 #pragma unroll 4
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
             const unsigned c = e % TC, y = e / TC;
-            fld[(int64_t)y * W + c] = narrow<E>(lds[c * SEG + swz(y)]);
+            if (c < ncol) fld[(int64_t)y * W + c] = narrow<E>(lds[c * SEG + swz(y)]);
         }
     });
 }
@@ -932,22 +962,26 @@ template <int L>
 __global__ __launch_bounds__(kThreads) void row_fft_kernel(SweepArgs a, int H) {
     constexpr int ROWS = RowShape<L>::ROWS;
     constexpr int TPR = RowShape<L>::TPR;
-    __shared__ float2 lds[ROWS * L];
+    constexpr int LS = RowShape<L>::LS;
+    constexpr int NE = RowShape<L>::NE;
+    __shared__ float2 lds[ROWS * LS];
     const unsigned tid = threadIdx.x;
     const int64_t total_rows = (int64_t)a.n_items * H;
     const int64_t grow0 = (int64_t)blockIdx.x * ROWS;
-    for (int i = 0; i < ROWS * L / kThreads; ++i) {
+    for (int i = 0; i < RowShape<L>::NL; ++i) {
         const unsigned e = tid + i * kThreads;
+        if (e >= (unsigned)NE) break;
         const int64_t gr = grow0 + e / L;
-        lds[(e / L) * L + swz(e % L)] =
+        lds[(e / L) * LS + swz(e % L)] =
             gr < total_rows ? a.field[a.items[gr / H].field_off + (gr % H) * L + e % L] : make_float2(0.f, 0.f);
     }
     __syncthreads();
-    stockham_fft<L, 1, TPR, false>(lds + (tid / TPR) * L, tid % TPR, a.tw_row);
-    for (int i = 0; i < ROWS * L / kThreads; ++i) {
+    stockham_fft<L, 1, TPR, false>(lds + (tid / TPR) * LS, tid % TPR, a.tw_row);
+    for (int i = 0; i < RowShape<L>::NL; ++i) {
         const unsigned e = tid + i * kThreads;
+        if (e >= (unsigned)NE) break;
         const int64_t gr = grow0 + e / L;
-        if (gr < total_rows) a.field[a.items[gr / H].field_off + (gr % H) * L + e % L] = lds[(e / L) * L + swz(e % L)];
+        if (gr < total_rows) a.field[a.items[gr / H].field_off + (gr % H) * L + e % L] = lds[(e / L) * LS + swz(e % L)];
     }
 }
 
@@ -959,13 +993,17 @@ __global__ __launch_bounds__(ColShape<L>::NTH) void col_fft_kernel(SweepArgs a, 
     constexpr int SEG = ColShape<L>::SEG;
     __shared__ float2 lds[TC * SEG];
     const unsigned tid = threadIdx.x;
-    const int64_t gc0 = (int64_t)blockIdx.x * TC;
-    const ItemDev it = a.items[gc0 / W];
-    float2* fld = a.field + it.field_off + gc0 % W;
-    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) lds[(e % TC) * SEG + swz(e / TC)] = fld[(int64_t)(e / TC) * W + e % TC];
+    const int tpi = tiles_per_item(W, TC);
+    const int x0 = (int)(blockIdx.x % tpi) * TC;
+    const unsigned ncol = (unsigned)min(TC, W - x0);
+    const ItemDev it = a.items[blockIdx.x / tpi];
+    float2* fld = a.field + it.field_off + x0;
+    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH)
+        lds[(e % TC) * SEG + swz(e / TC)] = e % TC < ncol ? fld[(int64_t)(e / TC) * W + e % TC] : make_float2(0.f, 0.f);
     __syncthreads();
     stockham_fft<L, 1, TPC, false>(lds + (tid / TPC) * SEG, tid % TPC, a.tw_col);
-    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) fld[(int64_t)(e / TC) * W + e % TC] = lds[(e % TC) * SEG + swz(e / TC)];
+    for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH)
+        if (e % TC < ncol) fld[(int64_t)(e / TC) * W + e % TC] = lds[(e % TC) * SEG + swz(e / TC)];
 }
 
 // Per-block, per-band partial sums of Re(conj(X_k) Y_k) with X = (Z_k + conj Z_-k)/2,
@@ -1024,28 +1062,144 @@ __global__ void load_real_kernel(SweepArgs a, int H, int W, const float* s_init)
     }
 }
 
-// Launch KERNEL<L>(args...) for the supported transform lengths.
-#define MF_DISPATCH(L, KERNEL, GRID, BLOCK, STREAM, ...)                                     \
-    switch (L) {                                                                             \
-        case 16: hipLaunchKernelGGL(KERNEL<16>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;     \
-        case 32: hipLaunchKernelGGL(KERNEL<32>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;     \
-        case 64: hipLaunchKernelGGL(KERNEL<64>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;     \
-        case 128: hipLaunchKernelGGL(KERNEL<128>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;   \
-        case 256: hipLaunchKernelGGL(KERNEL<256>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;   \
-        case 512: hipLaunchKernelGGL(KERNEL<512>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break;   \
-        case 1024: hipLaunchKernelGGL(KERNEL<1024>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-        case 2048: hipLaunchKernelGGL(KERNEL<2048>, GRID, BLOCK, 0, STREAM, __VA_ARGS__); break; \
-        default: return hipErrorInvalidValue;                                                \
+// ------------------------------------------------------ plan plumbing --
+__global__ void fill_items_kernel(ItemDev* out, const ProbDev* probs, const int32_t* pids, int n, int per, int local,
+                                  int64_t hw) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const int pid = pids[i / per];
+        const int q = i % per;
+        out[i] = ItemDev{pid, q, local ? (int64_t)i * hw : (int64_t)per * probs[pid].pix_off + (int64_t)q * hw};
     }
+}
+
+__global__ void zero_words_kernel(uint32_t* p, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = 0u;
+}
+
+__global__ void fill_int_kernel(int32_t* p, int32_t v, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        p[e] = v;
+}
+
+__global__ void band_dof_kernel(const int32_t* modes, int32_t prior_dof, int32_t* dof, int n) {
+    for (int b = blockIdx.x * blockDim.x + threadIdx.x; b < n; b += gridDim.x * blockDim.x)
+        dof[b] = max(0, modes[b] + prior_dof);
+}
+
+__global__ void add_kernel(const float* x, float* y, int64_t n) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
+        y[e] += x[e];
+}
+
+// One block per item: any NaN or infinity in the item's field lowers the
+// flag to the item's problem index.
+__global__ void finite_check_kernel(SweepArgs a, int64_t n, int32_t* flag) {
+    const ItemDev it = a.items[blockIdx.x];
+    bool bad = false;
+    with_storage(a.storage, [&](auto e0) {
+        using E = decltype(e0);
+        const E* fld = reinterpret_cast<const E*>(a.field) + it.field_off;
+        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+            const float2 v = widen(fld[i]);
+            bad |= !(isfinite(v.x) && isfinite(v.y));
+        }
+    });
+    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicMin(flag, it.prob);
+}
+
+// Loss terms per item (one item per problem, real fields).
+__global__ __launch_bounds__(kThreads) void loss_terms_kernel(SweepArgs a, int64_t n, const float* d,
+                                                              const float* s_wf, const float* s_true, float* grad_s,
+                                                              float* grad_d, double* part) {
+    __shared__ double red[2][kThreads];
+    const ItemDev it = a.items[blockIdx.y];
+    const ProbDev pr = a.probs[it.prob];
+    double lik = 0.0, l2 = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n; i += (int64_t)gridDim.x * kThreads) {
+        const int64_t g = pr.pix_off + i;
+        const float nb = a.nbar[g];
+        const float sv = s_wf[g];
+        const float e = sv - s_true[g];
+        // N_eff^-1 (d - s) with N_eff = Nbar + tau; 0 on missing pixels (Nbar = +inf)
+        const double r = isinf(nb) ? 0.0 : ((double)d[g] - (double)sv) / ((double)nb + (double)pr.tau);
+        lik += r * ((double)d[g] - (double)sv);
+        l2 += (double)e * (double)e;
+        grad_s[g] = e;
+        grad_d[g] = (float)r;
+    }
+    red[0][threadIdx.x] = lik;
+    red[1][threadIdx.x] = l2;
+    __syncthreads();
+    for (int w = kThreads / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) {
+            red[0][threadIdx.x] += red[0][threadIdx.x + w];
+            red[1][threadIdx.x] += red[1][threadIdx.x + w];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        double* o = part + ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * 2;
+        o[0] = red[0][0];
+        o[1] = red[1][0];
+    }
+}
+
+__global__ void loss_finish_kernel(SweepArgs a, const double* part, int nblocks, const double* power,
+                                   const double* amps, const int32_t* band_modes, const int32_t* band_base,
+                                   const int32_t* band_count, double* loss, double* grad_bands) {
+    __shared__ double red[64];
+    const ItemDev it = a.items[blockIdx.x];
+    const ProbDev pr = a.probs[it.prob];
+    const double n = (double)pr.H * (double)pr.W;
+    const int base = band_base[it.prob], cnt = band_count[it.prob];
+    double acc = 0.0;
+    for (int k = threadIdx.x; k < nblocks; k += blockDim.x) {
+        const double* o = part + ((int64_t)blockIdx.x * nblocks + k) * 2;
+        acc += 0.5 * (o[0] + o[1]);
+    }
+    for (int b = threadIdx.x; b < cnt; b += blockDim.x) {
+        const double th = amps[base + b], pw = power[base + b], m = (double)band_modes[base + b];
+        acc += 0.5 * (pw / (n * n * th) + m * log(n * th));
+        if (grad_bands) grad_bands[base + b] += -0.5 * pw / (n * n * th * th) + 0.5 * m / th;
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = 32; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[it.prob] = red[0];
+}
+
+// The transform lengths: powers of two (every kernel) and the other even
+// 2^a 3^b in [16, 2048] (the plain row and column kernels and the helpers).
+template <int... Ls>
+struct Lengths {};
+using Pow2Lengths = Lengths<16, 32, 64, 128, 256, 512, 1024, 2048>;
+using MixedLengths = Lengths<18, 24, 36, 48, 54, 72, 96, 108, 144, 162, 192, 216, 288, 324, 384, 432, 486, 576,
+                             648, 768, 864, 972, 1152, 1296, 1458, 1536, 1728, 1944>;
+
+// Call f(std::integral_constant<int, L>) for the length L of the list; false
+// if L is not in it.
+template <typename F, int... Ls>
+bool with_length(int L, Lengths<Ls...>, F&& f) {
+    return ((L == Ls ? (f(std::integral_constant<int, Ls>{}), true) : false) || ...);
+}
+template <typename F>
+bool with_any_length(int L, F&& f) {
+    return with_length(L, Pow2Lengths{}, f) || with_length(L, MixedLengths{}, f);
+}
 
 template <int MODE>
 hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
-    int rows = 2048 / W;
-    if (rows < 1) rows = 1;
+    const int rows = rows_per_block(W);
     const int64_t total = (int64_t)a.n_items * H;
     dim3 grid((unsigned)((total + rows - 1) / rows));
-    // middle sweeps of the sampler and the Wiener iteration on rows of 256 and more
-    const bool fused = MODE == kRowInvFwd && W >= 256 && a.pix_mode == kPixUpdate && !a.s_save && !a.plain_kernels;
+    // middle sweeps of the sampler and the Wiener iteration on rows of 256 and
+    // more (powers of two)
+    const bool fused = MODE == kRowInvFwd && W >= 256 && is_pow2(W) && a.pix_mode == kPixUpdate && !a.s_save &&
+                       !a.plain_kernels;
     if (fused) {
         const int rows_f = W == 512 ? 8 : 2048 / W;
         const dim3 grid((unsigned)((total + rows_f - 1) / rows_f));
@@ -1058,19 +1212,13 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
         }
         return hipGetLastError();
     }
-    switch (W) {
-#define MF_CASE(N) \
-    case N: hipLaunchKernelGGL((row_kernel<N, MODE>), grid, dim3(kThreads), 0, s, a, H); break;
-        MF_CASE(16) MF_CASE(32) MF_CASE(64) MF_CASE(128) MF_CASE(256) MF_CASE(512) MF_CASE(1024) MF_CASE(2048)
-#undef MF_CASE
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
+    const bool ok = with_any_length(W, [&](auto c) {
+        constexpr int N = decltype(c)::value;
+        hipLaunchKernelGGL((row_kernel<N, MODE>), grid, dim3(kThreads), 0, s, a, H);
+    });
+    return ok ? hipGetLastError() : hipErrorInvalidValue;
 }
 
-// Shape of ColShape<H> (the column-FFT kernel's tile).
-int col_tc(int H) { return H >= 2048 ? 8 : 16; }
-int col_threads(int H) { return H >= 1024 ? 1024 : (H >= 512 ? 512 : 256); }
 
 dim3 elementwise_grid(int64_t total) {
     int64_t b = (total + 255) / 256;
@@ -1082,8 +1230,7 @@ dim3 elementwise_grid(int64_t total) {
 }  // namespace
 
 int row_blocks_per_item(int W, int H) {
-    int rows = 2048 / W;
-    if (rows < 1) rows = 1;
+    const int rows = rows_per_block(W);
     return (H + rows - 1) / rows;
 }
 
@@ -1098,35 +1245,45 @@ hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_
 
 #define MF_COL_CASE(LL, TCC, NN)                                                              \
     if (H == LL && tc == TCC && nth == NN) {                                                   \
-        hipLaunchKernelGGL((col_kernel_t<LL, TCC, NN>), dim3((unsigned)(cols / TCC)), dim3(NN), 0, s, a, W); \
+        hipLaunchKernelGGL((col_kernel_t<LL, TCC, NN>), grid, dim3(NN), 0, s, a, W);           \
         return hipGetLastError();                                                              \
     }
 // H >= 256 without the gradient's stored transforms: the fused kernel
 #define MF_COL_CASE_F(LL, TCC, NN)                                                            \
     if (H == LL && tc == TCC && nth == NN) {                                                   \
         if (fused)                                                                             \
-            hipLaunchKernelGGL((col_kernel_f<LL, TCC, NN>), dim3((unsigned)(cols / TCC)), dim3(NN), 0, s, a, W); \
+            hipLaunchKernelGGL((col_kernel_f<LL, TCC, NN>), grid, dim3(NN), 0, s, a, W);       \
         else                                                                                   \
-            hipLaunchKernelGGL((col_kernel_t<LL, TCC, NN>), dim3((unsigned)(cols / TCC)), dim3(NN), 0, s, a, W); \
+            hipLaunchKernelGGL((col_kernel_t<LL, TCC, NN>), grid, dim3(NN), 0, s, a, W);       \
         return hipGetLastError();                                                              \
     }
 
 hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, hipStream_t s) {
-    if (tc > W || tc < 2) return hipErrorInvalidValue;
-    const int64_t cols = (int64_t)a.n_items * W;
+    if (tc < 2) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)((int64_t)a.n_items * ((W + tc - 1) / tc)));
     const bool fused = !a.t_store && !a.t_load && a.nPt && !a.plain_kernels;
     MF_COL_CASE(16, 16, 256) MF_COL_CASE(32, 16, 256) MF_COL_CASE(64, 16, 256) MF_COL_CASE(128, 16, 256)
     MF_COL_CASE_F(256, 16, 256) MF_COL_CASE_F(256, 8, 256) MF_COL_CASE_F(256, 16, 512) MF_COL_CASE_F(256, 8, 512)
     MF_COL_CASE_F(512, 16, 512) MF_COL_CASE_F(512, 8, 512) MF_COL_CASE_F(512, 16, 256) MF_COL_CASE_F(512, 16, 1024)
     MF_COL_CASE_F(1024, 16, 1024) MF_COL_CASE_F(1024, 8, 1024) MF_COL_CASE_F(1024, 8, 512) MF_COL_CASE_F(1024, 16, 512)
     MF_COL_CASE_F(2048, 8, 1024) MF_COL_CASE_F(2048, 8, 512) MF_COL_CASE_F(2048, 4, 512) MF_COL_CASE_F(2048, 4, 256)
-    return hipErrorInvalidValue;
+    // the other 2^a 3^b lengths: the plain kernel in its default tile
+    bool launched = false;
+    const bool ok = with_length(H, MixedLengths{}, [&](auto c) {
+        constexpr int N = decltype(c)::value;
+        if (tc == col_tc_of(N) && nth == col_nth_of(N)) {
+            hipLaunchKernelGGL((col_kernel_t<N, col_tc_of(N), col_nth_of(N)>), grid, dim3(col_nth_of(N)), 0, s, a, W);
+            launched = true;
+        }
+    });
+    return ok && launched ? hipGetLastError() : hipErrorInvalidValue;
 }
 #undef MF_COL_CASE
 #undef MF_COL_CASE_F
 
 // Tile shapes per column length; the first one for a length is its default
-// (the autotuner's choice on MI355X for the sampler's column kernel).
+// (the autotuner's choice on MI355X for the sampler's column kernel).  The
+// lengths with a factor 3 have their one default tile.
 int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
     static const int table[][3] = {{16, 16, 256}, {32, 16, 256}, {64, 16, 256}, {128, 16, 256},
                                    {256, 16, 256}, {256, 8, 256}, {256, 16, 512}, {256, 8, 512},
@@ -1140,13 +1297,19 @@ int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
             nth[n] = r[2];
             ++n;
         }
+    if (n == 0 && max_n > 0 && !is_pow2(H)) {
+        tc[0] = col_tc_of(H);
+        nth[0] = col_nth_of(H);
+        n = 1;
+    }
     return n;
 }
 
 hipError_t launch_band_slots_reduce(int W, int H, int tc, const SweepArgs& a, const int32_t* band_base,
                                     const int32_t* band_count, double* out, hipStream_t s) {
     (void)H;
-    hipLaunchKernelGGL(band_slots_reduce_kernel, dim3(a.n_items), dim3(64), 0, s, a, W / tc, band_base, band_count,
+    hipLaunchKernelGGL(band_slots_reduce_kernel, dim3(a.n_items), dim3(64), 0, s, a, (W + tc - 1) / tc, band_base,
+                       band_count,
                        out);
     return hipGetLastError();
 }
@@ -1208,18 +1371,78 @@ hipError_t launch_band_power(int W, int H, const SweepArgs& a, const float* x, c
                              const double* scale, double* out, hipStream_t s) {
     hipLaunchKernelGGL(pack_pair_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a, H, W,
                        x, y);
-    int rows = 2048 / W;
-    if (rows < 1) rows = 1;
+    const int rows = rows_per_block(W);
     const int64_t total_rows = (int64_t)a.n_items * H;
-    MF_DISPATCH(W, row_fft_kernel, dim3((unsigned)((total_rows + rows - 1) / rows)), dim3(kThreads), s, a, H);
-    const int tc = col_tc(H);
-    MF_DISPATCH(H, col_fft_kernel, dim3((unsigned)((int64_t)a.n_items * W / tc)), dim3(col_threads(H)), s, a, W);
+    const dim3 rgrid((unsigned)((total_rows + rows - 1) / rows));
+    if (!with_any_length(W, [&](auto c) {
+            hipLaunchKernelGGL(row_fft_kernel<decltype(c)::value>, rgrid, dim3(kThreads), 0, s, a, H);
+        }))
+        return hipErrorInvalidValue;
+    const int tc = col_tc_of(H);
+    const dim3 cgrid((unsigned)((int64_t)a.n_items * ((W + tc - 1) / tc)));
+    if (!with_any_length(H, [&](auto c) {
+            constexpr int N = decltype(c)::value;
+            hipLaunchKernelGGL(col_fft_kernel<N>, cgrid, dim3(ColShape<N>::NTH), 0, s, a, W);
+        }))
+        return hipErrorInvalidValue;
     // partial buffer: the caller provides a.partials sized n_items * nblocks * kMaxBands
     const int nblocks = 64;
     hipLaunchKernelGGL(band_partial_kernel, dim3(nblocks, a.n_items), dim3(kThreads), 0, s, a, H, W, band,
                        (int32_t)kMaxBands, a.partials);
     hipLaunchKernelGGL(band_sum_kernel, dim3(a.n_items), dim3(64), 0, s, a, a.partials, nblocks,
                        (int32_t)kMaxBands, band_base, band_count, scale, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_items(ItemDev* out, const ProbDev* probs, const int32_t* pids, int n_pids, int per,
+                             int local, int64_t hw, hipStream_t s) {
+    const int n = n_pids * per;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_items_kernel, elementwise_grid(n), dim3(256), 0, s, out, probs, pids, n, per, local, hw);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_words(void* p, int64_t n_words, hipStream_t s) {
+    if (n_words <= 0) return hipSuccess;
+    hipLaunchKernelGGL(zero_words_kernel, elementwise_grid(n_words), dim3(256), 0, s, static_cast<uint32_t*>(p),
+                       n_words);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_int(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(fill_int_kernel, elementwise_grid(n), dim3(256), 0, s, p, v, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_band_dof(const int32_t* modes, int32_t prior_dof, int32_t* dof, int n, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(band_dof_kernel, elementwise_grid(n), dim3(256), 0, s, modes, prior_dof, dof, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_add(const float* x, float* y, int64_t n, hipStream_t s) {
+    hipLaunchKernelGGL(add_kernel, elementwise_grid(n), dim3(256), 0, s, x, y, n);
+    return hipGetLastError();
+}
+
+hipError_t launch_finite_check(int W, int H, const SweepArgs& a, int32_t* flag, hipStream_t s) {
+    if (a.n_items <= 0) return hipSuccess;
+    hipLaunchKernelGGL(finite_check_kernel, dim3(a.n_items), dim3(256), 0, s, a, (int64_t)H * W, flag);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_terms(int W, int H, const SweepArgs& a, const float* d, const float* s_wf,
+                             const float* s_true, float* grad_s, float* grad_d, double* part, hipStream_t s) {
+    hipLaunchKernelGGL(loss_terms_kernel, dim3(kLossBlocks, a.n_items), dim3(kThreads), 0, s, a, (int64_t)H * W, d,
+                       s_wf, s_true, grad_s, grad_d, part);
+    return hipGetLastError();
+}
+
+hipError_t launch_loss_finish(const SweepArgs& a, const double* part, const double* power, const double* amps,
+                              const int32_t* band_modes, const int32_t* band_base, const int32_t* band_count,
+                              double* loss, double* grad_bands, hipStream_t s) {
+    hipLaunchKernelGGL(loss_finish_kernel, dim3(a.n_items), dim3(64), 0, s, a, part, kLossBlocks, power, amps,
+                       band_modes, band_base, band_count, loss, grad_bands);
     return hipGetLastError();
 }
 

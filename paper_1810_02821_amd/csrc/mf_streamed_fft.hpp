@@ -33,10 +33,11 @@ __device__ __forceinline__ void passes_before(float2* buf, unsigned lane, const 
 
 // One plan per transform length for every row kernel (the fused and the plain
 // row kernels, and hence split and resumed runs, then round alike): inverse
-// 16, RM..., RL and forward RL, RM..., 16 from 256 points up.
+// 16, RM..., RL and forward RL, RM..., 16 from 256 points up (powers of two;
+// other lengths, which only the plain kernels serve, take stockham_fft).
 template <int L, int TPG>
 __device__ __forceinline__ void row_inverse(float2* buf, unsigned lane, const float2* __restrict__ tw) {
-    if constexpr (L >= 256) {
+    if constexpr (L >= 256 && is_pow2(L)) {
         constexpr int RL = last_radix<L>();
         stockham_pass<L, 16, 1, TPG, true>(buf, lane, tw);
         passes_before<L, middle_radix<L>(), 16, RL, TPG, true>(buf, lane, tw);
@@ -47,7 +48,7 @@ __device__ __forceinline__ void row_inverse(float2* buf, unsigned lane, const fl
 }
 template <int L, int TPG>
 __device__ __forceinline__ void row_forward(float2* buf, unsigned lane, const float2* __restrict__ tw) {
-    if constexpr (L >= 256) {
+    if constexpr (L >= 256 && is_pow2(L)) {
         constexpr int RL = last_radix<L>();
         stockham_pass<L, RL, 1, TPG, false>(buf, lane, tw);
         passes_before<L, middle_radix<L>(), RL, 16, TPG, false>(buf, lane, tw);

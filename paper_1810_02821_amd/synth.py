@@ -101,14 +101,15 @@ def grf(H: int, W: int, spectrum: Spectrum, rng: np.random.Generator) -> np.ndar
 
 def tile_mask(H: int, W: int, frac: float, rng: np.random.Generator,
               tile: int = 4) -> np.ndarray:
-    """Boolean mask (True = missing) of round(frac * #tiles) aligned tiles."""
-    th, tw = H // tile, W // tile
+    """Boolean mask (True = missing) of round(frac * #tiles) aligned tiles
+    (sides that are not multiples of the tile end in partial tiles)."""
+    th, tw = -(-H // tile), -(-W // tile)
     n_tiles = th * tw
     k = int(round(frac * n_tiles))
     chosen = rng.permutation(n_tiles)[:k]
     m = np.zeros((th, tw), dtype=bool)
     m.flat[chosen] = True
-    return np.repeat(np.repeat(m, tile, axis=0), tile, axis=1)
+    return np.repeat(np.repeat(m, tile, axis=0), tile, axis=1)[:H, :W]
 
 
 @dataclasses.dataclass

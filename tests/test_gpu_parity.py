@@ -225,9 +225,9 @@ def test_backward_matches_oracle_vjp(torch_cuda, size, solve):
     rv = rel(plan.split(v)[0], v_ref)
     rd = rel(plan.split(gd)[0], gd_ref)
     gb = gb.cpu().numpy()
-    rb = float(np.max(np.abs(gb - gt_ref)) / np.max(np.abs(gt_ref)))
+    rb = float(np.linalg.norm(gb - gt_ref) / np.linalg.norm(gt_ref))
     print(f"info {info[0]} rel v {rv:.2e} grad_d {rd:.2e} bands {rb:.2e}")
-    assert rv < 1e-3 and rd < 1e-3 and rb < 1e-3
+    assert rv < REL_TOL and rd < REL_TOL and rb < REL_TOL
 
 
 def test_persistent_solve_batch_levels_and_residuals(torch_cuda):
@@ -432,3 +432,65 @@ def test_sampler_with_cooling_levels_matches_oracle(torch_cuda, size, form):
         worst = max(worst, rel(pair[:, 0] + 1j * pair[:, 1], s_ref.ravel()))
     print(f"worst rel {worst:.2e}")
     assert worst < REL_TOL
+
+
+@pytest.mark.parametrize("size,form", [(128, "persistent"), (256, "streamed"), (512, "streamed")])
+def test_thousand_sweeps_per_sample_parity_large(torch_cuda, size, form):
+    """Per-sample parity every 100th sweep up to 1000 on the same Philox stream:
+    the persistent kernel at the paper's image size, and the fused streamed
+    kernels (first pass from HBM, update in registers, last pass to HBM) at
+    256^2 and 512^2."""
+    mf = _mf()
+    banner(f"1000 sweeps {size}x{size} {form}")
+    prob = synth.config_128(8, size)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    seed = synth.philox_seed(8)
+    chains = 4 if size <= 128 else 2
+    flat, _ = plan.sample(d, seed, chains=chains, burn_in=0, n_samples=10, thin=100, form=form)
+    got = plan.sample_view(flat, 0, chains, 10).cpu().numpy()
+    worst = 0.0
+    for q in range(chains // 2):
+        ref, _ = om.sample_pair(prob, seed, 0, q, 0, 10, 100)
+        for h in range(2):
+            for k in range(10):
+                worst = max(worst, rel(got[2 * q + h, k], ref[h, k]))
+    print(f"worst rel over sweeps 100..1000: {worst:.2e}")
+    assert worst < REL_TOL
+
+
+def _golden_wiener_1024():
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "wiener_cg_1024.txt")
+    idx, val, norm = [], [], None
+    with open(path) as f:
+        for line in f:
+            if line.startswith("# norm"):
+                norm = float(line.split()[2])
+            elif not line.startswith("#"):
+                i, v = line.split()
+                idx.append(int(i))
+                val.append(float(v))
+    return np.array(idx), np.array(val), norm
+
+
+@pytest.mark.parametrize("solve_form", ["streamed"])
+def test_converged_wiener_1024_matches_cg(torch_cuda, solve_form):
+    """The converged messenger filter at 1024^2 (the paper-size recipe scaled
+    up; 30 cooling levels 1e3 -> 1, then 6000 sweeps at lambda = 1) against the
+    oracle's conjugate-gradient solution of Eq. 2-3 (pinned against the dense
+    solve), stored at 2048 seeded pixels with the solution's norm by
+    tests/golden/make_wiener_cg_1024.py."""
+    mf = _mf()
+    banner("converged Wiener filter 1024 vs CG")
+    idx, val, norm = _golden_wiener_1024()
+    prob = synth.config_128(0, 1024)
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    sch = mf.Schedule(list(np.geomspace(1e3, 1.0, 30)) + [1.0], [10] * 30 + [6000])
+    s, _ = plan.wiener(d, sch)
+    x = plan.split(s)[0].astype(np.float64)
+    r_pix = float(np.linalg.norm(x.ravel()[idx] - val) / np.linalg.norm(val))
+    r_norm = abs(np.linalg.norm(x) - norm) / norm
+    print(f"sampled pixels rel {r_pix:.2e}, norm rel {r_norm:.2e}")
+    assert r_pix < REL_TOL and r_norm < REL_TOL

@@ -74,12 +74,14 @@ def test_backward_with_response_matches_oracle(torch_cuda, solve):
     s_ref, _ = om.wiener(prob, sch_o)
     g = np.random.default_rng(6).standard_normal((64, 64))
     gd_ref, _, v_ref, _ = oa.wiener_vjp(prob, s_ref, g, sch_o)
-    gd, _, v, info = plan.wiener_backward(plan.concat([s_ref]), plan.concat([g]),
-                                          mf.Schedule([1.0], [0], 1e-8, 6000, 10), want_v=True,
+    # cooling levels first, then lambda = 1 until the residual reaches the
+    # FP32 floor (the residual test stops there, well inside the sweep cap)
+    adj = mf.Schedule(list(np.geomspace(1e3, 1.0, 30)) + [1.0], [10] * 30 + [0], 3e-6, 20000, 10)
+    gd, _, v, info = plan.wiener_backward(plan.concat([s_ref]), plan.concat([g]), adj, want_v=True,
                                           allow_not_converged=True)
     rv, rd = rel(plan.split(v)[0], v_ref), rel(plan.split(gd)[0], gd_ref)
     print(f"info {info[0]} rel v {rv:.2e} grad_d {rd:.2e}")
-    assert rv < 1e-3 and rd < 1e-3
+    assert rv < REL_TOL and rd < REL_TOL
 
 
 def test_unrolled_gradient_with_response_matches_oracle(torch_cuda):

@@ -47,7 +47,13 @@ def test_autograd_function_vjp_matches_oracle(torch_cuda):
     rd = rel(plan.split(d.grad)[0], gd_ref)
     rt = float(np.max(np.abs(theta.grad.cpu().numpy() - gt_ref)) / np.max(np.abs(gt_ref)))
     print(f"s {rs:.2e} grad_d {rd:.2e} grad_theta {rt:.2e}")
-    assert rs < REL_TOL and rd < 1e-3 and rt < 1e-3
+    assert rs < REL_TOL and rd < REL_TOL and rt < REL_TOL
+
+
+def _band_rel(got, ref):
+    """Relative L2 distance over the band vector."""
+    got, ref = np.asarray(got, dtype=np.float64), np.asarray(ref, dtype=np.float64)
+    return float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
 
 
 def test_band_loss_gradient_256_matches_oracle(torch_cuda):
@@ -59,8 +65,11 @@ def test_band_loss_gradient_256_matches_oracle(torch_cuda):
     banner("band loss gradient 256")
     prob = synth.config_bands(0, 256, 32)
     plan = mf.Plan([prob])
-    fwd, adj = _wf_schedules(mf, 5000)
-    loss = BandPosteriorLoss(plan, prob.noise_var.ravel())
+    # 10000 sweeps at lambda = 1 after the cooling levels: the FP64 messenger
+    # iteration is then within 1e-7 of the exact filter here, so what is left
+    # is the FP32 floor of the GPU solve
+    fwd, adj = _wf_schedules(mf, 10000)
+    loss = BandPosteriorLoss(plan)
     d = plan.concat([prob.d])
     theta = torch.tensor(np.asarray(prob.spectrum.amps), dtype=torch.float64, device="cuda")
     L, gd, gt, s = loss.value_and_grad(d, theta, plan.concat([prob.s_true]), fwd, adj)
@@ -69,10 +78,44 @@ def test_band_loss_gradient_256_matches_oracle(torch_cuda):
     gd_ref, gt_ref = oa.loss_grad(prob, s_ref, prob.s_true, solver="cg")
     rs = rel(plan.split(s)[0], s_ref)
     rd = rel(gd.cpu().numpy().reshape(256, 256), gd_ref)
-    rt = float(np.max(np.abs(gt.cpu().numpy() - gt_ref) / np.maximum(np.abs(gt_ref), 1e-3 * np.max(np.abs(gt_ref)))))
-    print(f"L {L:.6e} ref {L_ref:.6e}; s {rs:.2e} grad_d {rd:.2e} grad_theta {rt:.2e}")
-    assert abs(L - L_ref) < 1e-4 * abs(L_ref)
-    assert rs < REL_TOL and rd < 1e-3 and rt < 1e-2
+    rt = _band_rel(gt.cpu().numpy(), gt_ref)
+    worst_band = float(np.max(np.abs(gt.cpu().numpy() - gt_ref) / np.max(np.abs(gt_ref))))
+    print(f"L {L:.9e} ref {L_ref:.9e} rel {abs(L - L_ref) / abs(L_ref):.2e}; s {rs:.2e} grad_d {rd:.2e} "
+          f"grad_theta {rt:.2e} (worst band / max band {worst_band:.2e})")
+    assert abs(L - L_ref) < 1e-5 * abs(L_ref)
+    assert rs < REL_TOL and rd < REL_TOL and rt < REL_TOL
+
+
+def test_band_loss_with_response_matches_oracle(torch_cuda):
+    """mf_band_loss with a diagonal response (and pixels of zero response):
+    the likelihood term (d - A s)^T N^-1 (d - A s) uses the plan's own A and N,
+    against the oracle's loss and gradient at the oracle's converged filter."""
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("band loss with response 64")
+    prob = synth.config_bands(3, 64, 16)
+    rng = np.random.default_rng(103)
+    A = rng.uniform(0.5, 1.5, (64, 64))
+    A.flat[rng.choice(64 * 64, 40, replace=False)] = 0.0
+    prob.response = A
+    prob.mask = prob.mask | (A == 0)
+    nv = np.where(np.isfinite(prob.noise_var), prob.noise_var, 1.0)
+    prob.d = np.where(prob.mask, 0.0, A * prob.s_true + rng.standard_normal((64, 64)) * np.sqrt(nv))
+    plan = mf.Plan([prob])
+    d = plan.concat([prob.d])
+    s_ref, _ = om.wiener_cg(prob, tol=1e-12)
+    fwd, adj = _wf_schedules(mf, 6000)
+    s, _ = plan.wiener(d, fwd, allow_not_converged=True)
+    loss, gd, gt, _ = plan.band_loss(d, s, plan.concat([prob.s_true]), adj, allow_not_converged=True)
+    L_ref = oa.loss_terms(prob, s_ref, prob.s_true)
+    gd_ref, gt_ref = oa.loss_grad(prob, s_ref, prob.s_true, solver="cg")
+    L = float(loss.sum())
+    rd = rel(plan.split(gd)[0], gd_ref)
+    rt = _band_rel(gt.cpu().numpy(), gt_ref)
+    print(f"L {L:.9e} ref {L_ref:.9e}; s {rel(plan.split(s)[0], s_ref):.2e} grad_d {rd:.2e} grad_theta {rt:.2e}")
+    assert abs(L - L_ref) < 1e-5 * abs(L_ref)
+    assert rd < REL_TOL and rt < REL_TOL
+    assert np.all(plan.split(gd)[0][A == 0] == 0)
 
 
 def test_large_map_samples_2048(torch_cuda):
