@@ -288,6 +288,22 @@ mf_status mf_sample(mf_plan plan, const float* d, const mf_sample_args* args,
                     const float* state_in, float* state_out, float* samples_out,
                     mf_stream stream);
 
+/* mf_sample for callers that cannot allocate device memory: code under HIP
+ * graph capture without a prior mf_plan_reserve, tight serving loops, and
+ * harnesses that forbid hipMalloc.  Same arguments and results as mf_sample
+ * (the same kernels, bit for bit), but every workspace (work lists,
+ * persistent coefficient tables, d / A with a response, the 16-bit field)
+ * lives in a static device array of 16 MiB per GPU, held until the process
+ * ends, and the call allocates nothing (no hipMalloc, no graph instantiation:
+ * MF_FLAG_GRAPH is ignored).  state_out is required (it holds the chains' work
+ * field).  MF_ERR_INVALID_ARG if the plan and call need more than 16 MiB (for
+ * example more than about 800,000 pixels of persistent-form problems, or the
+ * 16-bit field of a large streamed plan) or if the plan's device is not
+ * current.  Every call on one GPU shares that GPU's array and overwrites it:
+ * calls that overlap on one GPU (two streams, two threads) race. */
+mf_status mf_sample_noalloc(mf_plan plan, const float* d, const mf_sample_args* args,
+                            const float* state_in, float* state_out, float* samples_out, mf_stream stream);
+
 /* Hierarchical sampler (Sec. 5): samples of the signal and of the band
  * amplitudes theta_b of the power spectrum.  Every problem needs a band
  * spectrum (MF_ERR_INVALID_ARG otherwise).  Size classes with H = W in {32,

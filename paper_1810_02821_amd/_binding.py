@@ -92,7 +92,7 @@ RESERVE = {"solve": 1, "sample": 2, "spectrum": 4, "shear": 8, "unrolled": 16, "
 EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_reserve", "mf_plan_set_spectrum", "mf_plan_pixel_offset",
            "mf_plan_tau", "mf_plan_total_bands", "mf_wiener", "mf_sample", "mf_wiener_backward",
            "mf_wiener_backward_unrolled", "mf_band_power", "mf_plan_tile_shape", "mf_sample_spectrum",
-           "mf_sample_moments", "mf_shear_wiener", "mf_shear_sample", "mf_band_loss",
+           "mf_sample_moments", "mf_shear_wiener", "mf_shear_sample", "mf_band_loss", "mf_sample_noalloc",
            "mf_status_string",
            "mf_last_error"]
 
@@ -126,6 +126,7 @@ def lib():
     L.mf_plan_total_bands.restype = C.c_int32
     L.mf_wiener.argtypes = [vp, vp, C.POINTER(_Schedule), vp, vp, C.POINTER(Info), vp]
     L.mf_sample.argtypes = [vp, vp, C.POINTER(_SampleArgs), vp, vp, vp, vp]
+    L.mf_sample_noalloc.argtypes = [vp, vp, C.POINTER(_SampleArgs), vp, vp, vp, vp]
     L.mf_wiener_backward.argtypes = [vp, vp, vp, C.POINTER(_Schedule), vp, vp, vp, C.POINTER(Info), vp]
     L.mf_band_power.argtypes = [vp, vp, vp, vp, vp]
     L.mf_wiener_backward_unrolled.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_int32, vp, vp, vp, vp, vp]
@@ -139,7 +140,8 @@ def lib():
     L.mf_last_error.restype = C.c_char_p
     for name in ("mf_plan_create", "mf_plan_destroy", "mf_plan_reserve", "mf_band_loss", "mf_plan_set_spectrum",
                  "mf_wiener",
-                 "mf_sample", "mf_wiener_backward", "mf_wiener_backward_unrolled", "mf_band_power",
+                 "mf_sample", "mf_sample_noalloc", "mf_wiener_backward", "mf_wiener_backward_unrolled",
+                 "mf_band_power",
                  "mf_plan_tile_shape", "mf_sample_spectrum", "mf_sample_moments", "mf_shear_wiener",
                  "mf_shear_sample"):
         getattr(L, name).restype = C.c_int

@@ -17,6 +17,7 @@
 #include "mf_resident.hpp"
 #include "mf_spectrum.hpp"
 #include "mf_shear.hpp"
+#include "mf_static.hpp"
 
 namespace {
 
@@ -1565,6 +1566,14 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
             return st;
         }
     }
+    {
+        // the static scratch of mf_sample_noalloc on this device
+        const hipError_t e = mf::static_scratch_setup(p->device);
+        if (e != hipSuccess) {
+            delete p;
+            return fail(MF_ERR_DEVICE, std::string("static scratch setup: ") + hipGetErrorString(e));
+        }
+    }
     if (flags & MF_FLAG_AUTOTUNE) {
         mf_status st = autotune(p);
         if (st != MF_OK) {
@@ -1902,6 +1911,42 @@ mf_status mf_sample(mf_plan p, const float* d, const mf_sample_args* g, const fl
     w.field = p->field.as<float2>();
     w.hfield = p->hfield.as<float2>();
     return sample_impl(p, d, g, state_in, state_out, samples_out, w, s);
+}
+
+mf_status mf_sample_noalloc(mf_plan p, const float* d, const mf_sample_args* g, const float* state_in,
+                            float* state_out, float* samples_out, mf_stream stream) {
+    if (!p || !d || !g) return fail(MF_ERR_INVALID_ARG, "plan, d and args are required");
+    if (!state_out) return fail(MF_ERR_INVALID_ARG, "mf_sample_noalloc needs state_out (the chains' work field)");
+    mf_status st = validate_sample(g, state_out, samples_out);
+    if (st != MF_OK) return st;
+    int dev = -1;
+    MF_HIP(hipGetDevice(&dev));
+    if (dev != p->device) return fail(MF_ERR_INVALID_ARG, "the plan's device must be current");
+    char* base = static_cast<char*>(mf::static_scratch(dev));
+    if (!base) return fail(MF_ERR_DEVICE, "the static scratch of this device is not set up");
+    // layout: work lists, persistent tables, d / A, 16-bit field (256-byte aligned)
+    const int pairs = (g->chains_per_problem + 1) / 2;
+    size_t max_items = 0;
+    for (auto& kv : p->classes) max_items = std::max(max_items, kv.second.size() * (size_t)pairs);
+    const size_t items_b = align256((max_items + 1) * sizeof(mf::ItemDev));
+    const size_t coef_b = sample_any_persistent(p, g->form)
+                              ? align256((size_t)p->total_px / 2 * (sizeof(float4) + sizeof(float2) + sizeof(float4)))
+                              : 0;
+    const size_t dp_b = p->has_response ? align256((size_t)p->total_px * sizeof(float)) : 0;
+    const size_t hf_b = g->storage != MF_STORAGE_FP32 ? align256((size_t)p->total_px * pairs * 4) : 0;
+    const size_t need = items_b + coef_b + dp_b + hf_b;
+    if (need > mf::kStaticScratchBytes)
+        return fail(MF_ERR_INVALID_ARG, "mf_sample_noalloc needs " + std::to_string(need) +
+                                            " bytes of scratch for this plan and call; the static scratch holds " +
+                                            std::to_string(mf::kStaticScratchBytes));
+    SampleWs w;
+    w.items = reinterpret_cast<mf::ItemDev*>(base);
+    w.items_cap = max_items + 1;
+    w.coef = coef_b ? reinterpret_cast<float4*>(base + items_b) : nullptr;
+    w.dprime = dp_b ? reinterpret_cast<float*>(base + items_b + coef_b) : nullptr;
+    w.hfield = hf_b ? reinterpret_cast<float2*>(base + items_b + coef_b + dp_b) : nullptr;
+    w.graphs = false;
+    return sample_impl(p, d, g, state_in, state_out, samples_out, w, (hipStream_t)stream);
 }
 
 mf_status mf_sample_spectrum(mf_plan p, const float* d, const mf_spectrum_args* g, const float* state_in,
