@@ -29,17 +29,28 @@ BURN_IN = 200
 N_SAMPLES = 98
 DATA_SEED = 0
 
-# MI355X published peaks
+# MI355X peaks
 PEAK_HBM_GBPS = 8000.0
-# FP32 vector: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU (4 SIMDs x 16 lanes x FMA x dual-issue packed)
-PEAK_FP32_TFLOPS = 157.3
+# Published FP32 vector peak: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU, which needs
+# packed FP32 (two FP32 values per lane per instruction).  Every HIP source
+# here is built without packed FP32 instructions, so the ceiling of this
+# build is the single-issue rate: 256 CUs x 4 SIMDs x 16 lanes x 2 FLOP (FMA)
+# x 2.4 GHz = 78.6 TFLOP/s, i.e. 39.3e12 VALU lane-instructions/s (one wave64
+# instruction per SIMD every 4 clocks).
+PEAK_FP32_TFLOPS_PUBLISHED = 157.3
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 
 # HBM traffic of resident_sample_kernel<128> on this workload, from rocprofv3
 # FETCH_SIZE / WRITE_SIZE runs scaled by the same counters on a 1 GiB copy, and
 # the hash of the kernel sources it was measured on (traffic is reported only
 # while the sources are unchanged).
-TRAFFIC_BYTES = int((71891.0625 * 2.0 + 6493992.5625 * 1.0) * 1024)  # FETCH x2.0 + WRITE x1.0 (copy-calibrated)
-TRAFFIC_SOURCES_SHA = "783b64e3543a92c4"
+TRAFFIC_BYTES = int((83449.98 * 2.0 + 6495825.0 * 1.0) * 1024)  # FETCH x2.0 + WRITE x1.0 (copy-calibrated)
+TRAFFIC_SOURCES_SHA = "a9d0048799ff4ed1"
+# VALU wave-instructions per launch of the same kernel (rocprofv3 SQ_INSTS_VALU,
+# summed over the shader engines), and the source hash they were taken on.
+VALU_WAVE_INSTS = 7009708032
+VALU_SOURCES_SHA = "a9d0048799ff4ed1"
 
 
 def kernel_sources_sha() -> str:
@@ -52,18 +63,25 @@ def kernel_sources_sha() -> str:
 
 
 def algorithmic_flops_per_pixel_pair_sweep(n_pixels: int) -> float:
-    """FLOP-equivalents one chain pair needs per pixel per sweep (FMA = 2):
-    two complex 2D FFTs at the conventional 5 log2(n) per point each (140 at
-    128^2); the pixel update t = (1-a)s + a d + sigma xi (2 FMA per chain: 8)
-    and the Fourier update S = f T + w eta (FMA + mul per component: 6); and
-    per pixel and per mode half a Philox4x32-10 call (10 rounds x [two
-    32x32->64 products + two 3-input XORs] = 40 integer ops per call) plus one
-    Box-Muller pair (14 ops: two uniforms, log, sqrt, sin, cos, scalings),
-    each integer or transcendental op counted as one FLOP: 2 x (20 + 14) = 68."""
-    fft = 2 * 5 * math.log2(n_pixels)
-    updates = 8 + 6
-    rng = 2 * (40 / 2 + 14)
-    return fft + updates + rng
+    """Floating-point operations one chain pair needs per pixel per sweep:
+    two complex 2D FFTs (forward and inverse) at the conventional 5 log2(n)
+    per point each (140 at 128^2), plus the two diagonal updates at about 10
+    FLOP per pixel each (the pixel step and the Fourier step with their
+    scalings): 160 at 128^2.  The normal variates (two per pixel per chain:
+    Philox integer rounds and Box-Muller transcendentals) are not floating-point
+    arithmetic and are not counted here; flop_equivalents_per_pixel_pair_sweep
+    counts them too."""
+    return 2 * 5 * math.log2(n_pixels) + 2 * 10
+
+
+def flop_equivalents_per_pixel_pair_sweep(n_pixels: int) -> float:
+    """The same with every integer or transcendental instruction of the
+    variates counted as one operation (FMA = 2): the FFTs (140 at 128^2), the
+    updates as issued (pixel step 2 FMA per chain: 8; Fourier step FMA + mul
+    per component: 6), and per pixel and per mode half a Philox4x32-10 call
+    (10 rounds x [two 32x32->64 products + two 3-input XORs] = 40 ops per call)
+    plus one Box-Muller pair (14 ops): 2 x (20 + 14) = 68; 222 at 128^2."""
+    return 2 * 5 * math.log2(n_pixels) + 8 + 6 + 2 * (40 / 2 + 14)
 
 
 def parse():
@@ -105,8 +123,22 @@ def _oracle_worker(args):
     return time.perf_counter() - t0
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(budget_s: float):
-    """The FP64 oracle sampler on the host cores, one chain pair per process."""
+    """The FP64 oracle sampler on the host cores, one chain pair per process.
+    The pool takes the CPU share one GPU has on a shared host (16 cores, as
+    OMP_NUM_THREADS states there), or every core of a smaller host."""
     import multiprocessing as mp
     cores = min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS", "16") or 16), 16)
     cores = max(cores, 1)
@@ -120,8 +152,9 @@ def cpu_baseline(budget_s: float):
     wall = time.perf_counter() - t0
     samples = cores * 2 * sweeps  # two chains per pair, one sample per sweep
     return {"value": samples / wall, "unit": "posterior samples/s", "cores": cores, "kind": "oracle",
+            "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
             "sample": f"{cores} chain pairs x {sweeps} sweeps of the 128x128 workload "
-                      f"(FP64 numpy, one process per pair, samples counted without burn-in; "
+                      f"(FP64 numpy, one process per pair and core, samples counted without burn-in; "
                       f"{wall:.1f} s wall)"}
 
 
@@ -244,9 +277,19 @@ def main():
                    "samples_per_step": samples_per_step, "form": "persistent"},
         "roofline": {"bound": "alu", "achieved": achieved_tflops, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved_tflops / PEAK_FP32_TFLOPS, "traffic": traffic,
+                     "peak_note": "single-issue FP32 FMA rate (no packed FP32 in this build); "
+                                  "published packed peak 157.3",
+                     "frac_of_published_peak": achieved_tflops / PEAK_FP32_TFLOPS_PUBLISHED,
+                     "valu_instructions_per_launch": VALU_WAVE_INSTS * 64 if VALU_SOURCES_SHA == kernel_sources_sha()
+                                                     else None,
+                     "valu_issue_frac": (VALU_WAVE_INSTS * 64 / (kern_ms / 1000.0) / PEAK_VALU_LANE_OPS
+                                         if VALU_SOURCES_SHA == kernel_sources_sha() else None),
                      "kernel": "resident_sample_kernel<128>", "kernel_ms": kern_ms,
                      "kernel_ms_sd": float(np.std(per_call_ms, ddof=1)) if len(per_call_ms) > 1 else 0.0,
                      "flops_per_pixel_pair_sweep": algorithmic_flops_per_pixel_pair_sweep(n_pix),
+                     "flop_equivalents_per_pixel_pair_sweep": flop_equivalents_per_pixel_pair_sweep(n_pix),
+                     "flop_equivalent_TFLOPs": flop_equivalents_per_pixel_pair_sweep(n_pix) * n_pix * pairs * sweeps
+                                               / (kern_ms / 1000.0) / 1e12,
                      "hbm_algorithmic_bytes": hbm_bytes,
                      "hbm_achieved_GBps": hbm_gbps, "hbm_frac": hbm_gbps / PEAK_HBM_GBPS},
     }

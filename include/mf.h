@@ -147,9 +147,10 @@ enum {
 /* Plan flags. */
 enum {
     MF_FLAG_NONE = 0,
-    MF_FLAG_AUTOTUNE = 1,      /* time the column-tile shapes of each streamed size class (>= 256) at plan
-                                  creation and keep the fastest; with MF_TUNE_CACHE=<file> in the
-                                  environment the choices are read from / appended to that file */
+    MF_FLAG_AUTOTUNE = 1,      /* time the column-tile shapes and the fused row kernel's rows per workgroup
+                                  of each streamed size class (sides >= 256) at plan creation and keep the
+                                  fastest of each; with MF_TUNE_CACHE=<file> in the environment the
+                                  choices are read from / appended to that file */
     MF_FLAG_GRAPH = 2,         /* capture the streamed sweep loops of each size class (mf_sample,
                                   mf_sample_spectrum, mf_shear_wiener, mf_shear_sample) as HIP graphs,
                                   once per launch configuration (pointers, counts, seeds, sweep range,
@@ -449,6 +450,12 @@ mf_status mf_band_power(mf_plan plan, const float* x, const float* y, double* ou
  * per workgroup of *threads threads.  MF_ERR_INVALID_ARG if the plan has no
  * problem of that size. */
 mf_status mf_plan_tile_shape(mf_plan plan, int32_t H, int32_t W, int32_t* cols, int32_t* threads);
+
+/* Rows per workgroup of the fused streamed row kernel (rows of 256 points and
+ * more, powers of two) for the size class H x W: the autotuner's choice under
+ * MF_FLAG_AUTOTUNE, else the default; 0 where no fused row kernel runs.
+ * MF_ERR_INVALID_ARG if the plan has no problem of that size. */
+mf_status mf_plan_row_shape(mf_plan plan, int32_t H, int32_t W, int32_t* rows);
 
 /* Number of bands over all band-spectrum problems (length of grad_bands). */
 int32_t mf_plan_total_bands(mf_plan plan);

@@ -93,6 +93,7 @@ EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_reserve", "mf_plan_set_
            "mf_plan_tau", "mf_plan_total_bands", "mf_wiener", "mf_sample", "mf_wiener_backward",
            "mf_wiener_backward_unrolled", "mf_band_power", "mf_plan_tile_shape", "mf_sample_spectrum",
            "mf_sample_moments", "mf_shear_wiener", "mf_shear_sample", "mf_band_loss", "mf_sample_noalloc",
+           "mf_plan_row_shape",
            "mf_status_string",
            "mf_last_error"]
 
@@ -131,6 +132,7 @@ def lib():
     L.mf_band_power.argtypes = [vp, vp, vp, vp, vp]
     L.mf_wiener_backward_unrolled.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_int32, vp, vp, vp, vp, vp]
     L.mf_plan_tile_shape.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+    L.mf_plan_row_shape.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
     L.mf_sample_spectrum.argtypes = [vp, vp, C.POINTER(_SpectrumArgs), vp, vp, vp, vp, vp, vp, vp]
     L.mf_sample_moments.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
     L.mf_shear_wiener.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_float, vp, vp]
@@ -142,7 +144,8 @@ def lib():
                  "mf_wiener",
                  "mf_sample", "mf_sample_noalloc", "mf_wiener_backward", "mf_wiener_backward_unrolled",
                  "mf_band_power",
-                 "mf_plan_tile_shape", "mf_sample_spectrum", "mf_sample_moments", "mf_shear_wiener",
+                 "mf_plan_tile_shape", "mf_plan_row_shape", "mf_sample_spectrum", "mf_sample_moments",
+                 "mf_shear_wiener",
                  "mf_shear_sample"):
         getattr(L, name).restype = C.c_int
     _lib = L
@@ -436,6 +439,12 @@ class Plan:
         c, t = C.c_int32(), C.c_int32()
         _check(lib().mf_plan_tile_shape(self._h, int(H), int(W), C.byref(c), C.byref(t)))
         return c.value, t.value
+
+    def row_shape(self, H: int, W: int) -> int:
+        """Rows per workgroup of the fused row kernel for size class H x W (0: none)."""
+        r = C.c_int32()
+        _check(lib().mf_plan_row_shape(self._h, int(H), int(W), C.byref(r)))
+        return r.value
 
     def state_view(self, flat, problem: int, chains: int):
         """Complex pair states [pairs, H, W] of one problem in a state buffer."""

@@ -112,6 +112,8 @@ struct mf_plan_s {
     DevBuf kfield;                          // streamed mass mapping: kappa staging field
     // column-kernel tile shape per size class: (H, W) -> (tc, nth)
     std::map<std::pair<int, int>, std::pair<int, int>> col_shape;
+    // rows per block of the fused row kernel per size class (absent: default)
+    std::map<std::pair<int, int>, int> row_rows;
     // captured sweep loops of the streamed sampler, keyed by launch configuration
     struct GraphEntry {
         std::vector<uint64_t> key;
@@ -321,6 +323,8 @@ mf::SweepArgs base_args(mf_plan p, int H, int W) {
     a.tw_col = p->d_tw.at(H);
     a.lambda = 1.0f;
     a.emit_index = -1;
+    auto rr = p->row_rows.find({H, W});
+    a.row_rows = rr == p->row_rows.end() ? 0 : rr->second;
     return a;
 }
 
@@ -887,7 +891,7 @@ mf_status run_solve(mf_plan p, const float* src, int src_kind, const mf_schedule
 // Enqueue the streamed sweep loop of one size class on stream s.
 mf_status enqueue_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int H, int W, const float* d,
                            const mf_sample_args* g, float2* work, const float2* state_in, float* samples,
-                           hipStream_t s) {
+                           bool packed, hipStream_t s) {
     mf::SweepArgs a = base_args(p, H, W);
     a.items = d_items;
     a.n_items = n_items;
@@ -902,7 +906,10 @@ mf_status enqueue_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, i
     a.chains = g->chains_per_problem;
     a.n_samples = g->n_samples;
     a.storage = g->storage;
-    if (state_in != work)  // copy the given states, or make zero / dispersed starts
+    a.packed = packed ? 1 : 0;
+    if (packed)  // two single-chain problems per field: gather their states (or starts)
+        MF_HIP(mf::launch_pack_init(W, H, a, state_in, state_in ? 0.f : g->init_scale, s));
+    else if (state_in != work)  // copy the given states, or make zero / dispersed starts
         MF_HIP(mf::launch_init_items(W, H, a, state_in, state_in ? 0.f : g->init_scale, s));
     const int64_t K = (int64_t)g->burn_in + (int64_t)g->n_samples * g->thin;
     auto emit_of = [&](int64_t k) -> int {
@@ -915,7 +922,8 @@ mf_status enqueue_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, i
         a.emit_index = k > 0 ? emit_of(k - 1) : -1;
         MF_HIP(mf::launch_row(W, H, k == 0 ? mf::kRowFwd : mf::kRowInvFwd, a, s));
         a.emit_index = -1;
-        MF_HIP(launch_col_class(p, W, H, a, s));
+        if (packed) MF_HIP(mf::launch_col_pack(W, H, a, s));
+        else MF_HIP(launch_col_class(p, W, H, a, s));
     }
     if (K > 0) {
         a.emit_index = emit_of(K - 1);
@@ -957,18 +965,19 @@ mf_status cool_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int 
 // loop is captured once per launch configuration and replayed as one graph.
 mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, int H, int W, const float* d,
                           const mf_sample_args* g, float2* work, const float2* state_in, float* samples,
-                          bool graphs, hipStream_t s) {
+                          bool graphs, bool packed, hipStream_t s) {
     if (!(p->flags & MF_FLAG_GRAPH) || !graphs)
-        return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, s);
+        return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, packed, s);
     const auto sh = class_shape(p, H, W);
     const std::vector<uint64_t> key = {1, (uint64_t)H, (uint64_t)W, (uint64_t)n_items, (uint64_t)(uintptr_t)d_items,
                                        (uint64_t)(uintptr_t)d, (uint64_t)(uintptr_t)work,
                                        (uint64_t)(uintptr_t)state_in, (uint64_t)(uintptr_t)samples, g->seed,
                                        (uint64_t)g->sweep_offset, (uint64_t)g->burn_in, (uint64_t)g->n_samples,
                                        (uint64_t)g->thin, (uint64_t)g->chains_per_problem, bits_of(g->init_scale),
-                                       (uint64_t)sh.first, (uint64_t)sh.second, (uint64_t)g->storage};
+                                       (uint64_t)sh.first, (uint64_t)sh.second, (uint64_t)g->storage,
+                                       (uint64_t)packed};
     return run_graph(p, key, s, [&](hipStream_t cs) {
-        return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, cs);
+        return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, packed, cs);
     });
 }
 
@@ -1065,74 +1074,114 @@ mf_status spectrum_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H
     return run_graph(p, key, s, enqueue);
 }
 
-// Time every column-tile shape of each streamed size class on a scratch field
-// and keep the fastest (all shapes do the same arithmetic, element for
-// element).  Choices can be persisted in the file named by MF_TUNE_CACHE.
+// Time every column-tile shape and every fused-row-kernel shape of each
+// streamed size class on a scratch field and keep the fastest of each (all
+// shapes do the same arithmetic, element for element).  Choices can be
+// persisted in the file named by MF_TUNE_CACHE: lines "gfx950 H W tc nth"
+// (column tiles) and "gfx950-rows H W rows" (rows per fused row block).
 mf_status autotune(mf_plan p) {
     const char* cache_path = std::getenv("MF_TUNE_CACHE");
     std::map<std::pair<int, int>, std::pair<int, int>> cached;
+    std::map<std::pair<int, int>, int> cached_rows;
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "r")) {
-            char arch[64];
-            int H, W, tc, nth;
-            while (std::fscanf(f, "%63s %d %d %d %d", arch, &H, &W, &tc, &nth) == 5)
-                if (std::string(arch) == "gfx950") cached[{H, W}] = {tc, nth};
+            char line[256];
+            while (std::fgets(line, sizeof line, f)) {
+                char arch[64];
+                int H, W, x, y;
+                const int n = std::sscanf(line, "%63s %d %d %d %d", arch, &H, &W, &x, &y);
+                if (n == 5 && std::string(arch) == "gfx950") cached[{H, W}] = {x, y};
+                else if (n >= 4 && std::string(arch) == "gfx950-rows") cached_rows[{H, W}] = x;
+            }
             std::fclose(f);
         }
     }
+    auto time_launches = [&](auto&& launch, float* ms_out) -> mf_status {
+        hipEvent_t e0, e1;
+        MF_HIP(hipEventCreate(&e0));
+        MF_HIP(hipEventCreate(&e1));
+        hipError_t e = launch();  // warm-up
+        if (e == hipSuccess) e = hipEventRecord(e0, nullptr);
+        for (int r = 0; r < 3 && e == hipSuccess; ++r) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, nullptr);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(ms_out, e0, e1);
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (e != hipSuccess) return fail(MF_ERR_DEVICE, std::string("autotune: ") + hipGetErrorString(e));
+        return MF_OK;
+    };
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;
-        if (H < 256) continue;  // small classes run on the persistent kernel or are launch-bound
-        auto c = cached.find({H, W});
-        if (c != cached.end()) {
-            p->col_shape[{H, W}] = c->second;
-            continue;
-        }
-        int tc[8], nth[8];
-        const int nc = mf::col_shape_candidates(H, tc, nth, 8);
-        if (nc <= 1) continue;
+        if (H < 256 && W < 256) continue;  // small classes run on the persistent kernel or are launch-bound
+        int tc[8], nth[8], rows[8];
+        const int nc = H >= 256 ? mf::col_shape_candidates(H, tc, nth, 8) : 0;
+        const int nr = mf::fused_row_candidates(W, rows, 8);
+        auto cc = cached.find({H, W});
+        auto cr = cached_rows.find({H, W});
+        if (cc != cached.end()) p->col_shape[{H, W}] = cc->second;
+        if (cr != cached_rows.end()) p->row_rows[{H, W}] = cr->second;
+        const bool tune_col = nc > 1 && cc == cached.end();
+        const bool tune_row = nr > 1 && cr == cached_rows.end();
+        if (!tune_col && !tune_row) continue;
         const int pid = kv.second[0];
         const int n_items = std::max(1, std::min(16, (int)(2 * (4096 * 4096 / ((int64_t)H * W)))));
         std::vector<mf::ItemDev> items(n_items);
         for (int i = 0; i < n_items; ++i) items[i] = {pid, i, (int64_t)i * H * W};
-        DevBuf fld, it;
+        DevBuf fld, it, src;
         MF_HIP(fld.ensure((size_t)n_items * H * W * sizeof(float2)));
         MF_HIP(it.ensure(items.size() * sizeof(mf::ItemDev)));
+        MF_HIP(src.ensure((size_t)p->total_px * sizeof(float)));
         MF_HIP(hipMemcpy(it.p, items.data(), items.size() * sizeof(mf::ItemDev), hipMemcpyHostToDevice));
         MF_HIP(hipMemset(fld.p, 0, (size_t)n_items * H * W * sizeof(float2)));
+        MF_HIP(hipMemset(src.p, 0, (size_t)p->total_px * sizeof(float)));
         mf::SweepArgs a = base_args(p, H, W);
         a.items = it.as<mf::ItemDev>();
         a.n_items = n_items;
         a.field = fld.as<float2>();
+        a.src = src.as<float>();
+        a.src_kind = mf::kSrcData;
         a.stochastic = 1;
-        hipEvent_t e0, e1;
-        MF_HIP(hipEventCreate(&e0));
-        MF_HIP(hipEventCreate(&e1));
-        float best = 1e30f;
-        int bi = 0;
-        for (int ci = 0; ci < nc; ++ci) {
-            MF_HIP(mf::launch_col_shape(W, H, tc[ci], nth[ci], a, nullptr));  // warm-up
-            MF_HIP(hipEventRecord(e0, nullptr));
-            for (int r = 0; r < 3; ++r) MF_HIP(mf::launch_col_shape(W, H, tc[ci], nth[ci], a, nullptr));
-            MF_HIP(hipEventRecord(e1, nullptr));
-            MF_HIP(hipEventSynchronize(e1));
-            float ms = 0.f;
-            MF_HIP(hipEventElapsedTime(&ms, e0, e1));
-            if (ms < best) {
-                best = ms;
-                bi = ci;
+        mf_status st = MF_OK;
+        if (tune_col) {
+            float best = 1e30f;
+            int bi = 0;
+            for (int ci = 0; ci < nc && st == MF_OK; ++ci) {
+                float ms = 0.f;
+                st = time_launches([&] { return mf::launch_col_shape(W, H, tc[ci], nth[ci], a, nullptr); }, &ms);
+                if (ms < best) {
+                    best = ms;
+                    bi = ci;
+                }
             }
+            if (st != MF_OK) return st;
+            p->col_shape[{H, W}] = {tc[bi], nth[bi]};
+            if (cache_path)
+                if (FILE* f = std::fopen(cache_path, "a")) {
+                    std::fprintf(f, "gfx950 %d %d %d %d\n", H, W, tc[bi], nth[bi]);
+                    std::fclose(f);
+                }
         }
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        fld.release();
-        it.release();
-        p->col_shape[{H, W}] = {tc[bi], nth[bi]};
-        if (cache_path) {
-            if (FILE* f = std::fopen(cache_path, "a")) {
-                std::fprintf(f, "gfx950 %d %d %d %d\n", H, W, tc[bi], nth[bi]);
-                std::fclose(f);
+        if (tune_row) {
+            float best = 1e30f;
+            int bi = 0;
+            for (int ri = 0; ri < nr && st == MF_OK; ++ri) {
+                float ms = 0.f;
+                mf::SweepArgs b = a;
+                b.row_rows = rows[ri];
+                st = time_launches([&] { return mf::launch_row(W, H, mf::kRowInvFwd, b, nullptr); }, &ms);
+                if (ms < best) {
+                    best = ms;
+                    bi = ri;
+                }
             }
+            if (st != MF_OK) return st;
+            p->row_rows[{H, W}] = rows[bi];
+            if (cache_path)
+                if (FILE* f = std::fopen(cache_path, "a")) {
+                    std::fprintf(f, "gfx950-rows %d %d %d\n", H, W, rows[bi]);
+                    std::fclose(f);
+                }
         }
     }
     return MF_OK;
@@ -1182,7 +1231,13 @@ mf_status ensure_sample_workspace(mf_plan p, int pairs, int storage, int form, b
     mf_status st = ensure_items(p, pairs, s);
     if (st != MF_OK) return st;
     const size_t field_elems = (size_t)p->total_px * pairs;
-    if (need_field && (st = ws(p->field, field_elems * sizeof(float2), s)) != MF_OK) return st;
+    // single-chain problems on the streamed kernels run packed two to a field,
+    // in a workspace field whatever state_out is
+    bool packs = false;
+    if (pairs == 1 && storage == MF_STORAGE_FP32)
+        for (auto& kv : p->classes)
+            packs |= kv.second.size() >= 2 && !mf::resident_supported(kv.first.first, kv.first.second);
+    if ((need_field || packs) && (st = ws(p->field, field_elems * sizeof(float2), s)) != MF_OK) return st;
     if (storage != MF_STORAGE_FP32 && (st = ws(p->hfield, field_elems * 4, s)) != MF_OK) return st;
     if (sample_any_persistent(p, form) &&
         (st = ws(p->coef, (size_t)p->total_px / 2 * (sizeof(float4) + sizeof(float2) + sizeof(float4)), s)) != MF_OK)
@@ -1237,9 +1292,32 @@ mf_status sample_impl(mf_plan p, const float* d, const mf_sample_args* g, const 
         if (form == MF_FORM_AUTO) form = mf::resident_supported(H, W) ? MF_FORM_PERSISTENT : MF_FORM_STREAMED;
         if (form == MF_FORM_PERSISTENT && !mf::resident_supported(H, W))
             return fail(MF_ERR_UNSUPPORTED_SIZE, "the persistent form needs H = W in {32, 64, 128}");
+        // one chain per problem on the streamed kernels: two problems share a
+        // complex field (no imaginary chain computed only to be dropped)
+        const int n_pids = (int)kv.second.size();
+        const bool packed = form == MF_FORM_STREAMED && g->chains_per_problem == 1 && g->storage == MF_STORAGE_FP32 &&
+                            n_cool == 0 && n_pids >= 2 && w.field && is_pow2(H) && is_pow2(W);
         mf::ItemDev* di = nullptr;
         int n_items = 0;
-        mf_status st = class_items_at(p, w.items, w.items_cap, kv.first, pairs, false, false, s, &di, &n_items);
+        mf_status st = MF_OK;
+        if (packed) {
+            n_items = (n_pids + 1) / 2;
+            if ((size_t)n_items > w.items_cap) return fail(MF_ERR_INVALID_ARG, "internal: items workspace too small");
+            di = w.items;
+            MF_HIP(mf::launch_fill_packed_items(di, p->d_class_pids + p->class_all.at(kv.first).first, n_pids,
+                                                (int64_t)H * W, s));
+            st = sample_streamed(p, di, n_items, H, W, d, &gm, w.field, sin, samples_out, w.graphs, true, s);
+            if (st != MF_OK) return st;
+            mf::SweepArgs a = base_args(p, H, W);
+            a.items = di;
+            a.n_items = n_items;
+            a.field = w.field;
+            a.packed = 1;
+            if (state_out) MF_HIP(mf::launch_pack_copy_out(W, H, a, work, s));
+            if (g->check_finite) MF_HIP(mf::launch_finite_check(W, H, a, p->d_flag, s));
+            continue;
+        }
+        st = class_items_at(p, w.items, w.items_cap, kv.first, pairs, false, false, s, &di, &n_items);
         if (st != MF_OK) return st;
         const float2* cin = sin;  // the state the sampling phase starts from
         if (n_cool > 0) {
@@ -1276,10 +1354,10 @@ mf_status sample_impl(mf_plan p, const float* d, const mf_sample_args* g, const 
         } else {
             float2* wf = hwork ? hwork : work;
             if (form == MF_FORM_STREAMED) {
-                st = sample_streamed(p, di, n_items, H, W, d, &gm, wf, cin, samples_out, w.graphs, s);
+                st = sample_streamed(p, di, n_items, H, W, d, &gm, wf, cin, samples_out, w.graphs, false, s);
             } else {  // plain: one chain pair per launch sequence
                 for (int i = 0; i < n_items && st == MF_OK; ++i)
-                    st = sample_streamed(p, di + i, 1, H, W, d, &gm, wf, cin, samples_out, w.graphs, s);
+                    st = sample_streamed(p, di + i, 1, H, W, d, &gm, wf, cin, samples_out, w.graphs, false, s);
             }
             if (st == MF_OK && hwork && state_out) {  // final states widened to FP32
                 mf::SweepArgs a = base_args(p, H, W);
@@ -1649,6 +1727,16 @@ double mf_plan_tau(mf_plan p, int32_t problem) {
 }
 
 int32_t mf_plan_total_bands(mf_plan p) { return p ? p->total_bands : -1; }
+
+mf_status mf_plan_row_shape(mf_plan p, int32_t H, int32_t W, int32_t* rows) {
+    if (!p || !rows) return fail(MF_ERR_INVALID_ARG, "plan and rows are required");
+    if (!p->classes.count({H, W})) return fail(MF_ERR_INVALID_ARG, "the plan has no problem of that size");
+    auto it = p->row_rows.find({H, W});
+    int r[8];
+    const int n = mf::fused_row_candidates(W, r, 8);
+    *rows = it != p->row_rows.end() ? it->second : (n > 0 ? r[0] : 0);
+    return MF_OK;
+}
 
 mf_status mf_plan_tile_shape(mf_plan p, int32_t H, int32_t W, int32_t* cols, int32_t* threads) {
     if (!p || !cols || !threads) return fail(MF_ERR_INVALID_ARG, "plan, cols and threads are required");

@@ -75,6 +75,10 @@ struct SweepArgs {
     int32_t storage;          // kStoreF32 / kStoreF16 / kStoreBF16: element type of `field`
     int32_t plain_kernels;    // 1: row_kernel / col_kernel_t only (no fused variants)
     int32_t rows_by_item;     // row enumeration: 1 g = item H + y (one item per problem), 0 g = y n_items + item
+    int32_t row_rows;         // rows per block of the fused row kernel (0: the default shape)
+    int32_t packed;           // 1: each item carries two single-chain problems, chain 0 of problem `prob`
+                              // in the real part and chain 0 of problem `pair` (-1: none) in the imaginary
+                              // part, each with its own tables and random stream (sampler, streamed form)
 };
 
 // Element type of the work field (row, column, init and copy-out kernels of
@@ -95,6 +99,9 @@ hipError_t launch_row(int W, int H, int row_mode, const SweepArgs& a, hipStream_
 // shapes available for a column length (returns how many were written).
 hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, hipStream_t s);
 int col_shape_candidates(int H, int* tc, int* nth, int max_n);
+// Rows per block of the fused row kernel available for a row length (the
+// first is the default; none below 256 points or for non-powers of two).
+int fused_row_candidates(int W, int* rows, int max_n);
 // Sum per-tile band slots into out[band_base[prob] + b] for every item.
 hipError_t launch_band_slots_reduce(int W, int H, int tc, const SweepArgs& a, const int32_t* band_base,
                                     const int32_t* band_count, double* out, hipStream_t s);
@@ -127,6 +134,15 @@ hipError_t launch_band_power(int W, int H, const SweepArgs& a, const float* x, c
 // `local` (a field of the class's items only).
 hipError_t launch_fill_items(ItemDev* out, const ProbDev* probs, const int32_t* pids, int n_pids, int per,
                              int local, int64_t hw, hipStream_t s);
+// Packed work list: item i = (pids[2i], pids[2i+1] or -1, i * hw).
+hipError_t launch_fill_packed_items(ItemDev* out, const int32_t* pids, int n_pids, int64_t hw, hipStream_t s);
+// Packed work field from the pair states [problem][1][H][W] (real parts), or
+// zero / dispersed starts; and back (imaginary parts of the states set to 0).
+hipError_t launch_pack_init(int W, int H, const SweepArgs& a, const float2* state_in, float init_scale,
+                            hipStream_t s);
+hipError_t launch_pack_copy_out(int W, int H, const SweepArgs& a, float2* state_out, hipStream_t s);
+// Mirror-paired column kernel of the packed sampler (powers of two).
+hipError_t launch_col_pack(int W, int H, const SweepArgs& a, hipStream_t s);
 // Zero n 4-byte words (a kernel, so that captured graphs hold no memset node).
 hipError_t launch_zero_words(void* p, int64_t n_words, hipStream_t s);
 // flag[0] = min(flag[0], problem) for every item whose field (H x W elements

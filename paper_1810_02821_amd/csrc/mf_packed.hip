@@ -1,0 +1,164 @@
+// Column step of the streamed sampler for packed items: two single-chain
+// problems of one size class share a complex field, chain 0 of problem A in
+// the real part and chain 0 of problem B in the imaginary part.  Each keeps
+// its own coefficients (noise, data, spectrum, tau) and its own random stream
+// (pair 0, the words a lone chain uses), so every chain equals the one the
+// unpacked sampler draws; the transforms are shared.
+//
+// With Z = F(t_A + i t_B), problem A's spectrum is (Z(k) + conj Z(-k)) / 2 and
+// B's (Z(k) - conj Z(-k)) / 2i.  Algorithm 1's Fourier step of each chain
+// (S_A = f_A A + w_A Re-part draw, S_B likewise; the Re part of w eta is
+// (w eta(k) + w conj eta(-k)) / 2) recombines into
+//   S(k) = f+ Z(k) + f- conj Z(-k)
+//          + w_A (eta_A(k) + conj eta_A(-k)) / 2 + i w_B (eta_B(k) + conj eta_B(-k)) / 2,
+// f+- = (f_A +- f_B) / 2, so every mode meets its mirror -k.  Column tiles
+// hold mirror pairs of columns (columns c and W - c, with the self-mirror
+// columns 0 and W/2 together in tile 0), as in the hierarchical sampler.
+#include "mf_device.hpp"
+#include "mf_kernels.hpp"
+#include "mf_streamed_fft.hpp"
+
+namespace mf {
+
+namespace {
+
+template <int L>
+struct PackShape {
+    static constexpr int TC = L >= 2048 ? 8 : 16;
+    static constexpr int NTH = L >= 1024 ? 1024 : (L >= 512 ? 512 : 256);
+    static constexpr int TPC = NTH / TC;
+    static constexpr int SEG = L + 32 / TC;
+};
+
+// Opaque copies: values derived from them are not kept live across the transforms.
+__device__ __forceinline__ unsigned opaque_u(unsigned v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Column held by slot s of tile j (slots s < half: columns j half + s; the
+// others their mirrors W - c, with column 0's mirror slot holding W/2).
+__device__ __forceinline__ int mirror_column(int j, int s, int half, int W) {
+    if (s < half) return j * half + s;
+    const int c = j * half + (s - half);
+    return c == 0 ? W / 2 : W - c;
+}
+
+// Harmonic-stage normal of mode e of pair 0 of problem pid.
+__device__ __forceinline__ float2 chain0_mode_normal(uint32_t e, uint32_t sweep, uint32_t pid, uint32_t k0,
+                                                     uint32_t k1) {
+    const Normals2 z = pair_normals(e >> 1, sweep, pid, kStageHarmonic, 0u, k0, k1);
+    return (e & 1u) ? z.b : z.a;
+}
+
+template <int L>
+__global__ __launch_bounds__(PackShape<L>::NTH) void col_pack_kernel(SweepArgs a, int W) {
+    constexpr int TC = PackShape<L>::TC, NTH = PackShape<L>::NTH, TPC = PackShape<L>::TPC, SEG = PackShape<L>::SEG;
+    constexpr int H = L;
+    constexpr int half = TC / 2;
+    __shared__ float2 lds[TC * SEG];
+    __shared__ float2 twl[L >= 256 ? L : 1];
+    const unsigned tid = threadIdx.x;
+    const int64_t t = xcd_block(blockIdx.x, gridDim.x);
+    const int item = (int)(t / (W / TC));
+    const int j = (int)(t % (W / TC));
+    const ItemDev it = a.items[item];
+    const ProbDev pa = a.probs[it.prob];
+    const ProbDev pb = it.pair >= 0 ? a.probs[it.pair] : pa;
+    float2* fld = a.field + it.field_off;
+
+    auto col_of = [&](int s) { return mirror_column(j, s, half, W); };
+    if constexpr (L >= 256) {
+        col_first_forward<L, TC, NTH, SEG>(lds, fld, W, tid, col_of);
+        for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];
+    } else {
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const int s = (int)(e % TC), y = (int)(e / TC);
+            lds[s * SEG + swz(y)] = fld[(int64_t)y * W + mirror_column(j, s, half, W)];
+        }
+    }
+    __syncthreads();
+    const unsigned cid = tid / TPC, lane = tid % TPC;
+    if constexpr (L >= 256) col_forward_rest<L, TPC>(lds + cid * SEG, lane, twl);
+    else stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
+
+    // one job per mode pair {k, -k}; in tile 0 the self-mirror columns 0
+    // (slot 0) and W/2 (slot half) take the rows ky <= H/2
+    const float TA = a.lambda * pa.tau, TB = a.lambda * pb.tau;
+    const float inv_n = 1.0f / ((float)H * (float)W);
+    const uint32_t pidA = (uint32_t)pa.pid, pidB = (uint32_t)pb.pid;
+    const int jobs = half * H + (j == 0 ? H / 2 + 1 : 0);
+#pragma unroll 1
+    for (int q = opaque_u(tid); q < jobs; q += NTH) {
+        int s, ky;
+        if (q < half * H) {
+            s = q % half;
+            ky = q / half;
+            if (j == 0 && s == 0 && ky > H / 2) continue;
+        } else {
+            s = half;
+            ky = q - half * H;
+        }
+        const bool self_col = j == 0 && (s == 0 || s == half);
+        const int p = self_col ? s : s + half;
+        const int my = (H - ky) & (H - 1);
+        const bool self = self_col && my == ky;
+        const int ck = mirror_column(j, s, half, W), cm = mirror_column(j, p, half, W);
+        float2& zk = lds[s * SEG + swz(ky)];
+        float2& zm = lds[p * SEG + swz(my)];
+        const float2 Zk = zk, Zm = zm;
+        const uint32_t ek = (uint32_t)(ky * W + ck), em = (uint32_t)(my * W + cm);
+        // isotropic spectra: n P(-k) = n P(k)
+        const float PA = a.nP[pa.pix_off + ek], PB = a.nP[pb.pix_off + ek];
+        const float rA = __builtin_amdgcn_rcpf(PA + TA), rB = __builtin_amdgcn_rcpf(PB + TB);
+        const float fA = PA * rA * inv_n, fB = PB * rB * inv_n;
+        const float wA = __builtin_amdgcn_sqrtf(PA * TA * rA * inv_n), wB = __builtin_amdgcn_sqrtf(PB * TB * rB * inv_n);
+        const float fp = 0.5f * (fA + fB), fm = 0.5f * (fA - fB);
+        float2 Nk = make_float2(0.f, 0.f), Nm = Nk;
+        if (a.stochastic) {
+            const float2 hkA = chain0_mode_normal(ek, a.sweep, pidA, a.key0, a.key1);
+            const float2 hmA = self ? hkA : chain0_mode_normal(em, a.sweep, pidA, a.key0, a.key1);
+            const float2 hkB = chain0_mode_normal(ek, a.sweep, pidB, a.key0, a.key1);
+            const float2 hmB = self ? hkB : chain0_mode_normal(em, a.sweep, pidB, a.key0, a.key1);
+            const float ha = 0.5f * wA, hb = it.pair >= 0 ? 0.5f * wB : 0.f;
+            // w_A (eta_A(k) + conj eta_A(-k)) / 2 + i w_B (eta_B(k) + conj eta_B(-k)) / 2, and with k, -k swapped
+            Nk = make_float2(fmaf(ha, hkA.x + hmA.x, -hb * (hkB.y - hmB.y)), fmaf(ha, hkA.y - hmA.y, hb * (hkB.x + hmB.x)));
+            Nm = make_float2(fmaf(ha, hmA.x + hkA.x, -hb * (hmB.y - hkB.y)), fmaf(ha, hmA.y - hkA.y, hb * (hmB.x + hkB.x)));
+        }
+        const float2 Sk = make_float2(fmaf(fp, Zk.x, fm * Zm.x) + Nk.x, fmaf(fp, Zk.y, -fm * Zm.y) + Nk.y);
+        const float2 Sm = make_float2(fmaf(fp, Zm.x, fm * Zk.x) + Nm.x, fmaf(fp, Zm.y, -fm * Zk.y) + Nm.y);
+        zk = Sk;
+        if (!self) zm = Sm;
+    }
+    __syncthreads();
+    if constexpr (L >= 256) {
+        col_inverse_head<L, TPC>(lds + opaque_u(cid) * SEG, opaque_u(lane), twl + opaque_u(0u));
+        col_last_inverse<L, TC, NTH, SEG>(lds, fld, W, opaque_u(tid), twl + opaque_u(0u), col_of);
+    } else {
+        stockham_fft<L, 1, TPC, true>(lds + opaque_u(cid) * SEG, opaque_u(lane), a.tw_col);
+        for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
+            const int s = (int)(e % TC), y = (int)(e / TC);
+            fld[(int64_t)y * W + mirror_column(j, s, half, W)] = lds[s * SEG + swz(y)];
+        }
+    }
+}
+
+}  // namespace
+
+hipError_t launch_col_pack(int W, int H, const SweepArgs& a, hipStream_t s) {
+    if (!is_pow2(W) || !is_pow2(H) || W < 16) return hipErrorInvalidValue;
+    switch (H) {
+#define MF_PACK_CASE(N)                                                                                  \
+    case N:                                                                                              \
+        hipLaunchKernelGGL((col_pack_kernel<N>), dim3((unsigned)((int64_t)a.n_items * (W / PackShape<N>::TC))), \
+                           dim3(PackShape<N>::NTH), 0, s, a, W);                                         \
+        break;
+        MF_PACK_CASE(16) MF_PACK_CASE(32) MF_PACK_CASE(64) MF_PACK_CASE(128) MF_PACK_CASE(256) MF_PACK_CASE(512)
+        MF_PACK_CASE(1024) MF_PACK_CASE(2048)
+#undef MF_PACK_CASE
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mf

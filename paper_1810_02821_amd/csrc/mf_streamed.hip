@@ -77,10 +77,47 @@ __device__ __forceinline__ float pix_a(float T, float nb) {
     return T * __builtin_amdgcn_rcpf(T + nb);
 }
 
+// Sample emission of one row segment value at pixel x: both chains of a
+// pair, or, packed, chain 0 of each of the two problems.
+struct RowEmit {
+    float* o0;
+    float* o1;
+    __device__ __forceinline__ void put(unsigned x, float2 s) const {
+        if (o0) o0[x] = s.x;
+        if (o1) o1[x] = s.y;
+    }
+};
+__device__ __forceinline__ RowEmit row_emit(const SweepArgs& a, const ItemDev& it, int y, int W) {
+    RowEmit e{nullptr, nullptr};
+    if (a.packed) {
+        const ProbDev pa = a.probs[it.prob];
+        const int64_t na = (int64_t)pa.H * pa.W;
+        e.o0 = a.samples + (int64_t)a.n_samples * pa.pix_off + (int64_t)a.emit_index * na + (int64_t)y * W;
+        if (it.pair >= 0) {
+            const ProbDev pb = a.probs[it.pair];
+            e.o1 = a.samples + (int64_t)a.n_samples * pb.pix_off + (int64_t)a.emit_index * na + (int64_t)y * W;
+        }
+        return e;
+    }
+    const ProbDev pr = a.probs[it.prob];
+    const int64_t base = (int64_t)a.chains * a.n_samples * pr.pix_off;
+    const int64_t n = (int64_t)pr.H * pr.W;
+    const int c0 = 2 * it.pair, c1 = 2 * it.pair + 1;
+    e.o0 = a.samples + base + ((int64_t)c0 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
+    if (c1 < a.chains) e.o1 = a.samples + base + ((int64_t)c1 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
+    return e;
+}
+
+// The second problem of a packed item (its own one when the item has no partner).
+__device__ __forceinline__ ProbDev partner_of(const SweepArgs& a, const ItemDev& it, const ProbDev& pr) {
+    return it.pair >= 0 ? a.probs[it.pair] : pr;
+}
+
 // Rows per block of the fused row kernel: twice row_kernel's at 512 pixels
 // (every lane busy in the radix-16 passes: the uneven batch's 512^2 row launch
 // 14% faster), the same elsewhere (twice as many rows ran the uneven batch's
 // 256^2 rows 5%, 1024^2 8% and 2048^2 4% slower).
+// The autotuner may pick another of the shapes of fused_row_candidates.
 template <int L>
 struct RowShapeF {
     static constexpr int ROWS = L == 512 ? 8 : 2048 / L;
@@ -163,16 +200,8 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
             for (unsigned x = lane; x < (unsigned)L; x += TPR)
                 a.s_save[it.field_off + (int64_t)y * W + x] = row[swz(x)];
         if (a.emit_index >= 0 && valid) {
-            const int64_t base = (int64_t)a.chains * a.n_samples * pr.pix_off;
-            const int64_t n = (int64_t)pr.H * pr.W;
-            const int c0 = 2 * it.pair, c1 = 2 * it.pair + 1;
-            float* o0 = a.samples + base + ((int64_t)c0 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
-            float* o1 = a.samples + base + ((int64_t)c1 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
-            for (unsigned x = lane; x < (unsigned)L; x += TPR) {
-                const float2 s = row[swz(x)];
-                o0[x] = s.x;
-                if (c1 < a.chains) o1[x] = s.y;
-            }
+            const RowEmit em = row_emit(a, it, y, W);
+            for (unsigned x = lane; x < (unsigned)L; x += TPR) em.put(x, row[swz(x)]);
         }
         if constexpr (!(MODE & kRowFwd)) {
             if (a.pix_mode == kPixAdjoint) {
@@ -214,6 +243,38 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
             // ---- pixel-space messenger update t = (1 - a) s + src + sigma_t xi
             const float T = a.lambda * pr.tau;
             double acc = 0.0;
+            if (a.packed) {
+                // chain 0 of problem A (real part) and of problem B (imaginary
+                // part), each with its own tables and stream (pair 0, words .x)
+                const ProbDev pb = partner_of(a, it, pr);
+                const float TB = a.lambda * pb.tau;
+#pragma unroll 2
+                for (unsigned pp = lane; pp < (unsigned)L / 2; pp += TPR) {
+                    const unsigned x = 2 * pp;
+                    const int64_t off = (int64_t)y * W + x;
+                    const float2 na = *reinterpret_cast<const float2*>(a.nbar + pr.pix_off + off);
+                    const float2 da = *reinterpret_cast<const float2*>(a.src + pr.pix_off + off);
+                    const float2 nbb = *reinterpret_cast<const float2*>(a.nbar + pb.pix_off + off);
+                    const float2 db = *reinterpret_cast<const float2*>(a.src + pb.pix_off + off);
+                    const uint32_t j = (uint32_t)(off >> 1);
+                    const Normals2 za = pair_normals(j, a.sweep, (uint32_t)pr.pid, kStagePixel, 0u, a.key0, a.key1);
+                    const Normals2 zb = pair_normals(j, a.sweep, (uint32_t)pb.pid, kStagePixel, 0u, a.key0, a.key1);
+                    const float aA[2] = {pix_a(T, na.x), pix_a(T, na.y)}, aB[2] = {pix_a(TB, nbb.x), pix_a(TB, nbb.y)};
+                    const float dA[2] = {da.x, da.y}, dB[2] = {db.x, db.y};
+                    const float zA[2] = {za.a.x, za.b.x}, zB[2] = {zb.a.x, zb.b.x};
+#pragma unroll
+                    for (int q = 0; q < 2; ++q) {
+                        float2& sv = row[swz(x + q)];
+                        const float omA = 1.0f - aA[q], omB = 1.0f - aB[q];
+                        const float sA = aA[q] > 0.f ? aA[q] * dA[q] : 0.f, sB = aB[q] > 0.f ? aB[q] * dB[q] : 0.f;
+                        const float gA = __builtin_amdgcn_sqrtf(fmaxf(T * omA, 0.f));
+                        const float gB = __builtin_amdgcn_sqrtf(fmaxf(TB * omB, 0.f));
+                        // an item without a partner keeps its imaginary part at zero
+                        sv = make_float2(fmaf(omA, sv.x, fmaf(gA, zA[q], sA)),
+                                         it.pair >= 0 ? fmaf(omB, sv.y, fmaf(gB, zB[q], sB)) : 0.f);
+                    }
+                }
+            } else
 #pragma unroll 2
             for (unsigned pp = lane; pp < (unsigned)L / 2; pp += TPR) {
                 const unsigned x = 2 * pp;
@@ -294,10 +355,10 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
 //      natural-order row straight to HBM.
 // The same arithmetic, pass for pass and pixel for pixel, as row_kernel with
 // the plan of row_inverse / row_forward, so the two round identically.
-template <int L>
+template <int L, int ROWS_>
 __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
-    constexpr int ROWS = RowShapeF<L>::ROWS;
-    constexpr int TPR = RowShapeF<L>::TPR;
+    constexpr int ROWS = ROWS_;
+    constexpr int TPR = kThreads / ROWS;
     constexpr int W = L;
     constexpr int RL = last_radix<L>();
     constexpr int NT16 = L / 16;                    // radix-16 butterflies per row
@@ -380,16 +441,39 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
             dft<RL, true>(v[i]);
             // v[i][r] is now the state at pixel x = j + r NTL
             if (a.emit_index >= 0 && valid) {
-                const int64_t base = (int64_t)a.chains * a.n_samples * pr.pix_off;
-                const int64_t n = (int64_t)pr.H * pr.W;
-                const int c0 = 2 * it.pair, c1 = 2 * it.pair + 1;
-                float* o0 = a.samples + base + ((int64_t)c0 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
-                float* o1 = a.samples + base + ((int64_t)c1 * a.n_samples + a.emit_index) * n + (int64_t)y * W;
+                const RowEmit em = row_emit(a, it, y, W);
+#pragma unroll
+                for (int r = 0; r < RL; ++r) em.put(j + r * NTL, v[i][r]);
+            }
+            if (a.packed) {
+                // two single-chain problems: for each pixel pair the even lane
+                // draws problem A's normals, the odd lane problem B's, and each
+                // passes the other the word of the other pixel
+                const ProbDev pb = partner_of(a, it, pr);
+                const float TB = a.lambda * pb.tau;
 #pragma unroll
                 for (int r = 0; r < RL; ++r) {
-                    o0[j + r * NTL] = v[i][r].x;
-                    if (c1 < a.chains) o1[j + r * NTL] = v[i][r].y;
+                    const unsigned x = j + r * NTL;
+                    const int64_t off = (int64_t)y * W + x;
+                    const uint32_t pj = (uint32_t)(off >> 1);
+                    const Normals2 nz = pair_normals(pj, a.sweep, (uint32_t)(odd ? pb.pid : pr.pid), kStagePixel, 0u,
+                                                     a.key0, a.key1);
+                    // even lane (pixel 2pj): keeps A's .a, sends A's .b; odd lane (pixel 2pj+1): keeps B's .b, sends B's .a
+                    const float keep = odd ? nz.b.x : nz.a.x;
+                    const float recv = swap_lanes(odd ? nz.a.x : nz.b.x);
+                    const float zA = odd ? recv : keep, zB = odd ? keep : recv;
+                    const float aA = pix_a(T, a.nbar[pr.pix_off + off]), aB = pix_a(TB, a.nbar[pb.pix_off + off]);
+                    const float dA = a.src[pr.pix_off + off], dB = a.src[pb.pix_off + off];
+                    const float omA = 1.0f - aA, omB = 1.0f - aB;
+                    const float sA = aA > 0.f ? aA * dA : 0.f, sB = aB > 0.f ? aB * dB : 0.f;
+                    const float gA = __builtin_amdgcn_sqrtf(fmaxf(T * omA, 0.f));
+                    const float gB = __builtin_amdgcn_sqrtf(fmaxf(TB * omB, 0.f));
+                    // an item without a partner keeps its imaginary part at zero
+                    v[i][r] = make_float2(fmaf(omA, v[i][r].x, fmaf(gA, zA, sA)),
+                                          it.pair >= 0 ? fmaf(omB, v[i][r].y, fmaf(gB, zB, sB)) : 0.f);
                 }
+                dft<RL, false>(v[i]);
+                continue;
             }
             // normals: the even lane draws the pairs of r < RL/2, the odd lane
             // those of r >= RL/2; each passes its partner the half it needs
@@ -1072,6 +1156,56 @@ __global__ void fill_items_kernel(ItemDev* out, const ProbDev* probs, const int3
     }
 }
 
+__global__ void fill_packed_items_kernel(ItemDev* out, const int32_t* pids, int n_pids, int64_t hw) {
+    const int n = (n_pids + 1) / 2;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+        out[i] = ItemDev{pids[2 * i], 2 * i + 1 < n_pids ? pids[2 * i + 1] : -1, (int64_t)i * hw};
+}
+
+// Packed work field from single-chain states: the real part of problem A's
+// pair-0 state, and of B's, or zero / dispersed (stage-2 words .x of each
+// problem's pair 0) starts.
+__global__ void pack_init_kernel(SweepArgs a, int H, int W, const float2* state_in, float init_scale) {
+    const int64_t n = (int64_t)H * W;
+    const int64_t total = (int64_t)a.n_items * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total / 2;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t g = 2 * e;
+        const int item = (int)(g / n);
+        const int64_t i = g % n;
+        const ItemDev it = a.items[item];
+        const ProbDev pa = a.probs[it.prob];
+        const ProbDev pb = it.pair >= 0 ? a.probs[it.pair] : pa;
+        float2 v0 = make_float2(0.f, 0.f), v1 = v0;
+        if (state_in) {
+            v0 = make_float2(state_in[pa.pix_off + i].x, state_in[pb.pix_off + i].x);
+            v1 = make_float2(state_in[pa.pix_off + i + 1].x, state_in[pb.pix_off + i + 1].x);
+        } else if (init_scale > 0.f) {
+            const Normals2 za = pair_normals((uint32_t)(i >> 1), 0u, (uint32_t)pa.pid, kStageInit, 0u, a.key0, a.key1);
+            const Normals2 zb = pair_normals((uint32_t)(i >> 1), 0u, (uint32_t)pb.pid, kStageInit, 0u, a.key0, a.key1);
+            v0 = make_float2(init_scale * za.a.x, init_scale * zb.a.x);
+            v1 = make_float2(init_scale * za.b.x, init_scale * zb.b.x);
+        }
+        if (it.pair < 0) v0.y = v1.y = 0.f;  // no partner: the imaginary part stays zero
+        a.field[it.field_off + i] = v0;
+        a.field[it.field_off + i + 1] = v1;
+    }
+}
+
+__global__ void pack_copy_out_kernel(SweepArgs a, int H, int W, float2* out) {
+    const int64_t n = (int64_t)H * W;
+    const int64_t total = (int64_t)a.n_items * n;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int item = (int)(e / n);
+        const int64_t i = e % n;
+        const ItemDev it = a.items[item];
+        const float2 v = a.field[it.field_off + i];
+        out[a.probs[it.prob].pix_off + i] = make_float2(v.x, 0.f);
+        if (it.pair >= 0) out[a.probs[it.pair].pix_off + i] = make_float2(v.y, 0.f);
+    }
+}
+
 __global__ void zero_words_kernel(uint32_t* p, int64_t n) {
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x)
         p[e] = 0u;
@@ -1093,19 +1227,26 @@ __global__ void add_kernel(const float* x, float* y, int64_t n) {
 }
 
 // One block per item: any NaN or infinity in the item's field lowers the
-// flag to the item's problem index.
+// flag to the item's problem index (packed items: the real part belongs to
+// problem `prob`, the imaginary part to `pair`).
 __global__ void finite_check_kernel(SweepArgs a, int64_t n, int32_t* flag) {
     const ItemDev it = a.items[blockIdx.x];
-    bool bad = false;
+    bool bad_a = false, bad_b = false;
     with_storage(a.storage, [&](auto e0) {
         using E = decltype(e0);
         const E* fld = reinterpret_cast<const E*>(a.field) + it.field_off;
         for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
             const float2 v = widen(fld[i]);
-            bad |= !(isfinite(v.x) && isfinite(v.y));
+            bad_a |= !isfinite(v.x);
+            bad_b |= !isfinite(v.y);
         }
     });
-    if (__syncthreads_or(bad) && threadIdx.x == 0) atomicMin(flag, it.prob);
+    if (!a.packed) bad_a |= bad_b;
+    const bool any_a = __syncthreads_or(bad_a), any_b = __syncthreads_or(bad_b);
+    if (threadIdx.x == 0) {
+        if (any_a) atomicMin(flag, it.prob);
+        if (a.packed && any_b && it.pair >= 0) atomicMin(flag, it.pair);
+    }
 }
 
 // Loss terms per item (one item per problem, real fields).
@@ -1201,16 +1342,19 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
     const bool fused = MODE == kRowInvFwd && W >= 256 && is_pow2(W) && a.pix_mode == kPixUpdate && !a.s_save &&
                        !a.plain_kernels;
     if (fused) {
-        const int rows_f = W == 512 ? 8 : 2048 / W;
+        const int rows_f = a.row_rows > 0 ? a.row_rows : (W == 512 ? 8 : 2048 / W);
         const dim3 grid((unsigned)((total + rows_f - 1) / rows_f));
-        switch (W) {
-            case 256: hipLaunchKernelGGL((row_kernel_f<256>), grid, dim3(kThreads), 0, s, a, H); break;
-            case 512: hipLaunchKernelGGL((row_kernel_f<512>), grid, dim3(kThreads), 0, s, a, H); break;
-            case 1024: hipLaunchKernelGGL((row_kernel_f<1024>), grid, dim3(kThreads), 0, s, a, H); break;
-            case 2048: hipLaunchKernelGGL((row_kernel_f<2048>), grid, dim3(kThreads), 0, s, a, H); break;
-            default: return hipErrorInvalidValue;
-        }
-        return hipGetLastError();
+#define MF_ROWF_CASE(LL, RR)                                                                  \
+    if (W == LL && rows_f == RR) {                                                             \
+        hipLaunchKernelGGL((row_kernel_f<LL, RR>), grid, dim3(kThreads), 0, s, a, H);         \
+        return hipGetLastError();                                                              \
+    }
+        MF_ROWF_CASE(256, 8) MF_ROWF_CASE(256, 4) MF_ROWF_CASE(256, 16)
+        MF_ROWF_CASE(512, 8) MF_ROWF_CASE(512, 4)
+        MF_ROWF_CASE(1024, 2) MF_ROWF_CASE(1024, 1) MF_ROWF_CASE(1024, 4)
+        MF_ROWF_CASE(2048, 1) MF_ROWF_CASE(2048, 2)
+#undef MF_ROWF_CASE
+        return hipErrorInvalidValue;
     }
     const bool ok = with_any_length(W, [&](auto c) {
         constexpr int N = decltype(c)::value;
@@ -1228,6 +1372,15 @@ dim3 elementwise_grid(int64_t total) {
 }
 
 }  // namespace
+
+int fused_row_candidates(int W, int* rows, int max_n) {
+    static const int table[][2] = {{256, 8}, {256, 4}, {256, 16}, {512, 8}, {512, 4},
+                                   {1024, 2}, {1024, 1}, {1024, 4}, {2048, 1}, {2048, 2}};
+    int n = 0;
+    for (const auto& r : table)
+        if (r[0] == W && n < max_n) rows[n++] = r[1];
+    return n;
+}
 
 int row_blocks_per_item(int W, int H) {
     const int rows = rows_per_block(W);
@@ -1399,6 +1552,26 @@ hipError_t launch_fill_items(ItemDev* out, const ProbDev* probs, const int32_t* 
     const int n = n_pids * per;
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(fill_items_kernel, elementwise_grid(n), dim3(256), 0, s, out, probs, pids, n, per, local, hw);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_packed_items(ItemDev* out, const int32_t* pids, int n_pids, int64_t hw, hipStream_t s) {
+    if (n_pids <= 0) return hipSuccess;
+    hipLaunchKernelGGL(fill_packed_items_kernel, elementwise_grid((n_pids + 1) / 2), dim3(256), 0, s, out, pids, n_pids,
+                       hw);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_init(int W, int H, const SweepArgs& a, const float2* state_in, float init_scale,
+                            hipStream_t s) {
+    hipLaunchKernelGGL(pack_init_kernel, elementwise_grid((int64_t)a.n_items * H * W / 2), dim3(256), 0, s, a, H, W,
+                       state_in, init_scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_pack_copy_out(int W, int H, const SweepArgs& a, float2* state_out, hipStream_t s) {
+    hipLaunchKernelGGL(pack_copy_out_kernel, elementwise_grid((int64_t)a.n_items * H * W), dim3(256), 0, s, a, H, W,
+                       state_out);
     return hipGetLastError();
 }
 

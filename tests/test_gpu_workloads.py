@@ -185,12 +185,45 @@ def test_autotuned_shapes_give_identical_samples(torch_cuda):
     a, _ = base.sample(d, 5, chains=2, burn_in=1, n_samples=2, form="streamed")
     b, _ = tuned.sample(d, 5, chains=2, burn_in=1, n_samples=2, form="streamed")
     shapes = {p.H: (base.tile_shape(p.H, p.W), tuned.tile_shape(p.H, p.W)) for p in probs}
-    print("default / tuned column tiles:", shapes)
+    rows = {p.H: (base.row_shape(p.H, p.W), tuned.row_shape(p.H, p.W)) for p in probs}
+    print("default / tuned column tiles:", shapes, "fused row rows:", rows)
     defaults = {256: (16, 256), 512: (16, 512), 1024: (8, 512), 2048: (8, 512)}
+    row_defaults = {256: 8, 512: 8, 1024: 2, 2048: 1}
+    row_choices = {256: (8, 4, 16), 512: (8, 4), 1024: (2, 1, 4), 2048: (1, 2)}
     for H, (dflt, tuned_shape) in shapes.items():
         assert dflt == defaults[H]
         assert tuned_shape[0] in (4, 8, 16) and tuned_shape[1] in (256, 512, 1024)
+        assert rows[H][0] == row_defaults[H] and rows[H][1] in row_choices[H]
     assert torch.equal(a, b)
+
+
+def test_every_fused_row_shape_gives_identical_samples(torch_cuda, tmp_path, monkeypatch):
+    """Each rows-per-workgroup choice of the fused row kernel (forced through
+    the tuning cache file) draws the default shape's samples bit for bit."""
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("fused row shapes 256/512/1024/2048")
+    probs = [synth.config_128(1, 256), synth.config_128(2, 512), synth.config_large(0, 1024),
+             synth.config_large(1, 2048)]
+    base = mf.Plan(probs)
+    d = base.concat([p.d for p in probs])
+    ref, _ = base.sample(d, 5, chains=2, burn_in=2, n_samples=2, form="streamed")
+    alts = {256: (4, 16), 512: (4,), 1024: (1, 4), 2048: (2,)}
+    for k in range(2):
+        cache = tmp_path / f"tune{k}.txt"
+        lines = []
+        for p in probs:
+            c = alts[p.H]
+            lines.append(f"gfx950 {p.H} {p.W} {base.tile_shape(p.H, p.W)[0]} {base.tile_shape(p.H, p.W)[1]}")
+            lines.append(f"gfx950-rows {p.H} {p.W} {c[k % len(c)]}")
+        cache.write_text("\n".join(lines) + "\n")
+        monkeypatch.setenv("MF_TUNE_CACHE", str(cache))
+        plan = mf.Plan(probs, autotune=True)
+        got = {p.H: plan.row_shape(p.H, p.W) for p in probs}
+        assert got == {p.H: alts[p.H][k % len(alts[p.H])] for p in probs}
+        out, _ = plan.sample(d, 5, chains=2, burn_in=2, n_samples=2, form="streamed")
+        assert torch.equal(out, ref), f"row shapes {got}"
+        plan.close()
 
 
 @pytest.mark.parametrize("size,ckpt", [(64, 7), (64, 500), (256, 20)])
