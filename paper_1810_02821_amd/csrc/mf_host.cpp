@@ -426,6 +426,12 @@ mf_status class_items(mf_plan p, std::pair<int, int> cls, int per, bool local, b
                           bands_only, s, out, n_out);
 }
 
+// A work item built on the host (with its copy of the problem record).
+mf::ItemDev item_of(mf_plan p, int pid, int pair, int64_t field_off) {
+    const HostProblem& hp = p->probs[pid];
+    return mf::ItemDev{pid, pair, field_off, hp.pix_off, (float)hp.tau, pid};
+}
+
 // Upload a host-built work list at element offset `slot` of the items
 // workspace (the residual tests' shrinking lists; those calls synchronise).
 mf_status put_items(mf_plan p, const std::vector<mf::ItemDev>& it, size_t slot, hipStream_t s,
@@ -449,7 +455,7 @@ mf_status solve_class(mf_plan p, const std::vector<int>& pids, int H, int W, con
                       std::vector<mf_info>& info, hipStream_t s) {
     const int n_items = (int)pids.size();
     std::vector<mf::ItemDev> items(n_items);  // host copy for the residual bookkeeping
-    for (int i = 0; i < n_items; ++i) items[i] = {pids[i], 0, p->probs[pids[i]].pix_off};
+    for (int i = 0; i < n_items; ++i) items[i] = item_of(p, pids[i], 0, p->probs[pids[i]].pix_off);
     mf::ItemDev* d_items = nullptr;
     int n_dev = 0;
     mf_status st = class_items(p, {H, W}, 1, false, false, s, &d_items, &n_dev);
@@ -1127,7 +1133,7 @@ mf_status autotune(mf_plan p) {
         const int pid = kv.second[0];
         const int n_items = std::max(1, std::min(16, (int)(2 * (4096 * 4096 / ((int64_t)H * W)))));
         std::vector<mf::ItemDev> items(n_items);
-        for (int i = 0; i < n_items; ++i) items[i] = {pid, i, (int64_t)i * H * W};
+        for (int i = 0; i < n_items; ++i) items[i] = item_of(p, pid, i, (int64_t)i * H * W);
         DevBuf fld, it, src;
         MF_HIP(fld.ensure((size_t)n_items * H * W * sizeof(float2)));
         MF_HIP(it.ensure(items.size() * sizeof(mf::ItemDev)));
@@ -1304,7 +1310,7 @@ mf_status sample_impl(mf_plan p, const float* d, const mf_sample_args* g, const 
             n_items = (n_pids + 1) / 2;
             if ((size_t)n_items > w.items_cap) return fail(MF_ERR_INVALID_ARG, "internal: items workspace too small");
             di = w.items;
-            MF_HIP(mf::launch_fill_packed_items(di, p->d_class_pids + p->class_all.at(kv.first).first, n_pids,
+            MF_HIP(mf::launch_fill_packed_items(di, p->d_probs, p->d_class_pids + p->class_all.at(kv.first).first, n_pids,
                                                 (int64_t)H * W, s));
             st = sample_streamed(p, di, n_items, H, W, d, &gm, w.field, sin, samples_out, w.graphs, true, s);
             if (st != MF_OK) return st;

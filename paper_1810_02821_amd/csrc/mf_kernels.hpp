@@ -14,11 +14,16 @@ struct ProbDev {
     int32_t pid;        // problem index (random-stream counter word)
 };
 
-// One unit of work: a chain pair of a problem (or a single real solve).
+// One unit of work: a chain pair of a problem (or a single real solve).  It
+// repeats the problem record's offset, tau and index, so that a streamed block
+// reads one record before it can address its field and tables, not two in turn.
 struct ItemDev {
     int32_t prob;
     int32_t pair;
     int64_t field_off;  // float2 offset of this item's field in the work buffer
+    int64_t pix_off;    // = probs[prob].pix_off
+    float tau;          // = probs[prob].tau
+    int32_t pid;        // = probs[prob].pid
 };
 
 // Cooling levels carried by value in the kernel arguments of the persistent
@@ -135,7 +140,8 @@ hipError_t launch_band_power(int W, int H, const SweepArgs& a, const float* x, c
 hipError_t launch_fill_items(ItemDev* out, const ProbDev* probs, const int32_t* pids, int n_pids, int per,
                              int local, int64_t hw, hipStream_t s);
 // Packed work list: item i = (pids[2i], pids[2i+1] or -1, i * hw).
-hipError_t launch_fill_packed_items(ItemDev* out, const int32_t* pids, int n_pids, int64_t hw, hipStream_t s);
+hipError_t launch_fill_packed_items(ItemDev* out, const ProbDev* probs, const int32_t* pids, int n_pids, int64_t hw,
+                                    hipStream_t s);
 // Packed work field from the pair states [problem][1][H][W] (real parts), or
 // zero / dispersed starts; and back (imaginary parts of the states set to 0).
 hipError_t launch_pack_init(int W, int H, const SweepArgs& a, const float2* state_in, float init_scale,

@@ -61,10 +61,10 @@ __device__ __forceinline__ void harmonic_update(float2 (&v)[16], const ResidentA
 template <int N>
 __global__ __launch_bounds__(Res<N>::NT, 4) void resident_sample_kernel(ResidentArgs a) {
     constexpr int P = Res<N>::P;
-    __shared__ __align__(16) float2 lds[N * N];
-    __shared__ float2 twl[N];  // twiddles: LDS latency instead of a cache hit's in every pass
+    __shared__ __align__(16) float2 lds[Res<N>::LDS];
+    __shared__ float2 twl[Res<N>::TWS];  // twiddle tables of the four passes
     const unsigned tid = threadIdx.x;
-    for (unsigned i = tid; i < (unsigned)N; i += Res<N>::NT) twl[i] = a.tw[i];
+    fill_twiddle_tables<N>(twl, a.tw, tid);
     __syncthreads();  // the first forward pass reads twiddles before any exchange barrier
     const ItemDev it = a.items[blockIdx.x];
     const ProbDev pr = a.probs[it.prob];
@@ -98,12 +98,12 @@ __global__ __launch_bounds__(Res<N>::NT, 4) void resident_sample_kernel(Resident
         ak.psrc = per_sweep(a.psrc);
         ak.mcoef = per_sweep(a.mcoef);
         const float2* tw = twl + per_sweep_zero();
-        // Everything indexed by the thread id (LDS addresses, counter words of
-        // the normal stream) is recomputed each sweep rather than kept live.
-        // Each half of the sweep gets its own copy so that the forward pass's
-        // LDS addresses are not kept alive for reuse by the inverse pass.
+        // The first half of the sweep (pixel draw, forward FFT) keeps what it
+        // indexes by the thread id (LDS bases, counter words) live across
+        // sweeps; the second half recomputes its own from an opaque copy of
+        // the id each sweep, since keeping both halves' live spills registers
+        // (16 complex values per thread, 4 waves per SIMD).
         unsigned t = tid;
-        asm volatile("" : "+v"(t));
         pixel_update<N>(v, ak, pr, it.pair, sweep, t);
         forward_fft<N>(v, lds, tw, t);
         unsigned t2 = tid;

@@ -10,9 +10,22 @@
 // update happens in pass D's registers and the pixel-space update in pass A's,
 // and LDS is touched only for the three exchanges between passes.
 //
-// LDS exchanges use pitch N with per-exchange XOR swizzles of the column, and
-// 16-byte accesses where a thread moves two adjacent elements, so that every
-// 16- or 32-lane phase of an LDS instruction touches distinct banks.
+// LDS exchanges place each row at a base of its own and keep the column in
+// order, so that the elements one thread moves in an exchange lie at constant
+// offsets from one base (the immediate offsets of ds_read/ds_write, no address
+// arithmetic per element), while every 16- or 32-lane phase of an LDS
+// instruction still touches distinct banks:
+//   E1  row y starts at y N + 2 s(y) + 32 (y / R1), s(y) = (P/2)(y % R1) + (y / R1) % (P/2):
+//       the R1 rows of one 16-lane phase of pass A's 16-byte accesses fall
+//       on disjoint 128-byte halves of the banks, and 16 consecutive rows
+//       (pass B's lanes) on 16 distinct 16-byte bank groups;
+//   E2  pitch N + 1 (pass B's lanes walk rows, pass C's walk columns);
+//   E3  pitch N (both sides' lanes walk columns).
+// Twiddles W_N^(a b) sit in LDS in one small table per pass, row a (the
+// thread's own index: x0 in A, k1 in B and D, y0 in C) by column b (the
+// register's), so that a thread's twiddles too lie at constant offsets from
+// one base.  Pass A's rows have pitch 9, so that the eight rows one wave reads
+// fall on distinct banks; the other passes read one or a few rows per wave.
 #pragma once
 #include "mf_device.hpp"
 
@@ -26,19 +39,51 @@ struct Res {
     static constexpr int NT = N * N / 16;                  // threads per workgroup
     static constexpr int TB = 16 / P;                      // radix-P tasks per thread
     static constexpr int R1 = 32 / P;                      // pass-A rows per 16-lane phase
-    static constexpr int SW2 = (N < 32 ? N : 32) - 1;
+    static constexpr int LDS = N * N + N * P;              // float2 elements of the exchange buffer (E1's extent)
+    // twiddle tables: A [x0 < P][k1 < 8] pitch 9, B [k1 < 8][x0 < P],
+    // C [y0 < 8][k1 < P], D [k1 < P][y0 < 8]
+    static constexpr int TWA = 0, TWB = TWA + 9 * P, TWC = TWB + 8 * P, TWD = TWC + 8 * P;
+    static constexpr int TWS = TWD + 8 * P;                // float2 elements of the four tables
 };
+
+// Fill the twiddle tables from W_N^r (r < N); every product a b is below N.
+// Visible to the block after its next barrier.
+template <int N>
+__device__ __forceinline__ void fill_twiddle_tables(float2* t, const float2* __restrict__ tw, unsigned tid) {
+    constexpr int P = Res<N>::P;
+    for (unsigned e = tid; e < (unsigned)Res<N>::TWS; e += Res<N>::NT) {
+        unsigned r;
+        if (e < (unsigned)Res<N>::TWB) {
+            const unsigned q = e - Res<N>::TWA, a = q / 9, b = q % 9;
+            r = b < 8 ? a * b : 0;
+        } else if (e < (unsigned)Res<N>::TWC) {
+            const unsigned q = e - Res<N>::TWB;
+            r = (q / P) * (q % P);
+        } else if (e < (unsigned)Res<N>::TWD) {
+            const unsigned q = e - Res<N>::TWC;
+            r = (q / P) * (q % P);
+        } else {
+            const unsigned q = e - Res<N>::TWD;
+            r = (q / 8) * (q % 8);
+        }
+        t[e] = tw[r];
+    }
+}
 
 // E1 (between passes A and B): row y, column k1 P + x0
 template <int N>
-__device__ __forceinline__ unsigned e1(unsigned r, unsigned c) {
+__device__ __forceinline__ unsigned e1_row(unsigned r) {
     constexpr unsigned P = Res<N>::P, R1 = Res<N>::R1;
-    return r * N + (c ^ (P * (r % R1) + 2 * ((r / R1) % (P / 2))));
+    return r * N + 2 * ((P / 2) * (r % R1) + (r / R1) % (P / 2)) + 32 * (r / R1);
+}
+template <int N>
+__device__ __forceinline__ unsigned e1(unsigned r, unsigned c) {
+    return e1_row<N>(r) + c;
 }
 // E2 (between passes B and C): row y, column kx
 template <int N>
 __device__ __forceinline__ unsigned e2(unsigned r, unsigned c) {
-    return r * N + (c ^ (r & (unsigned)Res<N>::SW2));
+    return r * (N + 1) + c;
 }
 // E3 (between passes C and D): row 8 k1 + y0, column kx
 template <int N>
@@ -85,8 +130,8 @@ __device__ __forceinline__ const T* per_sweep(const T* p) {
 }
 
 template <bool INV>
-__device__ __forceinline__ float2 twiddle(float2 v, const float2* __restrict__ tw, int idx) {
-    const float2 w = tw[idx];
+__device__ __forceinline__ float2 twiddle(float2 v, const float2* __restrict__ row, int col) {
+    const float2 w = row[col];
     return INV ? cmulc(v, w) : cmul(v, w);
 }
 
@@ -105,9 +150,9 @@ __device__ __forceinline__ void pass_A(float2 (&v)[16], const float2* __restrict
     for (int q = 0; q < 2; ++q) {
         dft_slice<8, INV>(v + 8 * q);
         if (!INV) {
-            const unsigned x0 = 2 * j + q;
+            const float2* row = tw + Res<N>::TWA + 9 * (2 * j + q);
 #pragma unroll
-            for (int k1 = 1; k1 < 8; ++k1) v[8 * q + k1] = twiddle<false>(v[8 * q + k1], tw, x0 * k1);
+            for (int k1 = 1; k1 < 8; ++k1) v[8 * q + k1] = twiddle<false>(v[8 * q + k1], row, k1);
         }
     }
 }
@@ -159,9 +204,9 @@ __device__ __forceinline__ void pass_B(float2 (&v)[16], const float2* __restrict
     for (int i = 0; i < TB; ++i) {
         dft_slice<P, INV>(v + P * i);
         if (INV) {
-            const unsigned k1 = (tid + i * NT) / N;
+            const float2* row = tw + Res<N>::TWB + P * ((tid + i * NT) / N);
 #pragma unroll
-            for (int x0 = 1; x0 < P; ++x0) v[P * i + x0] = twiddle<true>(v[P * i + x0], tw, x0 * k1);
+            for (int x0 = 1; x0 < P; ++x0) v[P * i + x0] = twiddle<true>(v[P * i + x0], row, x0);
         }
     }
 }
@@ -221,9 +266,9 @@ __device__ __forceinline__ void pass_C(float2 (&v)[16], const float2* __restrict
     for (int i = 0; i < TB; ++i) {
         dft_slice<P, INV>(v + P * i);
         if (!INV) {
-            const unsigned y0 = tid / N + i * (P / 2);
+            const float2* row = tw + Res<N>::TWC + P * (tid / N + i * (P / 2));
 #pragma unroll
-            for (int k1 = 1; k1 < P; ++k1) v[P * i + k1] = twiddle<false>(v[P * i + k1], tw, y0 * k1);
+            for (int k1 = 1; k1 < P; ++k1) v[P * i + k1] = twiddle<false>(v[P * i + k1], row, k1);
         }
     }
 }
@@ -270,17 +315,18 @@ __device__ __forceinline__ void store_E3_from_D(float2* lds, const float2 (&v)[1
 // inverse: radix-8 over k2 -> y0, then twiddle conj W_N^(y0 k1).
 template <int N, bool INV>
 __device__ __forceinline__ void pass_D(float2 (&v)[16], const float2* __restrict__ tw, unsigned tid) {
-    const unsigned k1 = tid / (N / 2);
+    const float2* row = tw + Res<N>::TWD + 8 * (tid / (N / 2));
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         dft_slice<8, INV>(v + 8 * q);
         if (INV) {
 #pragma unroll
-            for (int y0 = 1; y0 < 8; ++y0) v[8 * q + y0] = twiddle<true>(v[8 * q + y0], tw, y0 * k1);
+            for (int y0 = 1; y0 < 8; ++y0) v[8 * q + y0] = twiddle<true>(v[8 * q + y0], row, y0);
         }
     }
 }
 
+// tw: the four twiddle tables in LDS (fill_twiddle_tables).
 template <int N>
 __device__ __forceinline__ void forward_fft(float2 (&v)[16], float2* lds, const float2* __restrict__ tw, unsigned tid) {
     pass_A<N, false>(v, tw, tid);

@@ -137,10 +137,10 @@ __device__ __forceinline__ void harmonic_shear(float2 (&v)[16], float2* lds, con
 template <int N>
 __global__ __launch_bounds__(Res<N>::NT, 4) void resident_shear_kernel(ShearArgs a) {
     constexpr int P = Res<N>::P;
-    __shared__ __align__(16) float2 lds[N * N];
-    __shared__ float2 twl[N];  // twiddles in LDS (an LDS read returns sooner than a cache hit)
+    __shared__ __align__(16) float2 lds[Res<N>::LDS];
+    __shared__ float2 twl[Res<N>::TWS];  // twiddle tables of the four passes
     const unsigned tid = threadIdx.x;
-    for (unsigned i = tid; i < (unsigned)N; i += Res<N>::NT) twl[i] = a.tw[i];
+    fill_twiddle_tables<N>(twl, a.tw, tid);
     __syncthreads();
     const ItemDev it = a.items[blockIdx.x];
     const ProbDev pr = a.probs[it.prob];

@@ -72,11 +72,11 @@ __device__ __forceinline__ double block_sum(double x, double* red) {
 template <int N>
 __global__ __launch_bounds__(Res<N>::NT, 4) void resident_solve_kernel(SolveArgs a) {
     constexpr int P = Res<N>::P, NT = Res<N>::NT;
-    __shared__ __align__(16) float2 lds[N * N];
+    __shared__ __align__(16) float2 lds[Res<N>::LDS];
     __shared__ double red[NT / 64];
-    __shared__ float2 twl[N];  // twiddles in LDS (an LDS read returns sooner than a cache hit)
+    __shared__ float2 twl[Res<N>::TWS];  // twiddle tables of the four passes
     const unsigned tid = threadIdx.x;
-    for (unsigned i = tid; i < (unsigned)N; i += NT) twl[i] = a.tw[i];
+    fill_twiddle_tables<N>(twl, a.tw, tid);
     __syncthreads();
     const ItemDev it = a.items[blockIdx.x];
     const ProbDev pr = a.probs[it.prob];

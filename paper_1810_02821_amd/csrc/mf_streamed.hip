@@ -379,13 +379,6 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     const unsigned lane = tid % TPR;
     const int64_t total_rows = (int64_t)a.n_items * H;
     const int64_t grow0 = (int64_t)xcd_block(blockIdx.x, gridDim.x) * ROWS;
-    const float2* twr;
-    if constexpr (kTwLds) {
-        for (unsigned i = tid; i < (unsigned)L; i += kThreads) twl[i] = a.tw_row[i];  // visible after the next barrier
-        twr = twl;
-    } else {
-        twr = a.tw_row;
-    }
     for (unsigned r = tid; r < (unsigned)ROWS; r += kThreads) {
         const int64_t g = grow0 + r;
         row_item[r] = g < total_rows ? (int32_t)(a.rows_by_item ? g / H : g % a.n_items) : -1;
@@ -395,10 +388,34 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     const bool valid = row_item[rid] >= 0;
     const int item = valid ? row_item[rid] : 0;
     const int y = row_y[rid];
+    // One record read before the field: the item carries its problem's
+    // offset, tau and index.  The twiddle loads go out beside it (the table
+    // is visible after stage A's barrier), and the pixel tables of stage C
+    // beside the field loads, so that a block waits for memory twice before
+    // it computes (a single 256^2 problem has 32 blocks, all latency).
     const ItemDev it = a.items[item];
-    const ProbDev pr = a.probs[it.prob];
+    const float2* twr;
+    if constexpr (kTwLds) {
+        for (unsigned i = tid; i < (unsigned)L; i += kThreads) twl[i] = a.tw_row[i];
+        twr = twl;
+    } else {
+        twr = a.tw_row;
+    }
+    const ProbDev pr{H, W, it.pix_off, it.tau, it.pid};
     float2* row = lds + rid * L;
     const int64_t frow = it.field_off + (int64_t)y * W;
+    float pnb[ITL][RL], psr[ITL][RL];
+    if (!a.packed) {
+        const int64_t prow = pr.pix_off + (int64_t)y * W;
+#pragma unroll
+        for (int i = 0; i < ITL; ++i)
+#pragma unroll
+            for (int r = 0; r < RL; ++r) {
+                const unsigned x = lane + i * TPR + r * NTL;
+                pnb[i][r] = a.nbar[prow + x];
+                psr[i][r] = a.src[prow + x];
+            }
+    }
 
     // ---- A: first inverse pass (NS = 1), inputs from HBM
     with_storage(a.storage, [&](auto e0) {
@@ -502,9 +519,8 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const unsigned x = j + r * NTL;
-                const int64_t pix = pr.pix_off + (int64_t)y * W + x;
-                const float aa = pix_a(T, a.nbar[pix]);
-                const float sr = a.src[pix];
+                const float aa = pix_a(T, pnb[i][r]);
+                const float sr = psr[i][r];
                 const float oma = 1.0f - aa;
                 float src;
                 if (a.src_kind == kSrcData) src = aa > 0.f ? aa * sr : 0.f;
@@ -743,11 +759,25 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);
     const int item = (int)(t / (W / TC));
     const int x0 = (int)(t % (W / TC)) * TC;
+    // one record read before the field (the item carries its problem's
+    // offset, tau and index); the twiddles go out beside it and the mode
+    // table of phase C beside the field loads
     const ItemDev it = a.items[item];
-    const ProbDev pr = a.probs[it.prob];
-    const int64_t f0 = it.field_off + x0;
-
     for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];  // visible after phase A's barrier
+    const ProbDev pr{H, W, it.pix_off, it.tau, it.pid};
+    const int64_t f0 = it.field_off + x0;
+    float2 pnp[ITL][RL];
+    {
+        const unsigned pp = tid / TPP, lane = tid % TPP;
+        const float2* npt = a.nPt + pr.pix_off / 2 + (int64_t)((x0 + 2 * (int)pp) / 2) * H;
+#pragma unroll
+        for (int i = 0; i < ITL; ++i) {
+            const unsigned j = lane + i * TPP;
+#pragma unroll
+            for (int r = 0; r < RL; ++r)
+                pnp[i][r] = NTL % TPP == 0 || j < (unsigned)NTL ? npt[j + r * NTL] : make_float2(0.f, 0.f);
+        }
+    }
 
     // ---- A: first forward pass (NS = 1), inputs from HBM
     with_storage(a.storage, [&](auto e0) {
@@ -788,7 +818,6 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
         const float inv_n = 1.0f / ((float)H * (float)W);
         const unsigned pp = tid / TPP, lane = tid % TPP;
         const int kx0 = x0 + 2 * (int)pp;
-        const float2* npt = a.nPt + pr.pix_off / 2 + (int64_t)(kx0 / 2) * H;
         float2 v[ITL][2][RL];
 #pragma unroll
         for (int i = 0; i < ITL; ++i) {
@@ -810,7 +839,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
 #pragma unroll
                 for (int r = 0; r < RL; ++r) {
                     const unsigned ky = j + r * NTL;
-                    const float2 np = npt[ky];
+                    const float2 np = pnp[i][r];
                     float2 z[2] = {make_float2(0.f, 0.f), make_float2(0.f, 0.f)};
                     if (a.stochastic) {
                         const int64_t mode = (int64_t)ky * W + kx0;
@@ -1152,14 +1181,20 @@ __global__ void fill_items_kernel(ItemDev* out, const ProbDev* probs, const int3
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
         const int pid = pids[i / per];
         const int q = i % per;
-        out[i] = ItemDev{pid, q, local ? (int64_t)i * hw : (int64_t)per * probs[pid].pix_off + (int64_t)q * hw};
+        const ProbDev pr = probs[pid];
+        out[i] = ItemDev{pid, q, local ? (int64_t)i * hw : (int64_t)per * pr.pix_off + (int64_t)q * hw, pr.pix_off,
+                         pr.tau, pr.pid};
     }
 }
 
-__global__ void fill_packed_items_kernel(ItemDev* out, const int32_t* pids, int n_pids, int64_t hw) {
+__global__ void fill_packed_items_kernel(ItemDev* out, const ProbDev* probs, const int32_t* pids, int n_pids,
+                                         int64_t hw) {
     const int n = (n_pids + 1) / 2;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-        out[i] = ItemDev{pids[2 * i], 2 * i + 1 < n_pids ? pids[2 * i + 1] : -1, (int64_t)i * hw};
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const ProbDev pr = probs[pids[2 * i]];
+        out[i] = ItemDev{pids[2 * i], 2 * i + 1 < n_pids ? pids[2 * i + 1] : -1, (int64_t)i * hw, pr.pix_off, pr.tau,
+                         pr.pid};
+    }
 }
 
 // Packed work field from single-chain states: the real part of problem A's
@@ -1555,10 +1590,11 @@ hipError_t launch_fill_items(ItemDev* out, const ProbDev* probs, const int32_t* 
     return hipGetLastError();
 }
 
-hipError_t launch_fill_packed_items(ItemDev* out, const int32_t* pids, int n_pids, int64_t hw, hipStream_t s) {
+hipError_t launch_fill_packed_items(ItemDev* out, const ProbDev* probs, const int32_t* pids, int n_pids, int64_t hw,
+                                    hipStream_t s) {
     if (n_pids <= 0) return hipSuccess;
-    hipLaunchKernelGGL(fill_packed_items_kernel, elementwise_grid((n_pids + 1) / 2), dim3(256), 0, s, out, pids, n_pids,
-                       hw);
+    hipLaunchKernelGGL(fill_packed_items_kernel, elementwise_grid((n_pids + 1) / 2), dim3(256), 0, s, out, probs, pids,
+                       n_pids, hw);
     return hipGetLastError();
 }
 
