@@ -457,6 +457,17 @@ mf_status mf_plan_tile_shape(mf_plan plan, int32_t H, int32_t W, int32_t* cols, 
  * MF_ERR_INVALID_ARG if the plan has no problem of that size. */
 mf_status mf_plan_row_shape(mf_plan plan, int32_t H, int32_t W, int32_t* rows);
 
+/* Shapes of the size class H x W for launches too small to fill the GPU: a
+ * launch whose grid in the shapes above would have fewer workgroups than the
+ * GPU has compute units (256; a single Wiener solve or adjoint of a 256^2 or
+ * 512^2 image, a few chains) uses these instead.  Under MF_FLAG_AUTOTUNE they
+ * are timed on one work item; otherwise they are the candidates with the most
+ * workgroups.  *cols x *threads: column tile; *rows: rows per workgroup of the
+ * fused row kernel (0 where none runs).  Every shape computes the same values
+ * bit for bit.  MF_ERR_INVALID_ARG if the plan has no problem of that size. */
+mf_status mf_plan_narrow_shape(mf_plan plan, int32_t H, int32_t W, int32_t* cols, int32_t* threads,
+                               int32_t* rows);
+
 /* Number of bands over all band-spectrum problems (length of grad_bands). */
 int32_t mf_plan_total_bands(mf_plan plan);
 

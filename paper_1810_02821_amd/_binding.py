@@ -94,6 +94,7 @@ EXPORTS = ["mf_plan_create", "mf_plan_destroy", "mf_plan_reserve", "mf_plan_set_
            "mf_wiener_backward_unrolled", "mf_band_power", "mf_plan_tile_shape", "mf_sample_spectrum",
            "mf_sample_moments", "mf_shear_wiener", "mf_shear_sample", "mf_band_loss", "mf_sample_noalloc",
            "mf_plan_row_shape",
+           "mf_plan_narrow_shape",
            "mf_status_string",
            "mf_last_error"]
 
@@ -133,6 +134,8 @@ def lib():
     L.mf_wiener_backward_unrolled.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_int32, vp, vp, vp, vp, vp]
     L.mf_plan_tile_shape.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
     L.mf_plan_row_shape.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32)]
+    L.mf_plan_narrow_shape.argtypes = [vp, C.c_int32, C.c_int32, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                       C.POINTER(C.c_int32)]
     L.mf_sample_spectrum.argtypes = [vp, vp, C.POINTER(_SpectrumArgs), vp, vp, vp, vp, vp, vp, vp]
     L.mf_sample_moments.argtypes = [vp, vp, C.c_int32, C.c_int32, vp, vp, vp]
     L.mf_shear_wiener.argtypes = [vp, vp, C.POINTER(_Schedule), C.c_float, vp, vp]
@@ -144,7 +147,8 @@ def lib():
                  "mf_wiener",
                  "mf_sample", "mf_sample_noalloc", "mf_wiener_backward", "mf_wiener_backward_unrolled",
                  "mf_band_power",
-                 "mf_plan_tile_shape", "mf_plan_row_shape", "mf_sample_spectrum", "mf_sample_moments",
+                 "mf_plan_tile_shape", "mf_plan_row_shape", "mf_plan_narrow_shape", "mf_sample_spectrum",
+                 "mf_sample_moments",
                  "mf_shear_wiener",
                  "mf_shear_sample"):
         getattr(L, name).restype = C.c_int
@@ -445,6 +449,12 @@ class Plan:
         r = C.c_int32()
         _check(lib().mf_plan_row_shape(self._h, int(H), int(W), C.byref(r)))
         return r.value
+
+    def narrow_shape(self, H: int, W: int):
+        """(columns, threads, rows) used for size class H x W by launches too small to fill the GPU."""
+        c, t, r = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(lib().mf_plan_narrow_shape(self._h, int(H), int(W), C.byref(c), C.byref(t), C.byref(r)))
+        return c.value, t.value, r.value
 
     def state_view(self, flat, problem: int, chains: int):
         """Complex pair states [pairs, H, W] of one problem in a state buffer."""

@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <array>
 #include <map>
 #include <string>
 #include <vector>
@@ -112,6 +113,8 @@ struct mf_plan_s {
     DevBuf kfield;                          // streamed mass mapping: kappa staging field
     // column-kernel tile shape per size class: (H, W) -> (tc, nth)
     std::map<std::pair<int, int>, std::pair<int, int>> col_shape;
+    std::map<std::pair<int, int>, std::pair<int, int>> col_shape_narrow;  // tuned on one item
+    std::map<std::pair<int, int>, int> row_rows_narrow;
     // rows per block of the fused row kernel per size class (absent: default)
     std::map<std::pair<int, int>, int> row_rows;
     // captured sweep loops of the streamed sampler, keyed by launch configuration
@@ -308,8 +311,20 @@ std::pair<int, int> class_shape(mf_plan p, int H, int W) {
     return {tc[0], nth[0]};
 }
 
+// The tile of a launch over n_items work items: the class's shape, or its
+// narrow shape when the class's shape would leave CUs idle.
+std::pair<int, int> class_shape(mf_plan p, int H, int W, int64_t n_items) {
+    const auto wide = class_shape(p, H, W);
+    if (n_items * ((W + wide.first - 1) / wide.first) >= mf::kFillBlocks) return wide;
+    auto it = p->col_shape_narrow.find({H, W});
+    if (it != p->col_shape_narrow.end()) return it->second;
+    int tc = 0, nth = 0;
+    mf::narrow_col_shape(H, &tc, &nth);
+    return {tc, nth};
+}
+
 hipError_t launch_col_class(mf_plan p, int W, int H, const mf::SweepArgs& a, hipStream_t s) {
-    const auto sh = class_shape(p, H, W);
+    const auto sh = class_shape(p, H, W, a.n_items);
     return mf::launch_col_shape(W, H, sh.first, sh.second, a, s);
 }
 
@@ -325,6 +340,8 @@ mf::SweepArgs base_args(mf_plan p, int H, int W) {
     a.emit_index = -1;
     auto rr = p->row_rows.find({H, W});
     a.row_rows = rr == p->row_rows.end() ? 0 : rr->second;
+    auto rn = p->row_rows_narrow.find({H, W});
+    a.row_rows_narrow = rn == p->row_rows_narrow.end() ? 0 : rn->second;
     return a;
 }
 
@@ -974,7 +991,7 @@ mf_status sample_streamed(mf_plan p, const mf::ItemDev* d_items, int n_items, in
                           bool graphs, bool packed, hipStream_t s) {
     if (!(p->flags & MF_FLAG_GRAPH) || !graphs)
         return enqueue_streamed(p, d_items, n_items, H, W, d, g, work, state_in, samples, packed, s);
-    const auto sh = class_shape(p, H, W);
+    const auto sh = class_shape(p, H, W, n_items);
     const std::vector<uint64_t> key = {1, (uint64_t)H, (uint64_t)W, (uint64_t)n_items, (uint64_t)(uintptr_t)d_items,
                                        (uint64_t)(uintptr_t)d, (uint64_t)(uintptr_t)work,
                                        (uint64_t)(uintptr_t)state_in, (uint64_t)(uintptr_t)samples, g->seed,
@@ -1089,15 +1106,17 @@ mf_status autotune(mf_plan p) {
     const char* cache_path = std::getenv("MF_TUNE_CACHE");
     std::map<std::pair<int, int>, std::pair<int, int>> cached;
     std::map<std::pair<int, int>, int> cached_rows;
+    std::map<std::pair<int, int>, std::array<int, 3>> cached_narrow;
     if (cache_path) {
         if (FILE* f = std::fopen(cache_path, "r")) {
             char line[256];
             while (std::fgets(line, sizeof line, f)) {
                 char arch[64];
-                int H, W, x, y;
-                const int n = std::sscanf(line, "%63s %d %d %d %d", arch, &H, &W, &x, &y);
+                int H, W, x, y, z;
+                const int n = std::sscanf(line, "%63s %d %d %d %d %d", arch, &H, &W, &x, &y, &z);
                 if (n == 5 && std::string(arch) == "gfx950") cached[{H, W}] = {x, y};
                 else if (n >= 4 && std::string(arch) == "gfx950-rows") cached_rows[{H, W}] = x;
+                else if (n == 6 && std::string(arch) == "gfx950-narrow") cached_narrow[{H, W}] = {x, y, z};
             }
             std::fclose(f);
         }
@@ -1125,11 +1144,27 @@ mf_status autotune(mf_plan p) {
         const int nr = mf::fused_row_candidates(W, rows, 8);
         auto cc = cached.find({H, W});
         auto cr = cached_rows.find({H, W});
+        auto cn = cached_narrow.find({H, W});
         if (cc != cached.end()) p->col_shape[{H, W}] = cc->second;
         if (cr != cached_rows.end()) p->row_rows[{H, W}] = cr->second;
+        if (cn != cached_narrow.end()) {
+            p->col_shape_narrow[{H, W}] = {cn->second[0], cn->second[1]};
+            if (cn->second[2] > 0) p->row_rows_narrow[{H, W}] = cn->second[2];
+        }
         const bool tune_col = nc > 1 && cc == cached.end();
         const bool tune_row = nr > 1 && cr == cached_rows.end();
-        if (!tune_col && !tune_row) continue;
+        const bool tune_narrow = (nc > 1 || nr > 1) && cn == cached_narrow.end();
+        // whether the class's shapes (as chosen so far) leave CUs idle on one item
+        auto narrow_need = [&](bool* col_narrow, bool* row_narrow) {
+            const auto wide = class_shape(p, H, W);
+            auto rw = p->row_rows.find({H, W});
+            const int rows_w = rw != p->row_rows.end() ? rw->second : (nr > 0 ? rows[0] : 0);
+            *col_narrow = nc > 1 && (W + wide.first - 1) / wide.first < mf::kFillBlocks;
+            *row_narrow = nr > 1 && rows_w > 0 && (H + rows_w - 1) / rows_w < mf::kFillBlocks;
+        };
+        bool col_narrow = false, row_narrow = false;
+        narrow_need(&col_narrow, &row_narrow);
+        if (!tune_col && !tune_row && !(tune_narrow && (col_narrow || row_narrow))) continue;
         const int pid = kv.second[0];
         const int n_items = std::max(1, std::min(16, (int)(2 * (4096 * 4096 / ((int64_t)H * W)))));
         std::vector<mf::ItemDev> items(n_items);
@@ -1186,6 +1221,49 @@ mf_status autotune(mf_plan p) {
             if (cache_path)
                 if (FILE* f = std::fopen(cache_path, "a")) {
                     std::fprintf(f, "gfx950-rows %d %d %d\n", H, W, rows[bi]);
+                    std::fclose(f);
+                }
+        }
+        // the shapes of launches too small to fill the GPU, timed on one item
+        // (a single solve); only where the class's shapes would leave CUs idle
+        narrow_need(&col_narrow, &row_narrow);
+        if (tune_narrow && (col_narrow || row_narrow)) {
+            mf::SweepArgs b = a;
+            b.n_items = 1;
+            int ntc = 0, nnth = 0;
+            mf::narrow_col_shape(H, &ntc, &nnth);
+            int nrows = mf::narrow_row_rows(W);
+            if (col_narrow) {
+                float best = 1e30f;
+                for (int ci = 0; ci < nc && st == MF_OK; ++ci) {
+                    float ms = 0.f;
+                    st = time_launches([&] { return mf::launch_col_shape(W, H, tc[ci], nth[ci], b, nullptr); }, &ms);
+                    if (ms < best) {
+                        best = ms;
+                        ntc = tc[ci];
+                        nnth = nth[ci];
+                    }
+                }
+            }
+            if (row_narrow) {
+                float best = 1e30f;
+                for (int ri = 0; ri < nr && st == MF_OK; ++ri) {
+                    float ms = 0.f;
+                    mf::SweepArgs c = b;
+                    c.row_rows = c.row_rows_narrow = rows[ri];  // this shape in either regime
+                    st = time_launches([&] { return mf::launch_row(W, H, mf::kRowInvFwd, c, nullptr); }, &ms);
+                    if (ms < best) {
+                        best = ms;
+                        nrows = rows[ri];
+                    }
+                }
+            }
+            if (st != MF_OK) return st;
+            p->col_shape_narrow[{H, W}] = {ntc, nnth};
+            if (nrows > 0) p->row_rows_narrow[{H, W}] = nrows;
+            if (cache_path)
+                if (FILE* f = std::fopen(cache_path, "a")) {
+                    std::fprintf(f, "gfx950-narrow %d %d %d %d %d\n", H, W, ntc, nnth, nrows);
                     std::fclose(f);
                 }
         }
@@ -1417,7 +1495,7 @@ mf_status ensure_unrolled_workspace(mf_plan p, int K, int C, hipStream_t s) {
     for (auto& kv : p->classes) {
         const int H = kv.first.first, W = kv.first.second;
         n_max = std::max(n_max, kv.second.size() * (size_t)H * W);
-        const int tc = class_shape(p, H, W).first;
+        const int tc = class_shape(p, H, W, (int64_t)kv.second.size()).first;  // one item per problem
         tiles_max = std::max(tiles_max, kv.second.size() * (size_t)((W + tc - 1) / tc));
     }
     const size_t ncp = (size_t)(K + C - 1) / C;
@@ -1744,6 +1822,23 @@ mf_status mf_plan_row_shape(mf_plan p, int32_t H, int32_t W, int32_t* rows) {
     return MF_OK;
 }
 
+mf_status mf_plan_narrow_shape(mf_plan p, int32_t H, int32_t W, int32_t* cols, int32_t* threads, int32_t* rows) {
+    if (!p || !cols || !threads || !rows) return fail(MF_ERR_INVALID_ARG, "plan, cols, threads and rows are required");
+    if (!p->classes.count({H, W})) return fail(MF_ERR_INVALID_ARG, "the plan has no problem of that size");
+    auto it = p->col_shape_narrow.find({H, W});
+    int tc = 0, nth = 0;
+    mf::narrow_col_shape(H, &tc, &nth);
+    if (it != p->col_shape_narrow.end()) {
+        tc = it->second.first;
+        nth = it->second.second;
+    }
+    auto rn = p->row_rows_narrow.find({H, W});
+    *cols = tc;
+    *threads = nth;
+    *rows = rn != p->row_rows_narrow.end() ? rn->second : mf::narrow_row_rows(W);
+    return MF_OK;
+}
+
 mf_status mf_plan_tile_shape(mf_plan p, int32_t H, int32_t W, int32_t* cols, int32_t* threads) {
     if (!p || !cols || !threads) return fail(MF_ERR_INVALID_ARG, "plan, cols and threads are required");
     if (!p->classes.count({H, W})) return fail(MF_ERR_INVALID_ARG, "the plan has no problem of that size");
@@ -1846,7 +1941,7 @@ mf_status mf_wiener_backward_unrolled(mf_plan p, const float* d, const mf_schedu
         mf::ItemDev* di = nullptr;
         int n_items = 0;
         if ((st = class_items(p, kv.first, 1, true, false, s, &di, &n_items)) != MF_OK) return st;
-        const auto sh = class_shape(p, H, W);
+        const auto sh = class_shape(p, H, W, n_items);
         const size_t n_tiles = (size_t)n_items * ((W + sh.first - 1) / sh.first);
         float2* F = p->field.as<float2>();
         float2* FA = p->field_adj.as<float2>();

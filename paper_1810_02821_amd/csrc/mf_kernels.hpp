@@ -81,6 +81,7 @@ struct SweepArgs {
     int32_t plain_kernels;    // 1: row_kernel / col_kernel_t only (no fused variants)
     int32_t rows_by_item;     // row enumeration: 1 g = item H + y (one item per problem), 0 g = y n_items + item
     int32_t row_rows;         // rows per block of the fused row kernel (0: the default shape)
+    int32_t row_rows_narrow;  // the same when that shape leaves CUs idle (0: the narrow default)
     int32_t packed;           // 1: each item carries two single-chain problems, chain 0 of problem `prob`
                               // in the real part and chain 0 of problem `pair` (-1: none) in the imaginary
                               // part, each with its own tables and random stream (sampler, streamed form)
@@ -107,6 +108,12 @@ int col_shape_candidates(int H, int* tc, int* nth, int max_n);
 // Rows per block of the fused row kernel available for a row length (the
 // first is the default; none below 256 points or for non-powers of two).
 int fused_row_candidates(int W, int* rows, int max_n);
+// A launch whose grid in the default (or tuned) shape would have fewer blocks
+// than the GPU has CUs (a single solve, a few chains) takes the narrow shape
+// instead: tuned on one item, else the candidate with the most blocks.
+constexpr int kFillBlocks = 256;
+void narrow_col_shape(int H, int* tc, int* nth);
+int narrow_row_rows(int W);
 // Sum per-tile band slots into out[band_base[prob] + b] for every item.
 hipError_t launch_band_slots_reduce(int W, int H, int tc, const SweepArgs& a, const int32_t* band_base,
                                     const int32_t* band_count, double* out, hipStream_t s);

@@ -1377,7 +1377,9 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
     const bool fused = MODE == kRowInvFwd && W >= 256 && is_pow2(W) && a.pix_mode == kPixUpdate && !a.s_save &&
                        !a.plain_kernels;
     if (fused) {
-        const int rows_f = a.row_rows > 0 ? a.row_rows : (W == 512 ? 8 : 2048 / W);
+        const int rows_w = a.row_rows > 0 ? a.row_rows : (W == 512 ? 8 : 2048 / W);
+        const int rows_n = a.row_rows_narrow > 0 ? a.row_rows_narrow : narrow_row_rows(W);
+        const int rows_f = (total + rows_w - 1) / rows_w < kFillBlocks ? rows_n : rows_w;
         const dim3 grid((unsigned)((total + rows_f - 1) / rows_f));
 #define MF_ROWF_CASE(LL, RR)                                                                  \
     if (W == LL && rows_f == RR) {                                                             \
@@ -1385,7 +1387,7 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
         return hipGetLastError();                                                              \
     }
         MF_ROWF_CASE(256, 8) MF_ROWF_CASE(256, 4) MF_ROWF_CASE(256, 16)
-        MF_ROWF_CASE(512, 8) MF_ROWF_CASE(512, 4)
+        MF_ROWF_CASE(512, 8) MF_ROWF_CASE(512, 4) MF_ROWF_CASE(512, 2)
         MF_ROWF_CASE(1024, 2) MF_ROWF_CASE(1024, 1) MF_ROWF_CASE(1024, 4)
         MF_ROWF_CASE(2048, 1) MF_ROWF_CASE(2048, 2)
 #undef MF_ROWF_CASE
@@ -1409,12 +1411,20 @@ dim3 elementwise_grid(int64_t total) {
 }  // namespace
 
 int fused_row_candidates(int W, int* rows, int max_n) {
-    static const int table[][2] = {{256, 8}, {256, 4}, {256, 16}, {512, 8}, {512, 4},
+    static const int table[][2] = {{256, 8}, {256, 4}, {256, 16}, {512, 8}, {512, 4}, {512, 2},
                                    {1024, 2}, {1024, 1}, {1024, 4}, {2048, 1}, {2048, 2}};
     int n = 0;
     for (const auto& r : table)
         if (r[0] == W && n < max_n) rows[n++] = r[1];
     return n;
+}
+
+int narrow_row_rows(int W) {
+    int rows[8];
+    const int n = fused_row_candidates(W, rows, 8);
+    int best = n > 0 ? rows[0] : 0;
+    for (int i = 1; i < n; ++i) best = rows[i] < best ? rows[i] : best;
+    return best;
 }
 
 int row_blocks_per_item(int W, int H) {
@@ -1452,8 +1462,11 @@ hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, h
     const bool fused = !a.t_store && !a.t_load && a.nPt && !a.plain_kernels;
     MF_COL_CASE(16, 16, 256) MF_COL_CASE(32, 16, 256) MF_COL_CASE(64, 16, 256) MF_COL_CASE(128, 16, 256)
     MF_COL_CASE_F(256, 16, 256) MF_COL_CASE_F(256, 8, 256) MF_COL_CASE_F(256, 16, 512) MF_COL_CASE_F(256, 8, 512)
+    MF_COL_CASE_F(256, 4, 128) MF_COL_CASE_F(256, 4, 256)
     MF_COL_CASE_F(512, 16, 512) MF_COL_CASE_F(512, 8, 512) MF_COL_CASE_F(512, 16, 256) MF_COL_CASE_F(512, 16, 1024)
+    MF_COL_CASE_F(512, 8, 256) MF_COL_CASE_F(512, 4, 256)
     MF_COL_CASE_F(1024, 16, 1024) MF_COL_CASE_F(1024, 8, 1024) MF_COL_CASE_F(1024, 8, 512) MF_COL_CASE_F(1024, 16, 512)
+    MF_COL_CASE_F(1024, 4, 256)
     MF_COL_CASE_F(2048, 8, 1024) MF_COL_CASE_F(2048, 8, 512) MF_COL_CASE_F(2048, 4, 512) MF_COL_CASE_F(2048, 4, 256)
     // the other 2^a 3^b lengths: the plain kernel in its default tile
     bool launched = false;
@@ -1475,8 +1488,11 @@ hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, h
 int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
     static const int table[][3] = {{16, 16, 256}, {32, 16, 256}, {64, 16, 256}, {128, 16, 256},
                                    {256, 16, 256}, {256, 8, 256}, {256, 16, 512}, {256, 8, 512},
+                                   {256, 4, 128}, {256, 4, 256},
                                    {512, 16, 512}, {512, 8, 512}, {512, 16, 256}, {512, 16, 1024},
+                                   {512, 8, 256}, {512, 4, 256},
                                    {1024, 8, 512}, {1024, 16, 1024}, {1024, 8, 1024}, {1024, 16, 512},
+                                   {1024, 4, 256},
                                    {2048, 8, 512}, {2048, 8, 1024}, {2048, 4, 512}, {2048, 4, 256}};
     int n = 0;
     for (const auto& r : table)
@@ -1491,6 +1507,16 @@ int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
         n = 1;
     }
     return n;
+}
+
+void narrow_col_shape(int H, int* tc, int* nth) {
+    int t[16], n[16];
+    const int k = col_shape_candidates(H, t, n, 16);
+    int b = 0;
+    for (int i = 1; i < k; ++i)
+        if (t[i] < t[b] || (t[i] == t[b] && n[i] < n[b])) b = i;
+    *tc = k > 0 ? t[b] : col_tc_of(H);
+    *nth = k > 0 ? n[b] : col_nth_of(H);
 }
 
 hipError_t launch_band_slots_reduce(int W, int H, int tc, const SweepArgs& a, const int32_t* band_base,

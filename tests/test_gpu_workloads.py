@@ -189,11 +189,17 @@ def test_autotuned_shapes_give_identical_samples(torch_cuda):
     print("default / tuned column tiles:", shapes, "fused row rows:", rows)
     defaults = {256: (16, 256), 512: (16, 512), 1024: (8, 512), 2048: (8, 512)}
     row_defaults = {256: 8, 512: 8, 1024: 2, 2048: 1}
-    row_choices = {256: (8, 4, 16), 512: (8, 4), 1024: (2, 1, 4), 2048: (1, 2)}
+    row_choices = {256: (8, 4, 16), 512: (8, 4, 2), 1024: (2, 1, 4), 2048: (1, 2)}
+    # launches too small to fill the GPU: the shapes with the most workgroups
+    narrow_defaults = {256: (4, 128, 4), 512: (4, 256, 2), 1024: (4, 256, 1), 2048: (4, 256, 1)}
+    narrow = {p.H: (base.narrow_shape(p.H, p.W), tuned.narrow_shape(p.H, p.W)) for p in probs}
+    print("default / tuned narrow shapes:", narrow)
     for H, (dflt, tuned_shape) in shapes.items():
         assert dflt == defaults[H]
-        assert tuned_shape[0] in (4, 8, 16) and tuned_shape[1] in (256, 512, 1024)
+        assert tuned_shape[0] in (4, 8, 16) and tuned_shape[1] in (128, 256, 512, 1024)
         assert rows[H][0] == row_defaults[H] and rows[H][1] in row_choices[H]
+        assert narrow[H][0] == narrow_defaults[H]
+        assert narrow[H][1][0] in (4, 8, 16) and narrow[H][1][2] in row_choices[H]
     assert torch.equal(a, b)
 
 
@@ -224,6 +230,67 @@ def test_every_fused_row_shape_gives_identical_samples(torch_cuda, tmp_path, mon
         out, _ = plan.sample(d, 5, chains=2, burn_in=2, n_samples=2, form="streamed")
         assert torch.equal(out, ref), f"row shapes {got}"
         plan.close()
+
+
+COL_TILES = {256: ((16, 256), (8, 256), (16, 512), (8, 512), (4, 128), (4, 256)),
+             512: ((16, 512), (8, 512), (16, 256), (16, 1024), (8, 256), (4, 256)),
+             1024: ((8, 512), (16, 1024), (8, 1024), (16, 512), (4, 256))}
+
+
+def test_every_column_tile_gives_identical_samples(torch_cuda, tmp_path, monkeypatch):
+    """Each column tile of the streamed kernels, forced through the tuning
+    cache for both the wide and the narrow regime (one chain pair per problem
+    runs narrow at 256^2 and 512^2), draws the default shape's samples bit
+    for bit."""
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("column tiles 256/512/1024")
+    probs = [synth.config_128(1, 256), synth.config_128(2, 512), synth.config_large(0, 1024)]
+    base = mf.Plan(probs)
+    d = base.concat([p.d for p in probs])
+    ref, _ = base.sample(d, 9, chains=2, burn_in=2, n_samples=2, form="streamed")
+    for k in range(6):
+        cache = tmp_path / f"tiles{k}.txt"
+        lines = []
+        for p in probs:
+            tc, nth = COL_TILES[p.H][k % len(COL_TILES[p.H])]
+            lines.append(f"gfx950 {p.H} {p.W} {tc} {nth}")
+            lines.append(f"gfx950-rows {p.H} {p.W} {base.row_shape(p.H, p.W)}")
+            lines.append(f"gfx950-narrow {p.H} {p.W} {tc} {nth} {base.narrow_shape(p.H, p.W)[2]}")
+        cache.write_text("\n".join(lines) + "\n")
+        monkeypatch.setenv("MF_TUNE_CACHE", str(cache))
+        plan = mf.Plan(probs, autotune=True)
+        for p in probs:
+            assert plan.tile_shape(p.H, p.W) == COL_TILES[p.H][k % len(COL_TILES[p.H])]
+            assert plan.narrow_shape(p.H, p.W)[:2] == COL_TILES[p.H][k % len(COL_TILES[p.H])]
+        out, _ = plan.sample(d, 9, chains=2, burn_in=2, n_samples=2, form="streamed")
+        assert torch.equal(out, ref), f"tiles {k}"
+        plan.close()
+
+
+def test_narrow_solve_matches_wide_shapes(torch_cuda, tmp_path, monkeypatch):
+    """A single 256^2 Wiener solve runs in the narrow shapes (its default grid
+    would leave most CUs idle); forcing the wide shapes into the narrow regime
+    gives the same filter bit for bit, and both match the oracle."""
+    torch = torch_cuda
+    import paper_1810_02821_amd as mf
+    banner("narrow solve 256")
+    prob = synth.config_bands(3, 256, 32)
+    sch = mf.Schedule([100.0, 10.0, 1.0], [10, 10, 40])
+    base = mf.Plan([prob])
+    assert base.narrow_shape(256, 256) == (4, 128, 4)
+    d = base.concat([prob.d])
+    s_n, _ = base.wiener(d, sch, allow_not_converged=True)
+    cache = tmp_path / "wide.txt"
+    cache.write_text("gfx950 256 256 16 256\ngfx950-rows 256 256 8\ngfx950-narrow 256 256 16 256 8\n")
+    monkeypatch.setenv("MF_TUNE_CACHE", str(cache))
+    wide = mf.Plan([prob], autotune=True)
+    s_w, _ = wide.wiener(d, sch, allow_not_converged=True)
+    assert torch.equal(s_n, s_w)
+    ref = om.wiener(prob, om.Schedule((100.0, 10.0, 1.0), (10, 10, 40)))[0]
+    r = rel(base.split(s_n)[0], ref)
+    print(f"narrow solve vs oracle {r:.2e}")
+    assert r < REL_TOL
 
 
 @pytest.mark.parametrize("size,ckpt", [(64, 7), (64, 500), (256, 20)])
