@@ -355,8 +355,17 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
 //      natural-order row straight to HBM.
 // The same arithmetic, pass for pass and pixel for pixel, as row_kernel with
 // the plan of row_inverse / row_forward, so the two round identically.
-template <int L, int ROWS_>
+// Variants of the fused row kernel: pixel tables read in stage C (wide
+// launches, whose blocks hide the latency), read beside the field loads
+// (launches too small to fill the GPU), or either kind of item, a.packed
+// telling at run time whether each carries two single-chain problems (the
+// packed launches: built with both paths it takes 100 VGPRs at 512 points,
+// where a packed-only build took 130 and lost a wave per SIMD).
+enum RowVariant : int { kRowLoadLate = 0, kRowPrefetch = 1, kRowAny = 2 };
+
+template <int L, int ROWS_, int VAR>
 __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
+    constexpr bool kPrefetch = VAR == kRowPrefetch;
     constexpr int ROWS = ROWS_;
     constexpr int TPR = kThreads / ROWS;
     constexpr int W = L;
@@ -390,9 +399,9 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     const int y = row_y[rid];
     // One record read before the field: the item carries its problem's
     // offset, tau and index.  The twiddle loads go out beside it (the table
-    // is visible after stage A's barrier), and the pixel tables of stage C
-    // beside the field loads, so that a block waits for memory twice before
-    // it computes (a single 256^2 problem has 32 blocks, all latency).
+    // is visible after stage A's barrier); with kPrefetch the pixel tables of
+    // stage C go out beside the field loads, so that a block waits for memory
+    // twice before it computes.
     const ItemDev it = a.items[item];
     const float2* twr;
     if constexpr (kTwLds) {
@@ -404,8 +413,8 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     const ProbDev pr{H, W, it.pix_off, it.tau, it.pid};
     float2* row = lds + rid * L;
     const int64_t frow = it.field_off + (int64_t)y * W;
-    float pnb[ITL][RL], psr[ITL][RL];
-    if (!a.packed) {
+    float pnb[kPrefetch ? ITL : 1][kPrefetch ? RL : 1], psr[kPrefetch ? ITL : 1][kPrefetch ? RL : 1];
+    if constexpr (kPrefetch) {
         const int64_t prow = pr.pix_off + (int64_t)y * W;
 #pragma unroll
         for (int i = 0; i < ITL; ++i)
@@ -462,7 +471,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
 #pragma unroll
                 for (int r = 0; r < RL; ++r) em.put(j + r * NTL, v[i][r]);
             }
-            if (a.packed) {
+            if (VAR == kRowAny && a.packed) {
                 // two single-chain problems: for each pixel pair the even lane
                 // draws problem A's normals, the odd lane problem B's, and each
                 // passes the other the word of the other pixel
@@ -519,8 +528,16 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
 #pragma unroll
             for (int r = 0; r < RL; ++r) {
                 const unsigned x = j + r * NTL;
-                const float aa = pix_a(T, pnb[i][r]);
-                const float sr = psr[i][r];
+                float nb, sr;
+                if constexpr (kPrefetch) {
+                    nb = pnb[i][r];
+                    sr = psr[i][r];
+                } else {
+                    const int64_t pix = pr.pix_off + (int64_t)y * W + x;
+                    nb = a.nbar[pix];
+                    sr = a.src[pix];
+                }
+                const float aa = pix_a(T, nb);
                 const float oma = 1.0f - aa;
                 float src;
                 if (a.src_kind == kSrcData) src = aa > 0.f ? aa * sr : 0.f;
@@ -1264,13 +1281,16 @@ __global__ void add_kernel(const float* x, float* y, int64_t n) {
 // One block per item: any NaN or infinity in the item's field lowers the
 // flag to the item's problem index (packed items: the real part belongs to
 // problem `prob`, the imaginary part to `pair`).
-__global__ void finite_check_kernel(SweepArgs a, int64_t n, int32_t* flag) {
-    const ItemDev it = a.items[blockIdx.x];
+// Each item's field is scanned by `per` consecutive blocks (enough blocks over
+// all items to keep every CU streaming).
+__global__ void finite_check_kernel(SweepArgs a, int64_t n, int32_t per, int32_t* flag) {
+    const ItemDev it = a.items[blockIdx.x / per];
+    const int64_t b0 = blockIdx.x % per;
     bool bad_a = false, bad_b = false;
     with_storage(a.storage, [&](auto e0) {
         using E = decltype(e0);
         const E* fld = reinterpret_cast<const E*>(a.field) + it.field_off;
-        for (int64_t i = threadIdx.x; i < n; i += blockDim.x) {
+        for (int64_t i = b0 * blockDim.x + threadIdx.x; i < n; i += (int64_t)per * blockDim.x) {
             const float2 v = widen(fld[i]);
             bad_a |= !isfinite(v.x);
             bad_b |= !isfinite(v.y);
@@ -1379,12 +1399,19 @@ hipError_t launch_row_mode(int W, int H, const SweepArgs& a, hipStream_t s) {
     if (fused) {
         const int rows_w = a.row_rows > 0 ? a.row_rows : (W == 512 ? 8 : 2048 / W);
         const int rows_n = a.row_rows_narrow > 0 ? a.row_rows_narrow : narrow_row_rows(W);
-        const int rows_f = (total + rows_w - 1) / rows_w < kFillBlocks ? rows_n : rows_w;
+        const bool narrow = (total + rows_w - 1) / rows_w < kFillBlocks;
+        const int rows_f = narrow ? rows_n : rows_w;
+        const int var = a.packed ? kRowAny : (narrow ? kRowPrefetch : kRowLoadLate);
         const dim3 grid((unsigned)((total + rows_f - 1) / rows_f));
-#define MF_ROWF_CASE(LL, RR)                                                                  \
-    if (W == LL && rows_f == RR) {                                                             \
-        hipLaunchKernelGGL((row_kernel_f<LL, RR>), grid, dim3(kThreads), 0, s, a, H);         \
-        return hipGetLastError();                                                              \
+#define MF_ROWF_CASE(LL, RR)                                                                             \
+    if (W == LL && rows_f == RR) {                                                                        \
+        if (var == kRowAny)                                                                            \
+            hipLaunchKernelGGL((row_kernel_f<LL, RR, kRowAny>), grid, dim3(kThreads), 0, s, a, H);     \
+        else if (var == kRowPrefetch)                                                                     \
+            hipLaunchKernelGGL((row_kernel_f<LL, RR, kRowPrefetch>), grid, dim3(kThreads), 0, s, a, H);   \
+        else                                                                                              \
+            hipLaunchKernelGGL((row_kernel_f<LL, RR, kRowLoadLate>), grid, dim3(kThreads), 0, s, a, H);   \
+        return hipGetLastError();                                                                         \
     }
         MF_ROWF_CASE(256, 8) MF_ROWF_CASE(256, 4) MF_ROWF_CASE(256, 16)
         MF_ROWF_CASE(512, 8) MF_ROWF_CASE(512, 4) MF_ROWF_CASE(512, 2)
@@ -1662,7 +1689,12 @@ hipError_t launch_add(const float* x, float* y, int64_t n, hipStream_t s) {
 
 hipError_t launch_finite_check(int W, int H, const SweepArgs& a, int32_t* flag, hipStream_t s) {
     if (a.n_items <= 0) return hipSuccess;
-    hipLaunchKernelGGL(finite_check_kernel, dim3(a.n_items), dim3(256), 0, s, a, (int64_t)H * W, flag);
+    const int64_t n = (int64_t)H * W;
+    int64_t per = (2048 + a.n_items - 1) / a.n_items;  // about 2048 blocks in all
+    const int64_t most = (n + 255) / 256;
+    per = per < 1 ? 1 : (per > most ? most : per);
+    hipLaunchKernelGGL(finite_check_kernel, dim3((unsigned)(a.n_items * per)), dim3(256), 0, s, a, n, (int32_t)per,
+                       flag);
     return hipGetLastError();
 }
 
