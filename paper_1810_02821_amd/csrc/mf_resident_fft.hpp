@@ -20,7 +20,13 @@
 //       on disjoint 128-byte halves of the banks, and 16 consecutive rows
 //       (pass B's lanes) on 16 distinct 16-byte bank groups;
 //   E2  pitch N + 1 (pass B's lanes walk rows, pass C's walk columns);
-//   E3  pitch N (both sides' lanes walk columns).
+//   E3  pitch N + 1 as well (both sides' lanes walk columns).
+// Four of a sweep's twelve block barriers are not needed: in the exchanges
+// C -> C (E2 read, E3 written, and back), D -> D and A -> A each thread writes
+// exactly the addresses it has just read (E2 and E3 share a layout), and a
+// wave's LDS operations take effect in order, so no other thread can still be
+// waiting for what it overwrites.  A caller that writes LDS between two
+// transforms synchronises the block first.
 // Twiddles W_N^(a b) sit in LDS in one small table per pass, row a (the
 // thread's own index: x0 in A, k1 in B and D, y0 in C) by column b (the
 // register's), so that a thread's twiddles too lie at constant offsets from
@@ -88,7 +94,7 @@ __device__ __forceinline__ unsigned e2(unsigned r, unsigned c) {
 // E3 (between passes C and D): row 8 k1 + y0, column kx
 template <int N>
 __device__ __forceinline__ unsigned e3(unsigned r, unsigned c) {
-    return r * N + c;
+    return r * (N + 1) + c;
 }
 
 __device__ __forceinline__ void st2(float2* lds, unsigned i, float2 a, float2 b) {
@@ -297,18 +303,27 @@ __device__ __forceinline__ void load_C_from_E3(const float2* lds, float2 (&v)[16
     }
 }
 
+// (8-byte accesses: at pitch N + 1 a pair of columns is not 16-byte aligned)
 template <int N>
 __device__ __forceinline__ void load_D_from_E3(const float2* lds, float2 (&v)[16], unsigned tid) {
     const unsigned jx = tid % (N / 2), k1 = tid / (N / 2);
 #pragma unroll
-    for (int y0 = 0; y0 < 8; ++y0) ld2(lds, e3<N>(k1 * 8 + y0, 2 * jx), v[y0], v[8 + y0]);
+    for (int y0 = 0; y0 < 8; ++y0) {
+        const unsigned i = e3<N>(k1 * 8 + y0, 2 * jx);
+        v[y0] = lds[i];
+        v[8 + y0] = lds[i + 1];
+    }
 }
 
 template <int N>
 __device__ __forceinline__ void store_E3_from_D(float2* lds, const float2 (&v)[16], unsigned tid) {
     const unsigned jx = tid % (N / 2), k1 = tid / (N / 2);
 #pragma unroll
-    for (int y0 = 0; y0 < 8; ++y0) st2(lds, e3<N>(k1 * 8 + y0, 2 * jx), v[y0], v[8 + y0]);
+    for (int y0 = 0; y0 < 8; ++y0) {
+        const unsigned i = e3<N>(k1 * 8 + y0, 2 * jx);
+        lds[i] = v[y0];
+        lds[i + 1] = v[8 + y0];
+    }
 }
 
 // pass D: forward radix-8 over y0 -> k2 (ky = k1 + P k2);
@@ -338,12 +353,10 @@ __device__ __forceinline__ void forward_fft(float2 (&v)[16], float2* lds, const 
     store_E2_from_B<N>(lds, v, tid);
     __syncthreads();
     load_C_from_E2<N>(lds, v, tid);
-    __syncthreads();
     pass_C<N, false>(v, tw, tid);
-    store_E3_from_C<N>(lds, v, tid);
+    store_E3_from_C<N>(lds, v, tid);  // the addresses this thread read from E2
     __syncthreads();
     load_D_from_E3<N>(lds, v, tid);
-    __syncthreads();
     pass_D<N, false>(v, tw, tid);
 }
 
@@ -353,9 +366,8 @@ __device__ __forceinline__ void inverse_fft(float2 (&v)[16], float2* lds, const 
     store_E3_from_D<N>(lds, v, tid);
     __syncthreads();
     load_C_from_E3<N>(lds, v, tid);
-    __syncthreads();
     pass_C<N, true>(v, tw, tid);
-    store_E2_from_C<N>(lds, v, tid);
+    store_E2_from_C<N>(lds, v, tid);  // the addresses this thread read from E3
     __syncthreads();
     load_B_from_E2<N>(lds, v, tid);
     __syncthreads();
@@ -363,7 +375,6 @@ __device__ __forceinline__ void inverse_fft(float2 (&v)[16], float2* lds, const 
     store_E1_from_B<N>(lds, v, tid);
     __syncthreads();
     load_A_from_E1<N>(lds, v, tid);
-    __syncthreads();
     pass_A<N, true>(v, tw, tid);
 }
 

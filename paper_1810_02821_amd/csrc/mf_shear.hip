@@ -76,6 +76,7 @@ template <int N>
 __device__ __forceinline__ void harmonic_shear(float2 (&v)[16], float2* lds, const ShearArgs& a, const ProbDev& pr,
                                                float T, uint32_t sweep, int chain, unsigned tid) {
     constexpr int P = Res<N>::P;
+    __syncthreads();  // other threads may still read the forward transform's last exchange
     constexpr float n = (float)(N * N);
     constexpr float inv_n = 1.0f / (float)(N * N);
     const unsigned jx = tid % (N / 2), k1 = tid / (N / 2);

@@ -67,6 +67,7 @@ __device__ __forceinline__ void harmonic_pair(float2 (&v)[16], float2* lds, cons
     constexpr int P = Res<N>::P;
     const unsigned jx = tid % (N / 2), k1 = tid / (N / 2);
     const int16_t* band = a.band + pr.pix_off;
+    __syncthreads();  // other threads may still read the forward transform's last exchange
     // 1. Z to LDS in natural mode order
 #pragma unroll
     for (int k2 = 0; k2 < 8; ++k2) {
