@@ -82,44 +82,23 @@ __global__ __launch_bounds__(PackShape<L>::NTH) void col_pack_kernel(SweepArgs a
     if constexpr (L >= 256) col_forward_rest<L, TPC>(lds + cid * SEG, lane, twl);
     else stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
 
-    // one job per mode pair {k, -k}; in tile 0 the self-mirror columns 0
-    // (slot 0) and W/2 (slot half) take the rows ky <= H/2
     const float TA = a.lambda * pa.tau, TB = a.lambda * pb.tau;
     const float inv_n = 1.0f / ((float)H * (float)W);
     const uint32_t pidA = (uint32_t)pa.pid, pidB = (uint32_t)pb.pid;
-    const int jobs = half * H + (j == 0 ? H / 2 + 1 : 0);
-#pragma unroll 1
-    for (int q = opaque_u(tid); q < jobs; q += NTH) {
-        int s, ky;
-        if (q < half * H) {
-            s = q % half;
-            ky = q / half;
-            if (j == 0 && s == 0 && ky > H / 2) continue;
-        } else {
-            s = half;
-            ky = q - half * H;
-        }
-        const bool self_col = j == 0 && (s == 0 || s == half);
-        const int p = self_col ? s : s + half;
-        const int my = (H - ky) & (H - 1);
-        const bool self = self_col && my == ky;
-        const int ck = mirror_column(j, s, half, W), cm = mirror_column(j, p, half, W);
+    // Fourier step of mode k (slot s, row ky) and its mirror -k (slot p, row
+    // my), given both problems' n P(k) (= n P(-k): isotropic spectra) and
+    // harmonic normals at k and -k
+    auto update = [&](int s, int p, int ky, int my, bool self, float PA, float PB, float2 hkA, float2 hmA,
+                      float2 hkB, float2 hmB) {
         float2& zk = lds[s * SEG + swz(ky)];
         float2& zm = lds[p * SEG + swz(my)];
         const float2 Zk = zk, Zm = zm;
-        const uint32_t ek = (uint32_t)(ky * W + ck), em = (uint32_t)(my * W + cm);
-        // isotropic spectra: n P(-k) = n P(k)
-        const float PA = a.nP[pa.pix_off + ek], PB = a.nP[pb.pix_off + ek];
         const float rA = __builtin_amdgcn_rcpf(PA + TA), rB = __builtin_amdgcn_rcpf(PB + TB);
         const float fA = PA * rA * inv_n, fB = PB * rB * inv_n;
         const float wA = __builtin_amdgcn_sqrtf(PA * TA * rA * inv_n), wB = __builtin_amdgcn_sqrtf(PB * TB * rB * inv_n);
         const float fp = 0.5f * (fA + fB), fm = 0.5f * (fA - fB);
         float2 Nk = make_float2(0.f, 0.f), Nm = Nk;
         if (a.stochastic) {
-            const float2 hkA = chain0_mode_normal(ek, a.sweep, pidA, a.key0, a.key1);
-            const float2 hmA = self ? hkA : chain0_mode_normal(em, a.sweep, pidA, a.key0, a.key1);
-            const float2 hkB = chain0_mode_normal(ek, a.sweep, pidB, a.key0, a.key1);
-            const float2 hmB = self ? hkB : chain0_mode_normal(em, a.sweep, pidB, a.key0, a.key1);
             const float ha = 0.5f * wA, hb = it.pair >= 0 ? 0.5f * wB : 0.f;
             // w_A (eta_A(k) + conj eta_A(-k)) / 2 + i w_B (eta_B(k) + conj eta_B(-k)) / 2, and with k, -k swapped
             Nk = make_float2(fmaf(ha, hkA.x + hmA.x, -hb * (hkB.y - hmB.y)), fmaf(ha, hkA.y - hmA.y, hb * (hkB.x + hmB.x)));
@@ -129,6 +108,86 @@ __global__ __launch_bounds__(PackShape<L>::NTH) void col_pack_kernel(SweepArgs a
         const float2 Sm = make_float2(fmaf(fp, Zm.x, fm * Zk.x) + Nm.x, fmaf(fp, Zm.y, -fm * Zk.y) + Nm.y);
         zk = Sk;
         if (!self) zm = Sm;
+    };
+    if (j == 0) {
+        // tile 0: one job per mode pair {k, -k}; the self-mirror columns 0
+        // (slot 0) and W/2 (slot half) take the rows ky <= H/2
+        const int jobs = half * H + H / 2 + 1;
+#pragma unroll 1
+        for (int q = opaque_u(tid); q < jobs; q += NTH) {
+            int s, ky;
+            if (q < half * H) {
+                s = q % half;
+                ky = q / half;
+                if (s == 0 && ky > H / 2) continue;
+            } else {
+                s = half;
+                ky = q - half * H;
+            }
+            const bool self_col = s == 0 || s == half;
+            const int p = self_col ? s : s + half;
+            const int my = (H - ky) & (H - 1);
+            const bool self = self_col && my == ky;
+            const uint32_t ek = (uint32_t)(ky * W + mirror_column(j, s, half, W));
+            const uint32_t em = (uint32_t)(my * W + mirror_column(j, p, half, W));
+            float2 hkA{}, hmA{}, hkB{}, hmB{};
+            if (a.stochastic) {
+                hkA = chain0_mode_normal(ek, a.sweep, pidA, a.key0, a.key1);
+                hmA = self ? hkA : chain0_mode_normal(em, a.sweep, pidA, a.key0, a.key1);
+                hkB = chain0_mode_normal(ek, a.sweep, pidB, a.key0, a.key1);
+                hmB = self ? hkB : chain0_mode_normal(em, a.sweep, pidB, a.key0, a.key1);
+            }
+            update(s, p, ky, my, self, a.nP[pa.pix_off + ek], a.nP[pb.pix_off + ek], hkA, hmA, hkB, hmB);
+        }
+    } else {
+        // other tiles: one thread per row ky, all `half` columns c0 + s and
+        // their mirrors W - c0 - s.  A Philox call gives the normals of an
+        // element pair {2e, 2e+1}: the direct columns take half/2 calls per
+        // problem, and the mirror columns half/2 + 1, because the pair that
+        // holds W - c0 - 2pp - 1 (.b) also holds W - c0 - 2pp - 2 (.a), the
+        // next column pair's first mirror.  The same normals as one call per
+        // mode, in 9 calls per problem instead of 16 at half = 8.  The
+        // coefficients come from the column-pair table nPt, whose rows of one
+        // column pair are contiguous (the lanes' rows are).
+        const int c0 = j * half;
+        const float2* nptA = a.nPt + pa.pix_off / 2 + (int64_t)(c0 / 2) * H;
+        const float2* nptB = a.nPt + pb.pix_off / 2 + (int64_t)(c0 / 2) * H;
+#pragma unroll 1
+        for (int ky = opaque_u(tid); ky < H; ky += NTH) {
+            const int my = (H - ky) & (H - 1);
+            const uint32_t rk = (uint32_t)(ky * W), rm = (uint32_t)(my * W);
+            float2 cA{}, cB{};  // mirror normal of slot 2pp (.a of the pair holding W - c0 - 2pp)
+            if (a.stochastic) {
+                const uint32_t e = (rm + (uint32_t)(W - c0)) >> 1;
+                cA = pair_normals(e, a.sweep, pidA, kStageHarmonic, 0u, a.key0, a.key1).a;
+                cB = pair_normals(e, a.sweep, pidB, kStageHarmonic, 0u, a.key0, a.key1).a;
+            }
+#pragma unroll 1
+            for (int pp = 0; pp < half / 2; ++pp) {
+                float2 dA0{}, dA1{}, dB0{}, dB1{}, mA1{}, mB1{}, nA{}, nB{};
+                if (a.stochastic) {
+                    const uint32_t ed = (rk + (uint32_t)(c0 + 2 * pp)) >> 1;
+                    const Normals2 zA = pair_normals(ed, a.sweep, pidA, kStageHarmonic, 0u, a.key0, a.key1);
+                    const Normals2 zB = pair_normals(ed, a.sweep, pidB, kStageHarmonic, 0u, a.key0, a.key1);
+                    dA0 = zA.a;
+                    dA1 = zA.b;
+                    dB0 = zB.a;
+                    dB1 = zB.b;
+                    const uint32_t emx = (rm + (uint32_t)(W - c0 - 2 * pp - 2)) >> 1;
+                    const Normals2 mA = pair_normals(emx, a.sweep, pidA, kStageHarmonic, 0u, a.key0, a.key1);
+                    const Normals2 mB = pair_normals(emx, a.sweep, pidB, kStageHarmonic, 0u, a.key0, a.key1);
+                    mA1 = mA.b;  // column W - c0 - 2pp - 1
+                    mB1 = mB.b;
+                    nA = mA.a;   // column W - c0 - 2pp - 2: the next pair's slot 2pp + 2
+                    nB = mB.a;
+                }
+                const float2 PA = nptA[(int64_t)pp * H + ky], PB = nptB[(int64_t)pp * H + ky];
+                update(2 * pp, 2 * pp + half, ky, my, false, PA.x, PB.x, dA0, cA, dB0, cB);
+                update(2 * pp + 1, 2 * pp + 1 + half, ky, my, false, PA.y, PB.y, dA1, mA1, dB1, mB1);
+                cA = nA;
+                cB = nB;
+            }
+        }
     }
     __syncthreads();
     if constexpr (L >= 256) {
@@ -146,7 +205,7 @@ __global__ __launch_bounds__(PackShape<L>::NTH) void col_pack_kernel(SweepArgs a
 }  // namespace
 
 hipError_t launch_col_pack(int W, int H, const SweepArgs& a, hipStream_t s) {
-    if (!is_pow2(W) || !is_pow2(H) || W < 16) return hipErrorInvalidValue;
+    if (!is_pow2(W) || !is_pow2(H) || W < 16 || !a.nPt) return hipErrorInvalidValue;
     switch (H) {
 #define MF_PACK_CASE(N)                                                                                  \
     case N:                                                                                              \
