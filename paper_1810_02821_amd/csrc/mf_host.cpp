@@ -99,6 +99,7 @@ struct mf_plan_s {
     float* d_nP = nullptr;
     float2* d_nPt = nullptr;  // column-pair copy of nP for the streamed column kernel
     int16_t* d_band = nullptr;
+    int16_t* d_bandt = nullptr;  // the band map column-major per problem: [pix_off + kx H + ky]
     int32_t* d_band_base = nullptr;
     int32_t* d_band_count = nullptr;
     double* d_band_scale = nullptr;  // 1 / (n^2 theta_b^2)
@@ -143,6 +144,7 @@ struct mf_plan_s {
         (void)hipFree(d_nP);
         (void)hipFree(d_nPt);
         (void)hipFree(d_band);
+        (void)hipFree(d_bandt);
         (void)hipFree(d_band_base);
         (void)hipFree(d_band_count);
         (void)hipFree(d_band_scale);
@@ -262,6 +264,13 @@ mf_status upload_spectrum(mf_plan p, int i, hipStream_t stream) {
                           stream));
     MF_HIP(hipMemcpyAsync(p->d_band + hp.pix_off, band.data(), band.size() * sizeof(int16_t), hipMemcpyHostToDevice,
                           stream));
+    // column-major copy: a column's modes are contiguous (the row-per-thread
+    // Fourier step of the mirror-paired column kernel reads it across rows)
+    std::vector<int16_t> bandt((size_t)H * W);
+    for (int kx = 0; kx < W; ++kx)
+        for (int ky = 0; ky < H; ++ky) bandt[(size_t)kx * H + ky] = band[(size_t)ky * W + kx];
+    MF_HIP(hipMemcpyAsync(p->d_bandt + hp.pix_off, bandt.data(), bandt.size() * sizeof(int16_t),
+                          hipMemcpyHostToDevice, stream));
     std::vector<double> sc(hp.n_bands);
     if (hp.kind == MF_PK_BANDS) {
         for (int b = 0; b < hp.n_bands; ++b) sc[b] = 1.0 / (n * n * hp.amps[b] * hp.amps[b]);
@@ -1034,6 +1043,7 @@ mf_status spectrum_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H
     r.field = work;
     r.tw_col = p->d_tw.at(H);
     r.band = p->d_band;
+    r.bandt = p->d_bandt;
     r.band_base = p->d_band_base;
     r.band_count = p->d_band_count;
     r.dof = d_dof;
@@ -1682,6 +1692,7 @@ mf_status mf_plan_create(mf_plan* out, int32_t n_problems, const mf_problem* pro
     MF_TRY(hipMalloc(&p->d_nP, off * sizeof(float)));
     MF_TRY(hipMalloc(&p->d_nPt, off / 2 * sizeof(float2)));
     MF_TRY(hipMalloc(&p->d_band, off * sizeof(int16_t)));
+    MF_TRY(hipMalloc(&p->d_bandt, off * sizeof(int16_t)));
     MF_TRY(hipMalloc(&p->d_band_base, n_problems * sizeof(int32_t)));
     MF_TRY(hipMalloc(&p->d_band_count, n_problems * sizeof(int32_t)));
     MF_TRY(hipMalloc(&p->d_band_scale, std::max(bands, 1) * sizeof(double)));

@@ -50,6 +50,7 @@ struct SpectrumStreamArgs {
     float2* field;            // pair fields, items' layout
     const float2* tw_col;     // W_H^r
     const int16_t* band;      // per-mode band index (concatenated)
+    const int16_t* bandt;     // the same, column-major per problem: [pix_off + kx H + ky]
     const int32_t* band_base;
     const int32_t* band_count;
     const int32_t* dof;

@@ -98,40 +98,18 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
     if constexpr (L >= 256) col_forward_rest<L, TPC>(lds + cid * SEG, lane, twl);
     else stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
 
-    // one job per mode pair {k, -k}: a first-half slot with its partner slot
-    // (consecutive lanes take consecutive slots of a row, so the band-index
-    // reads of a wave cover a few short row segments); in tile 0 the
-    // self-mirror columns 0 (slot 0) and W/2 (slot half) take the rows
-    // ky <= H/2, whose partners -ky lie in the same column
     const int16_t* band = a.band + pr.pix_off;
     const uint32_t pid = (uint32_t)pr.pid, pair = (uint32_t)it.pair;
-    const int jobs = half * H + (j == 0 ? H / 2 + 1 : 0);
-#pragma unroll 1
-    for (int q = opaque(tid); q < jobs; q += NTH) {
-        int s, ky;
-        if (q < half * H) {
-            s = q % half;
-            ky = q / half;
-            if (j == 0 && s == 0 && ky > H / 2) continue;
-        } else {
-            s = half;
-            ky = q - half * H;
-        }
-        const bool self_col = j == 0 && (s == 0 || s == half);
-        const int p = self_col ? s : s + half;
-        const int my = (H - ky) & (H - 1);
-        const bool self = self_col && my == ky;
-        const int ck = pair_column(j, s, half, W), cm = pair_column(j, p, half, W);
+    // Fourier step of mode k (slot s, row ky, band b) and its mirror -k (slot
+    // p, row my; band(-k) = band(k): same |k|), given the chain pair's
+    // harmonic normals at k and -k
+    auto update = [&](int s, int p, int ky, int my, bool self, int b, float2 hk, float2 hm) {
         float2& zk = lds[s * SEG + swz(ky)];
         float2& zm = lds[p * SEG + swz(my)];
         const float2 Zk = zk, Zm = zm;
-        const uint32_t ek = (uint32_t)(ky * W + ck), em = (uint32_t)(my * W + cm);
-        const int b = band[ek];  // band(-k) = band(k): same |k|
         const float4 c = coef[b];
         const float fp = 0.5f * (c.x + c.z), fm = 0.5f * (c.x - c.z);
         const float wp = 0.5f * (c.y + c.w), wm = 0.5f * (c.y - c.w);
-        const float2 hk = mode_normal(ek, a.sweep, pid, pair, a.key0, a.key1);
-        const float2 hm = self ? hk : mode_normal(em, a.sweep, pid, pair, a.key0, a.key1);
         // S(k) = f_+ Z(k) + f_- conj Z(-k) + w_+ eta(k) + w_- conj eta(-k), and with k, -k swapped
         const float2 Sk = make_float2(fmaf(fp, Zk.x, fm * Zm.x) + fmaf(wp, hk.x, wm * hm.x),
                                       fmaf(fp, Zk.y, -fm * Zm.y) + fmaf(wp, hk.y, -wm * hm.y));
@@ -146,6 +124,62 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
             const double wgt = self ? 1.0 : 2.0;
             atomicAdd(&pw[0][b], wgt * (ar * ar + ai * ai));
             atomicAdd(&pw[1][b], wgt * (br * br + bi * bi));
+        }
+    };
+    if (j == 0) {
+        // tile 0: one job per mode pair {k, -k}, a first-half slot with its
+        // partner slot; the self-mirror columns 0 (slot 0) and W/2 (slot
+        // half) take the rows ky <= H/2, whose partners -ky lie in the same column
+        const int jobs = half * H + H / 2 + 1;
+#pragma unroll 1
+        for (int q = opaque(tid); q < jobs; q += NTH) {
+            int s, ky;
+            if (q < half * H) {
+                s = q % half;
+                ky = q / half;
+                if (s == 0 && ky > H / 2) continue;
+            } else {
+                s = half;
+                ky = q - half * H;
+            }
+            const bool self_col = s == 0 || s == half;
+            const int p = self_col ? s : s + half;
+            const int my = (H - ky) & (H - 1);
+            const bool self = self_col && my == ky;
+            const uint32_t ek = (uint32_t)(ky * W + pair_column(j, s, half, W));
+            const uint32_t em = (uint32_t)(my * W + pair_column(j, p, half, W));
+            const float2 hk = mode_normal(ek, a.sweep, pid, pair, a.key0, a.key1);
+            const float2 hm = self ? hk : mode_normal(em, a.sweep, pid, pair, a.key0, a.key1);
+            update(s, p, ky, my, self, band[ek], hk, hm);
+        }
+    } else {
+        // other tiles: one thread per row ky, all `half` columns c0 + s and
+        // their mirrors W - c0 - s.  A Philox call gives the normals of an
+        // element pair, so the direct columns take half/2 calls and the
+        // mirror columns half/2 + 1 (the pair holding W - c0 - 2pp - 1 also
+        // holds the next column pair's first mirror): the same normals as one
+        // call per mode, in 9 calls per row instead of 16 at half = 8.  Band
+        // indices come from the column-major map, contiguous across the lanes' rows.
+        const int c0 = j * half;
+        const int16_t* bt = a.bandt + pr.pix_off + (int64_t)c0 * H;
+#pragma unroll 1
+        for (int ky = opaque(tid); ky < H; ky += NTH) {
+            const int my = (H - ky) & (H - 1);
+            const uint32_t rk = (uint32_t)(ky * W), rm = (uint32_t)(my * W);
+            // mirror normal of slot 2pp (.a of the pair holding W - c0 - 2pp)
+            float2 carry = pair_normals((rm + (uint32_t)(W - c0)) >> 1, a.sweep, pid, kStageHarmonic, pair, a.key0,
+                                        a.key1).a;
+#pragma unroll 1
+            for (int pp = 0; pp < half / 2; ++pp) {
+                const Normals2 zd = pair_normals((rk + (uint32_t)(c0 + 2 * pp)) >> 1, a.sweep, pid, kStageHarmonic,
+                                                 pair, a.key0, a.key1);
+                const Normals2 zm = pair_normals((rm + (uint32_t)(W - c0 - 2 * pp - 2)) >> 1, a.sweep, pid,
+                                                 kStageHarmonic, pair, a.key0, a.key1);
+                const int b0 = bt[(int64_t)(2 * pp) * H + ky], b1 = bt[(int64_t)(2 * pp + 1) * H + ky];
+                update(2 * pp, 2 * pp + half, ky, my, false, b0, zd.a, carry);
+                update(2 * pp + 1, 2 * pp + 1 + half, ky, my, false, b1, zd.b, zm.b);
+                carry = zm.a;
+            }
         }
     }
     __syncthreads();
