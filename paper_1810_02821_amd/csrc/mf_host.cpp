@@ -675,6 +675,7 @@ mf_status shear_streamed(mf_plan p, const mf::ItemDev* di, int n_items, int H, i
     a.gamma = reinterpret_cast<const float2*>(gamma);
     a.nbar = p->d_nbar;
     a.nP = p->d_nP;
+    a.nPt = p->d_nPt;
     a.b_ratio = b_ratio;
     a.tw_row = p->d_tw.at(W);
     a.tw_col = p->d_tw.at(H);

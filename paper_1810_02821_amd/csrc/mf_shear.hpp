@@ -46,6 +46,7 @@ struct ShearStreamArgs {
     const float2* gamma;      // concatenated complex shear data
     const float* nbar;        // concatenated Nbar per component (+inf missing)
     const float* nP;          // concatenated n P_E(|k|)
+    const float2* nPt;        // column-pair copy: [pix_off/2 + (kx/2) H + ky] = (nP(ky,kx), nP(ky,kx+1))
     float b_ratio;
     const float2* tw_row;     // W_W^r
     const float2* tw_col;     // W_H^r

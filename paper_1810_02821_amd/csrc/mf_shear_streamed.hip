@@ -348,45 +348,90 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
         stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
     }
 
-    // E/B Fourier step, one job per mode pair {k, -k} (see col_pair_kernel)
+    // E/B Fourier step of mode k (slot s, row ky) and its mirror -k (slot p,
+    // row my), given n P(k) and the chain's harmonic normals at k and -k
     const float T = a.lambda * pr.tau;
     const float n = (float)H * (float)W;
     const float inv_n = 1.0f / n;
     const float* nP = a.nP + pr.pix_off;
     const uint32_t pid = (uint32_t)pr.pid, chain = (uint32_t)it.pair;
-    const int jobs = half * H + (j == 0 ? H / 2 + 1 : 0);
-#pragma unroll 1
-    for (int q = opaque(tid); q < jobs; q += NTH) {
-        int s, ky;
-        if (q < half * H) {
-            s = q % half;
-            ky = q / half;
-            if (j == 0 && s == 0 && ky > H / 2) continue;
-        } else {
-            s = half;
-            ky = q - half * H;
-        }
-        const bool self_col = j == 0 && (s == 0 || s == half);
-        const int p = self_col ? s : s + half;
-        const int my = (H - ky) & (H - 1);
-        const bool self = self_col && my == ky;
-        const int ck = pair_column(j, s, half, W), cm = pair_column(j, p, half, W);
+    auto update = [&](int s, int p, int ky, int my, bool self, float nPk, float2 hk, float2 hm) {
+        const int ck = pair_column(j, s, half, W);
         float2& zk = lds[s * SEG + swz(ky)];
         float2& zm = lds[p * SEG + swz(my)];
         const float2 dk = ks(ky, ck, H, W), dm = ks_mirror(dk, ky, ck, H, W);
         const float2 uk = mulc(zk, dk), um = mulc(zm, dm);
-        const Filt c = filt(nP[ky * W + ck], a.b_ratio, T, inv_n, n, ky == 0 && ck == 0);
+        const Filt c = filt(nPk, a.b_ratio, T, inv_n, n, ky == 0 && ck == 0);
         float2 Sk = make_float2(fmaf(c.fp, uk.x, c.fm * um.x), fmaf(c.fp, uk.y, -c.fm * um.y));
         float2 Sm = make_float2(fmaf(c.fp, um.x, c.fm * uk.x), fmaf(c.fp, um.y, -c.fm * uk.y));
         if (a.stochastic) {
-            const uint32_t ek = (uint32_t)(ky * W + ck), em = (uint32_t)(my * W + cm);
-            const float2 hk = mode_normal(ek, a.sweep, pid, chain, a.key0, a.key1);
-            const float2 hm = self ? hk : mode_normal(em, a.sweep, pid, chain, a.key0, a.key1);
             Sk = make_float2(Sk.x + fmaf(c.wp, hk.x, c.wm * hm.x), Sk.y + fmaf(c.wp, hk.y, -c.wm * hm.y));
             Sm = make_float2(Sm.x + fmaf(c.wp, hm.x, c.wm * hk.x), Sm.y + fmaf(c.wp, hm.y, -c.wm * hk.y));
         }
         zk = Sk;
         if (!self) zm = Sm;
+    };
+    if (j == 0 || H < NTH / 2) {
+        // one job per mode pair {k, -k} (see col_pair_kernel): tile 0, whose
+        // columns 0 and W/2 pair with themselves, and columns too short to
+        // give every thread a row
+        const int jobs = half * H + (j == 0 ? H / 2 + 1 : 0);
+#pragma unroll 1
+        for (int q = opaque(tid); q < jobs; q += NTH) {
+            int s, ky;
+            if (q < half * H) {
+                s = q % half;
+                ky = q / half;
+                if (j == 0 && s == 0 && ky > H / 2) continue;
+            } else {
+                s = half;
+                ky = q - half * H;
+            }
+            const bool self_col = j == 0 && (s == 0 || s == half);
+            const int p = self_col ? s : s + half;
+            const int my = (H - ky) & (H - 1);
+            const bool self = self_col && my == ky;
+            const int ck = pair_column(j, s, half, W), cm = pair_column(j, p, half, W);
+            float2 hk{}, hm{};
+            if (a.stochastic) {
+                hk = mode_normal((uint32_t)(ky * W + ck), a.sweep, pid, chain, a.key0, a.key1);
+                hm = self ? hk : mode_normal((uint32_t)(my * W + cm), a.sweep, pid, chain, a.key0, a.key1);
+            }
+            update(s, p, ky, my, self, nP[ky * W + ck], hk, hm);
+        }
+    } else {
+        // one thread per row across the tile's columns and their
+        // mirrors, each Philox call serving two modes (see col_pair_kernel);
+        // n P from the column-pair table, contiguous across the lanes' rows
+        const int c0 = j * half;
+        const float2* npt = a.nPt + pr.pix_off / 2 + (int64_t)(c0 / 2) * H;
+#pragma unroll 1
+        for (int ky = opaque(tid); ky < H; ky += NTH) {
+            const int my = (H - ky) & (H - 1);
+            const uint32_t rk = (uint32_t)(ky * W), rm = (uint32_t)(my * W);
+            float2 carry{};  // mirror normal of slot 2pp (.a of the pair holding W - c0 - 2pp)
+            if (a.stochastic)
+                carry = pair_normals((rm + (uint32_t)(W - c0)) >> 1, a.sweep, pid, kStageHarmonic, chain, a.key0,
+                                     a.key1).a;
+#pragma unroll 1
+            for (int pp = 0; pp < half / 2; ++pp) {
+                float2 d0{}, d1{}, m1{}, nx{};
+                if (a.stochastic) {
+                    const Normals2 zd = pair_normals((rk + (uint32_t)(c0 + 2 * pp)) >> 1, a.sweep, pid,
+                                                     kStageHarmonic, chain, a.key0, a.key1);
+                    const Normals2 zm = pair_normals((rm + (uint32_t)(W - c0 - 2 * pp - 2)) >> 1, a.sweep, pid,
+                                                     kStageHarmonic, chain, a.key0, a.key1);
+                    d0 = zd.a;
+                    d1 = zd.b;
+                    m1 = zm.b;
+                    nx = zm.a;
+                }
+                const float2 np = npt[(int64_t)pp * H + ky];
+                update(2 * pp, 2 * pp + half, ky, my, false, np.x, d0, carry);
+                update(2 * pp + 1, 2 * pp + 1 + half, ky, my, false, np.y, d1, m1);
+                carry = nx;
+            }
+        }
     }
     __syncthreads();
     float back = 1.0f;
@@ -460,7 +505,7 @@ hipError_t launch_shear_col(int W, int H, const ShearStreamArgs& a, hipStream_t 
     switch (H) {
 #define MF_CASE(LL)                                                                                              \
     case LL:                                                                                                     \
-        if (W < ShearColShape<LL>::TC) return hipErrorInvalidValue;                                              \
+        if (W < ShearColShape<LL>::TC || !a.nPt) return hipErrorInvalidValue;                                    \
         hipLaunchKernelGGL(shear_col_kernel<LL>, dim3((unsigned)((int64_t)a.n_items * (W / ShearColShape<LL>::TC))), \
                            dim3(ShearColShape<LL>::NTH), 0, s, a, W);                                            \
         break;
