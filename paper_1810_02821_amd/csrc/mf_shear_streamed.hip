@@ -368,6 +368,10 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
             Sk = make_float2(Sk.x + fmaf(c.wp, hk.x, c.wm * hm.x), Sk.y + fmaf(c.wp, hk.y, -c.wm * hm.y));
             Sm = make_float2(Sm.x + fmaf(c.wp, hm.x, c.wm * hk.x), Sm.y + fmaf(c.wp, hm.y, -c.wm * hk.y));
         }
+        if (!a.emit) {  // next state D kappa^ at once (an emitting sweep stages kappa^ first)
+            Sk = cmul(Sk, dk);
+            Sm = cmul(Sm, dm);
+        }
         zk = Sk;
         if (!self) zm = Sm;
     };
@@ -434,10 +438,9 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
         }
     }
     __syncthreads();
-    float back = 1.0f;
     if (a.emit) {
         // stage F_col^-1(kappa^) for the emission kernel, then transform back
-        // (the unnormalised round trip returns H kappa^)
+        // (the unnormalised round trip returns H kappa^) and take D kappa^
         stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
         float2* kout = a.kfield + it.field_off;
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
@@ -445,15 +448,14 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
             kout[(int64_t)y * W + pair_column(j, s, half, W)] = lds[s * SEG + swz(y)];
         }
         stockham_fft<L, 1, TPC, false>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
-        back = 1.0f / (float)H;
+        const float back = 1.0f / (float)H;
+        for (unsigned e = opaque(tid); e < (unsigned)(TC * L); e += NTH) {
+            const int s = (int)(e % TC), y = (int)(e / TC);
+            float2& v = lds[s * SEG + swz(y)];
+            v = cmul(v, cscale(ks(y, pair_column(j, s, half, W), H, W), back));
+        }
+        __syncthreads();
     }
-    // next state: D kappa^
-    for (unsigned e = opaque(tid); e < (unsigned)(TC * L); e += NTH) {
-        const int s = (int)(e % TC), y = (int)(e / TC);
-        float2& v = lds[s * SEG + swz(y)];
-        v = cmul(v, cscale(ks(y, pair_column(j, s, half, W), H, W), back));
-    }
-    __syncthreads();
     float2* fout = a.field + it.field_off;
     if constexpr (L >= 256) {
         // inverse transform, its last pass straight to HBM
