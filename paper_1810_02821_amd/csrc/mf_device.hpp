@@ -115,23 +115,80 @@ template <int R, bool INV> __device__ __forceinline__ void dft(float2 (&v)[R]) {
 }
 
 // ------------------------------------------------- Stockham pass over LDS --
-// LDS position of element i of a transform: the low five bits (one row of the
-// 64 x 4-byte banks for 8-byte elements) are XORed with a function of the
-// higher bits, which keeps every read and write of every pass below free of
-// bank conflicts for lengths 16..2048 (within one transform per 32 lanes).
+// Two families of LDS layouts for the element exchanges between passes.
+//
+// Layout -1: element i at swz(i).  The low five bits (one row of the 64 x
+// 4-byte banks for 8-byte elements) are XORed with a function of the higher
+// bits, which keeps every read and write of every pass below free of bank
+// conflicts for lengths 16..2048 (within one transform per 32 lanes).  Any
+// element's position needs its own address arithmetic.
+//
+// Layout A >= 0: element i at i + A floor(i / 32), that is A unused elements
+// after every block of 32.  The elements a thread reads (j + r NT) or writes
+// (o + r NS) then sit at one base plus constant offsets, which the ds
+// instructions take as immediates.  A is chosen per exchange by pad_of so
+// that the writing pass is free of bank conflicts within 32 lanes; the reads
+// (32 consecutive elements per 32 lanes) are free of them for every A.
 __device__ __forceinline__ unsigned swz(unsigned i) {
     const unsigned h = i >> 5;
     return i ^ (((h & 7u) ^ (((h >> 1) & 3u) << 3)) & 31u);
 }
+template <int A>
+__device__ __forceinline__ unsigned lpos(unsigned i) {
+    if constexpr (A < 0) return swz(i);
+    else return i + (unsigned)A * (i >> 5);
+}
 
-// One radix-R pass of a length-L transform held in `buf` (element i at
-// buf[swz(i)]).  `lane` in [0, TPG) indexes the TPG threads that own this
-// transform; NS is the product of the radices already applied.  Input in the
-// Stockham order of the previous pass, output in the order of the next; after
-// the last pass the sequence is in natural order.  `tw` holds W_L^r, r < L.
-// The pass reads every element into registers before writing (in place), so
-// it needs the two barriers; every thread of the block must call it.
-template <int L, int R, int NS, int TPG, bool INV>
+// Element j + r STEP of an exchange in layout A (reads of a pass with STEP =
+// L / R): a base and constant offsets when STEP is a multiple of 32.
+template <int A, int STEP>
+__device__ __forceinline__ unsigned lpos_step(unsigned j, int r) {
+    if constexpr (A >= 0 && STEP % 32 == 0) return lpos<A>(j) + r * (STEP + A * (STEP / 32));
+    else return lpos<A>(j + r * STEP);
+}
+// Element R j + r (r < R) in layout A (writes of a first pass, NS = 1): the
+// run stays inside one block of 32 when R divides 32.
+template <int A, int R>
+__device__ __forceinline__ unsigned lpos_run(unsigned j, int r) {
+    if constexpr (A >= 0 && 32 % R == 0) return lpos<A>(R * j) + r;
+    else return lpos<A>(R * j + r);
+}
+
+// True if the 32 lanes l < min(32, L / R) of a radix-R pass after NS points,
+// writing element (l / NS) NS R + l % NS + NS r for one r, hit 32 distinct
+// bank pairs under layout A, for every r.
+constexpr bool pad_writes_ok(int L, int R, int NS, int A) {
+    const int lanes = L / R < 32 ? L / R : 32;
+    for (int r = 0; r < R; ++r) {
+        unsigned seen = 0;
+        for (int l = 0; l < lanes; ++l) {
+            const int i = (l / NS) * NS * R + l % NS + NS * r;
+            const unsigned bit = 1u << ((i + A * (i >> 5)) & 31);
+            if (seen & bit) return false;
+            seen |= bit;
+        }
+    }
+    return true;
+}
+// Smallest pad for the exchange a radix-R pass after NS points writes.
+constexpr int pad_of(int L, int R, int NS) {
+    for (int A = 1; A <= 32; ++A)
+        if (pad_writes_ok(L, R, NS, A)) return A;
+    return 1;
+}
+// Elements an exchange of length L occupies under layout A (up to and
+// including the position of element L - 1).
+constexpr int pad_len(int L, int A) { return A < 0 ? L : L + A * ((L - 1) / 32); }
+
+// One radix-R pass of a length-L transform held in `buf`, reading the
+// exchange in layout AI and writing in layout AO.  `lane` in [0, TPG)
+// indexes the TPG threads that own this transform; NS is the product of the
+// radices already applied.  Input in the Stockham order of the previous pass,
+// output in the order of the next; after the last pass the sequence is in
+// natural order.  `tw` holds W_L^r, r < L.  The pass reads every element into
+// registers before writing (in place), so it needs the two barriers; every
+// thread of the block must call it.
+template <int L, int R, int NS, int TPG, bool INV, int AI = -1, int AO = -1>
 __device__ __forceinline__ void stockham_pass(float2* buf, unsigned lane, const float2* __restrict__ tw) {
     constexpr int NT = L / R;
     constexpr int TPT = (NT + TPG - 1) / TPG;
@@ -140,8 +197,14 @@ __device__ __forceinline__ void stockham_pass(float2* buf, unsigned lane, const 
     for (int t = 0; t < TPT; ++t) {
         const unsigned j = lane + t * TPG;
         if ((NT % TPG) == 0 || j < (unsigned)NT) {
+            if constexpr (AI >= 0 && NT % 32 == 0) {
+                const unsigned b = lpos<AI>(j);
 #pragma unroll
-            for (int r = 0; r < R; ++r) v[t][r] = buf[swz(j + r * NT)];
+                for (int r = 0; r < R; ++r) v[t][r] = buf[b + r * (NT + AI * (NT / 32))];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) v[t][r] = buf[lpos<AI>(j + r * NT)];
+            }
             if constexpr (NS > 1) {
                 const unsigned k = j % NS;
 #pragma unroll
@@ -160,8 +223,20 @@ __device__ __forceinline__ void stockham_pass(float2* buf, unsigned lane, const 
         if ((NT % TPG) == 0 || j < (unsigned)NT) {
             const unsigned k = j % NS;
             const unsigned o = (j / NS) * NS * R + k;
+            if constexpr (AO >= 0 && NS % 32 == 0) {
+                const unsigned b = lpos<AO>(o);
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[swz(o + r * NS)] = v[t][r];
+                for (int r = 0; r < R; ++r) buf[b + r * (NS + AO * (NS / 32))] = v[t][r];
+            } else if constexpr (AO >= 0 && 32 % NS == 0 && (NS * R) % 32 == 0) {
+                // o's low five bits are k < NS, so o + r NS stays below the
+                // next multiple of 32 past o + (r NS mod 32)
+                const unsigned b = lpos<AO>(o);
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[b + r * NS + AO * ((r * NS) >> 5)] = v[t][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < R; ++r) buf[lpos<AO>(o + r * NS)] = v[t][r];
+            }
         }
     }
     __syncthreads();

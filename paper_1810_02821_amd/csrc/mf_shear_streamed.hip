@@ -194,7 +194,14 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel_f(ShearStreamArg
     constexpr int NTL = L / RL;
     constexpr int ITL = NTL / TPR;
     static_assert(L >= 256 && NTL % TPR == 0 && RL % 2 == 0, "shear_row_kernel_f shape");
-    __shared__ float2 lds[ROWS * L];
+    // padded LDS layouts, as in the sampler's fused row kernel
+    constexpr int RM = middle_radix<L>();
+    constexpr int A1 = pad_of(L, 16, 1), AC = pad_after(L, RM, 16, RL, A1);
+    constexpr int AF = pad_of(L, RL, 1), AD = pad_after(L, RM, RL, 16, AF);
+    constexpr int AMAX = pad_max(L, RM, 16, RL, A1) > pad_max(L, RM, RL, 16, AF) ? pad_max(L, RM, 16, RL, A1)
+                                                                                 : pad_max(L, RM, RL, 16, AF);
+    constexpr int LP = pad_len(L, AMAX);  // row stride in LDS
+    __shared__ float2 lds[ROWS * LP];
     __shared__ int32_t row_item[ROWS], row_y[ROWS];
     const unsigned tid = threadIdx.x;
     const int64_t total_rows = (int64_t)a.n_items * H;
@@ -211,7 +218,7 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel_f(ShearStreamArg
     const int y = row_y[rid];
     const ItemDev it = a.items[item];
     const ProbDev pr = a.probs[it.prob];
-    float2* row = lds + rid * L;
+    float2* row = lds + rid * LP;
     float2* frow = a.field + it.field_off + (int64_t)y * W;
 
     // first inverse pass from HBM (a row past the end reads row 0 of item 0,
@@ -225,11 +232,11 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel_f(ShearStreamArg
             for (int r = 0; r < 16; ++r) v[r] = frow[j + r * NT16];
             dft<16, true>(v);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) row[swz(j * 16 + r)] = v[r];
+            for (int r = 0; r < 16; ++r) row[lpos_run<A1, 16>(j, r)] = v[r];
         }
     }
     __syncthreads();
-    passes_before<L, middle_radix<L>(), 16, RL, TPR, true>(row, lane, a.tw_row);
+    passes_before<L, RM, 16, RL, TPR, true, A1>(row, lane, a.tw_row);
 
     // last inverse pass, pixel step t = (1 - a) s + a gamma (+ sqrt(T (1 - a)) xi),
     // first forward pass
@@ -241,7 +248,7 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel_f(ShearStreamArg
         for (int i = 0; i < ITL; ++i) {
             const unsigned j = lane + i * TPR;
 #pragma unroll
-            for (int r = 0; r < RL; ++r) v[i][r] = row[swz(j + r * NTL)];
+            for (int r = 0; r < RL; ++r) v[i][r] = row[lpos_step<AC, NTL>(j, r)];
 #pragma unroll
             for (int r = 1; r < RL; ++r) v[i][r] = cmulc(v[i][r], a.tw_row[r * j]);
             dft<RL, true>(v[i]);
@@ -287,13 +294,13 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel_f(ShearStreamArg
         for (int i = 0; i < ITL; ++i) {
             const unsigned j = lane + i * TPR;
 #pragma unroll
-            for (int r = 0; r < RL; ++r) row[swz(j * RL + r)] = v[i][r];
+            for (int r = 0; r < RL; ++r) row[lpos_run<AF, RL>(j, r)] = v[i][r];
         }
         __syncthreads();
     }
 
     // middle forward passes, then the last one (NS = L/16) to HBM
-    passes_before<L, middle_radix<L>(), RL, 16, TPR, false>(row, opaque(lane), opaque(a.tw_row));
+    passes_before<L, RM, RL, 16, TPR, false, AF>(row, opaque(lane), opaque(a.tw_row));
     if (valid) {
         const unsigned lane2 = opaque(lane);
         const float2* tw = opaque(a.tw_row);
@@ -303,7 +310,7 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel_f(ShearStreamArg
             if (NT16 % TPR == 0 || j < (unsigned)NT16) {
                 float2 v[16];
 #pragma unroll
-                for (int r = 0; r < 16; ++r) v[r] = row[swz(j + r * NT16)];
+                for (int r = 0; r < 16; ++r) v[r] = row[lpos_step<AD, NT16>(j, r)];
 #pragma unroll
                 for (int r = 1; r < 16; ++r) v[r] = cmul(v[r], tw[r * j]);
                 dft<16, false>(v);

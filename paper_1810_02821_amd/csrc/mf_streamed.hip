@@ -364,7 +364,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel(SweepArgs a, int H) {
 enum RowVariant : int { kRowLoadLate = 0, kRowPrefetch = 1, kRowAny = 2 };
 
 template <int L, int ROWS_, int VAR>
-__global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
+__global__ __launch_bounds__(kThreads, ((L == 2048 && ROWS_ == 1 && VAR == 0) || (L == 512 && ROWS_ == 8 && VAR == 2)) ? 6 : 1) void row_kernel_f(SweepArgs a, int H) {
     constexpr bool kPrefetch = VAR == kRowPrefetch;
     constexpr int ROWS = ROWS_;
     constexpr int TPR = kThreads / ROWS;
@@ -375,12 +375,21 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
     constexpr int NTL = L / RL;                     // last-radix butterflies per row
     constexpr int ITL = NTL / TPR;
     static_assert(L >= 256 && NTL % TPR == 0 && RL % 2 == 0, "row_kernel_f shape");
-    __shared__ float2 lds[ROWS * L];
+    // padded LDS layouts: stage A writes A1, the middle inverse passes leave
+    // AC, stage C writes AF, the middle forward passes leave AD
+    constexpr int RM = middle_radix<L>();
+    constexpr int A1 = pad_of(L, 16, 1), AC = pad_after(L, RM, 16, RL, A1);
+    constexpr int AF = pad_of(L, RL, 1), AD = pad_after(L, RM, RL, 16, AF);
+    constexpr int AMAX = pad_max(L, RM, 16, RL, A1) > pad_max(L, RM, RL, 16, AF) ? pad_max(L, RM, 16, RL, A1)
+                                                                                 : pad_max(L, RM, RL, 16, AF);
+    constexpr int LP = pad_len(L, AMAX);  // row stride in LDS
+    __shared__ float2 lds[ROWS * LP];
     // twiddles in LDS up to 1024 points (1024^2 -8%, 512^2 -6%, 256^2 -5% per
     // sweep); at 2048 the extra 16 KiB would cost a resident block (+3%)
     constexpr bool kTwLds = L <= 1024;
     __shared__ float2 twl[kTwLds ? L : 1];
-    __shared__ double red[kThreads];
+    static_assert(ROWS * LP >= kThreads, "residual partials fit in the rows");
+    double* red = reinterpret_cast<double*>(lds);  // residual partials, once stage C has read the rows
     __shared__ int32_t row_item[ROWS], row_y[ROWS];
 
     const unsigned tid = threadIdx.x;
@@ -411,7 +420,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
         twr = a.tw_row;
     }
     const ProbDev pr{H, W, it.pix_off, it.tau, it.pid};
-    float2* row = lds + rid * L;
+    float2* row = lds + rid * LP;
     const int64_t frow = it.field_off + (int64_t)y * W;
     float pnb[kPrefetch ? ITL : 1][kPrefetch ? RL : 1], psr[kPrefetch ? ITL : 1][kPrefetch ? RL : 1];
     if constexpr (kPrefetch) {
@@ -442,14 +451,14 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
                 for (int r = 0; r < 16; ++r) v[i][r] = widen(fld[j + r * NT16]);
                 dft<16, true>(v[i]);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) row[swz(j * 16 + r)] = v[i][r];
+                for (int r = 0; r < 16; ++r) row[lpos_run<A1, 16>(j, r)] = v[i][r];
             }
         }
     });
     __syncthreads();
 
     // ---- B: middle inverse passes
-    passes_before<L, middle_radix<L>(), 16, RL, TPR, true>(row, lane, twr);
+    passes_before<L, RM, 16, RL, TPR, true, A1>(row, lane, twr);
 
     // ---- C: last inverse pass, emission, pixel update, first forward pass
     {
@@ -461,7 +470,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
         for (int i = 0; i < ITL; ++i) {
             const unsigned j = lane + i * TPR;
 #pragma unroll
-            for (int r = 0; r < RL; ++r) v[i][r] = row[swz(j + r * NTL)];
+            for (int r = 0; r < RL; ++r) v[i][r] = row[lpos_step<AC, NTL>(j, r)];
 #pragma unroll
             for (int r = 1; r < RL; ++r) v[i][r] = cmulc(v[i][r], twr[r * j]);
             dft<RL, true>(v[i]);
@@ -560,6 +569,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
             dft<RL, false>(v[i]);
         }
         if (a.check_t) {
+            __syncthreads();  // every thread has read its row
             red[tid] = acc;
             __syncthreads();
             if (lane == 0 && valid) {
@@ -573,13 +583,13 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
         for (int i = 0; i < ITL; ++i) {
             const unsigned j = lane + i * TPR;
 #pragma unroll
-            for (int r = 0; r < RL; ++r) row[swz(j * RL + r)] = v[i][r];
+            for (int r = 0; r < RL; ++r) row[lpos_run<AF, RL>(j, r)] = v[i][r];
         }
         __syncthreads();
     }
 
     // ---- D: middle forward passes, then the last one (NS = L/16) to HBM
-    passes_before<L, middle_radix<L>(), RL, 16, TPR, false>(row, fresh(lane), twr + fresh(0u));
+    passes_before<L, RM, RL, 16, TPR, false, AF>(row, fresh(lane), twr + fresh(0u));
     if (valid)
         with_storage(a.storage, [&](auto e0) {
             using E = decltype(e0);
@@ -592,7 +602,7 @@ __global__ __launch_bounds__(kThreads) void row_kernel_f(SweepArgs a, int H) {
                 const unsigned j = lane2 + i * TPR;
                 if (NT16 % TPR == 0 || j < (unsigned)NT16) {
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) v[i][r] = row[swz(j + r * NT16)];
+                    for (int r = 0; r < 16; ++r) v[i][r] = row[lpos_step<AD, NT16>(j, r)];
 #pragma unroll
                     for (int r = 1; r < 16; ++r) v[i][r] = cmul(v[i][r], tw[r * j]);
                     dft<16, false>(v[i]);

@@ -22,13 +22,31 @@ template <int L>
 constexpr int middle_radix() { return L == 256 ? 4 : 16; }
 
 // Radix-RM Stockham passes over LDS with NS = NS0, RM NS0, ... while
-// NS * RM * TAIL <= L and NS * TAIL < L: all passes before a final pass of radix TAIL.
-template <int L, int RM, int NS, int TAIL, int TPG, bool INV>
+// NS * RM * TAIL <= L and NS * TAIL < L: all passes before a final pass of
+// radix TAIL.  The first pass reads layout AI; with AI >= 0 every pass writes
+// the padded layout pad_of picks for it, otherwise the XOR swizzle.
+template <int L, int RM, int NS, int TAIL, int TPG, bool INV, int AI = -1>
 __device__ __forceinline__ void passes_before(float2* buf, unsigned lane, const float2* __restrict__ tw) {
     if constexpr (NS * RM * TAIL <= L && NS * TAIL < L) {
-        stockham_pass<L, RM, NS, TPG, INV>(buf, lane, tw);
-        passes_before<L, RM, NS * RM, TAIL, TPG, INV>(buf, lane, tw);
+        constexpr int AO = AI >= 0 ? pad_of(L, RM, NS) : -1;
+        stockham_pass<L, RM, NS, TPG, INV, AI, AO>(buf, lane, tw);
+        passes_before<L, RM, NS * RM, TAIL, TPG, INV, AO>(buf, lane, tw);
     }
+}
+// Layout passes_before<L, RM, NS, TAIL, ..., AI> leaves its output in, and the
+// largest pad among its input and the layouts it writes.
+constexpr int pad_after(int L, int RM, int NS, int TAIL, int AI) {
+    int a = AI;
+    for (; NS * RM * TAIL <= L && NS * TAIL < L; NS *= RM) a = AI >= 0 ? pad_of(L, RM, NS) : -1;
+    return a;
+}
+constexpr int pad_max(int L, int RM, int NS, int TAIL, int AI) {
+    int m = AI;
+    for (; NS * RM * TAIL <= L && NS * TAIL < L; NS *= RM) {
+        const int a = AI >= 0 ? pad_of(L, RM, NS) : -1;
+        m = a > m ? a : m;
+    }
+    return m;
 }
 
 // One plan per transform length for every row kernel (the fused and the plain
