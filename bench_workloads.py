@@ -140,6 +140,21 @@ def uneven(args):
                                              "pixel_sweeps_per_s": px[int(sz)] * sweeps / tc,
                                              "form": "persistent" if sz <= 128 else "streamed"}
         del cplan, cd, cst
+    # the same batch on the default shapes (autotuner off)
+    print("[bench] uneven: default shapes", file=sys.stderr, flush=True)
+    dplan = mf.Plan(probs, autotune=False, graph=True)
+    dd = dplan.concat([p.d for p in probs])
+    dst = dplan.state_buffer(1)
+    drun = lambda: dplan.sample(dd, 1000, chains=1, burn_in=sweeps, n_samples=0, form="auto",
+                                state_out=dst, samples=False)
+    drun()
+    td = _timed(drun, 1)
+    default_shapes = {"seconds": td, "pixel_sweeps_per_s": total_px * sweeps / td,
+                      "tile_shapes": {f"{s}x{s}": list(dplan.tile_shape(int(s), int(s)))
+                                      for s in np.unique(sizes) if s >= 256},
+                      "row_shapes": {f"{s}x{s}": dplan.row_shape(int(s), int(s))
+                                     for s in np.unique(sizes) if s >= 256}}
+    del dplan, dd, dst
     print(json.dumps({"workload": "uneven", "metric": "pixel-sweeps/s, 4096 uneven problems, 500 sweeps",
                       "value": total_px * sweeps / t, "unit": "pixel-sweeps/s (one chain per problem)",
                       "seconds": t, "problems_per_size": {int(s): int(np.sum(sizes == s)) for s in np.unique(sizes)},
@@ -147,7 +162,10 @@ def uneven(args):
                       "plan_seconds": t_plan, "generate_seconds": t_gen,
                       "graph": True, "autotune": True,
                       "tile_shapes": {f"{s}x{s}": list(plan.tile_shape(int(s), int(s)))
-                                      for s in np.unique(sizes) if s >= 256}}), flush=True)
+                                      for s in np.unique(sizes) if s >= 256},
+                      "row_shapes": {f"{s}x{s}": plan.row_shape(int(s), int(s))
+                                     for s in np.unique(sizes) if s >= 256},
+                      "default_shapes": default_shapes, "autotune_speedup": td / t}), flush=True)
 
 
 def grad(args):
