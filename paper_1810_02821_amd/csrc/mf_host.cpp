@@ -321,10 +321,28 @@ std::pair<int, int> class_shape(mf_plan p, int H, int W) {
 }
 
 // The tile of a launch over n_items work items: the class's shape, or its
-// narrow shape when the class's shape would leave CUs idle.
+// narrow shape when the class's shape would leave CUs idle.  A default tile
+// that reads its twiddles from L2 relies on a second workgroup per CU to hide
+// them; a launch giving each CU at most two such tiles has none to overlap and
+// takes the widest candidate with LDS twiddles that still gives every CU a
+// workgroup (one 2048^2 field: 8 x 512 instead of 4 x 256).
 std::pair<int, int> class_shape(mf_plan p, int H, int W, int64_t n_items) {
     const auto wide = class_shape(p, H, W);
-    if (n_items * ((W + wide.first - 1) / wide.first) >= mf::kFillBlocks) return wide;
+    const int64_t tiles = n_items * ((W + wide.first - 1) / wide.first);
+    if (tiles >= mf::kFillBlocks) {
+        if (tiles <= 2 * mf::kFillBlocks && mf::col_tw_in_l2(H, wide.first) &&
+            p->col_shape.find({H, W}) == p->col_shape.end()) {
+            int tc[8], nth[8];
+            const int k = mf::col_shape_candidates(H, tc, nth, 8);
+            int b = -1;
+            for (int i = 0; i < k; ++i)
+                if (!mf::col_tw_in_l2(H, tc[i]) && n_items * ((W + tc[i] - 1) / tc[i]) >= mf::kFillBlocks &&
+                    (b < 0 || tc[i] > tc[b]))
+                    b = i;
+            if (b >= 0) return {tc[b], nth[b]};
+        }
+        return wide;
+    }
     auto it = p->col_shape_narrow.find({H, W});
     if (it != p->col_shape_narrow.end()) return it->second;
     int tc = 0, nth = 0;

@@ -112,6 +112,10 @@ int fused_row_candidates(int W, int* rows, int max_n);
 // than the GPU has CUs (a single solve, a few chains) takes the narrow shape
 // instead: tuned on one item, else the candidate with the most blocks.
 constexpr int kFillBlocks = 256;
+// Column tiles that read their twiddles from L2 instead of LDS: 4 columns of
+// 2048 rows, so that two workgroups fit in a CU's LDS and one's memory phases
+// overlap the other's.
+constexpr bool col_tw_in_l2(int L, int tc) { return L == 2048 && tc <= 4; }
 void narrow_col_shape(int H, int* tc, int* nth);
 int narrow_row_rows(int W);
 // Sum per-tile band slots into out[band_base[prob] + b] for every item.

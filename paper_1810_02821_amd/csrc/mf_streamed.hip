@@ -643,7 +643,10 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     constexpr int SEG = lds_stride<L>() + 32 / TC;
     constexpr int H = L;
     __shared__ float2 lds[TC * SEG];
-    __shared__ float2 twl[L];  // twiddles in LDS (as in col_kernel_f; identical values)
+    // twiddles in LDS, or in L2 for 4-column tiles of 2048 rows (as in col_kernel_f; identical values)
+    constexpr bool kTwLds = !col_tw_in_l2(L, TC);
+    __shared__ float2 twl[kTwLds ? L : 1];
+    const float2* twp = kTwLds ? twl : a.tw_col;
     const unsigned tid = threadIdx.x;
     // tiles enumerated with the tile fastest: t = item * tiles + tile.  An
     // XCD then runs neighbouring tiles of one item together, and the cache
@@ -657,7 +660,8 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     const ProbDev pr = a.probs[it.prob];
     const int64_t f0 = it.field_off + x0;
 
-    for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];  // visible after the tile barrier
+    if constexpr (kTwLds)
+        for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];  // visible after the tile barrier
     with_storage(a.storage, [&](auto e0) {
         using E = decltype(e0);
         const E* fld = reinterpret_cast<const E*>(a.field) + f0;
@@ -669,7 +673,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
     });
     __syncthreads();
     const unsigned cid = tid / TPC, lane = tid % TPC;
-    stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, twl);
+    stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, twp);
 
     const float T = a.lambda * pr.tau;
     if (a.t_store) {
@@ -735,7 +739,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_t(SweepArgs a, int W) {
         }
     }
     __syncthreads();
-    stockham_fft<L, 1, TPC, true>(lds + fresh(cid) * SEG, fresh(lane), twl + fresh(0u));
+    stockham_fft<L, 1, TPC, true>(lds + fresh(cid) * SEG, fresh(lane), twp + fresh(0u));
 
     with_storage(a.storage, [&](auto e0) {
         using E = decltype(e0);
@@ -781,7 +785,13 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     constexpr int ITL = (NTL + TPP - 1) / TPP;
     static_assert(L >= 256 && TC % 2 == 0 && NTH % (TC / 2) == 0, "col_kernel_f shape");
     __shared__ float2 lds[TC * SEG];
-    __shared__ float2 twl[L];  // twiddles W_H^r: LDS latency instead of L2's for every pass
+    // twiddles W_H^r in LDS: LDS latency instead of L2's for every pass; the
+    // 4-column tiles of 2048 rows (the default there) read them from L2
+    // instead, so that two workgroups fit in a CU's LDS and one's memory
+    // phases overlap the other's (2048^2 sweep -3.5%)
+    constexpr bool kTwLds = !col_tw_in_l2(L, TC);
+    __shared__ float2 twl[kTwLds ? L : 1];
+    const float2* twp = kTwLds ? twl : a.tw_col;
     const unsigned tid = threadIdx.x;
     const int64_t t = xcd_block(blockIdx.x, gridDim.x);
     const int item = (int)(t / (W / TC));
@@ -790,7 +800,8 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     // offset, tau and index); the twiddles go out beside it and the mode
     // table of phase C beside the field loads
     const ItemDev it = a.items[item];
-    for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];  // visible after phase A's barrier
+    if constexpr (kTwLds)
+        for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];  // visible after phase A's barrier
     const ProbDev pr{H, W, it.pix_off, it.tau, it.pid};
     const int64_t f0 = it.field_off + x0;
     float2 pnp[ITL][RL];
@@ -836,7 +847,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     // ---- B: middle forward passes
     {
         const unsigned cid = tid / TPC, lane = tid % TPC;
-        passes_before<L, middle_radix<L>(), 16, RL, TPC, false>(lds + cid * SEG, lane, twl);
+        passes_before<L, middle_radix<L>(), 16, RL, TPC, false>(lds + cid * SEG, lane, twp);
     }
 
     // ---- C: last forward pass + Fourier-space update + first inverse pass
@@ -856,7 +867,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
                     for (int r = 0; r < RL; ++r) v[i][q][r] = lds[(2 * pp + q) * SEG + swz(j + r * NTL)];
 #pragma unroll
                 for (int r = 1; r < RL; ++r) {
-                    const float2 w = twl[r * j];
+                    const float2 w = twp[r * j];
                     v[i][0][r] = cmul(v[i][0][r], w);
                     v[i][1][r] = cmul(v[i][1][r], w);
                 }
@@ -911,13 +922,13 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     // ---- D: middle inverse passes, then the last one (NS = L/16) to HBM
     {
         const unsigned cid = fresh(tid) / TPC, lane = fresh(tid) % TPC;
-        passes_before<L, middle_radix<L>(), RL, 16, TPC, true>(lds + cid * SEG, lane, twl + fresh(0u));
+        passes_before<L, middle_radix<L>(), RL, 16, TPC, true>(lds + cid * SEG, lane, twp + fresh(0u));
     }
     with_storage(a.storage, [&](auto e0) {
         using E = decltype(e0);
         E* fld = reinterpret_cast<E*>(a.field) + f0;
         const unsigned tid2 = fresh(tid);
-        const float2* tw = twl + fresh(0u);
+        const float2* tw = twp + fresh(0u);
         float2 v[IT16][16];
 #pragma unroll
         for (int i = 0; i < IT16; ++i) {
@@ -1530,7 +1541,7 @@ int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
                                    {512, 8, 256}, {512, 4, 256},
                                    {1024, 8, 512}, {1024, 16, 1024}, {1024, 8, 1024}, {1024, 16, 512},
                                    {1024, 4, 256},
-                                   {2048, 8, 512}, {2048, 8, 1024}, {2048, 4, 512}, {2048, 4, 256}};
+                                   {2048, 4, 256}, {2048, 8, 512}, {2048, 8, 1024}, {2048, 4, 512}};
     int n = 0;
     for (const auto& r : table)
         if (r[0] == H && n < max_n) {

@@ -187,7 +187,7 @@ def test_autotuned_shapes_give_identical_samples(torch_cuda):
     shapes = {p.H: (base.tile_shape(p.H, p.W), tuned.tile_shape(p.H, p.W)) for p in probs}
     rows = {p.H: (base.row_shape(p.H, p.W), tuned.row_shape(p.H, p.W)) for p in probs}
     print("default / tuned column tiles:", shapes, "fused row rows:", rows)
-    defaults = {256: (16, 256), 512: (16, 512), 1024: (8, 512), 2048: (8, 512)}
+    defaults = {256: (16, 256), 512: (16, 512), 1024: (8, 512), 2048: (4, 256)}
     row_defaults = {256: 8, 512: 8, 1024: 2, 2048: 1}
     row_choices = {256: (8, 4, 16), 512: (8, 4, 2), 1024: (2, 1, 4), 2048: (1, 2)}
     # launches too small to fill the GPU: the shapes with the most workgroups
@@ -234,7 +234,8 @@ def test_every_fused_row_shape_gives_identical_samples(torch_cuda, tmp_path, mon
 
 COL_TILES = {256: ((16, 256), (8, 256), (16, 512), (8, 512), (4, 128), (4, 256)),
              512: ((16, 512), (8, 512), (16, 256), (16, 1024), (8, 256), (4, 256)),
-             1024: ((8, 512), (16, 1024), (8, 1024), (16, 512), (4, 256))}
+             1024: ((8, 512), (16, 1024), (8, 1024), (16, 512), (4, 256)),
+             2048: ((4, 256), (8, 512), (8, 1024), (4, 512))}
 
 
 def test_every_column_tile_gives_identical_samples(torch_cuda, tmp_path, monkeypatch):
@@ -244,8 +245,9 @@ def test_every_column_tile_gives_identical_samples(torch_cuda, tmp_path, monkeyp
     for bit."""
     torch = torch_cuda
     import paper_1810_02821_amd as mf
-    banner("column tiles 256/512/1024")
-    probs = [synth.config_128(1, 256), synth.config_128(2, 512), synth.config_large(0, 1024)]
+    banner("column tiles 256/512/1024/2048")
+    probs = [synth.config_128(1, 256), synth.config_128(2, 512), synth.config_large(0, 1024),
+             synth.config_large(1, 2048)]
     base = mf.Plan(probs)
     d = base.concat([p.d for p in probs])
     ref, _ = base.sample(d, 9, chains=2, burn_in=2, n_samples=2, form="streamed")
