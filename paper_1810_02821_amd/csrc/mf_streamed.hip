@@ -778,9 +778,17 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     constexpr int TC = TC_;
     constexpr int NTH = NTH_;
     constexpr int TPC = NTH / TC;
-    constexpr int SEG = L + 32 / TC;
     constexpr int H = L;
     constexpr int RL = last_radix<L>();
+    // padded layouts (as in the fused row kernel): phase A writes A1, the
+    // middle forward passes leave AC, phase C writes AF, the middle inverse
+    // passes leave AD; the slot stride keeps phases A and D free of conflicts
+    constexpr int RM = middle_radix<L>();
+    constexpr int A1 = pad_of(L, 16, 1), AC = pad_after(L, RM, 16, RL, A1);
+    constexpr int AF = pad_of(L, RL, 1), AD = pad_after(L, RM, RL, 16, AF);
+    constexpr int AMAX = pad_max(L, RM, 16, RL, A1) > pad_max(L, RM, RL, 16, AF) ? pad_max(L, RM, 16, RL, A1)
+                                                                                 : pad_max(L, RM, RL, 16, AF);
+    constexpr int SEG = tile_seg(TC, A1, AD, pad_len(L, AMAX));
     constexpr int NT16 = L / 16;                            // radix-16 butterflies per column
     constexpr int IT16 = (TC * NT16 + NTH - 1) / NTH;       // per thread in phases A and D
     constexpr int NTL = L / RL;                             // last-radix butterflies per column
@@ -841,7 +849,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
                 const unsigned c = b % TC, j = b / TC;
                 dft<16, false>(v[i]);
 #pragma unroll
-                for (int r = 0; r < 16; ++r) lds[c * SEG + swz(j * 16 + r)] = v[i][r];
+                for (int r = 0; r < 16; ++r) lds[c * SEG + lpos_run<A1, 16>(j, r)] = v[i][r];
             }
         }
     });
@@ -850,7 +858,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     // ---- B: middle forward passes
     {
         const unsigned cid = tid / TPC, lane = tid % TPC;
-        passes_before<L, middle_radix<L>(), 16, RL, TPC, false>(lds + cid * SEG, lane, twp);
+        passes_before<L, RM, 16, RL, TPC, false, A1>(lds + cid * SEG, lane, twp);
     }
 
     // ---- C: last forward pass + Fourier-space update + first inverse pass
@@ -867,7 +875,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int r = 0; r < RL; ++r) v[i][q][r] = lds[(2 * pp + q) * SEG + swz(j + r * NTL)];
+                    for (int r = 0; r < RL; ++r) v[i][q][r] = lds[(2 * pp + q) * SEG + lpos_step<AC, NTL>(j, r)];
 #pragma unroll
                 for (int r = 1; r < RL; ++r) {
                     const float2 w = twp[r * j];
@@ -916,7 +924,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
-                    for (int r = 0; r < RL; ++r) lds[(2 * pp + q) * SEG + swz(j * RL + r)] = v[i][q][r];
+                    for (int r = 0; r < RL; ++r) lds[(2 * pp + q) * SEG + lpos_run<AF, RL>(j, r)] = v[i][q][r];
             }
         }
         __syncthreads();
@@ -925,7 +933,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     // ---- D: middle inverse passes, then the last one (NS = L/16) to HBM
     {
         const unsigned cid = fresh(tid) / TPC, lane = fresh(tid) % TPC;
-        passes_before<L, middle_radix<L>(), RL, 16, TPC, true>(lds + cid * SEG, lane, twp + fresh(0u));
+        passes_before<L, RM, RL, 16, TPC, true, AF>(lds + cid * SEG, lane, twp + fresh(0u));
     }
     with_storage(a.storage, [&](auto e0) {
         using E = decltype(e0);
@@ -939,7 +947,7 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
             if ((TC * NT16) % NTH == 0 || b < (unsigned)(TC * NT16)) {
                 const unsigned c = b % TC, j = b / TC;
 #pragma unroll
-                for (int r = 0; r < 16; ++r) v[i][r] = lds[c * SEG + swz(j + r * NT16)];
+                for (int r = 0; r < 16; ++r) v[i][r] = lds[c * SEG + lpos_step<AD, NT16>(j, r)];
 #pragma unroll
                 for (int r = 1; r < 16; ++r) v[i][r] = cmulc(v[i][r], tw[r * j]);
                 dft<16, true>(v[i]);

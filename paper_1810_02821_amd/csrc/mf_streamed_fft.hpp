@@ -49,6 +49,44 @@ constexpr int pad_max(int L, int RM, int NS, int TAIL, int AI) {
     return m;
 }
 
+// Column tiles in padded layouts: TC slots of SEG elements.  The phases that
+// cross slots are the first forward pass, whose 32 lanes (slot c = l mod TC,
+// butterfly j = l / TC) store elements 16 j + r in layout A1, and the last
+// inverse pass, whose lanes load elements j + r L/16 in layout AD.  Their
+// bank-pair multiplicities (the most of 32 lanes sharing one), summed:
+constexpr int tile_conflicts(int TC, int SEG, int A1, int AD) {
+    int total = 0;
+    for (int phase = 0; phase < 2; ++phase) {
+        int worst = 1;
+        for (int j0 = 0; j0 < 64; j0 += 32 / TC) {
+            int cnt[32] = {};
+            for (int l = 0; l < 32; ++l) {
+                const int c = l % TC, j = j0 + l / TC;
+                const int i = phase == 0 ? 16 * j : j;
+                const int A = phase == 0 ? A1 : AD;
+                const int b = (c * SEG + i + A * (i >> 5)) & 31;
+                cnt[b] += 1;
+                worst = cnt[b] > worst ? cnt[b] : worst;
+            }
+        }
+        total += worst;
+    }
+    return total;
+}
+// Slot stride of such a tile: the smallest of the 32 strides from `need` up
+// with the fewest conflicts.
+constexpr int tile_seg(int TC, int A1, int AD, int need) {
+    int best = need, bc = 1 << 30;
+    for (int sg = need; sg < need + 32; ++sg) {
+        const int c = tile_conflicts(TC, sg, A1, AD);
+        if (c < bc) {
+            bc = c;
+            best = sg;
+        }
+    }
+    return best;
+}
+
 // One plan per transform length for every row kernel (the fused and the plain
 // row kernels, and hence split and resumed runs, then round alike): inverse
 // 16, RM..., RL and forward RL, RM..., 16 from 256 points up (powers of two;
