@@ -53,7 +53,15 @@ __device__ __forceinline__ float2 chain0_mode_normal(uint32_t e, uint32_t sweep,
 
 template <int L>
 __global__ __launch_bounds__(PackShape<L>::NTH) void col_pack_kernel(SweepArgs a, int W) {
-    constexpr int TC = PackShape<L>::TC, NTH = PackShape<L>::NTH, TPC = PackShape<L>::TPC, SEG = PackShape<L>::SEG;
+    constexpr int TC = PackShape<L>::TC, NTH = PackShape<L>::NTH, TPC = PackShape<L>::TPC;
+    // padded exchange layouts from 256 rows (the HBM-side passes) where they
+    // keep the resident workgroups per CU, else the XOR swizzle
+    constexpr int kExtra = 8 * L;  // twiddles and tables beside the tile
+    constexpr bool kPad = L >= 256 && lds_keeps_blocks(TC * PackShape<L>::SEG * 8 + kExtra,
+                                                       TC * PairLayout<L, TC>::SEG * 8 + kExtra);
+    constexpr int A1 = kPad ? PairLayout<L, TC>::A1 : -1, AN = kPad ? PairLayout<L, TC>::AN : -1;
+    constexpr int AD = kPad ? PairLayout<L, TC>::AD : -1;
+    constexpr int SEG = kPad ? PairLayout<L, TC>::SEG : PackShape<L>::SEG;
     constexpr int H = L;
     constexpr int half = TC / 2;
     __shared__ float2 lds[TC * SEG];
@@ -69,7 +77,7 @@ __global__ __launch_bounds__(PackShape<L>::NTH) void col_pack_kernel(SweepArgs a
 
     auto col_of = [&](int s) { return mirror_column(j, s, half, W); };
     if constexpr (L >= 256) {
-        col_first_forward<L, TC, NTH, SEG>(lds, fld, W, tid, col_of);
+        col_first_forward<L, TC, NTH, SEG, A1>(lds, fld, W, tid, col_of);
         for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];
     } else {
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
@@ -79,7 +87,7 @@ __global__ __launch_bounds__(PackShape<L>::NTH) void col_pack_kernel(SweepArgs a
     }
     __syncthreads();
     const unsigned cid = tid / TPC, lane = tid % TPC;
-    if constexpr (L >= 256) col_forward_rest<L, TPC>(lds + cid * SEG, lane, twl);
+    if constexpr (L >= 256) col_forward_rest<L, TPC, A1>(lds + cid * SEG, lane, twl);
     else stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
 
     const float TA = a.lambda * pa.tau, TB = a.lambda * pb.tau;
@@ -90,8 +98,8 @@ __global__ __launch_bounds__(PackShape<L>::NTH) void col_pack_kernel(SweepArgs a
     // harmonic normals at k and -k
     auto update = [&](int s, int p, int ky, int my, bool self, float PA, float PB, float2 hkA, float2 hmA,
                       float2 hkB, float2 hmB) {
-        float2& zk = lds[s * SEG + swz(ky)];
-        float2& zm = lds[p * SEG + swz(my)];
+        float2& zk = lds[s * SEG + lpos<AN>(ky)];
+        float2& zm = lds[p * SEG + lpos<AN>(my)];
         const float2 Zk = zk, Zm = zm;
         const float rA = __builtin_amdgcn_rcpf(PA + TA), rB = __builtin_amdgcn_rcpf(PB + TB);
         const float fA = PA * rA * inv_n, fB = PB * rB * inv_n;
@@ -191,8 +199,8 @@ __global__ __launch_bounds__(PackShape<L>::NTH) void col_pack_kernel(SweepArgs a
     }
     __syncthreads();
     if constexpr (L >= 256) {
-        col_inverse_head<L, TPC>(lds + opaque_u(cid) * SEG, opaque_u(lane), twl + opaque_u(0u));
-        col_last_inverse<L, TC, NTH, SEG>(lds, fld, W, opaque_u(tid), twl + opaque_u(0u), col_of);
+        col_inverse_head<L, TPC, AN>(lds + opaque_u(cid) * SEG, opaque_u(lane), twl + opaque_u(0u));
+        col_last_inverse<L, TC, NTH, SEG, AD>(lds, fld, W, opaque_u(tid), twl + opaque_u(0u), col_of);
     } else {
         stockham_fft<L, 1, TPC, true>(lds + opaque_u(cid) * SEG, opaque_u(lane), a.tw_col);
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {

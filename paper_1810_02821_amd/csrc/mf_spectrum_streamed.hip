@@ -62,7 +62,15 @@ __device__ __forceinline__ float2 mode_normal(uint32_t e, uint32_t sweep, uint32
 
 template <int L>
 __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStreamArgs a, int W) {
-    constexpr int TC = PairShape<L>::TC, NTH = PairShape<L>::NTH, TPC = PairShape<L>::TPC, SEG = PairShape<L>::SEG;
+    constexpr int TC = PairShape<L>::TC, NTH = PairShape<L>::NTH, TPC = PairShape<L>::TPC;
+    // padded exchange layouts from 256 rows (the HBM-side passes) where they
+    // keep the resident workgroups per CU, else the XOR swizzle
+    constexpr int kExtra = 8 * L + (int)(sizeof(double) * 2 * kNB + sizeof(float4) * kNB);  // twiddles and tables beside the tile
+    constexpr bool kPad = L >= 256 && lds_keeps_blocks(TC * PairShape<L>::SEG * 8 + kExtra,
+                                                       TC * PairLayout<L, TC>::SEG * 8 + kExtra);
+    constexpr int A1 = kPad ? PairLayout<L, TC>::A1 : -1, AN = kPad ? PairLayout<L, TC>::AN : -1;
+    constexpr int AD = kPad ? PairLayout<L, TC>::AD : -1;
+    constexpr int SEG = kPad ? PairLayout<L, TC>::SEG : PairShape<L>::SEG;
     constexpr int H = L;
     constexpr int half = TC / 2;
     __shared__ float2 lds[TC * SEG];
@@ -82,7 +90,7 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
     auto col_of = [&](int s) { return pair_column(j, s, half, W); };
     if constexpr (L >= 256) {
         // first forward pass straight from HBM (plan of mf_streamed_fft.hpp)
-        col_first_forward<L, TC, NTH, SEG>(lds, fld, W, tid, col_of);
+        col_first_forward<L, TC, NTH, SEG, A1>(lds, fld, W, tid, col_of);
     } else {
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
             const int s = (int)(e % TC), y = (int)(e / TC);
@@ -95,7 +103,7 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
         for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];
     __syncthreads();
     const unsigned cid = tid / TPC, lane = tid % TPC;
-    if constexpr (L >= 256) col_forward_rest<L, TPC>(lds + cid * SEG, lane, twl);
+    if constexpr (L >= 256) col_forward_rest<L, TPC, A1>(lds + cid * SEG, lane, twl);
     else stockham_fft<L, 1, TPC, false>(lds + cid * SEG, lane, a.tw_col);
 
     const int16_t* band = a.band + pr.pix_off;
@@ -104,8 +112,8 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
     // p, row my; band(-k) = band(k): same |k|), given the chain pair's
     // harmonic normals at k and -k
     auto update = [&](int s, int p, int ky, int my, bool self, int b, float2 hk, float2 hm) {
-        float2& zk = lds[s * SEG + swz(ky)];
-        float2& zm = lds[p * SEG + swz(my)];
+        float2& zk = lds[s * SEG + lpos<AN>(ky)];
+        float2& zm = lds[p * SEG + lpos<AN>(my)];
         const float2 Zk = zk, Zm = zm;
         const float4 c = coef[b];
         const float fp = 0.5f * (c.x + c.z), fm = 0.5f * (c.x - c.z);
@@ -190,8 +198,8 @@ __global__ __launch_bounds__(PairShape<L>::NTH) void col_pair_kernel(SpectrumStr
         }
     if constexpr (L >= 256) {
         // inverse transform, its last pass straight to HBM
-        col_inverse_head<L, TPC>(lds + opaque(cid) * SEG, opaque(lane), twl + opaque(0u));
-        col_last_inverse<L, TC, NTH, SEG>(lds, fld, W, opaque(tid), twl + opaque(0u), col_of);
+        col_inverse_head<L, TPC, AN>(lds + opaque(cid) * SEG, opaque(lane), twl + opaque(0u));
+        col_last_inverse<L, TC, NTH, SEG, AD>(lds, fld, W, opaque(tid), twl + opaque(0u), col_of);
     } else {
         stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {

@@ -780,15 +780,21 @@ __global__ __launch_bounds__(NTH_) void col_kernel_f(SweepArgs a, int W) {
     constexpr int TPC = NTH / TC;
     constexpr int H = L;
     constexpr int RL = last_radix<L>();
-    // padded layouts (as in the fused row kernel): phase A writes A1, the
-    // middle forward passes leave AC, phase C writes AF, the middle inverse
-    // passes leave AD; the slot stride keeps phases A and D free of conflicts
+    // padded layouts (as in the fused row kernel) where they keep the
+    // resident workgroups per CU, else the XOR swizzle: phase A writes A1,
+    // the middle forward passes leave AC, phase C writes AF, the middle
+    // inverse passes leave AD; the slot stride keeps phases A and D free of
+    // conflicts
     constexpr int RM = middle_radix<L>();
-    constexpr int A1 = pad_of(L, 16, 1), AC = pad_after(L, RM, 16, RL, A1);
-    constexpr int AF = pad_of(L, RL, 1), AD = pad_after(L, RM, RL, 16, AF);
-    constexpr int AMAX = pad_max(L, RM, 16, RL, A1) > pad_max(L, RM, RL, 16, AF) ? pad_max(L, RM, 16, RL, A1)
-                                                                                 : pad_max(L, RM, RL, 16, AF);
-    constexpr int SEG = tile_seg(TC, A1, AD, pad_len(L, AMAX));
+    constexpr int P1 = pad_of(L, 16, 1), PF = pad_of(L, RL, 1);
+    constexpr int PMAX = pad_max(L, RM, 16, RL, P1) > pad_max(L, RM, RL, 16, PF) ? pad_max(L, RM, 16, RL, P1)
+                                                                                 : pad_max(L, RM, RL, 16, PF);
+    constexpr int PSEG = tile_seg(TC, P1, pad_after(L, RM, RL, 16, PF), pad_len(L, PMAX));
+    constexpr int kExtra = col_tw_in_l2(L, TC) ? 0 : 8 * L;
+    constexpr bool kPad = lds_keeps_blocks(TC * (L + 32 / TC) * 8 + kExtra, TC * PSEG * 8 + kExtra);
+    constexpr int A1 = kPad ? P1 : -1, AC = pad_after(L, RM, 16, RL, A1);
+    constexpr int AF = kPad ? PF : -1, AD = pad_after(L, RM, RL, 16, AF);
+    constexpr int SEG = kPad ? PSEG : L + 32 / TC;
     constexpr int NT16 = L / 16;                            // radix-16 butterflies per column
     constexpr int IT16 = (TC * NT16 + NTH - 1) / NTH;       // per thread in phases A and D
     constexpr int NTL = L / RL;                             // last-radix butterflies per column

@@ -2,6 +2,8 @@
 // mapping): one radix sequence per length for the plain and the fused kernels,
 // so that both round every butterfly alike.
 #pragma once
+#include <algorithm>
+
 #include "mf_device.hpp"
 
 namespace mf {
@@ -123,8 +125,27 @@ __device__ __forceinline__ float swap_lanes(float v) {
 // of L rows, slot c of column col_of(c), each its own LDS segment of SEG.
 // The first forward radix-16 pass reads its inputs straight from HBM (a wave
 // covers TC slots of 64/TC rows) and writes its outputs to LDS; the rest of
-// the forward transform (radix RM..., RL) runs in LDS.
-template <int L, int TC, int NTH, int SEG, typename ColOf>
+// the forward transform (radix RM..., RL) runs in LDS and leaves the modes in
+// natural order.  The helpers take the exchange layouts of PairLayout (or
+// the XOR swizzle, layout -1, for every exchange).
+template <int L, int TC>
+struct PairLayout {
+    static constexpr int RL = last_radix<L>(), RM = middle_radix<L>();
+    static constexpr int A1 = pad_of(L, 16, 1);                  // first forward pass writes
+    static constexpr int AC = pad_after(L, RM, 16, RL, A1);      // middle forward passes leave
+    static constexpr int AN = pad_of(L, RL, L / RL);             // natural-order modes
+    static constexpr int AF = pad_of(L, RL, 1);                  // first inverse pass writes
+    static constexpr int AD = pad_after(L, RM, RL, 16, AF);      // middle inverse passes leave
+    static constexpr int AMAX = std::max({pad_max(L, RM, 16, RL, A1), AN, pad_max(L, RM, RL, 16, AF)});
+    static constexpr int SEG = tile_seg(TC, A1, AD, pad_len(L, AMAX));
+};
+
+// LDS per CU on gfx950, and whether a kernel whose LDS grows from `before`
+// to `after` bytes per workgroup keeps as many resident workgroups per CU.
+constexpr int kLdsPerCU = 160 * 1024;
+constexpr bool lds_keeps_blocks(int before, int after) { return kLdsPerCU / after >= kLdsPerCU / before; }
+
+template <int L, int TC, int NTH, int SEG, int A1 = -1, typename ColOf>
 __device__ __forceinline__ void col_first_forward(float2* lds, const float2* fld, int W, unsigned tid, ColOf col_of) {
     constexpr int NT16 = L / 16;
     constexpr int IT16 = (TC * NT16 + NTH - 1) / NTH;
@@ -139,25 +160,28 @@ __device__ __forceinline__ void col_first_forward(float2* lds, const float2* fld
             for (int r = 0; r < 16; ++r) v[r] = fld[(int64_t)(j + r * NT16) * W + col];
             dft<16, false>(v);
 #pragma unroll
-            for (int r = 0; r < 16; ++r) lds[c * SEG + swz(j * 16 + r)] = v[r];
+            for (int r = 0; r < 16; ++r) lds[c * SEG + lpos_run<A1, 16>(j, r)] = v[r];
         }
     }
 }
-template <int L, int TPC>
+template <int L, int TPC, int A1 = -1>
 __device__ __forceinline__ void col_forward_rest(float2* buf, unsigned lane, const float2* __restrict__ tw) {
-    constexpr int RL = last_radix<L>();
-    passes_before<L, middle_radix<L>(), 16, RL, TPC, false>(buf, lane, tw);
-    stockham_pass<L, RL, L / RL, TPC, false>(buf, lane, tw);
+    constexpr int RL = last_radix<L>(), RM = middle_radix<L>();
+    constexpr int AC = pad_after(L, RM, 16, RL, A1);
+    constexpr int AN = A1 >= 0 ? pad_of(L, RL, L / RL) : -1;
+    passes_before<L, RM, 16, RL, TPC, false, A1>(buf, lane, tw);
+    stockham_pass<L, RL, L / RL, TPC, false, AC, AN>(buf, lane, tw);
 }
 // Inverse counterpart: radix RL, RM... in LDS, then the last radix-16 pass
 // writes natural-order rows straight to HBM.
-template <int L, int TPC>
+template <int L, int TPC, int AN = -1>
 __device__ __forceinline__ void col_inverse_head(float2* buf, unsigned lane, const float2* __restrict__ tw) {
     constexpr int RL = last_radix<L>();
-    stockham_pass<L, RL, 1, TPC, true>(buf, lane, tw);
-    passes_before<L, middle_radix<L>(), RL, 16, TPC, true>(buf, lane, tw);
+    constexpr int AF = AN >= 0 ? pad_of(L, RL, 1) : -1;
+    stockham_pass<L, RL, 1, TPC, true, AN, AF>(buf, lane, tw);
+    passes_before<L, middle_radix<L>(), RL, 16, TPC, true, AF>(buf, lane, tw);
 }
-template <int L, int TC, int NTH, int SEG, typename ColOf>
+template <int L, int TC, int NTH, int SEG, int AD = -1, typename ColOf>
 __device__ __forceinline__ void col_last_inverse(const float2* lds, float2* fld, int W, unsigned tid,
                                                  const float2* __restrict__ tw, ColOf col_of) {
     constexpr int NT16 = L / 16;
@@ -170,7 +194,7 @@ __device__ __forceinline__ void col_last_inverse(const float2* lds, float2* fld,
             const int64_t col = col_of((int)c);
             float2 v[16];
 #pragma unroll
-            for (int r = 0; r < 16; ++r) v[r] = lds[c * SEG + swz(j + r * NT16)];
+            for (int r = 0; r < 16; ++r) v[r] = lds[c * SEG + lpos_step<AD, NT16>(j, r)];
 #pragma unroll
             for (int r = 1; r < 16; ++r) v[r] = cmulc(v[r], tw[r * j]);
             dft<16, true>(v);
