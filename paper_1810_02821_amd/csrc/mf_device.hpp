@@ -251,13 +251,17 @@ template <int REM>
 constexpr int next_radix() {
     return REM % 16 == 0 ? 16 : REM % 8 == 0 ? 8 : REM % 4 == 0 ? 4 : REM % 2 == 0 ? 2 : 3;
 }
-template <int L, int NS, int TPG, bool INV>
+// A whole transform in LDS, reading layout AI and leaving its natural-order
+// output in layout AOUT; with AI >= 0 the exchanges between its passes take
+// the pads pad_of picks, otherwise the XOR swizzle.
+template <int L, int NS, int TPG, bool INV, int AI = -1, int AOUT = -1>
 __device__ __forceinline__ void stockham_fft(float2* buf, unsigned lane, const float2* __restrict__ tw) {
     if constexpr (NS < L) {
         constexpr int R = next_radix<L / NS>();
         static_assert((L / NS) % R == 0, "transform length must be 2^a 3^b");
-        stockham_pass<L, R, NS, TPG, INV>(buf, lane, tw);
-        stockham_fft<L, NS * R, TPG, INV>(buf, lane, tw);
+        constexpr int AO = NS * R == L ? AOUT : (AI >= 0 ? pad_of(L, R, NS) : -1);
+        stockham_pass<L, R, NS, TPG, INV, AI, AO>(buf, lane, tw);
+        stockham_fft<L, NS * R, TPG, INV, AO, AOUT>(buf, lane, tw);
     }
 }
 

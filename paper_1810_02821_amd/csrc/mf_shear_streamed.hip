@@ -324,7 +324,15 @@ __global__ __launch_bounds__(kRowThreads) void shear_row_kernel_f(ShearStreamArg
 template <int L>
 __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearStreamArgs a, int W) {
     constexpr int TC = ShearColShape<L>::TC, NTH = ShearColShape<L>::NTH, TPC = ShearColShape<L>::TPC;
-    constexpr int SEG = ShearColShape<L>::SEG;
+    // padded exchange layouts from 256 rows (the HBM-side passes) where they
+    // keep the resident workgroups per CU, else the XOR swizzle; an emission
+    // sweep's round trip starts and ends in the natural-order layout AN
+    constexpr int kExtra = 8 * L;  // the twiddle table beside the tile
+    constexpr bool kPad = L >= 256 && lds_keeps_blocks(TC * ShearColShape<L>::SEG * 8 + kExtra,
+                                                       TC * PairLayout<L, TC>::SEG * 8 + kExtra);
+    constexpr int A1 = kPad ? PairLayout<L, TC>::A1 : -1, AN = kPad ? PairLayout<L, TC>::AN : -1;
+    constexpr int AD = kPad ? PairLayout<L, TC>::AD : -1;
+    constexpr int SEG = kPad ? PairLayout<L, TC>::SEG : ShearColShape<L>::SEG;
     constexpr int H = L;
     constexpr int half = TC / 2;
     __shared__ float2 lds[TC * SEG];
@@ -343,9 +351,9 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
     if constexpr (L >= 256) {
         // first forward pass straight from HBM (plan of mf_streamed_fft.hpp)
         for (unsigned i = tid; i < (unsigned)L; i += NTH) twl[i] = a.tw_col[i];
-        col_first_forward<L, TC, NTH, SEG>(lds, fin, W, tid, col_of);
+        col_first_forward<L, TC, NTH, SEG, A1>(lds, fin, W, tid, col_of);
         __syncthreads();
-        col_forward_rest<L, TPC>(lds + cid * SEG, lane, twl);
+        col_forward_rest<L, TPC, A1>(lds + cid * SEG, lane, twl);
     } else {
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
             const int s = (int)(e % TC), y = (int)(e / TC);
@@ -364,8 +372,8 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
     const uint32_t pid = (uint32_t)pr.pid, chain = (uint32_t)it.pair;
     auto update = [&](int s, int p, int ky, int my, bool self, float nPk, float2 hk, float2 hm) {
         const int ck = pair_column(j, s, half, W);
-        float2& zk = lds[s * SEG + swz(ky)];
-        float2& zm = lds[p * SEG + swz(my)];
+        float2& zk = lds[s * SEG + lpos<AN>(ky)];
+        float2& zm = lds[p * SEG + lpos<AN>(my)];
         const float2 dk = ks(ky, ck, H, W), dm = ks_mirror(dk, ky, ck, H, W);
         const float2 uk = mulc(zk, dk), um = mulc(zm, dm);
         const Filt c = filt(nPk, a.b_ratio, T, inv_n, n, ky == 0 && ck == 0);
@@ -448,17 +456,17 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
     if (a.emit) {
         // stage F_col^-1(kappa^) for the emission kernel, then transform back
         // (the unnormalised round trip returns H kappa^) and take D kappa^
-        stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
+        stockham_fft<L, 1, TPC, true, AN, AN>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
         float2* kout = a.kfield + it.field_off;
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
             const int s = (int)(e % TC), y = (int)(e / TC);
-            kout[(int64_t)y * W + pair_column(j, s, half, W)] = lds[s * SEG + swz(y)];
+            kout[(int64_t)y * W + pair_column(j, s, half, W)] = lds[s * SEG + lpos<AN>(y)];
         }
-        stockham_fft<L, 1, TPC, false>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
+        stockham_fft<L, 1, TPC, false, AN, AN>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
         const float back = 1.0f / (float)H;
         for (unsigned e = opaque(tid); e < (unsigned)(TC * L); e += NTH) {
             const int s = (int)(e % TC), y = (int)(e / TC);
-            float2& v = lds[s * SEG + swz(y)];
+            float2& v = lds[s * SEG + lpos<AN>(y)];
             v = cmul(v, cscale(ks(y, pair_column(j, s, half, W), H, W), back));
         }
         __syncthreads();
@@ -466,8 +474,8 @@ __global__ __launch_bounds__(ShearColShape<L>::NTH) void shear_col_kernel(ShearS
     float2* fout = a.field + it.field_off;
     if constexpr (L >= 256) {
         // inverse transform, its last pass straight to HBM
-        col_inverse_head<L, TPC>(lds + opaque(cid) * SEG, opaque(lane), twl + opaque(0u));
-        col_last_inverse<L, TC, NTH, SEG>(lds, fout, W, opaque(tid), twl + opaque(0u), col_of);
+        col_inverse_head<L, TPC, AN>(lds + opaque(cid) * SEG, opaque(lane), twl + opaque(0u));
+        col_last_inverse<L, TC, NTH, SEG, AD>(lds, fout, W, opaque(tid), twl + opaque(0u), col_of);
     } else {
         stockham_fft<L, 1, TPC, true>(lds + opaque(cid) * SEG, opaque(lane), opaque(a.tw_col));
         for (unsigned e = tid; e < (unsigned)(TC * L); e += NTH) {
