@@ -141,9 +141,13 @@ struct PairLayout {
 };
 
 // LDS per CU on gfx950, and whether a kernel whose LDS grows from `before`
-// to `after` bytes per workgroup keeps as many resident workgroups per CU.
+// to `after` bytes per workgroup keeps as many resident workgroups per CU,
+// or at least four (small tiles, whose launches are rarely LDS-bound).
 constexpr int kLdsPerCU = 160 * 1024;
-constexpr bool lds_keeps_blocks(int before, int after) { return kLdsPerCU / after >= kLdsPerCU / before; }
+constexpr bool lds_keeps_blocks(int before, int after) {
+    const int b = kLdsPerCU / before, a = kLdsPerCU / after;
+    return a >= (b < 4 ? b : 4);
+}
 
 template <int L, int TC, int NTH, int SEG, int A1 = -1, typename ColOf>
 __device__ __forceinline__ void col_first_forward(float2* lds, const float2* fld, int W, unsigned tid, ColOf col_of) {
