@@ -58,6 +58,29 @@ def test_packed_chains_match_oracle(torch_cuda, graph):
     assert worst < REL_TOL
 
 
+@pytest.mark.parametrize("size,count", [(1024, 3), (2048, 2)])
+def test_packed_long_columns_match_oracle(torch_cuda, size, count):
+    """The packed column step at 1024 and 2048 rows (padded LDS layouts; at
+    1024 an odd count leaves one problem alone in its field)."""
+    mf = _mf()
+    banner(f"packed single chains {size}^2 x {count}")
+    probs = synth.config_uneven(22 + size // 1024, n_problems=count, sizes=(size,), weights=(1.0,))
+    plan = mf.Plan(probs)
+    d = plan.concat([p.d for p in probs])
+    st = plan.state_buffer(1)
+    flat, _ = plan.sample(d, 57, chains=1, burn_in=1, n_samples=1, form="streamed", state_out=st)
+    worst = 0.0
+    for i, p in enumerate(probs):
+        got = plan.sample_view(flat, i, 1, 1).cpu().numpy()
+        ref, s_ref = om.sample_pair(p, 57, i, 0, 1, 1)
+        worst = max(worst, rel(got[0, 0], ref[0, 0]))
+        sv = plan.state_view(st, i, 1).cpu().numpy()[0]
+        worst = max(worst, rel(sv.real, s_ref.real))
+        assert np.all(sv.imag == 0)
+    print(f"worst {worst:.2e}")
+    assert worst < REL_TOL
+
+
 def test_packed_resume_and_dispersed_start(torch_cuda):
     """A packed run split at sweep 5 and resumed from its states equals the
     uninterrupted packed run bit for bit; dispersed starts match the oracle."""

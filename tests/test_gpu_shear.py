@@ -98,7 +98,8 @@ def test_streamed_shear_wiener_matches_oracle(torch_cuda, H, W, b_ratio):
         assert r < REL_TOL
 
 
-@pytest.mark.parametrize("H,W,b_ratio", [(256, 256, 0.3), (128, 64, 0.0), (2048, 16, 0.5), (16, 1024, 0.3)])
+@pytest.mark.parametrize("H,W,b_ratio", [(256, 256, 0.3), (128, 64, 0.0), (2048, 16, 0.5), (16, 1024, 0.3),
+                                         (1024, 16, 0.2), (512, 32, 0.4)])
 def test_streamed_shear_samples_match_oracle(torch_cuda, H, W, b_ratio):
     import paper_1810_02821_amd as mf
     banner(f"streamed shear samples {H}x{W} b {b_ratio}")

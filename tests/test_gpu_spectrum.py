@@ -106,7 +106,8 @@ def test_hierarchical_batch_and_resume(torch_cuda):
 
 
 @pytest.mark.parametrize("H,W,prior", [(256, 256, (4, 0.5)), (64, 128, (0, 0.0)), (128, 64, (2, 0.1)),
-                                         (2048, 16, (0, 0.0)), (16, 1024, (0, 0.0)), (512, 32, (3, 0.2))])
+                                         (2048, 16, (0, 0.0)), (16, 1024, (0, 0.0)), (512, 32, (3, 0.2)),
+                                         (1024, 16, (2, 0.3))])
 def test_streamed_hierarchical_samples_match_oracle(torch_cuda, H, W, prior):
     """Size classes outside the persistent kernel (256^2 and more, or H != W)
     run on the streamed kernels with mirror-paired column tiles; the long
