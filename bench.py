@@ -45,12 +45,12 @@ PEAK_VALU_LANE_OPS = 256 * 4 * 16 * 2.4e9
 # FETCH_SIZE / WRITE_SIZE runs scaled by the same counters on a 1 GiB copy, and
 # the hash of the kernel sources it was measured on (traffic is reported only
 # while the sources are unchanged).
-TRAFFIC_BYTES = int((173772.77 * 2.0 + 6492739.58 * 1.0) * 1024)  # FETCH x2.0 + WRITE x1.0 (copy-calibrated)
-TRAFFIC_SOURCES_SHA = "99d47a1f7ad4daed"
+TRAFFIC_BYTES = int((180924.27 * 2.0 + 6493822.31 * 1.0) * 1024)  # FETCH x2.0 + WRITE x1.0 (copy-calibrated)
+TRAFFIC_SOURCES_SHA = "44634bfa8470990b"
 # VALU wave-instructions per launch of the same kernel (rocprofv3 SQ_INSTS_VALU,
 # summed over the shader engines), and the source hash they were taken on.
 VALU_WAVE_INSTS = 6124336128
-VALU_SOURCES_SHA = "99d47a1f7ad4daed"
+VALU_SOURCES_SHA = "44634bfa8470990b"
 
 
 def kernel_sources_sha() -> str:

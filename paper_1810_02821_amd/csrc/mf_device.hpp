@@ -129,12 +129,12 @@ template <int R, bool INV> __device__ __forceinline__ void dft(float2 (&v)[R]) {
 // instructions take as immediates.  A is chosen per exchange by pad_of so
 // that the writing pass is free of bank conflicts within 32 lanes; the reads
 // (32 consecutive elements per 32 lanes) are free of them for every A.
-__device__ __forceinline__ unsigned swz(unsigned i) {
+__host__ __device__ __forceinline__ unsigned swz(unsigned i) {
     const unsigned h = i >> 5;
     return i ^ (((h & 7u) ^ (((h >> 1) & 3u) << 3)) & 31u);
 }
 template <int A>
-__device__ __forceinline__ unsigned lpos(unsigned i) {
+__host__ __device__ __forceinline__ unsigned lpos(unsigned i) {
     if constexpr (A < 0) return swz(i);
     else return i + (unsigned)A * (i >> 5);
 }
@@ -142,16 +142,28 @@ __device__ __forceinline__ unsigned lpos(unsigned i) {
 // Element j + r STEP of an exchange in layout A (reads of a pass with STEP =
 // L / R): a base and constant offsets when STEP is a multiple of 32.
 template <int A, int STEP>
-__device__ __forceinline__ unsigned lpos_step(unsigned j, int r) {
+__host__ __device__ __forceinline__ unsigned lpos_step(unsigned j, int r) {
     if constexpr (A >= 0 && STEP % 32 == 0) return lpos<A>(j) + r * (STEP + A * (STEP / 32));
     else return lpos<A>(j + r * STEP);
 }
 // Element R j + r (r < R) in layout A (writes of a first pass, NS = 1): the
 // run stays inside one block of 32 when R divides 32.
 template <int A, int R>
-__device__ __forceinline__ unsigned lpos_run(unsigned j, int r) {
+__host__ __device__ __forceinline__ unsigned lpos_run(unsigned j, int r) {
     if constexpr (A >= 0 && 32 % R == 0) return lpos<A>(R * j) + r;
     else return lpos<A>(R * j + r);
+}
+
+// Element o + r NS in layout A, written by a radix-R pass after NS points
+// with o = (j / NS) NS R + j mod NS: a base and constant offsets when NS is a
+// multiple of 32, or when NS divides 32 and NS R is a multiple of 32 (then
+// o's low five bits are j mod NS < NS, so o + r NS stays in the block of
+// o + (r NS mod 32)).
+template <int A, int R, int NS>
+__host__ __device__ __forceinline__ unsigned lpos_write(unsigned o, int r) {
+    if constexpr (A >= 0 && NS % 32 == 0) return lpos<A>(o) + r * (NS + A * (NS / 32));
+    else if constexpr (A >= 0 && 32 % NS == 0 && (NS * R) % 32 == 0) return lpos<A>(o) + r * NS + A * ((r * NS) >> 5);
+    else return lpos<A>(o + r * NS);
 }
 
 // True if the 32 lanes l < min(32, L / R) of a radix-R pass after NS points,
@@ -197,14 +209,8 @@ __device__ __forceinline__ void stockham_pass(float2* buf, unsigned lane, const 
     for (int t = 0; t < TPT; ++t) {
         const unsigned j = lane + t * TPG;
         if ((NT % TPG) == 0 || j < (unsigned)NT) {
-            if constexpr (AI >= 0 && NT % 32 == 0) {
-                const unsigned b = lpos<AI>(j);
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[t][r] = buf[b + r * (NT + AI * (NT / 32))];
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) v[t][r] = buf[lpos<AI>(j + r * NT)];
-            }
+            for (int r = 0; r < R; ++r) v[t][r] = buf[lpos_step<AI, NT>(j, r)];
             if constexpr (NS > 1) {
                 const unsigned k = j % NS;
 #pragma unroll
@@ -223,20 +229,8 @@ __device__ __forceinline__ void stockham_pass(float2* buf, unsigned lane, const 
         if ((NT % TPG) == 0 || j < (unsigned)NT) {
             const unsigned k = j % NS;
             const unsigned o = (j / NS) * NS * R + k;
-            if constexpr (AO >= 0 && NS % 32 == 0) {
-                const unsigned b = lpos<AO>(o);
 #pragma unroll
-                for (int r = 0; r < R; ++r) buf[b + r * (NS + AO * (NS / 32))] = v[t][r];
-            } else if constexpr (AO >= 0 && 32 % NS == 0 && (NS * R) % 32 == 0) {
-                // o's low five bits are k < NS, so o + r NS stays below the
-                // next multiple of 32 past o + (r NS mod 32)
-                const unsigned b = lpos<AO>(o);
-#pragma unroll
-                for (int r = 0; r < R; ++r) buf[b + r * NS + AO * ((r * NS) >> 5)] = v[t][r];
-            } else {
-#pragma unroll
-                for (int r = 0; r < R; ++r) buf[lpos<AO>(o + r * NS)] = v[t][r];
-            }
+            for (int r = 0; r < R; ++r) buf[lpos_write<AO, R, NS>(o, r)] = v[t][r];
         }
     }
     __syncthreads();
