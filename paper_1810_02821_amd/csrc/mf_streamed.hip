@@ -1552,7 +1552,7 @@ hipError_t launch_col_shape(int W, int H, int tc, int nth, const SweepArgs& a, h
 // lengths with a factor 3 have their one default tile.
 int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
     static const int table[][3] = {{16, 16, 256}, {32, 16, 256}, {64, 16, 256}, {128, 16, 256},
-                                   {256, 16, 256}, {256, 8, 256}, {256, 16, 512}, {256, 8, 512},
+                                   {256, 8, 256}, {256, 16, 256}, {256, 16, 512}, {256, 8, 512},
                                    {256, 4, 128}, {256, 4, 256},
                                    {512, 16, 512}, {512, 8, 512}, {512, 16, 256}, {512, 16, 1024},
                                    {512, 8, 256}, {512, 4, 256},
