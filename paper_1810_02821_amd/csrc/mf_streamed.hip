@@ -1554,10 +1554,10 @@ int col_shape_candidates(int H, int* tc, int* nth, int max_n) {
     static const int table[][3] = {{16, 16, 256}, {32, 16, 256}, {64, 16, 256}, {128, 16, 256},
                                    {256, 8, 256}, {256, 16, 256}, {256, 16, 512}, {256, 8, 512},
                                    {256, 4, 128}, {256, 4, 256},
-                                   {512, 16, 512}, {512, 8, 512}, {512, 16, 256}, {512, 16, 1024},
-                                   {512, 8, 256}, {512, 4, 256},
-                                   {1024, 8, 512}, {1024, 16, 1024}, {1024, 8, 1024}, {1024, 16, 512},
-                                   {1024, 4, 256},
+                                   {512, 8, 256}, {512, 16, 512}, {512, 8, 512}, {512, 16, 256},
+                                   {512, 16, 1024}, {512, 4, 256},
+                                   {1024, 4, 256}, {1024, 8, 512}, {1024, 16, 1024}, {1024, 8, 1024},
+                                   {1024, 16, 512},
                                    {2048, 4, 256}, {2048, 8, 512}, {2048, 8, 1024}, {2048, 4, 512}};
     int n = 0;
     for (const auto& r : table)

@@ -187,7 +187,7 @@ def test_autotuned_shapes_give_identical_samples(torch_cuda):
     shapes = {p.H: (base.tile_shape(p.H, p.W), tuned.tile_shape(p.H, p.W)) for p in probs}
     rows = {p.H: (base.row_shape(p.H, p.W), tuned.row_shape(p.H, p.W)) for p in probs}
     print("default / tuned column tiles:", shapes, "fused row rows:", rows)
-    defaults = {256: (8, 256), 512: (16, 512), 1024: (8, 512), 2048: (4, 256)}
+    defaults = {256: (8, 256), 512: (8, 256), 1024: (4, 256), 2048: (4, 256)}
     row_defaults = {256: 8, 512: 8, 1024: 2, 2048: 1}
     row_choices = {256: (8, 4, 16), 512: (8, 4, 2), 1024: (2, 1, 4), 2048: (1, 2)}
     # launches too small to fill the GPU: the shapes with the most workgroups
