@@ -30,10 +30,12 @@ struct ShearRowShape {
     static constexpr int TPR = kRowThreads / ROWS;
 };
 
+// 32 threads per column from 256 rows (at 256, 512 threads ran the 256^2
+// hierarchical and mass-mapping samplers 3.5% and 5% faster than 256).
 template <int L>
 struct ShearColShape {
     static constexpr int TC = L >= 2048 ? 8 : 16;
-    static constexpr int NTH = L >= 1024 ? 1024 : (L >= 512 ? 512 : 256);
+    static constexpr int NTH = L >= 1024 ? 1024 : (L >= 256 ? 512 : 256);
     static constexpr int TPC = NTH / TC;
     static constexpr int SEG = L + 32 / TC;
 };
