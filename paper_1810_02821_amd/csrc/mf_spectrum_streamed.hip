@@ -26,12 +26,15 @@ namespace {
 constexpr int kNB = kMaxBandsPerProblem;
 constexpr uint32_t kStageSpectrum = 3;
 
-// 32 threads per column from 256 rows (at 256, 512 threads ran the 256^2
-// hierarchical and mass-mapping samplers 3.5% and 5% faster than 256).
+// Tiles of the mirror-paired column kernel, timed on the hierarchical and
+// mass-mapping samplers: 16 columns below 512 rows (512 threads at 256), 8
+// columns from 512 rows with 256 threads at 512, 512 at 1024 and 1024 at 2048
+// (at 512 and 1024 rows 3.8-11.6% faster than 16 columns of 512 and 1024
+// threads).
 template <int L>
 struct PairShape {
-    static constexpr int TC = L >= 2048 ? 8 : 16;
-    static constexpr int NTH = L >= 1024 ? 1024 : (L >= 256 ? 512 : 256);
+    static constexpr int TC = L >= 512 ? 8 : 16;
+    static constexpr int NTH = L >= 2048 ? 1024 : (L == 1024 ? 512 : (L == 256 ? 512 : 256));
     static constexpr int TPC = NTH / TC;
     static constexpr int SEG = L + 32 / TC;
 };
