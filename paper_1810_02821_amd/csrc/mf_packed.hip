@@ -23,12 +23,13 @@ namespace mf {
 namespace {
 
 // Tile of the packed column step: 16 columns (8 and their mirrors), 8 from
-// 2048 rows; 32 threads per column from 256 rows (at 256, 512 threads ran the
-// uneven batch's 256^2 class 1.8% faster than 256).
+// 1024 rows; 32 threads per column at 256 and 512 rows (at 256, 512 threads
+// ran the uneven batch's 256^2 class 1.8% faster than 256), 64 at 1024 (8 x
+// 512: 7% faster on 1024^2 problems than 16 x 1024), 128 at 2048.
 template <int L>
 struct PackShape {
-    static constexpr int TC = L >= 2048 ? 8 : 16;
-    static constexpr int NTH = L >= 1024 ? 1024 : (L >= 256 ? 512 : 256);
+    static constexpr int TC = L >= 1024 ? 8 : 16;
+    static constexpr int NTH = L >= 2048 ? 1024 : (L >= 256 ? 512 : 256);
     static constexpr int TPC = NTH / TC;
     static constexpr int SEG = L + 32 / TC;
 };
